@@ -1,0 +1,236 @@
+/*
+ * mgs.h -- C ABI of the MI355X (gfx950) order-independent Gaussian splatting pass.
+ *
+ * The pass renders 3D Gaussians (mean, scale, rotation, opacity, first-order SH
+ * colour; Appendix B of Mobile-GS, arXiv 2603.11531) with the paper's sort-free,
+ * depth-aware order-independent blend (Sec. 3.1, Eq. 2 and Eq. 3) and its
+ * view-dependent enhancement MLP (Eq. 4).  A conventional sorted alpha-blend
+ * path (Eq. 11) is provided for comparison.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array pointers are DEVICE pointers unless stated otherwise; struct
+ *   arguments themselves (mgs_camera, mgs_gaussians, ...) are HOST structs read
+ *   during the call only.
+ * - The caller owns all device memory.  The library never allocates or frees
+ *   device memory and keeps no mutable global state; calls on different streams
+ *   are independent.
+ * - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
+ *   stream).  MGS_OK means "validated and enqueued"; buffers must stay valid
+ *   until the stream reaches the work.
+ * - Per-Gaussian inputs are structure-of-arrays float32 ("[3][n]" = three
+ *   planes of n floats).  Images are planar float32 [3][H][W].
+ * - Pixel (i, j) has its centre at (i + 0.5, j + 0.5); camera space is
+ *   x right, y down, z forward; x_c = R * x_world + t.
+ * - Tiles are 16 x 16 pixels, numbered row-major t = ty * tiles_x + tx with
+ *   tiles_x = ceil(W / 16), tiles_y = ceil(H / 16).
+ * - Return codes: MGS_OK (0) or a negative MGS_ERR_*; no exception crosses the
+ *   ABI.  mgs_last_error() returns a thread-local description of the last error.
+ */
+#ifndef MGS_H
+#define MGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGS_OK                 0
+#define MGS_ERR_INVALID_ARG   (-1)  /* NULL required pointer, bad size, misaligned pointer */
+#define MGS_ERR_CAPACITY      (-2)  /* pair count exceeded the caller's capacity           */
+#define MGS_ERR_HIP           (-3)  /* a HIP launch or runtime call failed                 */
+#define MGS_ERR_UNSUPPORTED   (-4)  /* valid but not supported (e.g. tile size != 16)      */
+
+#define MGS_TILE        16
+#define MGS_MLP_IN      22          /* [P_i(3), s_i(3), r_i(4), Y_i(12)]                  */
+#define MGS_MLP_HIDDEN  64
+/* Bytes of the packed enhancement-MLP weights written by mgs_mlp_pack. */
+#define MGS_MLP_PACKED_BYTES 15360
+/* Floats per projected Gaussian record ("splat"), see mgs_projected. */
+#define MGS_SPLAT_FLOATS 12
+
+/* Pinhole camera.  R is row-major world->camera (rows: right, down, forward). */
+typedef struct mgs_camera {
+    float   R[9];
+    float   t[3];
+    float   fx, fy, cx, cy;
+    int32_t width, height;
+    float   near_z;           /* Gaussians with camera depth <= near_z are culled */
+} mgs_camera;
+
+/* Gaussian attributes (Appendix B), SoA float32 device arrays. */
+typedef struct mgs_gaussians {
+    int64_t      n;
+    const float *mean;          /* [3][n] world position mu                          */
+    const float *log_scale;     /* [3][n] s = exp(log_scale)                          */
+    const float *quat;          /* [4][n] rotation (w, x, y, z), need not be unit     */
+    const float *opacity_logit; /* [n]    o = sigmoid(opacity_logit)                  */
+    const float *sh;            /* [12][n] SH degree-1 coefficients, plane 3k + ch    */
+} mgs_gaussians;
+
+/* Gradients with respect to the raw attributes; same layout as mgs_gaussians. */
+typedef struct mgs_gaussians_grad {
+    float *mean, *log_scale, *quat, *opacity_logit, *sh;
+} mgs_gaussians_grad;
+
+/*
+ * Projected Gaussians, written by mgs_project.
+ *   splat   [n][12] float32, three float4 per Gaussian:
+ *             (mx, my, log2(o_eff), w)   screen-space mean, log2 effective opacity, Eq. 3 weight
+ *             (kA, beta, kG, depth)      the exponent of Eq. 2 as two non-negative parts:
+ *                                        log2(alpha) = log2(o_eff) + kA t^2 + kG dy^2,
+ *                                        t = dx + beta dy, (dx, dy) = pixel - mean, and for the
+ *                                        2D covariance [[a, b], [b, c]] (determinant det):
+ *                                        kA = -(1/2) log2(e) c / det, beta = -b / c,
+ *                                        kG = -(1/2) log2(e) / c; depth = camera z
+ *             (r, g, b, o_eff)           SH colour, effective opacity
+ *   rect    [n][2] uint32: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive tile range
+ *   n_tiles [n] uint32: tiles covered (0 = culled)
+ * Pointers must be 16-byte aligned (splat) / 8-byte (rect) / 4-byte (n_tiles).
+ */
+typedef struct mgs_projected {
+    float    *splat;
+    uint32_t *rect;
+    uint32_t *n_tiles;
+} mgs_projected;
+
+/* Thread-local message of the last error (static storage, never NULL). */
+const char *mgs_last_error(void);
+/* Library version string. */
+const char *mgs_version(void);
+
+/*
+ * Enhancement-MLP parameters (Eq. 4), one contiguous float32 array of
+ * MGS_MLP_PARAMS values, row-major [out][in] matrices:
+ *   W1 [64][22] @ MGS_MLP_OFF_W1, b1 [64] @ MGS_MLP_OFF_B1, W2 [64][64] @ MGS_MLP_OFF_W2,
+ *   b2 [64] @ MGS_MLP_OFF_B2, w_phi [64] @ MGS_MLP_OFF_WPHI, b_phi @ MGS_MLP_OFF_BPHI,
+ *   w_o [64] @ MGS_MLP_OFF_WO, b_o @ MGS_MLP_OFF_BO.
+ * The network is F = ReLU(W2 ReLU(W1 x + b1) + b2), phi = ReLU(w_phi . F + b_phi),
+ * m = sigmoid(w_o . F + b_o), x = [P_i, s_i, r_i, Y_i].  Gradients use the same layout.
+ */
+#define MGS_MLP_OFF_W1    0
+#define MGS_MLP_OFF_B1    1408
+#define MGS_MLP_OFF_W2    1472
+#define MGS_MLP_OFF_B2    5568
+#define MGS_MLP_OFF_WPHI  5632
+#define MGS_MLP_OFF_BPHI  5696
+#define MGS_MLP_OFF_WO    5697
+#define MGS_MLP_OFF_BO    5761
+#define MGS_MLP_PARAMS    5762
+
+/*
+ * mgs_mlp_pack -- MLP parameters -> packed bfloat16 MFMA operands for mgs_enhance.
+ * In: params (device, MGS_MLP_PARAMS floats).  Out: `packed`, MGS_MLP_PACKED_BYTES
+ * bytes of device memory, 16-byte aligned.  Weights are rounded to bfloat16
+ * (nearest-even); biases stay float32.  Re-run after every weight update.
+ */
+int mgs_mlp_pack(const float *params, void *packed, void *stream);
+
+/*
+ * mgs_enhance -- view-dependent enhancement, Eq. 4 (Sec. 3.1).
+ * For every Gaussian: P_i = (mu - t_v)/|mu - t_v| with t_v the camera centre,
+ * s = exp(log_scale), r = normalised quaternion, Y = SH coefficients; runs the
+ * packed MLP with bfloat16 inputs and float32 accumulation.
+ * Out: phi [n] (>= 0) and omod [n] (in (0, 1)), float32 device arrays.
+ * The opacity head modulates the stored opacity: o_eff = sigmoid(logit) * omod.
+ */
+int mgs_enhance(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp,
+                float *phi, float *omod, void *stream);
+
+/*
+ * mgs_project -- per-Gaussian preprocessing for Eq. 2 / Eq. 3.
+ * Camera-space depth d, EWA projection Sigma' = J W Sigma W^T J^T + 0.3 I of
+ * Sigma = R S S^T R^T (J clamped to 1.3x the half field of view), first-order
+ * SH colour c = max(0, 1/2 + C0 Y0 + C1 (-P_y Y1 + P_z Y2 - P_x Y3)),
+ * o_eff = sigmoid(logit) * omod, weight w = phi^2 + phi/d^2 + exp(s_max/d)
+ * (Eq. 3), and the inclusive tile rectangle of the pixel centres inside the
+ * bounding box of {alpha >= alpha_min}.
+ * phi / omod may be NULL (then phi = 1, omod = 1: the MLP's initial state).
+ * Culled (n_tiles = 0): d <= near_z, o_eff < alpha_min, empty pixel range.
+ * tile must be MGS_TILE.  alpha_min in (0, 1).
+ */
+int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
+                const float *omod, int tile, float alpha_min, mgs_projected *out,
+                void *stream);
+
+/*
+ * mgs_bin_workspace -- device workspace bytes mgs_bin needs for n Gaussians,
+ * a tile grid of tiles_x * tiles_y and at most `capacity` tile/Gaussian pairs.
+ */
+int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes);
+
+/*
+ * mgs_bin -- tile binning with no depth sort (atomic-free prefix sums).
+ * From rect / n_tiles of mgs_project: P = sum(n_tiles) pairs are laid out per
+ * tile; the list of tile t is gids[tile_offsets[t] .. tile_offsets[t+1]) in
+ * ascending Gaussian index.  The result is deterministic (bit-identical runs).
+ * Out: tile_offsets [T + 1] uint32, gids [capacity] uint32, n_pairs [1]
+ * uint32 (device) = P.  If P > capacity nothing but n_pairs is written; the
+ * caller detects the overflow from n_pairs after synchronising (this keeps
+ * the call free of host synchronisation).
+ * ws/ws_bytes: workspace of at least mgs_bin_workspace() bytes, 256-byte aligned.
+ */
+int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
+            size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
+            uint32_t *n_pairs, void *stream);
+
+/*
+ * mgs_blend_oit -- the depth-aware order-independent composite, Eq. 2.
+ * For every pixel p over its tile's list: a = o_eff exp(-q/2),
+ * q = dx^T Sigma'^-1 dx; pairs with a < alpha_min are skipped;
+ * alpha = min(a, alpha_max); N += alpha w c, D += alpha w, T *= (1 - alpha);
+ * C = (1 - T) N / D + T bg, or C = bg when no Gaussian contributes.
+ * Out: image [3][H][W] float32; aux [5][H][W] float32 = (N/D rgb, D, T) or NULL.
+ * bg is a HOST array of 3 floats.
+ */
+int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                  const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
+                  float alpha_max, float *image, float *aux, void *stream);
+
+/*
+ * Sorted comparison path (3DGS alpha blending, Eq. 11, Appendix B).
+ * mgs_bin_sorted: like mgs_bin but each tile's list is in ascending camera
+ * depth (ties by Gaussian index): LSD radix sort of 64-bit (tile << 32 |
+ * depth bits) keys.  Same outputs and overflow rule as mgs_bin.
+ * mgs_blend_sorted: front-to-back C = sum_k c_k alpha_k T_k + T bg, compositing
+ * a contributor only while the transmittance before it is >= t_stop.
+ */
+int mgs_bin_sorted_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes);
+int mgs_bin_sorted(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
+                   size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
+                   uint32_t *n_pairs, void *stream);
+int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                     const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
+                     float alpha_max, float t_stop, float *image, void *stream);
+
+/*
+ * mgs_render_backward -- gradients of the OIT pass (Eq. 2, Eq. 3, Eq. 4) with
+ * respect to the raw Gaussian attributes and, with the MLP, its parameters.
+ * It recomputes per-pixel-pair terms from the forward's aux (N/D rgb, D, T):
+ * no per-fragment state is kept.  The reduction over pixels and tiles uses
+ * no float atomics, so results are bit-reproducible.
+ * In: g, cam, proj / tile_offsets / gids (exactly as used by the forward,
+ * capacity = the gids capacity passed to mgs_bin), aux [5][H][W] from
+ * mgs_blend_oit, dL_dimage [3][H][W], bg (HOST, 3 floats), alpha_min / alpha_max
+ * of the forward.  MLP: mlp_params (MGS_MLP_PARAMS floats, device) plus the
+ * forward's phi / omod, or all three NULL when the forward ran without the MLP.
+ * Out: *out (same SoA layout as mgs_gaussians, fully overwritten) and, with the
+ * MLP, dmlp [MGS_MLP_PARAMS] (overwritten).  The MLP gradient passes straight
+ * through the forward's bfloat16 roundings.
+ * ws: mgs_render_backward_workspace() bytes, 256-byte aligned.
+ */
+int mgs_render_backward_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, int with_mlp,
+                                  size_t *bytes);
+int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam, const float *mlp_params,
+                        const float *phi, const float *omod, const mgs_projected *proj,
+                        const uint32_t *tile_offsets, const uint32_t *gids, uint64_t capacity,
+                        const float *aux, const float *dL_dimage, const float bg[3], float alpha_min,
+                        float alpha_max, void *ws, size_t ws_bytes, mgs_gaussians_grad *out,
+                        float *dmlp, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGS_H */

@@ -31,7 +31,7 @@ __all__ = [
     "ALPHA_MIN", "ALPHA_MAX", "DILATION", "JAC_CLAMP", "T_STOP", "SH_C0", "SH_C1",
     "AMBIG_LOG", "to64", "quat_to_rotmat", "activate", "camera_space", "sh1_color",
     "mlp_features", "enhance", "depth_weight", "ewa_cov2d", "project", "bin_lists",
-    "bin_lists_bruteforce", "pixel_grid", "eval_pixels_oit", "render_oit",
+    "bin_lists_bruteforce", "bin_lists_sorted", "pixel_grid", "eval_pixels_oit", "render_oit",
     "render_sorted", "render", "camera_tensors", "oit_pixel_variants",
 ]
 
@@ -278,6 +278,23 @@ def bin_lists(rect, n_tiles, tiles_x, tiles_y):
     offsets = torch.zeros(T + 1, dtype=torch.int64)
     offsets[1:] = torch.cumsum(counts, 0)
     return offsets, gids
+
+
+def bin_lists_sorted(rect, n_tiles, depth, tiles_x, tiles_y):
+    """Per-tile lists ordered by (depth, index) -- the sorted comparison path (Eq. 11).
+
+    ``depth`` is taken as given (the caller passes the precision the sort key
+    has).  Returns (tile_offsets, gids) like ``bin_lists``.
+    """
+    offs, gids = bin_lists(rect, n_tiles, tiles_x, tiles_y)
+    depth = torch.as_tensor(np.asarray(depth), dtype=DT)
+    out = gids.clone()
+    for t in range(tiles_x * tiles_y):
+        a, b = int(offs[t]), int(offs[t + 1])
+        if b - a > 1:
+            seg = gids[a:b]
+            out[a:b] = seg[torch.sort(depth[seg], stable=True).indices]
+    return offs, out
 
 
 def bin_lists_bruteforce(rect, n_tiles, tiles_x, tiles_y):

@@ -1,0 +1,149 @@
+"""ctypes binding of libmgs.so (the C ABI declared in include/mgs.h).
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every step of the render pass runs in the library's
+kernels.  Importing this module fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgs.so")
+
+MGS_OK = 0
+MGS_ERR_INVALID_ARG = -1
+MGS_ERR_CAPACITY = -2
+MGS_ERR_HIP = -3
+MGS_ERR_UNSUPPORTED = -4
+MGS_TILE = 16
+MGS_MLP_PACKED_BYTES = 15360
+MGS_SPLAT_FLOATS = 12
+MGS_MLP_PARAMS = 5762
+MLP_LAYOUT = (("W1", 0, (64, 22)), ("b1", 1408, (64,)), ("W2", 1472, (64, 64)), ("b2", 5568, (64,)),
+              ("w_phi", 5632, (64,)), ("b_phi", 5696, ()), ("w_o", 5697, (64,)), ("b_o", 5761, ()))
+
+EXPORTED = [
+    "mgs_last_error", "mgs_version", "mgs_mlp_pack", "mgs_enhance", "mgs_project",
+    "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_bin_sorted_workspace",
+    "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
+    "mgs_render_backward",
+]
+
+
+class MgsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mgs error {code}: {msg}")
+        self.code = code
+
+
+class mgs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("near_z", C.c_float)]
+
+
+class mgs_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class mgs_gaussians_grad(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class mgs_projected(C.Structure):
+    _fields_ = [("splat", C.c_void_p), ("rect", C.c_void_p), ("n_tiles", C.c_void_p)]
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2603_11531_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, u64, f32 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_float
+    P = C.POINTER
+    sig = {
+        "mgs_last_error": (C.c_char_p, []),
+        "mgs_version": (C.c_char_p, []),
+        "mgs_mlp_pack": (i32, [vp, vp, vp]),
+        "mgs_enhance": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, vp]),
+        "mgs_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, P(mgs_projected), vp]),
+        "mgs_bin_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
+        "mgs_bin": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
+        "mgs_blend_oit": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, vp, vp,
+                                vp]),
+        "mgs_bin_sorted_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
+        "mgs_bin_sorted": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
+        "mgs_blend_sorted": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, f32,
+                                   vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    lib.mgs_render_backward_workspace.restype = i32
+    lib.mgs_render_backward_workspace.argtypes = [i64, i32, i32, u64, i32, P(C.c_size_t)]
+    lib.mgs_render_backward.restype = i32
+    lib.mgs_render_backward.argtypes = [
+        P(mgs_gaussians), P(mgs_camera), vp, vp, vp, P(mgs_projected), vp, vp, u64, vp, vp, P(C.c_float), f32,
+        f32, vp, C.c_size_t, P(mgs_gaussians_grad), vp, vp]
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def check(code):
+    if code != MGS_OK:
+        raise MgsError(code, lib().mgs_last_error().decode())
+    return code
+
+
+def ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_camera(cam) -> mgs_camera:
+    c = mgs_camera()
+    for i, v in enumerate(list(map(float, cam.R.reshape(-1)))):
+        c.R[i] = v
+    for i, v in enumerate(list(map(float, cam.t.reshape(-1)))):
+        c.t[i] = v
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height, c.near_z = int(cam.width), int(cam.height), float(cam.near)
+    return c
+
+
+def make_gaussians(scene) -> mgs_gaussians:
+    """``scene`` = dict of device float32 tensors in the SoA layout of mgs.h."""
+    g = mgs_gaussians()
+    g.n = int(scene["opacity_logit"].numel())
+    g.mean, g.log_scale, g.quat = (ptr(scene[k]).value for k in ("mean", "log_scale", "quat"))
+    g.opacity_logit, g.sh = ptr(scene["opacity_logit"]).value, ptr(scene["sh"]).value
+    return g
+
+
+def make_projected(splat, rect, n_tiles) -> mgs_projected:
+    p = mgs_projected()
+    p.splat, p.rect, p.n_tiles = ptr(splat).value, ptr(rect).value, ptr(n_tiles).value
+    return p
+
+
+def bg_array(bg):
+    return (C.c_float * 3)(*[float(v) for v in bg])

@@ -1,0 +1,453 @@
+// mgs_bin / mgs_bin_sorted: tile binning by prefix sums, with no atomics.
+//
+//   1. exclusive scan of n_tiles            -> first pair slot of every Gaussian, P
+//   2. expand: each wave flattens the pairs of 64 consecutive Gaussians and
+//      writes (key, gid) for every covered tile with coalesced stores
+//   3. stable LSD radix sort on the key (digit histograms per block, a scan of
+//      the digit-major histogram, stable scatter); ranks inside a wave come from
+//      ballot-matched digits, so nothing is ordered by atomics and the output is
+//      bit-identical from run to run
+//   4. tile ranges from the sorted keys
+//
+// For the order-independent path the key is the tile id alone (about 13 bits:
+// two radix passes), so each list stays in ascending Gaussian order.  The
+// sorted comparison path uses the 64-bit key (tile << 32 | depth bits), i.e.
+// the usual depth sort, which needs 32 + tile bits of radix passes.
+#include "common.h"
+
+namespace mgs {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;     // 4096 elements per block
+constexpr int RADIX_THREADS = 256;
+constexpr int RADIX_WAVES = RADIX_THREADS / 64;
+constexpr int RADIX_ITERS = 8;                            // 64-key steps per wave
+constexpr int RADIX_TILE = RADIX_THREADS * RADIX_ITERS;   // 2048 keys per block
+constexpr int RADIX_MAX_BITS = 8;
+constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const unsigned l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive scan over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const unsigned l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o, 64);
+        if (l >= unsigned(o)) v += u;
+    }
+    return v;
+}
+
+// ----------------------------------------------------------------- device scan
+// Block-wise exclusive scan of uint32 values in three launches: block totals,
+// a one-block scan of the totals (64-bit, the grand total clamped to 2^32-1),
+// then the per-block scan with its offset.
+__global__ void __launch_bounds__(SCAN_THREADS)
+scan_reduce_kernel(const uint32_t *__restrict__ in, int64_t n, uint64_t *__restrict__ sums) {
+    __shared__ uint64_t wsum[SCAN_THREADS / 64];
+    const int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) s += in[base + k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane_id() == 0) wsum[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) t += wsum[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+scan_sums_kernel(uint64_t *__restrict__ sums, int nb, uint32_t *__restrict__ total) {
+    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const uint64_t v = i < nb ? sums[i] : 0;
+        const uint64_t inc = wave_incl_scan(v);
+        if (lane_id() == 63) wsum[threadIdx.x / 64] = inc;
+        __syncthreads();
+        uint64_t wpre = 0;
+        for (int w = 0; w < int(threadIdx.x / 64); ++w) wpre += wsum[w];
+        const uint64_t c = carry;
+        if (i < nb) sums[i] = c + wpre + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + wpre + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) {
+        const uint64_t t = carry;
+        *total = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(t);
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+scan_apply_kernel(const uint32_t *__restrict__ in, int64_t n, const uint64_t *__restrict__ sums,
+                  uint32_t *__restrict__ out) {
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    const uint32_t inc = wave_incl_scan(s);
+    if (lane_id() == 63) wsum[threadIdx.x / 64] = inc;
+    __syncthreads();
+    uint32_t pre = uint32_t(sums[blockIdx.x]);
+    for (int w = 0; w < int(threadIdx.x / 64); ++w) pre += wsum[w];
+    pre += inc - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = pre;
+        pre += v[k];
+    }
+}
+
+size_t scan_tmp_elems(int64_t n) { return size_t((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+int scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *tmp, uint32_t *total,
+                   hipStream_t s) {
+    const unsigned nb = unsigned((n + SCAN_TILE - 1) / SCAN_TILE);
+    if (nb > 0) {
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, tmp);
+        MGS_LAUNCH_CHECK("scan_reduce_kernel");
+    }
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, tmp, int(nb), total);
+    MGS_LAUNCH_CHECK("scan_sums_kernel");
+    if (nb > 0) {
+        hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, tmp, out);
+        MGS_LAUNCH_CHECK("scan_apply_kernel");
+    }
+    return MGS_OK;
+}
+
+// ----------------------------------------------------------------- expand
+struct TileKey {
+    __device__ __forceinline__ uint32_t operator()(uint32_t tile, const float4 *) const { return tile; }
+};
+struct TileDepthKey {
+    __device__ __forceinline__ uint64_t operator()(uint32_t tile, const float4 *rec1) const {
+        // depth > near_z > 0 for every listed Gaussian, so its IEEE bits order like the value
+        return (uint64_t(tile) << 32) | uint64_t(__float_as_uint(rec1->w));
+    }
+};
+
+template <typename K, typename KeyFn>
+__global__ void __launch_bounds__(256)
+expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
+              const uint32_t *__restrict__ first, const float4 *__restrict__ splat, int64_t n,
+              int tiles_x, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+              K *__restrict__ keys, uint32_t *__restrict__ vals, KeyFn keyfn) {
+    __shared__ uint32_t s_excl[4][64];
+    __shared__ uint2 s_rect[4][64];
+    if (uint64_t(*n_pairs) > capacity) return;
+    const int w = threadIdx.x / 64;
+    const unsigned l = lane_id();
+    const int64_t g0 = (int64_t(blockIdx.x) * 4 + w) * 64;
+    if (g0 >= n) return;                      // wave-uniform
+    const int64_t g = g0 + l;
+    const uint32_t cnt = g < n ? ntiles[g] : 0u;
+    const uint32_t inc = wave_incl_scan(cnt);
+    const uint32_t total = __shfl(inc, 63, 64);
+    s_excl[w][l] = inc - cnt;
+    s_rect[w][l] = g < n ? rect[g] : make_uint2(0u, 0u);
+    const uint32_t base = first[g0];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t p = l; p < total; p += 64) {
+        // last j with excl[j] <= p (it has a non-zero count)
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (s_excl[w][lo + step] <= p) lo += step;
+        const uint32_t k = p - s_excl[w][lo];
+        const uint2 r = s_rect[w][lo];
+        const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu;
+        const uint32_t wdt = x1 - x0 + 1;
+        const uint32_t ty = y0 + k / wdt;
+        const uint32_t tx = x0 + k % wdt;
+        const uint32_t tile = ty * uint32_t(tiles_x) + tx;
+        const int64_t gg = g0 + lo;
+        keys[base + p] = keyfn(tile, splat + 3 * gg + 1);
+        vals[base + p] = uint32_t(gg);
+    }
+}
+
+// ----------------------------------------------------------------- radix sort
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
+    return uint32_t(key >> shift) & mask;
+}
+
+// Ballot match: lanes of `active` holding the same digit as this lane.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t active) {
+    uint64_t peers = active;
+    for (int b = 0; b < bits; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return peers;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(RADIX_THREADS)
+radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+                     int shift, int bits, uint32_t *__restrict__ counts, int nblocks) {
+    __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
+    const uint32_t P = *n_pairs;
+    const int nd = 1 << bits;
+    const uint32_t mask = uint32_t(nd - 1);
+    for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / 64;
+    const unsigned l = lane_id();
+    if (uint64_t(P) <= capacity) {
+        const int64_t base = int64_t(blockIdx.x) * RADIX_TILE + w * (RADIX_ITERS * 64);
+        for (int it = 0; it < RADIX_ITERS; ++it) {
+            const int64_t idx = base + it * 64 + l;
+            const bool ok = idx < int64_t(P);
+            const uint64_t active = __ballot(ok);
+            if (active == 0) break;
+            const uint32_t d = ok ? digit_of(keys[idx], shift, mask) : 0u;
+            const uint64_t peers = match_digit(d, bits, active);
+            if (ok && (peers >> l) == 1ull) cnt[w][d] += uint32_t(__popcll(peers));  // highest lane of its digit
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS) {
+        uint32_t s = 0;
+        for (int ww = 0; ww < RADIX_WAVES; ++ww) s += cnt[ww][d];
+        counts[int64_t(d) * nblocks + blockIdx.x] = s;
+    }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(RADIX_THREADS)
+radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+                       const uint32_t *__restrict__ n_pairs, uint64_t capacity, int shift, int bits,
+                       const uint32_t *__restrict__ offsets, int nblocks, K *__restrict__ keys_out,
+                       uint32_t *__restrict__ vals_out) {
+    __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
+    const uint32_t P = *n_pairs;
+    if (uint64_t(P) > capacity) return;
+    if (int64_t(blockIdx.x) * RADIX_TILE >= int64_t(P)) return;      // block-uniform
+    const int nd = 1 << bits;
+    const uint32_t mask = uint32_t(nd - 1);
+    for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / 64;
+    const unsigned l = lane_id();
+    const int64_t base = int64_t(blockIdx.x) * RADIX_TILE + w * (RADIX_ITERS * 64);
+    K key[RADIX_ITERS];
+    uint32_t rank[RADIX_ITERS];
+    uint32_t dig[RADIX_ITERS];
+#pragma unroll
+    for (int it = 0; it < RADIX_ITERS; ++it) {
+        const int64_t idx = base + it * 64 + l;
+        const bool ok = idx < int64_t(P);
+        const uint64_t active = __ballot(ok);
+        key[it] = ok ? keys_in[idx] : K(0);
+        const uint32_t d = ok ? digit_of(key[it], shift, mask) : 0u;
+        dig[it] = d;
+        rank[it] = 0;
+        if (active != 0) {
+            const uint64_t peers = match_digit(d, bits, active);
+            const uint32_t before = ok ? cnt[w][d] : 0u;
+            rank[it] = before + uint32_t(__popcll(peers & lanemask_lt()));
+            __builtin_amdgcn_wave_barrier();
+            if (ok && (peers >> l) == 1ull) cnt[w][d] = before + uint32_t(__popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    // exclusive prefix over waves, plus the block's global digit offset
+    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS) {
+        uint32_t s = offsets[int64_t(d) * nblocks + blockIdx.x];
+        for (int ww = 0; ww < RADIX_WAVES; ++ww) {
+            const uint32_t c = cnt[ww][d];
+            cnt[ww][d] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RADIX_ITERS; ++it) {
+        const int64_t idx = base + it * 64 + l;
+        if (idx < int64_t(P)) {
+            const uint32_t dst = cnt[w][dig[it]] + rank[it];
+            keys_out[dst] = key[it];
+            vals_out[dst] = vals_in[idx];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- tile ranges
+template <typename K>
+__global__ void __launch_bounds__(256)
+tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+                   int shift, uint32_t n_tiles, uint32_t *__restrict__ offsets) {
+    const uint32_t P = *n_pairs;
+    if (uint64_t(P) > capacity) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > int64_t(P)) return;
+    if (i < int64_t(P)) {
+        const int64_t t = int64_t(keys[i] >> shift);
+        const int64_t tp = i > 0 ? int64_t(keys[i - 1] >> shift) : -1;
+        for (int64_t u = tp + 1; u <= t; ++u) offsets[u] = uint32_t(i);
+    } else {
+        const int64_t tl = P > 0 ? int64_t(keys[P - 1] >> shift) : -1;
+        for (int64_t u = tl + 1; u <= int64_t(n_tiles); ++u) offsets[u] = P;
+    }
+}
+
+// ----------------------------------------------------------------- host side
+inline int bits_for(uint64_t v) {
+    int b = 0;
+    while ((uint64_t(1) << b) < v) ++b;
+    return b;
+}
+
+struct BinLayout {
+    size_t off_first, off_scan, off_keys0, off_keys1, off_vals1, off_hist, off_hscan, off_ptot, total;
+    int nblocks;
+};
+
+
+template <typename K>
+BinLayout bin_layout(int64_t n, uint64_t capacity) {
+    BinLayout L;
+    const int64_t nb = int64_t((capacity + RADIX_TILE - 1) / RADIX_TILE);
+    L.nblocks = int(nb > 0 ? nb : 1);
+    const int64_t hist_elems = int64_t(RADIX_MAX_DIGITS) * L.nblocks;
+    size_t o = 0;
+    L.off_first = o; o = align_up(o + size_t(n > 0 ? n : 1) * 4, 256);
+    L.off_scan = o;  o = align_up(o + (scan_tmp_elems(n) > scan_tmp_elems(hist_elems) ? scan_tmp_elems(n)
+                                                                                       : scan_tmp_elems(hist_elems)) * 8, 256);
+    L.off_keys0 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * sizeof(K), 256);
+    L.off_keys1 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * sizeof(K), 256);
+    L.off_vals1 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * 4, 256);
+    L.off_hist = o;  o = align_up(o + size_t(hist_elems) * 4, 256);
+    L.off_hscan = o; o = align_up(o + size_t(hist_elems) * 4, 256);
+    L.off_ptot = o;  o = align_up(o + 16, 256);
+    L.total = o;
+    return L;
+}
+
+template <typename K, typename KeyFn>
+int bin_impl(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws, size_t ws_bytes,
+             uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
+             hipStream_t s, int key_bits, int range_shift) {
+    int rc;
+    MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
+    if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
+    MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
+    MGS_REQUIRE(tile_offsets && n_pairs, "tile_offsets / n_pairs is NULL");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity must be < 2^32 - 1");
+    MGS_REQUIRE(capacity == 0 || gids, "gids is NULL");
+    MGS_REQUIRE(ws && aligned(ws, 256), "workspace must be non-NULL and 256-byte aligned");
+    const BinLayout L = bin_layout<K>(n, capacity);
+    MGS_REQUIRE(ws_bytes >= L.total, "workspace too small (%zu < %zu)", ws_bytes, L.total);
+    char *w = static_cast<char *>(ws);
+    uint32_t *first = reinterpret_cast<uint32_t *>(w + L.off_first);
+    uint64_t *stmp = reinterpret_cast<uint64_t *>(w + L.off_scan);
+    K *k0 = reinterpret_cast<K *>(w + L.off_keys0);
+    K *k1 = reinterpret_cast<K *>(w + L.off_keys1);
+    uint32_t *v1 = reinterpret_cast<uint32_t *>(w + L.off_vals1);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + L.off_hist);
+    uint32_t *hscan = reinterpret_cast<uint32_t *>(w + L.off_hscan);
+    uint32_t *ptot = reinterpret_cast<uint32_t *>(w + L.off_ptot);
+    const uint32_t T = uint32_t(tiles_x) * uint32_t(tiles_y);
+
+    // 1. pair slots
+    if ((rc = scan_exclusive(proj->n_tiles, first, n, stmp, n_pairs, s)) != MGS_OK) return rc;
+    // 2. expand
+    const int npass = (key_bits + RADIX_MAX_BITS - 1) / RADIX_MAX_BITS;
+    K *kin = k0, *kout = k1;
+    uint32_t *vbuf[2] = {gids, v1};
+    uint32_t *vin = vbuf[npass % 2];
+    if (n > 0) {
+        const unsigned eb = unsigned((n + 255) / 256);
+        hipLaunchKernelGGL((expand_kernel<K, KeyFn>), dim3(eb), dim3(256), 0, s,
+                           reinterpret_cast<const uint2 *>(proj->rect), proj->n_tiles, first,
+                           reinterpret_cast<const float4 *>(proj->splat), n, tiles_x, n_pairs,
+                           capacity, kin, vin, KeyFn());
+        MGS_LAUNCH_CHECK("expand_kernel");
+    }
+    // 3. radix passes (digits of at most 8 bits, spread evenly)
+    if (capacity > 0) {
+        int shift = 0;
+        for (int p = 0; p < npass; ++p) {
+            const int bits = (key_bits - shift + (npass - p) - 1) / (npass - p);
+            uint32_t *vout = vbuf[(npass - 1 - p) % 2];
+            hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
+                               n_pairs, capacity, shift, bits, hist, L.nblocks);
+            MGS_LAUNCH_CHECK("radix_upsweep_kernel");
+            const int64_t helems = int64_t(1 << bits) * L.nblocks;
+            if ((rc = scan_exclusive(hist, hscan, helems, stmp, ptot, s)) != MGS_OK) return rc;
+            hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
+                               vin, n_pairs, capacity, shift, bits, hscan, L.nblocks, kout, vout);
+            MGS_LAUNCH_CHECK("radix_downsweep_kernel");
+            K *tk = kin; kin = kout; kout = tk;
+            vin = vout;
+            shift += bits;
+        }
+    }
+    // 4. ranges
+    const uint64_t nthreads = capacity + 1;
+    hipLaunchKernelGGL((tile_ranges_kernel<K>), dim3(unsigned((nthreads + 255) / 256)), dim3(256), 0, s, kin,
+                       n_pairs, capacity, range_shift, T, tile_offsets);
+    MGS_LAUNCH_CHECK("tile_ranges_kernel");
+    return MGS_OK;
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes) {
+    MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
+    MGS_REQUIRE(n >= 0 && tiles_x > 0 && tiles_y > 0, "bad sizes");
+    *bytes = mgs::bin_layout<uint32_t>(n, capacity).total;
+    return MGS_OK;
+}
+
+extern "C" int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
+                       size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
+                       uint32_t *n_pairs, void *stream) {
+    const int key_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
+    return mgs::bin_impl<uint32_t, mgs::TileKey>(proj, n, tiles_x, tiles_y, ws, ws_bytes, tile_offsets, gids,
+                                                  capacity, n_pairs, mgs::as_stream(stream),
+                                                  key_bits > 0 ? key_bits : 1, 0);
+}
+
+extern "C" int mgs_bin_sorted_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity,
+                                        size_t *bytes) {
+    MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
+    MGS_REQUIRE(n >= 0 && tiles_x > 0 && tiles_y > 0, "bad sizes");
+    *bytes = mgs::bin_layout<uint64_t>(n, capacity).total;
+    return MGS_OK;
+}
+
+extern "C" int mgs_bin_sorted(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
+                              size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
+                              uint32_t *n_pairs, void *stream) {
+    const int tile_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
+    return mgs::bin_impl<uint64_t, mgs::TileDepthKey>(proj, n, tiles_x, tiles_y, ws, ws_bytes, tile_offsets,
+                                                       gids, capacity, n_pairs, mgs::as_stream(stream),
+                                                       32 + (tile_bits > 0 ? tile_bits : 1), 32);
+}

@@ -1,0 +1,111 @@
+// Internal helpers shared by the gfx950 kernels and the C-ABI glue.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "mgs.h"
+
+namespace mgs {
+
+// Thread-local error text (defined in status.hip).
+int set_error(int code, const char *fmt, ...);
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned(const void *p, size_t a) {
+    return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+#define MGS_REQUIRE(cond, ...)                                              \
+    do {                                                                    \
+        if (!(cond)) return ::mgs::set_error(MGS_ERR_INVALID_ARG, __VA_ARGS__); \
+    } while (0)
+
+#define MGS_LAUNCH_CHECK(name)                                              \
+    do {                                                                    \
+        hipError_t e_ = hipGetLastError();                                  \
+        if (e_ != hipSuccess)                                               \
+            return ::mgs::set_error(MGS_ERR_HIP, "%s: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+// Camera as passed by value to kernels.
+struct CamK {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int W, H;
+    float near_z;
+    float campos[3];   // t_v = -R^T t
+    int tiles_x, tiles_y;
+};
+
+inline CamK make_camk(const mgs_camera *c) {
+    CamK k;
+    for (int i = 0; i < 9; ++i) k.R[i] = c->R[i];
+    for (int i = 0; i < 3; ++i) k.t[i] = c->t[i];
+    k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy;
+    k.W = c->width; k.H = c->height; k.near_z = c->near_z;
+    for (int i = 0; i < 3; ++i)
+        k.campos[i] = -(c->R[0 * 3 + i] * c->t[0] + c->R[1 * 3 + i] * c->t[1] + c->R[2 * 3 + i] * c->t[2]);
+    k.tiles_x = (c->width + MGS_TILE - 1) / MGS_TILE;
+    k.tiles_y = (c->height + MGS_TILE - 1) / MGS_TILE;
+    return k;
+}
+
+inline int check_camera(const mgs_camera *c) {
+    MGS_REQUIRE(c != nullptr, "camera is NULL");
+    MGS_REQUIRE(c->width > 0 && c->height > 0, "image size %dx%d must be positive", c->width, c->height);
+    MGS_REQUIRE(c->width <= 16 * 65535 && c->height <= 16 * 65535, "image too large");
+    MGS_REQUIRE(c->fx > 0.f && c->fy > 0.f, "focal lengths must be positive");
+    MGS_REQUIRE(c->near_z > 0.f, "near_z must be positive");
+    return MGS_OK;
+}
+
+inline int check_gaussians(const mgs_gaussians *g) {
+    MGS_REQUIRE(g != nullptr, "gaussians is NULL");
+    MGS_REQUIRE(g->n >= 0 && g->n < (int64_t(1) << 31), "n = %lld out of range", (long long)g->n);
+    if (g->n == 0) return MGS_OK;
+    MGS_REQUIRE(g->mean && g->log_scale && g->quat && g->opacity_logit && g->sh,
+                "a Gaussian attribute pointer is NULL");
+    return MGS_OK;
+}
+
+inline int check_projected(const mgs_projected *p, int64_t n) {
+    MGS_REQUIRE(p != nullptr, "projected is NULL");
+    if (n == 0) return MGS_OK;
+    MGS_REQUIRE(p->splat && p->rect && p->n_tiles, "a projected pointer is NULL");
+    MGS_REQUIRE(aligned(p->splat, 16), "splat must be 16-byte aligned");
+    MGS_REQUIRE(aligned(p->rect, 8), "rect must be 8-byte aligned");
+    MGS_REQUIRE(aligned(p->n_tiles, 4), "n_tiles must be 4-byte aligned");
+    return MGS_OK;
+}
+
+constexpr float LOG2E = 1.4426950408889634f;
+
+// Device-wide exclusive scan of uint32 values (bin.hip); tmp holds scan_tmp_elems(n) uint64,
+// *total receives the sum clamped to 2^32 - 1.
+size_t scan_tmp_elems(int64_t n);
+int scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *tmp, uint32_t *total, hipStream_t s);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// float32 -> bfloat16 bit pattern, round to nearest even (NaN stays NaN).
+__host__ __device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return uint16_t((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf16_round(float f) {
+    uint32_t u = uint32_t(bf16_bits_rne(f)) << 16;
+    float r;
+    __builtin_memcpy(&r, &u, 4);
+    return r;
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+}  // namespace mgs

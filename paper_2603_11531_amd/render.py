@@ -1,0 +1,192 @@
+"""Python front end of the render pass: device buffers + the C-ABI calls in order.
+
+Everything numeric runs in libmgs.so; this module allocates torch device
+tensors, passes their pointers and the current stream, and manages the pair
+capacity of the tile lists (the only data-dependent size of the pass).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_STOP = 1e-4
+
+
+def _u32_to_i64(t):
+    return t.to(torch.int64) & 0xFFFFFFFF
+
+
+class DeviceScene:
+    """Gaussian attributes resident in device memory (SoA float32, see mgs.h)."""
+
+    KEYS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+
+    def __init__(self, scene, device="cuda"):
+        self.t = {k: torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.float32)).to(device)
+                  for k in self.KEYS}
+        self.n = int(self.t["opacity_logit"].numel())
+        self.struct = L.make_gaussians(self.t)
+
+    @classmethod
+    def from_tensors(cls, tensors):
+        obj = cls.__new__(cls)
+        obj.t = {k: tensors[k].contiguous() for k in cls.KEYS}
+        obj.n = int(obj.t["opacity_logit"].numel())
+        obj.struct = L.make_gaussians(obj.t)
+        return obj
+
+    def nbytes(self):
+        return sum(v.numel() * 4 for v in self.t.values())
+
+
+class DeviceMLP:
+    """MLP parameters on the device (one float32 array, layout of mgs.h) plus the
+    packed bf16 MFMA operands that mgs_enhance reads."""
+
+    def __init__(self, mlp, device="cuda"):
+        flat = np.zeros(L.MGS_MLP_PARAMS, np.float32)
+        for name, off, shape in L.MLP_LAYOUT:
+            v = np.asarray(mlp[name], np.float32).reshape(-1)
+            flat[off:off + v.size] = v
+        self.params = torch.as_tensor(flat).to(device)
+        self.packed = torch.empty(L.MGS_MLP_PACKED_BYTES // 4, dtype=torch.float32, device=device)
+        self.repack()
+
+    def repack(self, stream=None):
+        L.check(L.lib().mgs_mlp_pack(L.ptr(self.params), L.ptr(self.packed), L.stream_ptr(stream)))
+
+    @staticmethod
+    def unflatten(flat):
+        """Split a float array in the mgs.h MLP layout into named numpy arrays."""
+        flat = np.asarray(flat)
+        return {name: flat[off:off + int(np.prod(shape)) if shape else off + 1].reshape(shape)
+                for name, off, shape in L.MLP_LAYOUT}
+
+
+class Renderer:
+    """Reusable buffers for one (N, W, H) shape; one call per stage or ``render``."""
+
+    def __init__(self, n, width, height, device="cuda", capacity=None):
+        self.device = torch.device(device)
+        self.n, self.W, self.H = int(n), int(width), int(height)
+        self.tiles_x = (self.W + L.MGS_TILE - 1) // L.MGS_TILE
+        self.tiles_y = (self.H + L.MGS_TILE - 1) // L.MGS_TILE
+        self.T = self.tiles_x * self.tiles_y
+        nn = max(1, self.n)
+        self.splat = torch.empty(nn, L.MGS_SPLAT_FLOATS, dtype=torch.float32, device=self.device)
+        self.rect = torch.empty(nn, 2, dtype=torch.int32, device=self.device)
+        self.n_tiles = torch.empty(nn, dtype=torch.int32, device=self.device)
+        self.phi = torch.empty(nn, dtype=torch.float32, device=self.device)
+        self.omod = torch.empty(nn, dtype=torch.float32, device=self.device)
+        # zero-initialised so a blend after an overflowed bin reads empty lists, never garbage
+        self.tile_offsets = torch.zeros(self.T + 1, dtype=torch.int32, device=self.device)
+        self.n_pairs = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.image = torch.empty(3, self.H, self.W, dtype=torch.float32, device=self.device)
+        self.aux = None
+        self.proj = L.make_projected(self.splat, self.rect, self.n_tiles)
+        self.capacity = 0
+        self.gids = None
+        self.ws = None
+        self.ws_sorted = None
+        self.ensure_capacity(capacity if capacity is not None else max(1024, 4 * self.n))
+
+    # -- capacity -----------------------------------------------------------
+    def ensure_capacity(self, cap, sorted_path=False):
+        cap = int(cap)
+        lib = L.lib()
+        if cap > self.capacity or self.gids is None:
+            self.capacity = cap
+            self.gids = torch.zeros(max(1, cap), dtype=torch.int32, device=self.device)
+            self.ws = None
+            self.ws_sorted = None
+        if self.ws is None and not sorted_path:
+            nb = L.C.c_size_t()
+            L.check(lib.mgs_bin_workspace(self.n, self.tiles_x, self.tiles_y, self.capacity, L.C.byref(nb)))
+            self.ws = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device=self.device)
+        if self.ws_sorted is None and sorted_path:
+            nb = L.C.c_size_t()
+            L.check(lib.mgs_bin_sorted_workspace(self.n, self.tiles_x, self.tiles_y, self.capacity,
+                                                 L.C.byref(nb)))
+            self.ws_sorted = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device=self.device)
+
+    # -- stages -------------------------------------------------------------
+    def enhance(self, scene: DeviceScene, cam_s, mlp: DeviceMLP, stream=None):
+        L.check(L.lib().mgs_enhance(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
+                                    L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
+
+    def project(self, scene: DeviceScene, cam_s, use_mlp=False, alpha_min=ALPHA_MIN, stream=None):
+        phi = L.ptr(self.phi) if use_mlp else None
+        om = L.ptr(self.omod) if use_mlp else None
+        L.check(L.lib().mgs_project(L.C.byref(scene.struct), L.C.byref(cam_s), phi, om, L.MGS_TILE,
+                                    alpha_min, L.C.byref(self.proj), L.stream_ptr(stream)))
+
+    def bin(self, sorted_path=False, stream=None):
+        self.ensure_capacity(self.capacity, sorted_path)
+        lib = L.lib()
+        fn = lib.mgs_bin_sorted if sorted_path else lib.mgs_bin
+        ws = self.ws_sorted if sorted_path else self.ws
+        L.check(fn(L.C.byref(self.proj), self.n, self.tiles_x, self.tiles_y, L.ptr(ws), ws.numel() * 4,
+                   L.ptr(self.tile_offsets), L.ptr(self.gids), self.capacity, L.ptr(self.n_pairs),
+                   L.stream_ptr(stream)))
+
+    def blend_oit(self, cam_s, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, want_aux=False,
+                  stream=None):
+        if want_aux and self.aux is None:
+            self.aux = torch.empty(5, self.H, self.W, dtype=torch.float32, device=self.device)
+        L.check(L.lib().mgs_blend_oit(L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids),
+                                      L.C.byref(cam_s), L.MGS_TILE, L.bg_array(bg), alpha_min, alpha_max,
+                                      L.ptr(self.image), L.ptr(self.aux) if want_aux else None,
+                                      L.stream_ptr(stream)))
+
+    def blend_sorted(self, cam_s, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_stop=T_STOP,
+                     stream=None):
+        L.check(L.lib().mgs_blend_sorted(L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids),
+                                         L.C.byref(cam_s), L.MGS_TILE, L.bg_array(bg), alpha_min, alpha_max,
+                                         t_stop, L.ptr(self.image), L.stream_ptr(stream)))
+
+    def pairs(self):
+        return int(_u32_to_i64(self.n_pairs)[0])
+
+    # -- whole pass -----------------------------------------------------------
+    def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
+               check_capacity=True, stream=None):
+        """enhance -> project -> bin -> blend.  With check_capacity the host reads the pair
+        count once and re-bins with a larger capacity on overflow."""
+        cam_s = L.make_camera(cam)
+        if mlp is not None:
+            self.enhance(scene, cam_s, mlp, stream)
+        self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream)
+        self.bin(sorted_path, stream)
+        if check_capacity:
+            P = self.pairs()      # synchronises
+            if P > self.capacity:
+                self.ensure_capacity(int(P * 1.25) + 1024, sorted_path)
+                self.bin(sorted_path, stream)
+        if sorted_path:
+            self.blend_sorted(cam_s, bg, stream=stream)
+        else:
+            self.blend_oit(cam_s, bg, want_aux=want_aux, stream=stream)
+        return self.image
+
+    # -- views for tests ---------------------------------------------------------
+    def lists(self):
+        P = self.pairs()
+        return _u32_to_i64(self.tile_offsets).cpu(), _u32_to_i64(self.gids[:P]).cpu()
+
+    def decoded(self):
+        """Projected record as float64 numpy arrays (for stage parity checks)."""
+        s = self.splat.double().cpu().numpy()
+        rect = _u32_to_i64(self.rect).cpu().numpy()
+        LOG2E = 1.4426950408889634
+        A = s[:, 4] / (-0.5 * LOG2E)
+        out = dict(mean2d=s[:, 0:2], log2o=s[:, 2], w=s[:, 3], A=A, beta=s[:, 5],
+                   inv_c=s[:, 6] / (-0.5 * LOG2E), depth=s[:, 7], color=s[:, 8:11], o_eff=s[:, 11],
+                   rect=np.stack([rect[:, 0] & 0xFFFF, rect[:, 0] >> 16, rect[:, 1] & 0xFFFF, rect[:, 1] >> 16], 1),
+                   n_tiles=_u32_to_i64(self.n_tiles).cpu().numpy())
+        return out

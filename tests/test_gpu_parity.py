@@ -1,0 +1,334 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: tile lists bit-exact; float32 image max abs <= 1e-4 per channel
+(with the ambiguity rule for pairs at the alpha cut); BF16-MLP path <= 1e-4
+against the oracle's BF16 emulation, and <= 2e-2 / PSNR >= 50 dB against the
+plain FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import mgs_data
+import oracle as O
+from gpu_helpers import (compare_oit_image, oracle_project, psnr, sampled_pixel_check, say,
+                         upload_projected_from_oracle)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11531_amd as M
+    M._lib.lib()
+    return M
+
+
+def _render_gpu(M, scene, cam, mlp=None, bg=(0, 0, 0), sorted_path=False, want_aux=False, capacity=None):
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height, capacity=capacity)
+    dm = M.DeviceMLP(mlp) if mlp is not None else None
+    img = R.render(ds, cam, dm, bg=bg, sorted_path=sorted_path, want_aux=want_aux)
+    torch.cuda.synchronize()
+    return R, img.double().cpu()
+
+
+# ------------------------------------------------------------------ projection
+def test_project_matches_oracle_small(M):
+    say("test_project_matches_oracle_small")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    R, _ = _render_gpu(M, scene, cam)
+    d = R.decoded()
+    pr, camt = oracle_project(scene, cam)
+    vis_o = pr["visible"].numpy()
+    vis_g = d["n_tiles"] > 0
+    cov = pr["cov2d"].detach().numpy()
+    a, b, c = cov[:, 0, 0], cov[:, 0, 1], cov[:, 1, 1]
+    both = vis_o & vis_g
+    assert both.sum() > 1000
+    rel = lambda x, y: np.abs(x - y) / np.maximum(np.abs(y), 1e-3)
+    assert rel(d["mean2d"][both], pr["mean2d"].detach().numpy()[both]).max() < 1e-5
+    assert rel(d["w"][both], pr["w"].detach().numpy()[both]).max() < 1e-5
+    assert np.abs(d["color"][both] - pr["color"].detach().numpy()[both]).max() < 1e-5
+    assert rel(d["o_eff"][both], pr["o_eff"].detach().numpy()[both]).max() < 1e-5
+    assert rel(d["depth"][both], pr["depth"].detach().numpy()[both]).max() < 1e-5
+    det = a * c - b * b
+    assert rel(d["A"][both], (c / det)[both]).max() < 1e-5
+    assert np.abs(d["beta"][both] - (-b / c)[both]).max() < 1e-5
+    assert rel(d["inv_c"][both], (1.0 / c)[both]).max() < 1e-5
+    # visibility and rects agree except for splats whose support edge sits on a pixel-centre boundary
+    diff = np.nonzero((vis_o != vis_g) | (np.any(d["rect"] != pr["rect"].numpy(), axis=1) & both))[0]
+    assert len(diff) <= 2, diff
+
+
+# ------------------------------------------------------------------ lists
+@pytest.mark.parametrize("W,H,n,seed", [(128, 128, 2000, 0), (200, 120, 3000, 1), (17, 33, 500, 2)])
+def test_bin_lists_bit_exact_on_oracle_rects(M, W, H, n, seed):
+    say(f"test_bin_lists_bit_exact_on_oracle_rects W={W} H={H} n={n}")
+    scene = mgs_data.make_scene_uniform(n, seed, ls_mu=-2.5)
+    cam = mgs_data.look_at((0.3, 0.1, -3.0), width=W, height=H, f=float(W))
+    pr, camt = oracle_project(scene, cam)
+    R = M.Renderer(n, W, H, capacity=int(pr["n_tiles"].sum()))
+    upload_projected_from_oracle(R, pr, camt)
+    R.bin()
+    torch.cuda.synchronize()
+    offs, gids = R.lists()
+    o_offs, o_gids = O.bin_lists(pr["rect"], pr["n_tiles"], R.tiles_x, R.tiles_y)
+    assert R.pairs() == int(pr["n_tiles"].sum())
+    assert torch.equal(offs, o_offs) and torch.equal(gids, o_gids)
+    # depth-sorted lists (sort key = the float32 depth held in the record)
+    R.bin(sorted_path=True)
+    torch.cuda.synchronize()
+    offs2, gids2 = R.lists()
+    depth32 = pr["depth"].detach().to(torch.float32).to(torch.float64)
+    s_offs, s_gids = O.bin_lists_sorted(pr["rect"], pr["n_tiles"], depth32, R.tiles_x, R.tiles_y)
+    assert torch.equal(offs2, s_offs) and torch.equal(gids2, s_gids)
+
+
+def test_bin_is_deterministic_and_overflow_is_reported(M):
+    say("test_bin_is_deterministic_and_overflow_is_reported")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, 128, 128, capacity=1)
+    cam_s = M._lib.make_camera(cams[0])
+    R.project(ds, cam_s)
+    R.bin()
+    torch.cuda.synchronize()
+    P = R.pairs()
+    assert P > 1                       # overflow reported through n_pairs
+    R.ensure_capacity(P)
+    R.bin()
+    a = [t.clone() for t in R.lists()]
+    R.bin()
+    b = R.lists()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ blend
+def test_blend_on_oracle_records(M):
+    say("test_blend_on_oracle_records")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    pr, camt = oracle_project(scene, cam)
+    R = M.Renderer(scene["mean"].shape[1], 128, 128, capacity=int(pr["n_tiles"].sum()))
+    upload_projected_from_oracle(R, pr, camt)
+    R.bin()
+    bg = (0.25, 0.5, 0.75)
+    R.blend_oit(M._lib.make_camera(cam), bg, want_aux=True)
+    torch.cuda.synchronize()
+    img, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), variants=True)
+    err, nfail = compare_oit_image(R.image.cpu(), V, flagged, TOL)
+    say(f"  max err {err:.3e}, fails {nfail}, flagged {flagged}")
+    assert nfail == 0 and flagged == 0
+
+
+def test_end_to_end_small_oit(M):
+    say("test_end_to_end_small_oit")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    bg = (0.0, 0.0, 0.0)
+    R, img = _render_gpu(M, scene, cam, bg=bg, want_aux=True)
+    pr, camt = oracle_project(scene, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), variants=True)
+    err, nfail = compare_oit_image(img, V, flagged, TOL)
+    say(f"  max err {err:.3e}, fails {nfail}, flagged {flagged}, P={R.pairs()}")
+    assert nfail == 0 and flagged == 0
+    assert float(img.std()) > 0.01
+    # aux (F, D, T) follows the same sums
+    a = R.aux.double().cpu()
+    has = aux[3] > 0
+    assert float((a[4] - aux[4]).abs().max()) < 1e-3
+    assert float(((a[3] - aux[3]).abs() / aux[3].clamp(min=1e-3))[has].max()) < 1e-3
+
+
+@pytest.mark.parametrize("W,H", [(96, 72), (33, 17), (1, 1), (250, 130)])
+def test_end_to_end_ragged_sizes_and_background(M, W, H):
+    say(f"test_end_to_end_ragged_sizes W={W} H={H}")
+    scene = mgs_data.make_scene_uniform(800, 7, ls_mu=-2.8)
+    cam = mgs_data.look_at((0.2, -0.4, -3.2), width=W, height=H, f=float(max(W, 8)))
+    bg = (0.3, 0.6, 0.1)
+    R, img = _render_gpu(M, scene, cam, bg=bg)
+    pr, camt = oracle_project(scene, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), variants=True)
+    err, nfail = compare_oit_image(img, V, flagged, TOL)
+    say(f"  max err {err:.3e}, fails {nfail}")
+    assert nfail == 0
+
+
+def test_empty_and_degenerate_scenes(M):
+    say("test_empty_and_degenerate_scenes")
+    cam = mgs_data.look_at((0, 0, -4), width=40, height=24, f=40.0)
+    bg = (0.1, 0.2, 0.3)
+    empty = {k: v[..., :0].copy() for k, v in mgs_data.make_scene_uniform(1, 0).items()}
+    R, img = _render_gpu(M, empty, cam, bg=bg)
+    assert torch.allclose(img, torch.tensor(bg, dtype=torch.float64)[:, None, None].expand(3, 24, 40))
+    # all behind the camera
+    sc = mgs_data.make_scene_uniform(50, 3)
+    sc["mean"][2] = -10.0
+    R, img = _render_gpu(M, sc, cam, bg=bg)
+    assert R.pairs() == 0
+    assert torch.allclose(img, torch.tensor(bg, dtype=torch.float64)[:, None, None].expand(3, 24, 40))
+    # one huge Gaussian covering the whole image plus small ones
+    sc = mgs_data.make_scene_uniform(30, 4)
+    sc["log_scale"][:, 0] = 0.5
+    sc["mean"][:, 0] = 0.0
+    R, img = _render_gpu(M, sc, cam, bg=bg)
+    pr, camt = oracle_project(sc, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), variants=True)
+    err, nfail = compare_oit_image(img, V, flagged, TOL)
+    assert nfail == 0, err
+
+
+def test_render_is_bit_reproducible(M):
+    say("test_render_is_bit_reproducible")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    _, a = _render_gpu(M, scene, cams[0])
+    _, b = _render_gpu(M, scene, cams[0])
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ enhancement MLP
+def test_enhance_matches_bf16_emulation(M):
+    say("test_enhance_matches_bf16_emulation")
+    scene = mgs_data.make_scene_unbounded(5000, 3)
+    cam = mgs_data.circle_poses(4, 10.0, 320, 200, f=320.0)[1]
+    mlp = mgs_data.make_mlp(4)
+    ds = M.DeviceScene(scene)
+    dm = M.DeviceMLP(mlp)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    R.enhance(ds, M._lib.make_camera(cam), dm)
+    torch.cuda.synchronize()
+    phi_g, m_g = R.phi.double().cpu(), R.omod.double().cpu()
+    camt = O.camera_tensors(cam)
+    p = O.scene_params(scene)
+    act = O.activate(p)
+    _, _, P = O.camera_space(p["mean"], camt)
+    x = O.mlp_features(P, act["s"], act["q"], p["sh"])
+    with torch.no_grad():
+        phi_e, m_e = O.enhance(x, O.mlp_params(mlp), bf16=True)
+        phi_f, m_f = O.enhance(x, O.mlp_params(mlp), bf16=False)
+    e_phi = float((phi_g - phi_e).abs().max())
+    e_m = float((m_g - m_e).abs().max())
+    say(f"  vs bf16 emulation: phi {e_phi:.2e} m {e_m:.2e}; vs fp64: phi "
+        f"{float((phi_g - phi_f).abs().max()):.2e} m {float((m_g - m_f).abs().max()):.2e}")
+    assert e_phi < 2e-2 * float(phi_e.abs().max()) and e_m < 1e-2
+    # the bulk agrees much more tightly (rare bf16 rounding flips aside)
+    assert float((phi_g - phi_e).abs().median()) < 1e-5 and float((m_g - m_e).abs().median()) < 1e-5
+    assert float((phi_g - phi_f).abs().max()) < 5e-2 and float((m_g - m_f).abs().max()) < 2e-2
+
+
+def test_end_to_end_with_mlp(M):
+    say("test_end_to_end_with_mlp")
+    scene = mgs_data.make_scene_unbounded(20000, 5)
+    cam = mgs_data.circle_poses(8, 10.0, 200, 132, f=200.0)[3]
+    mlp = mgs_data.make_mlp(6)
+    bg = (0.0, 0.0, 0.0)
+    R, img = _render_gpu(M, scene, cam, mlp=mlp, bg=bg)
+    pr_e, camt = oracle_project(scene, cam, mlp=mlp, bf16=True)
+    ref_e, _, V, flagged = O.render_oit(pr_e, camt, np.array(bg), mode="binned", variants=True)
+    err, nfail = compare_oit_image(img, V, flagged, TOL)
+    pr_f, _ = oracle_project(scene, cam, mlp=mlp, bf16=False)
+    ref_f, _ = O.render_oit(pr_f, camt, np.array(bg), mode="binned")
+    e64 = float((img - ref_f).abs().max())
+    ps = psnr(img, ref_f)
+    say(f"  vs bf16-emulation: max {err:.3e} fails {nfail}; vs fp64: max {e64:.3e} psnr {ps:.1f} dB")
+    assert e64 <= 2e-2 and ps >= 50.0
+    # pixels off by more than 1e-4 from the emulation come only from bf16 rounding flips
+    assert nfail <= max(2, img[0].numel() // 2000)
+
+
+# ------------------------------------------------------------------ sorted comparison path
+def test_sorted_path_matches_oracle(M):
+    say("test_sorted_path_matches_oracle")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    bg = (0.2, 0.1, 0.4)
+    R, img = _render_gpu(M, scene, cam, bg=bg, sorted_path=True)
+    pr, camt = oracle_project(scene, cam)
+    ref, flags = O.render_sorted(pr, camt, np.array(bg), return_flags=True)
+    err = (img - ref).abs().amax(dim=0)
+    ok = ~flags
+    say(f"  max err (unflagged) {float(err[ok].max()):.3e}, flagged {int(flags.sum())}")
+    assert float(err[ok].max()) <= TOL
+    assert int(flags.sum()) <= img[0].numel() // 100
+
+
+# ------------------------------------------------------------------ full-size workload
+@pytest.mark.parametrize("sorted_path", [False, True])
+def test_unbounded_full_size_sampled(M, sorted_path):
+    """1M Gaussians at 1600x1063 (the benchmark workload): lists bit-exact on oracle rects,
+    image checked at sampled pixels against the oracle's per-pixel evaluation."""
+    say(f"test_unbounded_full_size_sampled sorted={sorted_path}")
+    scene, cams, mlp, _ = mgs_data.make_config("unbounded", seed=0)
+    cam = cams[0]
+    bg = (0.0, 0.0, 0.0)
+    R, img = _render_gpu(M, scene, cam, mlp=mlp, bg=bg, sorted_path=sorted_path)
+    say(f"  P = {R.pairs()}")
+    pr, camt = oracle_project(scene, cam, mlp=mlp, bf16=True)
+    lists = O.bin_lists(pr["rect"], pr["n_tiles"], R.tiles_x, R.tiles_y)
+    if sorted_path:
+        return _sorted_sampled(img, pr, camt, bg, lists)
+    worst, fails = sampled_pixel_check(img, pr, camt, bg, lists, 1500, 11, TOL)
+    say(f"  sampled: worst {worst:.3e} fails {fails}")
+    assert fails <= 3          # bf16 rounding flips of phi / m (see test_end_to_end_with_mlp)
+    # lists: the GPU binning of the oracle's own rects is bit-exact
+    upload_projected_from_oracle(R, pr, camt)
+    R.ensure_capacity(int(pr["n_tiles"].sum()) + 16)
+    R.bin()
+    torch.cuda.synchronize()
+    offs, gids = R.lists()
+    assert torch.equal(offs, lists[0]) and torch.equal(gids, lists[1])
+
+
+def _sorted_sampled(img, pr, camt, bg, lists):
+    rng = np.random.default_rng(5)
+    H, W = camt["H"], camt["W"]
+    tiles_x = (W + 15) // 16
+    offs, gids = lists
+    bad = 0
+    for p in rng.choice(H * W, 600, replace=False):
+        j, i = divmod(int(p), W)
+        t = (j // 16) * tiles_x + i // 16
+        g = gids[int(offs[t]):int(offs[t + 1])]
+        if g.numel() == 0:
+            continue
+        sub = {k: (v[g] if torch.is_tensor(v) and v.dim() > 0 and v.shape[0] == pr["depth"].shape[0] else v)
+               for k, v in pr.items()}
+        sub_img, flags = _render_pixel_sorted(sub, i, j, bg)
+        if flags:
+            continue
+        bad += float((img[:, j, i] - sub_img).abs().max()) > TOL
+    assert bad <= 3
+
+
+def _render_pixel_sorted(sub, i, j, bg):
+    dep = sub["depth"].detach()
+    order = torch.sort(dep, stable=True).indices
+    m2, con, o, col = sub["mean2d"][order], sub["conic"][order], sub["o_eff"][order], sub["color"][order]
+    dx = i + 0.5 - m2[:, 0]
+    dy = j + 0.5 - m2[:, 1]
+    a = o * torch.exp(-0.5 * (con[:, 0] * dx * dx + 2 * con[:, 1] * dx * dy + con[:, 2] * dy * dy))
+    T = 1.0
+    C = torch.zeros(3, dtype=torch.float64)
+    flag = False
+    for k in range(a.numel()):
+        ak = float(a[k])
+        if abs(math.log(max(ak, 1e-300) / O.ALPHA_MIN)) < O.AMBIG_LOG:
+            flag = True
+        if ak < O.ALPHA_MIN:
+            continue
+        if T < O.T_STOP:
+            break
+        if abs(T / O.T_STOP - 1) < 1e-3:
+            flag = True
+        al = min(ak, O.ALPHA_MAX)
+        C += al * T * col[k]
+        T *= 1 - al
+    return C + T * torch.tensor(np.asarray(bg, np.float64)), flag
