@@ -132,8 +132,13 @@ def mlp_features(P, s, q, sh):
 
 
 def bf16_round(x):
-    """Round to bfloat16 (round-to-nearest-even) the way a float32 kernel does: via float32."""
-    return x.to(torch.float32).to(torch.bfloat16).to(DT)
+    """Round to bfloat16 (round-to-nearest-even) the way a float32 kernel does: via float32.
+
+    The rounding models the precision of the kernel's MFMA inputs; for gradients it
+    is the identity (straight-through), so the gradient itself is never rounded.
+    """
+    r = x.detach().to(torch.float32).to(torch.bfloat16).to(DT)
+    return x + (r - x).detach() if x.requires_grad else r
 
 
 def enhance(x, mlp, bf16=False):

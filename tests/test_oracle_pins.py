@@ -576,3 +576,11 @@ def test_oracle_autograd_matches_central_differences():
             assert abs(fd - float(g_ad[idx])) <= 1e-5 * (1 + abs(fd)), (name, idx)
             checked += 1
     assert checked >= 20
+
+
+def test_bf16_rounding_passes_gradients_straight_through():
+    x = torch.tensor([0.1234567, -3.3, 7.0], dtype=torch.float64, requires_grad=True)
+    y = O.bf16_round(x)
+    assert y.tolist() == O.bf16_round(x.detach()).tolist()
+    (y * torch.tensor([0.3, -1.7, 2.5], dtype=torch.float64)).sum().backward()
+    assert x.grad.tolist() == [0.3, -1.7, 2.5]          # not rounded to bfloat16
