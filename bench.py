@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sorted", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
     return ap.parse_args()
 
@@ -84,6 +86,46 @@ def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
                        f"project + tile lists for all Gaussians ({t_pre:.1f} s), OIT blend of "
                        f"{len(sample)} random non-empty tiles ({t_blend_sample:.1f} s) scaled to all "
                        f"{len(nonempty)} non-empty tiles; s/frame = {t_frame:.1f}")}
+
+
+SERVE_SIZES = (200_000, 400_000, 600_000, 800_000, 1_000_000, 1_500_000, 2_000_000, 2_500_000)
+SERVE_RES = ((640, 480), (1280, 720), (1600, 1063), (1920, 1080))
+
+
+def serving_leg(n_requests, rate=2000.0):
+    """8 resident scenes, Poisson arrivals of random poses at mixed resolutions, MLP on:
+    the continuous-batching server vs a one-frame-per-launch loop on the same stream."""
+    import numpy as np
+    import torch
+
+    import mgs_data
+    from paper_2603_11531_amd import serve
+    reg = serve.SceneRegistry()
+    for k, n in enumerate(SERVE_SIZES):
+        reg.add(f"s{k}", mgs_data.make_scene_uniform(n, 10 + k), mgs_data.make_mlp(11 + k))
+    srv = serve.Server(reg, max_batch=8, max_gaussians=12_000_000, max_tiles=8 * 8160, capacity=320_000_000,
+                       n_slots=2, image_budget_bytes=8 << 30, use_graphs=True)
+    srv.calibrate(SERVE_RES)
+    names = list(reg.scenes)
+    warm = serve.poisson_requests(names, rate, 16, seed=99, resolutions=SERVE_RES)
+    srv.run(warm)
+    serve.run_plain_loop(reg, serve.poisson_requests(names, rate, 16, seed=98, resolutions=SERVE_RES))
+    reqs = serve.poisson_requests(names, rate, n_requests, seed=2, resolutions=SERVE_RES)
+    served = srv.run(reqs)
+    st_b = serve.latency_stats(served)
+    reqs_p = serve.poisson_requests(names, rate, n_requests, seed=2, resolutions=SERVE_RES)
+    served_p = serve.run_plain_loop(reg, reqs_p)
+    st_p = serve.latency_stats(served_p)
+    by_id = {r.rid: r for r in served_p}
+    same = all(torch.equal(r.image, by_id[r.rid].image) for r in served if r.rid in by_id)
+    paths = {}
+    for r in served:
+        paths[r.path] = paths.get(r.path, 0) + 1
+    r3 = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"offered_req_per_s": rate, "resident_gaussians": int(sum(SERVE_SIZES)),
+            "batched": r3(st_b), "plain_loop": r3(st_p),
+            "batched_vs_plain_frames": round(st_b["frames_per_s"] / st_p["frames_per_s"], 3),
+            "images_identical_to_plain": bool(same), "paths": paths, "rejected": len(srv.rejected)}
 
 
 def main():
@@ -214,6 +256,13 @@ def main():
                      "units_per_launch": round(evals), "flop_per_unit": BLEND_FLOP_PER_EVAL,
                      "avg_launch_ms": round(blend_ms, 4)},
     }
+    if not args.no_serve:
+        log("serving leg ...")
+        del R
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args.serve_requests)
+        out["serve_p50_ms"] = out["serving"]["batched"]["p50_ms"]
+        out["serve_p99_ms"] = out["serving"]["batched"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams, mlp)

@@ -230,6 +230,46 @@ int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam, const flo
                         float alpha_max, void *ws, size_t ws_bytes, mgs_gaussians_grad *out,
                         float *dmlp, void *stream);
 
+/*
+ * Batched rendering for serving (several resident scenes, mixed resolutions and
+ * poses in one fixed launch sequence).  A request names a resident scene, its
+ * packed MLP (or NULL for the MLP's initial state phi = 1, m = 1), a camera,
+ * a background and an output image [3][H][W] (device).
+ */
+typedef struct mgs_request {
+    mgs_gaussians g;
+    const void   *packed_mlp;
+    mgs_camera    cam;
+    float         bg[3];
+    float        *image;
+} mgs_request;
+
+#define MGS_BATCH_MAX_REQUESTS 64
+
+/*
+ * mgs_batch_workspace -- bytes of workspace for batches of at most max_gaussians
+ * Gaussians in total (each request's count rounded up to a multiple of 64),
+ * max_tiles 16x16 tiles in total, and `capacity` tile/Gaussian pairs in total.
+ */
+int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uint64_t capacity, size_t *bytes);
+
+/*
+ * mgs_render_batch -- renders every request of a batch with the OIT pass (Eq. 2-4):
+ * enhance -> project -> bin -> blend, each one launch for the whole batch.
+ * `requests` (device array of mgs_request) and `*n_requests` (device int32,
+ * 0..MGS_BATCH_MAX_REQUESTS) are read on the device, and every grid is sized by the
+ * limits, so the call enqueues the same work for any batch and can be captured in a
+ * hipGraph and replayed after the caller rewrites the request table.
+ * Out: each request's image; n_pairs (device uint32) = total pairs (no image is
+ * valid if it exceeds capacity; the caller re-renders with a larger capacity);
+ * status (device int32[2], may be NULL) = {1 if the batch fit the limits else 0,
+ * number of requests rendered}.  Images are bit-identical to mgs_blend_oit of the
+ * same request rendered alone.
+ */
+int mgs_render_batch(const mgs_request *requests, const int32_t *n_requests, int64_t max_gaussians,
+                     int64_t max_tiles, uint64_t capacity, float alpha_min, float alpha_max, void *ws,
+                     size_t ws_bytes, uint32_t *n_pairs, int32_t *status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

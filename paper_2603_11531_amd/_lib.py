@@ -30,7 +30,7 @@ EXPORTED = [
     "mgs_last_error", "mgs_version", "mgs_mlp_pack", "mgs_enhance", "mgs_project",
     "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_bin_sorted_workspace",
     "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
-    "mgs_render_backward",
+    "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch",
 ]
 
 
@@ -60,6 +60,11 @@ class mgs_projected(C.Structure):
     _fields_ = [("splat", C.c_void_p), ("rect", C.c_void_p), ("n_tiles", C.c_void_p)]
 
 
+class mgs_request(C.Structure):
+    _fields_ = [("g", mgs_gaussians), ("packed_mlp", C.c_void_p), ("cam", mgs_camera), ("bg", C.c_float * 3),
+                ("image", C.c_void_p)]
+
+
 def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2603_11531_amd.build`")
@@ -85,6 +90,10 @@ def load(path=LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    lib.mgs_batch_workspace.restype = i32
+    lib.mgs_batch_workspace.argtypes = [i64, i64, u64, P(C.c_size_t)]
+    lib.mgs_render_batch.restype = i32
+    lib.mgs_render_batch.argtypes = [vp, vp, i64, i64, u64, f32, f32, vp, C.c_size_t, vp, vp, vp]
     lib.mgs_render_backward_workspace.restype = i32
     lib.mgs_render_backward_workspace.argtypes = [i64, i32, i32, u64, i32, P(C.c_size_t)]
     lib.mgs_render_backward.restype = i32

@@ -125,8 +125,10 @@ bwd_blend_kernel(const float4 *__restrict__ splat, const uint2 *__restrict__ rec
             const uint2 rc = rect[g];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
             const uint64_t slot = uint64_t(first[g]) + uint64_t(ty - int(y0)) * (x1 - x0 + 1) + uint64_t(tx - int(x0));
+            if (slot < cap) {
 #pragma unroll
-            for (int k = 0; k < NPART; ++k) part[k * cap + slot] = acc[k];
+                for (int k = 0; k < NPART; ++k) part[k * cap + slot] = acc[k];
+            }
         }
     }
 }
@@ -134,11 +136,13 @@ bwd_blend_kernel(const float4 *__restrict__ splat, const uint2 *__restrict__ rec
 // ------------------------------------------------------------------ 2. per-Gaussian reduce
 __global__ void __launch_bounds__(256)
 bwd_reduce_kernel(const uint32_t *__restrict__ first, const uint32_t *__restrict__ ntiles, int64_t n,
-                  const float *__restrict__ part, uint64_t cap, float *__restrict__ gr) {
+                  const float *__restrict__ part, uint64_t cap, const uint32_t *__restrict__ n_pairs,
+                  float *__restrict__ gr) {
     const int64_t g = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     if (g >= n) return;
-    const uint32_t nt = ntiles[g];
+    // lists that overflowed their capacity in the forward carry no gradient
+    const uint32_t nt = uint64_t(*n_pairs) <= cap ? ntiles[g] : 0u;
     const uint64_t e0 = first[g];
     float acc[NPART];
 #pragma unroll
@@ -545,7 +549,7 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
                        log2f(alpha_min), alpha_max, aux, dL_dimage, part, uint64_t(capacity > 0 ? capacity : 1));
     MGS_LAUNCH_CHECK("bwd_blend_kernel");
     hipLaunchKernelGGL(bwd_reduce_kernel, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, first, proj->n_tiles, n,
-                       part, uint64_t(capacity > 0 ? capacity : 1), gr);
+                       part, uint64_t(capacity > 0 ? capacity : 1), ptot, gr);
     MGS_LAUNCH_CHECK("bwd_reduce_kernel");
     hipLaunchKernelGGL(bwd_gauss_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, *g, k, phi, omod,
                        proj->n_tiles, gr, *out, gphi, gom);

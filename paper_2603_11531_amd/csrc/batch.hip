@@ -1,0 +1,206 @@
+// mgs_render_batch: a batch of render requests (resident scenes, mixed resolutions and
+// poses) in one fixed sequence of launches whose grids depend only on the workspace
+// limits -- the request table and its count live in device memory, so the whole
+// sequence can be captured once in a hipGraph and replayed for any batch that fits.
+//
+// Every request keeps its own index space: Gaussians of request r are projected
+// into the global range [gbase[r], gbase[r] + n_r) and its tiles get global ids
+// [tbase[r], tbase[r+1]); one binning pass sorts all requests' pairs by global tile
+// id, and the blend runs one workgroup per global tile.  The per-tile lists hold the
+// same Gaussians in the same order as a single-view render, so every image is
+// bit-identical to rendering its request alone.
+#include "batch.h"
+#include "blend_math.h"
+#include "mlp_math.h"
+#include "proj_math.h"
+
+namespace mgs {
+
+static_assert(BATCH_MAX_REQ == MGS_BATCH_MAX_REQUESTS, "batch limit");
+
+__global__ void batch_plan_kernel(const mgs_request *__restrict__ reqs, const int32_t *__restrict__ n_req,
+                                  uint64_t max_gauss, uint64_t max_tiles, BatchPlan *__restrict__ plan) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int nr = *n_req;
+    int ok = (nr >= 0 && nr <= BATCH_MAX_REQ) ? 1 : 0;
+    if (!ok) nr = 0;
+    uint64_t g = 0, t = 0;
+    for (int r = 0; r < nr; ++r) {
+        const mgs_request &q = reqs[r];
+        const int tx = (q.cam.width + MGS_TILE - 1) / MGS_TILE, ty = (q.cam.height + MGS_TILE - 1) / MGS_TILE;
+        if (q.g.n < 0 || q.cam.width <= 0 || q.cam.height <= 0 || q.cam.fx <= 0.f || q.cam.fy <= 0.f ||
+            q.image == nullptr)
+            ok = 0;
+        plan->gbase[r] = uint32_t(g);
+        plan->tbase[r] = uint32_t(t);
+        plan->tiles_x[r] = uint32_t(tx > 0 ? tx : 1);
+        g += (uint64_t(q.g.n > 0 ? q.g.n : 0) + 63) / 64 * 64;
+        t += uint64_t(tx > 0 ? tx : 0) * uint64_t(ty > 0 ? ty : 0);
+    }
+    if (g > max_gauss || t > max_tiles) ok = 0;
+    if (!ok) { nr = 0; g = 0; t = 0; }
+    plan->gbase[nr] = uint32_t(g);
+    plan->tbase[nr] = uint32_t(t);
+    plan->nreq = nr;
+    plan->ok = ok;
+    plan->n_total = uint32_t(g);
+    plan->t_total = uint32_t(t);
+}
+
+// Enhancement MLP over all requests that carry one; one wave per 64-Gaussian group.
+__global__ void __launch_bounds__(256)
+batch_enhance_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan,
+                     float *__restrict__ phi, float *__restrict__ omod) {
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][64 * FEAT_STRIDE];
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int nreq = plan->nreq;
+    if (nreq == 0) return;
+    const int64_t ngroups = plan->n_total / 64;
+    MlpFrags F;
+    const void *loaded = nullptr;
+    for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
+        const int r = find_request(plan->gbase, nreq, uint32_t(grp * 64));
+        const mgs_request &q = reqs[r];
+        if (q.packed_mlp == nullptr) continue;                       // wave-uniform
+        if (q.packed_mlp != loaded) {
+            load_mlp(static_cast<const uint8_t *>(q.packed_mlp), l, F);
+            loaded = q.packed_mlp;
+        }
+        const int64_t i0 = grp * 64 - plan->gbase[r];
+        enhance_group(q.g, camk_device(q.cam), i0, F, s_x[w], phi, omod, grp * 64);
+    }
+}
+
+// Projection of every request's Gaussians into the global index space; padding and
+// unused slots up to max_gauss get n_tiles = 0.
+__global__ void __launch_bounds__(256)
+batch_project_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan, int64_t max_gauss,
+                     const float *__restrict__ phi, const float *__restrict__ omod, float alpha_min,
+                     float4 *__restrict__ splat, uint2 *__restrict__ rect_out, uint32_t *__restrict__ ntiles_out) {
+    const int nreq = plan->nreq;
+    const uint32_t ntot = plan->n_total;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < max_gauss;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        if (k < int64_t(ntot)) {
+            const int r = find_request(plan->gbase, nreq, uint32_t(k));
+            const mgs_request &q = reqs[r];
+            const int64_t i = k - plan->gbase[r];
+            if (i < q.g.n) {
+                GaussIn in = load_gauss(q.g, i, nullptr, nullptr);
+                if (q.packed_mlp != nullptr) {
+                    in.phi = phi[k];
+                    in.om = omod[k];
+                }
+                store_proj(project_gaussian(in, camk_device(q.cam), alpha_min), k, splat, rect_out, ntiles_out);
+                continue;
+            }
+        }
+        rect_out[k] = make_uint2(0u, 0u);
+        ntiles_out[k] = 0u;
+    }
+}
+
+// One workgroup per global tile: the tile of its request, into the request's image.
+__global__ void __launch_bounds__(BLEND_THREADS)
+batch_blend_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan,
+                   const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
+                   const uint32_t *__restrict__ gids, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+                   float log2_amin, float amax) {
+    const uint32_t gt = blockIdx.x;
+    if (gt >= plan->t_total) return;                                  // block-uniform
+    if (uint64_t(*n_pairs) > capacity) return;                        // lists were not built
+    const int r = find_request(plan->tbase, plan->nreq, gt);
+    const mgs_request &q = reqs[r];
+    const uint32_t lt = gt - plan->tbase[r];
+    const uint32_t tx = plan->tiles_x[r];
+    blend_tile<false>(splat, gids, offs[gt], offs[gt + 1], int(lt % tx), int(lt / tx), q.cam.width, q.cam.height,
+                      q.bg[0], q.bg[1], q.bg[2], log2_amin, amax, 0.0f, q.image, nullptr);
+}
+
+__global__ void batch_status_kernel(const BatchPlan *__restrict__ plan, int32_t *__restrict__ status) {
+    status[0] = plan->ok;
+    status[1] = plan->nreq;
+}
+
+struct BatchLayout {
+    size_t plan, phi, omod, splat, rect, ntiles, offs, gids, bin, total;
+};
+
+inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t capacity) {
+    BatchLayout L;
+    const size_t ng = size_t(max_gauss > 0 ? max_gauss : 1), cap = size_t(capacity > 0 ? capacity : 1);
+    size_t o = 0;
+    L.plan = o;   o = align_up(o + sizeof(BatchPlan), 256);
+    L.phi = o;    o = align_up(o + ng * 4, 256);
+    L.omod = o;   o = align_up(o + ng * 4, 256);
+    L.splat = o;  o = align_up(o + ng * 48, 256);
+    L.rect = o;   o = align_up(o + ng * 8, 256);
+    L.ntiles = o; o = align_up(o + ng * 4, 256);
+    L.offs = o;   o = align_up(o + (size_t(max_tiles) + 1) * 4, 256);
+    L.gids = o;   o = align_up(o + cap * 4, 256);
+    L.bin = o;    o = align_up(o + bin_batch_workspace(int64_t(ng), uint32_t(max_tiles), capacity), 256);
+    L.total = o;
+    return L;
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uint64_t capacity, size_t *bytes) {
+    MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
+    MGS_REQUIRE(max_gaussians > 0 && max_gaussians < (int64_t(1) << 31), "max_gaussians out of range");
+    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 24), "max_tiles out of range");
+    MGS_REQUIRE(capacity > 0 && capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    *bytes = mgs::batch_layout(max_gaussians, max_tiles, capacity).total;
+    return MGS_OK;
+}
+
+extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_requests, int64_t max_gaussians,
+                                int64_t max_tiles, uint64_t capacity, float alpha_min, float alpha_max, void *ws,
+                                size_t ws_bytes, uint32_t *n_pairs, int32_t *status, void *stream) {
+    using namespace mgs;
+    MGS_REQUIRE(requests && n_requests && n_pairs, "requests / n_requests / n_pairs is NULL");
+    MGS_REQUIRE(max_gaussians > 0 && max_gaussians < (int64_t(1) << 31), "max_gaussians out of range");
+    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 24), "max_tiles out of range");
+    MGS_REQUIRE(capacity > 0 && capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    MGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f && alpha_max > alpha_min && alpha_max < 1.f, "bad alpha range");
+    const BatchLayout L = batch_layout(max_gaussians, max_tiles, capacity);
+    MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= L.total, "workspace too small (%zu < %zu)", ws_bytes, L.total);
+    hipStream_t s = as_stream(stream);
+    char *w = static_cast<char *>(ws);
+    BatchPlan *plan = reinterpret_cast<BatchPlan *>(w + L.plan);
+    float *phi = reinterpret_cast<float *>(w + L.phi);
+    float *omod = reinterpret_cast<float *>(w + L.omod);
+    float4 *splat = reinterpret_cast<float4 *>(w + L.splat);
+    uint2 *rect = reinterpret_cast<uint2 *>(w + L.rect);
+    uint32_t *ntiles = reinterpret_cast<uint32_t *>(w + L.ntiles);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(w + L.offs);
+    uint32_t *gids = reinterpret_cast<uint32_t *>(w + L.gids);
+
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(64), 0, s, requests, n_requests, uint64_t(max_gaussians),
+                       uint64_t(max_tiles), plan);
+    MGS_LAUNCH_CHECK("batch_plan_kernel");
+    const int64_t groups = (max_gaussians + 63) / 64;
+    const unsigned eblocks = unsigned(groups / 4 + 1 < 1024 ? groups / 4 + 1 : 1024);
+    hipLaunchKernelGGL(batch_enhance_kernel, dim3(eblocks), dim3(256), 0, s, requests, plan, phi, omod);
+    MGS_LAUNCH_CHECK("batch_enhance_kernel");
+    const unsigned pblocks = unsigned((max_gaussians + 255) / 256 < 8192 ? (max_gaussians + 255) / 256 : 8192);
+    hipLaunchKernelGGL(batch_project_kernel, dim3(pblocks), dim3(256), 0, s, requests, plan, max_gaussians, phi, omod,
+                       alpha_min, splat, rect, ntiles);
+    MGS_LAUNCH_CHECK("batch_project_kernel");
+    mgs_projected proj;
+    proj.splat = reinterpret_cast<float *>(splat);
+    proj.rect = reinterpret_cast<uint32_t *>(rect);
+    proj.n_tiles = ntiles;
+    int rc = bin_batch(&proj, max_gaussians, plan, uint32_t(max_tiles), w + L.bin, L.total - L.bin, offs, gids,
+                       capacity, n_pairs, s);
+    if (rc != MGS_OK) return rc;
+    hipLaunchKernelGGL(batch_blend_kernel, dim3(unsigned(max_tiles)), dim3(BLEND_THREADS), 0, s, requests, plan,
+                       splat, offs, gids, n_pairs, capacity, log2f(alpha_min), alpha_max);
+    MGS_LAUNCH_CHECK("batch_blend_kernel");
+    if (status) {
+        hipLaunchKernelGGL(batch_status_kernel, dim3(1), dim3(1), 0, s, plan, status);
+        MGS_LAUNCH_CHECK("batch_status_kernel");
+    }
+    return MGS_OK;
+}

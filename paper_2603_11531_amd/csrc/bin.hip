@@ -13,7 +13,7 @@
 // two radix passes), so each list stays in ascending Gaussian order.  The
 // sorted comparison path uses the 64-bit key (tile << 32 | depth bits), i.e.
 // the usual depth sort, which needs 32 + tile bits of radix passes.
-#include "common.h"
+#include "batch.h"
 
 namespace mgs {
 
@@ -22,8 +22,9 @@ constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;     // 4096 elements per block
 constexpr int RADIX_THREADS = 256;
 constexpr int RADIX_WAVES = RADIX_THREADS / 64;
-constexpr int RADIX_ITERS = 8;                            // 64-key steps per wave
-constexpr int RADIX_TILE = RADIX_THREADS * RADIX_ITERS;   // 2048 keys per block
+constexpr int RADIX_ITERS = 16;                           // 64-key steps per wave
+constexpr int RADIX_TILE = RADIX_THREADS * RADIX_ITERS;   // 4096 keys per block
+constexpr int EXPAND_SMALL = 16;                          // pairs a lane writes on its own
 constexpr int RADIX_MAX_BITS = 8;
 constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
 
@@ -137,56 +138,107 @@ int scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *tmp, 
     return MGS_OK;
 }
 
+// Exclusive scan of one value per thread over a 256-thread block (all threads call).
+template <typename T>
+__device__ __forceinline__ T block_excl_scan256(T v, T *s_wsum /* [4] */) {
+    const unsigned l = lane_id();
+    const int w = threadIdx.x >> 6;
+    const T inc = wave_incl_scan(v);
+    if (l == 63) s_wsum[w] = inc;
+    __syncthreads();
+    T pre = 0;
+    for (int k = 0; k < w; ++k) pre += s_wsum[k];
+    __syncthreads();
+    return pre + inc - v;
+}
+
+// ----------------------------------------------------------------- pair counts
+// Sum of n_tiles over each group of 256 Gaussians (the expand kernel's block).
+__global__ void __launch_bounds__(256)
+count_reduce_kernel(const uint32_t *__restrict__ ntiles, int64_t n, uint64_t *__restrict__ sums) {
+    __shared__ uint64_t wsum[4];
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    uint64_t v = g < n ? ntiles[g] : 0u;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
 // ----------------------------------------------------------------- expand
 struct TileKey {
-    __device__ __forceinline__ uint32_t operator()(uint32_t tile, const float4 *) const { return tile; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t tile, float) const { return tile; }
 };
 struct TileDepthKey {
-    __device__ __forceinline__ uint64_t operator()(uint32_t tile, const float4 *rec1) const {
-        // depth > near_z > 0 for every listed Gaussian, so its IEEE bits order like the value
-        return (uint64_t(tile) << 32) | uint64_t(__float_as_uint(rec1->w));
+    // depth > near_z > 0 for every listed Gaussian, so its IEEE bits order like the value
+    __device__ __forceinline__ uint64_t operator()(uint32_t tile, float depth) const {
+        return (uint64_t(tile) << 32) | uint64_t(__float_as_uint(depth));
     }
 };
 
-template <typename K, typename KeyFn>
+// One block per 256 Gaussians.  The block's first pair slot comes from the scanned
+// per-block counts; inside the block a wave/LDS scan gives every Gaussian its slot.
+// Gaussians with at most EXPAND_SMALL tiles are written by their own lane (row by
+// row over the rectangle); larger ones are written by the whole wave.
+// Global tile id of tile (tx, ty) of Gaussian g's view: a single view, or a batch of views.
+struct GridMap {
+    uint32_t tiles_x;
+    __device__ __forceinline__ uint32_t base(int64_t, uint32_t &tx) const { tx = tiles_x; return 0u; }
+};
+struct BatchMap {
+    const BatchPlan *plan;
+    __device__ __forceinline__ uint32_t base(int64_t g, uint32_t &tx) const {
+        const int r = find_request(plan->gbase, plan->nreq, uint32_t(g));
+        tx = plan->tiles_x[r];
+        return plan->tbase[r];
+    }
+};
+
+template <typename K, typename KeyFn, typename Map>
 __global__ void __launch_bounds__(256)
 expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
-              const uint32_t *__restrict__ first, const float4 *__restrict__ splat, int64_t n,
-              int tiles_x, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+              const uint64_t *__restrict__ block_first, const float4 *__restrict__ splat, int64_t n,
+              Map map, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
               K *__restrict__ keys, uint32_t *__restrict__ vals, KeyFn keyfn) {
-    __shared__ uint32_t s_excl[4][64];
-    __shared__ uint2 s_rect[4][64];
-    if (uint64_t(*n_pairs) > capacity) return;
-    const int w = threadIdx.x / 64;
-    const unsigned l = lane_id();
-    const int64_t g0 = (int64_t(blockIdx.x) * 4 + w) * 64;
-    if (g0 >= n) return;                      // wave-uniform
-    const int64_t g = g0 + l;
+    __shared__ uint32_t s_wsum[4];
+    if (uint64_t(*n_pairs) > capacity) return;          // block-uniform
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const uint32_t cnt = g < n ? ntiles[g] : 0u;
-    const uint32_t inc = wave_incl_scan(cnt);
-    const uint32_t total = __shfl(inc, 63, 64);
-    s_excl[w][l] = inc - cnt;
-    s_rect[w][l] = g < n ? rect[g] : make_uint2(0u, 0u);
-    const uint32_t base = first[g0];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t p = l; p < total; p += 64) {
-        // last j with excl[j] <= p (it has a non-zero count)
-        int lo = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (s_excl[w][lo + step] <= p) lo += step;
-        const uint32_t k = p - s_excl[w][lo];
-        const uint2 r = s_rect[w][lo];
-        const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu;
-        const uint32_t wdt = x1 - x0 + 1;
-        const uint32_t ty = y0 + k / wdt;
-        const uint32_t tx = x0 + k % wdt;
-        const uint32_t tile = ty * uint32_t(tiles_x) + tx;
-        const int64_t gg = g0 + lo;
-        keys[base + p] = keyfn(tile, splat + 3 * gg + 1);
-        vals[base + p] = uint32_t(gg);
+    const uint32_t excl = block_excl_scan256<uint32_t>(cnt, s_wsum);
+    const uint32_t base = uint32_t(block_first[blockIdx.x]) + excl;
+    uint2 r = make_uint2(0u, 0u);
+    float depth = 0.f;
+    uint32_t tbase = 0u, tiles_x = 0u;
+    if (cnt > 0) {
+        r = rect[g];
+        depth = splat[3 * g + 1].w;
+        tbase = map.base(g, tiles_x);
+    }
+    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+    if (cnt > 0 && cnt <= uint32_t(EXPAND_SMALL)) {
+        uint32_t p = base;
+        for (uint32_t ty = y0; ty <= y1; ++ty)
+            for (uint32_t tx = x0; tx <= x1; ++tx, ++p) {
+                keys[p] = keyfn(tbase + ty * tiles_x + tx, depth);
+                vals[p] = uint32_t(g);
+            }
+    }
+    uint64_t big = __ballot(cnt > uint32_t(EXPAND_SMALL));
+    const unsigned l = lane_id();
+    while (big) {
+        const int j = __builtin_ctzll(big);
+        big &= big - 1;
+        const uint32_t bj = __shfl(base, j, 64), cj = __shfl(cnt, j, 64);
+        const uint32_t xj = __shfl(x0, j, 64), yj = __shfl(y0, j, 64), x1j = __shfl(x1, j, 64);
+        const float dj = __shfl(depth, j, 64);
+        const uint32_t tbj = __shfl(tbase, j, 64), txj = __shfl(tiles_x, j, 64);
+        const uint32_t gj = uint32_t(g - l + j);
+        const uint32_t wdt = x1j - xj + 1;
+        for (uint32_t p = l; p < cj; p += 64) {
+            const uint32_t ty = yj + p / wdt, tx = xj + p % wdt;
+            keys[bj + p] = keyfn(tbj + ty * txj + tx, dj);
+            vals[bj + p] = gj;
+        }
     }
 }
 
@@ -206,6 +258,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
     return peers;
 }
 
+// Per-block digit counts, digit-major: counts[d * nblocks + block].
 template <typename K>
 __global__ void __launch_bounds__(RADIX_THREADS)
 radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
@@ -231,39 +284,80 @@ radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS) {
-        uint32_t s = 0;
-        for (int ww = 0; ww < RADIX_WAVES; ++ww) s += cnt[ww][d];
-        counts[int64_t(d) * nblocks + blockIdx.x] = s;
-    }
+    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS)
+        counts[int64_t(d) * nblocks + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
 }
 
+// One block per digit: exclusive scan of that digit's per-block counts, and its total.
+__global__ void __launch_bounds__(256)
+radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, uint32_t *__restrict__ digit_total) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_tot;
+    uint32_t *row = counts + int64_t(blockIdx.x) * nblocks;
+    uint32_t carry = 0;
+    constexpr int ITEMS = 8;
+    for (int b0 = 0; b0 < nblocks; b0 += 256 * ITEMS) {
+        const int i0 = b0 + threadIdx.x * ITEMS;
+        uint32_t v[ITEMS], s = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            v[k] = i0 + k < nblocks ? row[i0 + k] : 0u;
+            s += v[k];
+        }
+        uint32_t pre = block_excl_scan256<uint32_t>(s, s_wsum);
+        if (threadIdx.x == 255) s_tot = pre + s;
+        __syncthreads();
+        pre += carry;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (i0 + k < nblocks) row[i0 + k] = pre;
+            pre += v[k];
+        }
+        carry += s_tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+// Stable scatter of one 4096-key block: ranks from ballot-matched digits, the
+// block's keys reordered by digit in LDS, then written out in runs (coalesced).
 template <typename K>
 __global__ void __launch_bounds__(RADIX_THREADS)
 radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
                        const uint32_t *__restrict__ n_pairs, uint64_t capacity, int shift, int bits,
-                       const uint32_t *__restrict__ offsets, int nblocks, K *__restrict__ keys_out,
-                       uint32_t *__restrict__ vals_out) {
+                       const uint32_t *__restrict__ colscan, const uint32_t *__restrict__ digit_total,
+                       int nblocks, K *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
     __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
+    __shared__ uint32_t s_lstart[RADIX_MAX_DIGITS], s_gstart[RADIX_MAX_DIGITS];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ K sk[RADIX_TILE];
+    __shared__ uint32_t sv[RADIX_TILE];
     const uint32_t P = *n_pairs;
-    if (uint64_t(P) > capacity) return;
-    if (int64_t(blockIdx.x) * RADIX_TILE >= int64_t(P)) return;      // block-uniform
+    if (uint64_t(P) > capacity) return;                                   // block-uniform
+    const int64_t blk0 = int64_t(blockIdx.x) * RADIX_TILE;
+    if (blk0 >= int64_t(P)) return;                                        // block-uniform
     const int nd = 1 << bits;
     const uint32_t mask = uint32_t(nd - 1);
-    for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+    const int t = threadIdx.x;
+    for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+    {
+        const uint32_t dt = t < nd ? digit_total[t] : 0u;
+        const uint32_t ex = block_excl_scan256<uint32_t>(dt, s_wsum);      // contains __syncthreads
+        if (t < nd) s_gstart[t] = ex + colscan[int64_t(t) * nblocks + blockIdx.x];
+    }
     __syncthreads();
-    const int w = threadIdx.x / 64;
+    const int w = t / 64;
     const unsigned l = lane_id();
-    const int64_t base = int64_t(blockIdx.x) * RADIX_TILE + w * (RADIX_ITERS * 64);
+    const int64_t base = blk0 + w * (RADIX_ITERS * 64);
     K key[RADIX_ITERS];
-    uint32_t rank[RADIX_ITERS];
-    uint32_t dig[RADIX_ITERS];
+    uint32_t val[RADIX_ITERS], rank[RADIX_ITERS], dig[RADIX_ITERS];
 #pragma unroll
     for (int it = 0; it < RADIX_ITERS; ++it) {
         const int64_t idx = base + it * 64 + l;
         const bool ok = idx < int64_t(P);
         const uint64_t active = __ballot(ok);
         key[it] = ok ? keys_in[idx] : K(0);
+        val[it] = ok ? vals_in[idx] : 0u;
         const uint32_t d = ok ? digit_of(key[it], shift, mask) : 0u;
         dig[it] = d;
         rank[it] = 0;
@@ -277,24 +371,34 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
         }
     }
     __syncthreads();
-    // exclusive prefix over waves, plus the block's global digit offset
-    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS) {
-        uint32_t s = offsets[int64_t(d) * nblocks + blockIdx.x];
+    uint32_t tot = 0;
+    if (t < nd) {
         for (int ww = 0; ww < RADIX_WAVES; ++ww) {
-            const uint32_t c = cnt[ww][d];
-            cnt[ww][d] = s;
-            s += c;
+            const uint32_t c = cnt[ww][t];
+            cnt[ww][t] = tot;
+            tot += c;
         }
     }
+    const uint32_t lex = block_excl_scan256<uint32_t>(tot, s_wsum);        // contains __syncthreads
+    if (t < nd) s_lstart[t] = lex;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < RADIX_ITERS; ++it) {
         const int64_t idx = base + it * 64 + l;
         if (idx < int64_t(P)) {
-            const uint32_t dst = cnt[w][dig[it]] + rank[it];
-            keys_out[dst] = key[it];
-            vals_out[dst] = vals_in[idx];
+            const uint32_t lp = s_lstart[dig[it]] + cnt[w][dig[it]] + rank[it];
+            sk[lp] = key[it];
+            sv[lp] = val[it];
         }
+    }
+    __syncthreads();
+    const int nloc = int(int64_t(P) - blk0 < RADIX_TILE ? int64_t(P) - blk0 : RADIX_TILE);
+    for (int lp = t; lp < nloc; lp += RADIX_THREADS) {
+        const K k = sk[lp];
+        const uint32_t d = digit_of(k, shift, mask);
+        const uint32_t dst = s_gstart[d] + uint32_t(lp) - s_lstart[d];
+        keys_out[dst] = k;
+        vals_out[dst] = sv[lp];
     }
 }
 
@@ -325,39 +429,36 @@ inline int bits_for(uint64_t v) {
 }
 
 struct BinLayout {
-    size_t off_first, off_scan, off_keys0, off_keys1, off_vals1, off_hist, off_hscan, off_ptot, total;
-    int nblocks;
+    size_t off_sums, off_keys0, off_keys1, off_vals1, off_hist, off_dtot, total;
+    int nblocks, nsums;
 };
-
 
 template <typename K>
 BinLayout bin_layout(int64_t n, uint64_t capacity) {
     BinLayout L;
     const int64_t nb = int64_t((capacity + RADIX_TILE - 1) / RADIX_TILE);
     L.nblocks = int(nb > 0 ? nb : 1);
-    const int64_t hist_elems = int64_t(RADIX_MAX_DIGITS) * L.nblocks;
+    L.nsums = int((n + 255) / 256) + 1;
+    const size_t cap = size_t(capacity > 0 ? capacity : 1);
     size_t o = 0;
-    L.off_first = o; o = align_up(o + size_t(n > 0 ? n : 1) * 4, 256);
-    L.off_scan = o;  o = align_up(o + (scan_tmp_elems(n) > scan_tmp_elems(hist_elems) ? scan_tmp_elems(n)
-                                                                                       : scan_tmp_elems(hist_elems)) * 8, 256);
-    L.off_keys0 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * sizeof(K), 256);
-    L.off_keys1 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * sizeof(K), 256);
-    L.off_vals1 = o; o = align_up(o + size_t(capacity > 0 ? capacity : 1) * 4, 256);
-    L.off_hist = o;  o = align_up(o + size_t(hist_elems) * 4, 256);
-    L.off_hscan = o; o = align_up(o + size_t(hist_elems) * 4, 256);
-    L.off_ptot = o;  o = align_up(o + 16, 256);
+    L.off_sums = o;  o = align_up(o + size_t(L.nsums) * 8, 256);
+    L.off_keys0 = o; o = align_up(o + cap * sizeof(K), 256);
+    L.off_keys1 = o; o = align_up(o + cap * sizeof(K), 256);
+    L.off_vals1 = o; o = align_up(o + cap * 4, 256);
+    L.off_hist = o;  o = align_up(o + size_t(RADIX_MAX_DIGITS) * L.nblocks * 4, 256);
+    L.off_dtot = o;  o = align_up(o + RADIX_MAX_DIGITS * 4, 256);
     L.total = o;
     return L;
 }
 
-template <typename K, typename KeyFn>
-int bin_impl(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws, size_t ws_bytes,
+template <typename K, typename KeyFn, typename Map>
+int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws, size_t ws_bytes,
              uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
              hipStream_t s, int key_bits, int range_shift) {
     int rc;
     MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
     if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
-    MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
+    MGS_REQUIRE(T > 0, "bad tile grid");
     MGS_REQUIRE(tile_offsets && n_pairs, "tile_offsets / n_pairs is NULL");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity must be < 2^32 - 1");
     MGS_REQUIRE(capacity == 0 || gids, "gids is NULL");
@@ -365,28 +466,30 @@ int bin_impl(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, voi
     const BinLayout L = bin_layout<K>(n, capacity);
     MGS_REQUIRE(ws_bytes >= L.total, "workspace too small (%zu < %zu)", ws_bytes, L.total);
     char *w = static_cast<char *>(ws);
-    uint32_t *first = reinterpret_cast<uint32_t *>(w + L.off_first);
-    uint64_t *stmp = reinterpret_cast<uint64_t *>(w + L.off_scan);
+    uint64_t *sums = reinterpret_cast<uint64_t *>(w + L.off_sums);
     K *k0 = reinterpret_cast<K *>(w + L.off_keys0);
     K *k1 = reinterpret_cast<K *>(w + L.off_keys1);
     uint32_t *v1 = reinterpret_cast<uint32_t *>(w + L.off_vals1);
     uint32_t *hist = reinterpret_cast<uint32_t *>(w + L.off_hist);
-    uint32_t *hscan = reinterpret_cast<uint32_t *>(w + L.off_hscan);
-    uint32_t *ptot = reinterpret_cast<uint32_t *>(w + L.off_ptot);
-    const uint32_t T = uint32_t(tiles_x) * uint32_t(tiles_y);
+    uint32_t *dtot = reinterpret_cast<uint32_t *>(w + L.off_dtot);
+    const unsigned nb256 = unsigned((n + 255) / 256);
 
-    // 1. pair slots
-    if ((rc = scan_exclusive(proj->n_tiles, first, n, stmp, n_pairs, s)) != MGS_OK) return rc;
+    // 1. pair slots: per-256-Gaussian counts, scanned (the grand total is P)
+    if (nb256 > 0) {
+        hipLaunchKernelGGL(count_reduce_kernel, dim3(nb256), dim3(256), 0, s, proj->n_tiles, n, sums);
+        MGS_LAUNCH_CHECK("count_reduce_kernel");
+    }
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums, int(nb256), n_pairs);
+    MGS_LAUNCH_CHECK("scan_sums_kernel");
     // 2. expand
     const int npass = (key_bits + RADIX_MAX_BITS - 1) / RADIX_MAX_BITS;
     K *kin = k0, *kout = k1;
     uint32_t *vbuf[2] = {gids, v1};
     uint32_t *vin = vbuf[npass % 2];
-    if (n > 0) {
-        const unsigned eb = unsigned((n + 255) / 256);
-        hipLaunchKernelGGL((expand_kernel<K, KeyFn>), dim3(eb), dim3(256), 0, s,
-                           reinterpret_cast<const uint2 *>(proj->rect), proj->n_tiles, first,
-                           reinterpret_cast<const float4 *>(proj->splat), n, tiles_x, n_pairs,
+    if (nb256 > 0) {
+        hipLaunchKernelGGL((expand_kernel<K, KeyFn, Map>), dim3(nb256), dim3(256), 0, s,
+                           reinterpret_cast<const uint2 *>(proj->rect), proj->n_tiles, sums,
+                           reinterpret_cast<const float4 *>(proj->splat), n, map, n_pairs,
                            capacity, kin, vin, KeyFn());
         MGS_LAUNCH_CHECK("expand_kernel");
     }
@@ -399,10 +502,10 @@ int bin_impl(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, voi
             hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
                                n_pairs, capacity, shift, bits, hist, L.nblocks);
             MGS_LAUNCH_CHECK("radix_upsweep_kernel");
-            const int64_t helems = int64_t(1 << bits) * L.nblocks;
-            if ((rc = scan_exclusive(hist, hscan, helems, stmp, ptot, s)) != MGS_OK) return rc;
+            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, dtot);
+            MGS_LAUNCH_CHECK("radix_colscan_kernel");
             hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
-                               vin, n_pairs, capacity, shift, bits, hscan, L.nblocks, kout, vout);
+                               vin, n_pairs, capacity, shift, bits, hist, dtot, L.nblocks, kout, vout);
             MGS_LAUNCH_CHECK("radix_downsweep_kernel");
             K *tk = kin; kin = kout; kout = tk;
             vin = vout;
@@ -417,6 +520,18 @@ int bin_impl(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, voi
     return MGS_OK;
 }
 
+int bin_batch(const mgs_projected *proj, int64_t n_max, const BatchPlan *plan, uint32_t max_tiles, void *ws,
+              size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
+              hipStream_t s) {
+    const int key_bits = bits_for(max_tiles);
+    return bin_impl<uint32_t, TileKey>(proj, n_max, BatchMap{plan}, max_tiles, ws, ws_bytes, tile_offsets, gids,
+                                       capacity, n_pairs, s, key_bits > 0 ? key_bits : 1, 0);
+}
+
+size_t bin_batch_workspace(int64_t n_max, uint32_t, uint64_t capacity) {
+    return bin_layout<uint32_t>(n_max, capacity).total;
+}
+
 }  // namespace mgs
 
 extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes) {
@@ -429,9 +544,11 @@ extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t c
 extern "C" int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
                        size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
                        uint32_t *n_pairs, void *stream) {
+    MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
     const int key_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
-    return mgs::bin_impl<uint32_t, mgs::TileKey>(proj, n, tiles_x, tiles_y, ws, ws_bytes, tile_offsets, gids,
-                                                  capacity, n_pairs, mgs::as_stream(stream),
+    return mgs::bin_impl<uint32_t, mgs::TileKey>(proj, n, mgs::GridMap{uint32_t(tiles_x)},
+                                                  uint32_t(tiles_x) * uint32_t(tiles_y), ws, ws_bytes, tile_offsets,
+                                                  gids, capacity, n_pairs, mgs::as_stream(stream),
                                                   key_bits > 0 ? key_bits : 1, 0);
 }
 
@@ -446,8 +563,10 @@ extern "C" int mgs_bin_sorted_workspace(int64_t n, int tiles_x, int tiles_y, uin
 extern "C" int mgs_bin_sorted(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
                               size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
                               uint32_t *n_pairs, void *stream) {
+    MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
     const int tile_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
-    return mgs::bin_impl<uint64_t, mgs::TileDepthKey>(proj, n, tiles_x, tiles_y, ws, ws_bytes, tile_offsets,
-                                                       gids, capacity, n_pairs, mgs::as_stream(stream),
+    return mgs::bin_impl<uint64_t, mgs::TileDepthKey>(proj, n, mgs::GridMap{uint32_t(tiles_x)},
+                                                       uint32_t(tiles_x) * uint32_t(tiles_y), ws, ws_bytes,
+                                                       tile_offsets, gids, capacity, n_pairs, mgs::as_stream(stream),
                                                        32 + (tile_bits > 0 ? tile_bits : 1), 32);
 }

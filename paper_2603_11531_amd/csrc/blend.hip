@@ -11,16 +11,13 @@
 // Gaussians (ballot over the masks, scalar bit loop), so a wave never spends
 // VALU cycles on a splat that cannot reach its 64 pixels.
 //
-// Per pixel-Gaussian pair the OIT inner loop is: 2 subtractions, 3 FMA and
-// 2 multiplies for the exponent, 1 exp2, 1 compare/select, 1 min and 6 for the
-// accumulation of N (rgb), D and T -- all float32 VALU, no sort, no order.
+// Per pixel-Gaussian pair the OIT inner loop is: 5 FMA for the exponent (a
+// polynomial in the lane's offset, see quad_poly), compare/select, min, exp2,
+// and 5 FMA to accumulate N (rgb, colours pre-multiplied by w), D and T -- all
+// float32 VALU, no sort, no order.
 #include "blend_math.h"
 
 namespace mgs {
-
-constexpr int BLEND_THREADS = 256;
-constexpr int BLEND_BATCH = 256;
-__device__ __forceinline__ int tile_index(int b) { return b; }
 
 template <bool SORTED>
 __global__ void __launch_bounds__(BLEND_THREADS)
@@ -28,111 +25,9 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
              const uint32_t *__restrict__ gids, CamK cam, float bgr, float bgg, float bgb,
              float log2_amin, float amax, float t_stop, float *__restrict__ image,
              float *__restrict__ aux) {
-    __shared__ float4 s_r0[BLEND_BATCH];
-    __shared__ float4 s_r1[BLEND_BATCH];
-    __shared__ float4 s_r2[BLEND_BATCH];
-    __shared__ uint32_t s_mask[BLEND_BATCH];
-    __shared__ int s_done[4];
-
-    const int tile = tile_index(blockIdx.x);
-    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int w = threadIdx.x >> 6;
-    const int l = threadIdx.x & 63;
-    const int px = tx * 16 + (w & 1) * 8 + (l & 7);
-    const int py = ty * 16 + (w >> 1) * 8 + (l >> 3);
-    const float fpx = float(px) + 0.5f, fpy = float(py) + 0.5f;
-    const uint32_t start = offs[tile], end = offs[tile + 1];
-
-    float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
-    bool wave_done = false;
-
-    for (uint32_t b = start; b < end; b += BLEND_BATCH) {
-        __syncthreads();
-        const uint32_t i = b + threadIdx.x;
-        uint32_t mask = 0;
-        if (i < end) {
-            const uint32_t g = gids[i];
-            const float4 r0 = splat[3 * size_t(g) + 0];
-            const float4 r1 = splat[3 * size_t(g) + 1];
-            const float4 r2 = splat[3 * size_t(g) + 2];
-            s_r0[threadIdx.x] = r0;
-            s_r1[threadIdx.x] = r1;
-            s_r2[threadIdx.x] = r2;
-            mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
-        }
-        s_mask[threadIdx.x] = mask;
-        if (SORTED && l == 0) s_done[w] = wave_done ? 1 : 0;
-        __syncthreads();
-        if (SORTED && s_done[0] && s_done[1] && s_done[2] && s_done[3]) break;
-        if (SORTED && wave_done) continue;
-        for (int grp = 0; grp < BLEND_BATCH / 64; ++grp) {
-            uint64_t bal = __ballot((s_mask[grp * 64 + l] >> w) & 1u);
-            while (bal) {
-                const int j = grp * 64 + __builtin_ctzll(bal);
-                bal &= bal - 1;
-                const float4 r0 = s_r0[j];
-                const float4 r1 = s_r1[j];
-                const float4 r2 = s_r2[j];
-                const float dx = fpx - r0.x;
-                const float dy = fpy - r0.y;
-                const float t = fmaf(r1.y, dy, dx);
-                const float e = fmaf(r1.x * t, t, fmaf(r1.z * dy, dy, r0.z));
-                if (!SORTED) {
-                    const float al = e >= log2_amin ? fminf(fast_exp2(e), amax) : 0.0f;
-                    const float aw = al * r0.w;
-                    Nr = fmaf(aw, r2.x, Nr);
-                    Ng = fmaf(aw, r2.y, Ng);
-                    Nb = fmaf(aw, r2.z, Nb);
-                    D += aw;
-                    T = fmaf(-T, al, T);
-                } else {
-                    const float al = (e >= log2_amin && T >= t_stop) ? fminf(fast_exp2(e), amax) : 0.0f;
-                    const float at = al * T;
-                    Nr = fmaf(at, r2.x, Nr);
-                    Ng = fmaf(at, r2.y, Ng);
-                    Nb = fmaf(at, r2.z, Nb);
-                    T = fmaf(-T, al, T);
-                }
-            }
-            if (SORTED) {
-                wave_done = __ballot(T >= t_stop) == 0ull;
-                if (wave_done) break;
-            }
-        }
-    }
-
-    if (px < cam.W && py < cam.H) {
-        const size_t hw = size_t(cam.W) * cam.H;
-        const size_t p = size_t(py) * cam.W + px;
-        float cr, cg, cb;
-        if (!SORTED) {
-            if (D > 0.f) {
-                const float inv = 1.0f / D;
-                const float fr = Nr * inv, fg = Ng * inv, fb = Nb * inv;
-                const float f = 1.0f - T;
-                cr = fmaf(f, fr, T * bgr);
-                cg = fmaf(f, fg, T * bgg);
-                cb = fmaf(f, fb, T * bgb);
-                if (aux) {
-                    aux[p] = fr; aux[hw + p] = fg; aux[2 * hw + p] = fb;
-                    aux[3 * hw + p] = D; aux[4 * hw + p] = T;
-                }
-            } else {
-                cr = bgr; cg = bgg; cb = bgb;
-                if (aux) {
-                    aux[p] = 0.f; aux[hw + p] = 0.f; aux[2 * hw + p] = 0.f;
-                    aux[3 * hw + p] = 0.f; aux[4 * hw + p] = 1.f;
-                }
-            }
-        } else {
-            cr = fmaf(T, bgr, Nr);
-            cg = fmaf(T, bgg, Ng);
-            cb = fmaf(T, bgb, Nb);
-        }
-        image[p] = cr;
-        image[hw + p] = cg;
-        image[2 * hw + p] = cb;
-    }
+    const int tile = blockIdx.x;
+    blend_tile<SORTED>(splat, gids, offs[tile], offs[tile + 1], tile % cam.tiles_x, tile / cam.tiles_x, cam.W,
+                       cam.H, bgr, bgg, bgb, log2_amin, amax, t_stop, image, aux);
 }
 
 inline int blend_common_checks(const mgs_projected *proj, const uint32_t *offs, const uint32_t *gids,

@@ -52,4 +52,153 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, int tx, 
     return m;
 }
 
+constexpr int BLEND_THREADS = 256;
+constexpr int BLEND_BATCH = 128;
+
+// Exponent of a splat as a polynomial in the lane's offset (x, y) from its
+// quadrant's centre, x, y in {-3.5 .. 3.5}:
+//   log2(alpha) = c0 + cx x + cy y + cxx x^2 + cxy x y + cyy y^2
+// (the same quadratic form as log2(o) + kA t^2 + kG dy^2, re-centred once per
+// staged splat and quadrant so the per-pixel work is five FMAs).
+__device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float yc, float4 &qa, float4 &qb) {
+    const float kA = r1.x, beta = r1.y, kG = r1.z;
+    const float u0 = xc - r0.x, v0 = yc - r0.y;
+    const float t0 = fmaf(beta, v0, u0);
+    qa.x = r0.z + kA * t0 * t0 + kG * v0 * v0;
+    qa.y = 2.0f * kA * t0;
+    qa.z = 2.0f * fmaf(kA * t0, beta, kG * v0);
+    qa.w = kA;
+    qb.x = 2.0f * kA * beta;
+    qb.y = fmaf(kA * beta, beta, kG);
+}
+
+// Composite one 16x16 tile (tile coordinates tx, ty) from its list gids[start, end)
+// into image / aux of a W x H view.  Called by a whole 256-thread workgroup.
+template <bool SORTED>
+__device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
+                                           uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
+                                           float bgg, float bgb, float log2_amin, float amax, float t_stop,
+                                           float *__restrict__ image, float *__restrict__ aux) {
+    // per quadrant and staged splat: polynomial (c0, cx, cy, cxx), (cxy, cyy, -, -) and the colour
+    // (OIT: (w r, w g, w b, w); sorted: (r, g, b, 0)), one 48-byte record so a wave reads all three
+    // with one address register
+    __shared__ float4 s_rec[4][BLEND_BATCH][3];
+    __shared__ uint32_t s_mask[BLEND_BATCH];
+    __shared__ int s_done[4];
+
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int px = tx * 16 + (w & 1) * 8 + (l & 7);
+    const int py = ty * 16 + (w >> 1) * 8 + (l >> 3);
+    // lane offset from the quadrant centre, and its products
+    const float lx = float(l & 7) - 3.5f, ly = float(l >> 3) - 3.5f;
+    const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
+
+    float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
+    bool wave_done = false;
+
+    for (uint32_t b = start; b < end; b += BLEND_BATCH) {
+        __syncthreads();
+        if (threadIdx.x < BLEND_BATCH) {
+            const uint32_t i = b + threadIdx.x;
+            uint32_t mask = 0;
+            if (i < end) {
+                const uint32_t g = gids[i];
+                const float4 r0 = splat[3 * size_t(g) + 0];
+                const float4 r1 = splat[3 * size_t(g) + 1];
+                const float4 r2 = splat[3 * size_t(g) + 2];
+                mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
+                const float4 col = SORTED ? make_float4(r2.x, r2.y, r2.z, 0.f)
+                                          : make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if ((mask >> q) & 1u) {
+                        float4 qa;
+                        float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
+                        quad_poly(r0, r1, float(tx * 16 + (q & 1) * 8) + 4.0f, float(ty * 16 + (q >> 1) * 8) + 4.0f,
+                                  qa, qb);
+                        s_rec[q][threadIdx.x][0] = qa;
+                        s_rec[q][threadIdx.x][1] = qb;
+                        s_rec[q][threadIdx.x][2] = col;
+                    }
+                }
+            }
+            s_mask[threadIdx.x] = mask;
+        }
+        if (SORTED && l == 0) s_done[w] = wave_done ? 1 : 0;
+        __syncthreads();
+        if (SORTED && s_done[0] && s_done[1] && s_done[2] && s_done[3]) break;
+        if (SORTED && wave_done) continue;
+        const int wu = __builtin_amdgcn_readfirstlane(w);       // wave-uniform quadrant index
+        const float4(*rec_w)[3] = s_rec[wu];
+        for (int grp = 0; grp < BLEND_BATCH / 64; ++grp) {
+            uint64_t bal = __ballot((s_mask[grp * 64 + l] >> w) & 1u);
+            while (bal) {
+                const int j = grp * 64 + __builtin_ctzll(bal);
+                bal &= bal - 1;
+                const float4 qa = rec_w[j][0];
+                const float4 qb = rec_w[j][1];
+                const float4 cw = rec_w[j][2];
+                float e = fmaf(qa.y, lx, qa.x);
+                e = fmaf(qa.z, ly, e);
+                e = fmaf(qa.w, lxx, e);
+                e = fmaf(qb.x, lxy, e);
+                e = fmaf(qb.y, lyy, e);
+                if (!SORTED) {
+                    const float al = e >= log2_amin ? fminf(fast_exp2(e), amax) : 0.0f;
+                    Nr = fmaf(al, cw.x, Nr);
+                    Ng = fmaf(al, cw.y, Ng);
+                    Nb = fmaf(al, cw.z, Nb);
+                    D = fmaf(al, cw.w, D);
+                    T = fmaf(-T, al, T);
+                } else {
+                    const float al = (e >= log2_amin && T >= t_stop) ? fminf(fast_exp2(e), amax) : 0.0f;
+                    const float at = al * T;
+                    Nr = fmaf(at, cw.x, Nr);
+                    Ng = fmaf(at, cw.y, Ng);
+                    Nb = fmaf(at, cw.z, Nb);
+                    T = fmaf(-T, al, T);
+                }
+            }
+            if (SORTED) {
+                wave_done = __ballot(T >= t_stop) == 0ull;
+                if (wave_done) break;
+            }
+        }
+    }
+
+    if (px < W && py < H) {
+        const size_t hw = size_t(W) * H;
+        const size_t p = size_t(py) * W + px;
+        float cr, cg, cb;
+        if (!SORTED) {
+            if (D > 0.f) {
+                const float inv = 1.0f / D;
+                const float fr = Nr * inv, fg = Ng * inv, fb = Nb * inv;
+                const float f = 1.0f - T;
+                cr = fmaf(f, fr, T * bgr);
+                cg = fmaf(f, fg, T * bgg);
+                cb = fmaf(f, fb, T * bgb);
+                if (aux) {
+                    aux[p] = fr; aux[hw + p] = fg; aux[2 * hw + p] = fb;
+                    aux[3 * hw + p] = D; aux[4 * hw + p] = T;
+                }
+            } else {
+                cr = bgr; cg = bgg; cb = bgb;
+                if (aux) {
+                    aux[p] = 0.f; aux[hw + p] = 0.f; aux[2 * hw + p] = 0.f;
+                    aux[3 * hw + p] = 0.f; aux[4 * hw + p] = 1.f;
+                }
+            }
+        } else {
+            cr = fmaf(T, bgr, Nr);
+            cg = fmaf(T, bgg, Ng);
+            cb = fmaf(T, bgb, Nb);
+        }
+        image[p] = cr;
+        image[hw + p] = cg;
+        image[2 * hw + p] = cb;
+    }
+}
+
 }  // namespace mgs

@@ -14,25 +14,9 @@
 // next weight matrix is permuted to match -- which mgs_mlp_pack does once.
 // No shuffles or LDS round trips between layers.  All weight fragments
 // (14 x 16 bytes per lane) stay in registers for the wave's lifetime.
-#include "common.h"
+#include "mlp_math.h"
 
 namespace mgs {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
-
-// Packed layout (bytes): L1 fragments [4 mb][64 lanes][8]        @ 0
-//                        L2 fragments [4 mb][2 kc][64 lanes][8]  @ 4096
-//                        head fragments [2 kc][64 lanes][8]      @ 12288
-//                        b1[64] f32 @ 14336, b2[64] f32 @ 14592, b_phi, b_o @ 14848
-constexpr int PK_L1 = 0, PK_L2 = 4096, PK_H = 12288, PK_B1 = 14336, PK_B2 = 14592, PK_BH = 14848;
-static_assert(PK_BH + 8 <= MGS_MLP_PACKED_BYTES, "packed MLP size");
-
-// Input neuron fed by K-slot j of K-chunk kc in lane group g (see header comment).
-__host__ __device__ __forceinline__ int perm_neuron(int kc, int g, int j) {
-    return 16 * (2 * kc + (j >> 2)) + 4 * g + (j & 3);
-}
 
 __global__ void __launch_bounds__(256)
 mlp_pack_kernel(const float *__restrict__ prm, uint8_t *__restrict__ packed) {
@@ -71,114 +55,17 @@ mlp_pack_kernel(const float *__restrict__ prm, uint8_t *__restrict__ packed) {
     }
 }
 
-__device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
-    f32x8 v;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        v[i] = fmaxf(lo[i], 0.0f);
-        v[i + 4] = fmaxf(hi[i], 0.0f);
-    }
-    return __builtin_convertvector(v, bf16x8);
-}
-
-constexpr int FEAT_STRIDE = 40;   // bf16 per LDS row (32 + 8 padding)
-
 __global__ void __launch_bounds__(256)
 enhance_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, float *__restrict__ phi,
                float *__restrict__ omod) {
     __shared__ __attribute__((aligned(16))) __bf16 s_x[4][64 * FEAT_STRIDE];
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
-    const int lg = l >> 4;           // lane group
-    const int64_t n = g.n;
-    const int64_t ngroups = (n + 63) / 64;
-
-    // weight fragments and biases, resident for the wave's lifetime
-    const bf16x8 *pl1 = reinterpret_cast<const bf16x8 *>(packed + PK_L1);
-    const bf16x8 *pl2 = reinterpret_cast<const bf16x8 *>(packed + PK_L2);
-    const bf16x8 *phh = reinterpret_cast<const bf16x8 *>(packed + PK_H);
-    const float *fb1 = reinterpret_cast<const float *>(packed + PK_B1);
-    const float *fb2 = reinterpret_cast<const float *>(packed + PK_B2);
-    const float *fbh = reinterpret_cast<const float *>(packed + PK_BH);
-    bf16x8 A1[4], A2[4][2], AH[2];
-    f32x4 B1[4], B2[4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        A1[mb] = pl1[mb * 64 + l];
-        A2[mb][0] = pl2[(mb * 2 + 0) * 64 + l];
-        A2[mb][1] = pl2[(mb * 2 + 1) * 64 + l];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            B1[mb][i] = fb1[16 * mb + 4 * lg + i];
-            B2[mb][i] = fb2[16 * mb + 4 * lg + i];
-        }
-    }
-    AH[0] = phh[l];
-    AH[1] = phh[64 + l];
-    const float bphi = fbh[0], bo = fbh[1];
-
-    __bf16 *xs = s_x[w];
-    for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
-        const int64_t i = grp * 64 + l;
-        f32x8 f[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
-        if (i < n) {
-            const float mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
-            const float vx = mx - cam.campos[0], vy = my - cam.campos[1], vz = mz - cam.campos[2];
-            const float vn = rsqrtf(vx * vx + vy * vy + vz * vz);
-            float qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
-            const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
-            const float qi = qn2 > 0.f ? rsqrtf(qn2) : 0.f;
-            f[0][0] = vx * vn; f[0][1] = vy * vn; f[0][2] = vz * vn;
-            f[0][3] = expf(g.log_scale[i]);
-            f[0][4] = expf(g.log_scale[n + i]);
-            f[0][5] = expf(g.log_scale[2 * n + i]);
-            f[0][6] = qw * qi; f[0][7] = qx * qi;
-            f[1][0] = qy * qi; f[1][1] = qz * qi;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                const float y = g.sh[k * n + i];
-                const int slot = 10 + k;
-                f[slot >> 3][slot & 7] = y;
-            }
-        }
-        bf16x8 *row = reinterpret_cast<bf16x8 *>(xs + l * FEAT_STRIDE);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) row[c] = __builtin_convertvector(f[c], bf16x8);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(xs + (nb * 16 + (l & 15)) * FEAT_STRIDE + 8 * lg);
-            f32x4 h1[4];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) h1[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[mb], xb, B1[mb], 0, 0, 0);
-            const bf16x8 x2a = relu_pack(h1[0], h1[1]);
-            const bf16x8 x2b = relu_pack(h1[2], h1[3]);
-            f32x4 h2[4];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) {
-                h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[mb][0], x2a, B2[mb], 0, 0, 0);
-                h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[mb][1], x2b, h2[mb], 0, 0, 0);
-            }
-            const bf16x8 xha = relu_pack(h2[0], h2[1]);
-            const bf16x8 xhb = relu_pack(h2[2], h2[3]);
-            f32x4 hz = {0.f, 0.f, 0.f, 0.f};
-            f32x4 hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH[0], xha, hz, 0, 0, 0);
-            hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH[1], xhb, hd, 0, 0, 0);
-            const int64_t gi = grp * 64 + nb * 16 + l;
-            if (l < 16 && gi < n) {
-                phi[gi] = fmaxf(hd[0] + bphi, 0.0f);
-                omod[gi] = 1.0f / (1.0f + expf(-(hd[1] + bo)));
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    const int64_t ngroups = (g.n + 63) / 64;
+    MlpFrags F;
+    load_mlp(packed, l, F);
+    for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4)
+        enhance_group(g, cam, grp * 64, F, s_x[w], phi, omod, grp * 64);
 }
 
 }  // namespace mgs

@@ -140,4 +140,50 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
     return f;
 }
 
+// Everything mgs_project writes for one Gaussian.
+struct ProjOut {
+    float4 r0, r1, r2;
+    uint2 rect;
+    uint32_t n_tiles;
+};
+
+__device__ __forceinline__ ProjOut project_gaussian(const GaussIn &in, const CamK &cam, float alpha_min) {
+    const GaussFwd f = gauss_forward(in, cam);
+    // exact bounding box of {alpha >= alpha_min} = {q <= 2 ln(o_eff / alpha_min)}
+    const float kq = 2.0f * logf(fmaxf(f.o, alpha_min) / alpha_min);
+    const float ex = sqrtf(kq * f.a), ey = sqrtf(kq * f.c);
+    const float fW = float(cam.W), fH = float(cam.H);
+    const float i0 = fminf(fmaxf(ceilf(f.mx - ex - 0.5f), 0.0f), fW);
+    const float i1 = fminf(fmaxf(floorf(f.mx + ex - 0.5f), -1.0f), fW - 1.0f);
+    const float j0 = fminf(fmaxf(ceilf(f.my - ey - 0.5f), 0.0f), fH);
+    const float j1 = fminf(fmaxf(floorf(f.my + ey - 0.5f), -1.0f), fH - 1.0f);
+    const bool vis = f.front && (f.o >= alpha_min) && (f.qnorm > 0.0f) && (i0 <= i1) && (j0 <= j1) &&
+                     (f.det > 0.0f) && isfinite(f.mx) && isfinite(f.my);
+    ProjOut o;
+    o.n_tiles = 0;
+    o.rect = make_uint2(0u, 0u);
+    if (vis) {
+        const uint32_t tx0 = uint32_t(i0) / MGS_TILE, tx1 = uint32_t(i1) / MGS_TILE;
+        const uint32_t ty0 = uint32_t(j0) / MGS_TILE, ty1 = uint32_t(j1) / MGS_TILE;
+        o.n_tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        o.rect = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
+    }
+    const float kA = -0.5f * LOG2E * (f.c / f.det);   // log2(alpha) = log2(o) + kA t^2 + kG dy^2
+    const float beta = -f.b / f.c;                   // t = dx + beta * dy
+    const float kG = -0.5f * LOG2E / f.c;
+    o.r0 = make_float4(f.mx, f.my, log2f(fmaxf(f.o, 1e-30f)), f.w);
+    o.r1 = make_float4(kA, beta, kG, f.front ? f.z : -1.0f);
+    o.r2 = make_float4(f.col[0], f.col[1], f.col[2], f.o);
+    return o;
+}
+
+__device__ __forceinline__ void store_proj(const ProjOut &o, int64_t k, float4 *__restrict__ splat,
+                                           uint2 *__restrict__ rect_out, uint32_t *__restrict__ ntiles_out) {
+    splat[3 * k + 0] = o.r0;
+    splat[3 * k + 1] = o.r1;
+    splat[3 * k + 2] = o.r2;
+    rect_out[k] = o.rect;
+    ntiles_out[k] = o.n_tiles;
+}
+
 }  // namespace mgs

@@ -1,0 +1,315 @@
+"""Continuous-batching render server over mgs_render_batch.
+
+* Scenes stay resident in HBM (``SceneRegistry``).
+* Requests (scene, camera, background) arrive on an open-loop clock; the server
+  admits queued requests into a batch slot while the slot's limits (requests,
+  Gaussians, tiles, pair capacity) and the output-image memory budget allow.
+* Each slot owns a workspace, a pinned request table and a CUDA/HIP stream; with
+  ``use_graphs`` the slot's launch sequence (table upload + mgs_render_batch) is
+  captured once in a graph and replayed for every batch.  Two or more slots keep
+  batches in flight together, so requests that arrive while others render are
+  admitted as soon as a slot and memory free up.
+* Latency = completion (GPU event) - arrival; reported as p50 / p99 with
+  throughput.  A batch whose pairs exceeded the slot capacity is re-rendered
+  request by request on the single-view path (same kernels, same images).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .render import ALPHA_MAX, ALPHA_MIN, DeviceMLP, DeviceScene, Renderer
+
+MAX_REQ = 64
+N_ALIGN = 64
+
+
+def _tiles(w, h):
+    return ((w + 15) // 16) * ((h + 15) // 16)
+
+
+@dataclass
+class Request:
+    rid: int
+    scene: str
+    cam: object            # mgs_data.Camera
+    arrival: float         # seconds on the server clock
+    bg: tuple = (0.0, 0.0, 0.0)
+    image: torch.Tensor = None
+    done: float = None
+    path: str = ""
+
+
+class SceneRegistry:
+    """Resident scenes: id -> (DeviceScene, DeviceMLP or None)."""
+
+    def __init__(self):
+        self.scenes = {}
+
+    def add(self, name, scene, mlp=None, device="cuda"):
+        ds = scene if isinstance(scene, DeviceScene) else DeviceScene(scene, device)
+        dm = mlp if (mlp is None or isinstance(mlp, DeviceMLP)) else DeviceMLP(mlp, device)
+        self.scenes[name] = (ds, dm)
+
+    def __getitem__(self, k):
+        return self.scenes[k]
+
+    def resident_bytes(self):
+        return sum(ds.nbytes() for ds, _ in self.scenes.values())
+
+
+class BatchSlot:
+    """Workspace + request table + stream for one in-flight batch."""
+
+    def __init__(self, max_gaussians, max_tiles, capacity, device="cuda", use_graphs=True):
+        self.max_gaussians, self.max_tiles, self.capacity = int(max_gaussians), int(max_tiles), int(capacity)
+        self.device = torch.device(device)
+        nb = C.c_size_t()
+        L.check(L.lib().mgs_batch_workspace(self.max_gaussians, self.max_tiles, self.capacity, C.byref(nb)))
+        self.ws = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device=self.device)
+        self.req_size = C.sizeof(L.mgs_request)
+        self.table_host = torch.zeros(MAX_REQ * self.req_size + 16, dtype=torch.uint8).pin_memory()
+        self.table_dev = torch.zeros(MAX_REQ * self.req_size + 16, dtype=torch.uint8, device=self.device)
+        self.n_pairs = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.status = torch.zeros(2, dtype=torch.int32, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.done_event = torch.cuda.Event(enable_timing=True)
+        self.requests = []
+        self.graph = None
+        self.use_graphs = use_graphs
+
+    def _n_ptr(self):
+        return C.c_void_p(self.table_dev.data_ptr() + MAX_REQ * self.req_size)
+
+    def _enqueue(self):
+        """Table upload + the batched render, on self.stream."""
+        self.table_dev.copy_(self.table_host, non_blocking=True)
+        L.check(L.lib().mgs_render_batch(
+            C.c_void_p(self.table_dev.data_ptr()), self._n_ptr(), self.max_gaussians, self.max_tiles,
+            self.capacity, ALPHA_MIN, ALPHA_MAX, L.ptr(self.ws), self.ws.numel() * 4, L.ptr(self.n_pairs),
+            L.ptr(self.status), L.stream_ptr(self.stream)))
+
+    def write_table(self, reqs, registry):
+        arr = (L.mgs_request * MAX_REQ)()
+        for k, r in enumerate(reqs):
+            ds, dm = registry[r.scene]
+            q = arr[k]
+            q.g = ds.struct
+            q.packed_mlp = dm.packed.data_ptr() if dm is not None else None
+            q.cam = L.make_camera(r.cam)
+            for c in range(3):
+                q.bg[c] = float(r.bg[c])
+            q.image = r.image.data_ptr()
+        raw = bytes(arr) + np.int32(len(reqs)).tobytes()
+        self.table_host[:len(raw)].copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+
+    def launch(self, reqs, registry):
+        self.requests = list(reqs)
+        self.write_table(reqs, registry)
+        with torch.cuda.stream(self.stream):
+            if self.use_graphs:
+                if self.graph is None:
+                    self._enqueue()                      # warm-up outside capture
+                    self.stream.synchronize()
+                    self.graph = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(self.graph, stream=self.stream):
+                        self._enqueue()
+                self.graph.replay()
+            else:
+                self._enqueue()
+            self.done_event.record(self.stream)
+
+    def ready(self):
+        return self.done_event.query()
+
+    def overflowed(self):
+        return (int(self.n_pairs.cpu()[0]) & 0xFFFFFFFF) > self.capacity
+
+
+class Server:
+    """Open-loop continuous-batching server (see the module docstring)."""
+
+    def __init__(self, registry, max_batch=16, max_gaussians=8_000_000, max_tiles=None, capacity=64_000_000,
+                 n_slots=2, image_budget_bytes=2 << 30, use_graphs=True, device="cuda"):
+        self.reg = registry
+        self.max_batch = min(int(max_batch), MAX_REQ)
+        self.max_gaussians = int(max_gaussians)
+        self.max_tiles = int(max_tiles if max_tiles is not None else self.max_batch * _tiles(1920, 1080))
+        self.capacity = int(capacity)
+        self.image_budget = int(image_budget_bytes)
+        self.device = torch.device(device)
+        self.slots = [BatchSlot(self.max_gaussians, self.max_tiles, self.capacity, device, use_graphs)
+                      for _ in range(n_slots)]
+        self.image_bytes_in_use = 0
+        self.rejected = []
+        self.pair_est = {}           # (scene, W, H) -> pairs of one view (from calibrate)
+
+    def calibrate(self, resolutions, margin=1.3, radius=4.0):
+        """Measure the pair count of one view per (scene, resolution) on the single-view path;
+        admission then keeps the batch's estimated pairs within the slot capacity."""
+        import mgs_data
+        for name, (ds, dm) in self.reg.scenes.items():
+            for W, H in resolutions:
+                cam = mgs_data.look_at((0.0, 0.0, -radius), width=W, height=H, f=float(W))
+                R = Renderer(ds.n, W, H, device=self.device)
+                R.render(ds, cam, dm)
+                self.pair_est[(name, W, H)] = int(R.pairs() * margin) + 1024
+                del R
+        torch.cuda.synchronize()
+
+    # -- footprint ------------------------------------------------------------
+    def footprint(self, r):
+        """(padded Gaussians, tiles, image bytes, estimated pairs) a request needs in a batch."""
+        ds, _ = self.reg[r.scene]
+        n = (ds.n + N_ALIGN - 1) // N_ALIGN * N_ALIGN
+        pairs = self.pair_est.get((r.scene, r.cam.width, r.cam.height), 0)
+        return n, _tiles(r.cam.width, r.cam.height), 12 * r.cam.width * r.cam.height, pairs
+
+    def admissible_alone(self, r):
+        n, t, b, p = self.footprint(r)
+        return n <= self.max_gaussians and t <= self.max_tiles and b <= self.image_budget
+
+    # -- one run --------------------------------------------------------------
+    def run(self, requests, clock_start=None, idle_sleep=20e-6):
+        """Serve ``requests`` (sorted by arrival, seconds from start); returns the served list."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        queue = deque()
+        served = []
+        free = list(self.slots)
+        busy = []
+        ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref.record()
+        while pending or queue or busy:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                if self.admissible_alone(r):
+                    queue.append(r)
+                else:
+                    self.rejected.append(r)
+            progressed = False
+            for slot in list(busy):
+                if slot.ready():
+                    busy.remove(slot)
+                    free.append(slot)
+                    progressed = True
+                    t_done = ref.elapsed_time(slot.done_event) * 1e-3
+                    if slot.overflowed():
+                        for r in slot.requests:
+                            self._render_alone(r)
+                            r.done = time.perf_counter() - t0
+                            r.path = "single-view retry"
+                    else:
+                        for r in slot.requests:
+                            r.done = t_done
+                            r.path = "batch"
+                    for r in slot.requests:
+                        self.image_bytes_in_use -= 12 * r.cam.width * r.cam.height
+                    served.extend(slot.requests)
+            while free and queue:
+                batch, n_sum, t_sum, p_sum = [], 0, 0, 0
+                while queue and len(batch) < self.max_batch:
+                    n, t, b, p = self.footprint(queue[0])
+                    if n_sum + n > self.max_gaussians or t_sum + t > self.max_tiles or \
+                            self.image_bytes_in_use + b > self.image_budget or \
+                            (batch and p_sum + p > self.capacity):
+                        break
+                    r = queue.popleft()
+                    r.image = torch.empty(3, r.cam.height, r.cam.width, dtype=torch.float32, device=self.device)
+                    self.image_bytes_in_use += b
+                    n_sum += n
+                    t_sum += t
+                    p_sum += p
+                    batch.append(r)
+                if not batch:
+                    break
+                slot = free.pop()
+                slot.launch(batch, self.reg)
+                busy.append(slot)
+                progressed = True
+            if not progressed:
+                if pending and not queue and not busy:
+                    time.sleep(max(0.0, min(pending[0].arrival - now, 1e-3)))
+                else:
+                    time.sleep(idle_sleep)
+        torch.cuda.synchronize()
+        return served
+
+    def _render_alone(self, r):
+        ds, dm = self.reg[r.scene]
+        R = Renderer(ds.n, r.cam.width, r.cam.height, device=self.device)
+        img = R.render(ds, r.cam, dm, bg=r.bg)
+        torch.cuda.synchronize()
+        r.image = img.clone()
+
+
+def run_plain_loop(registry, requests, device="cuda"):
+    """Baseline: one request at a time, one frame per launch sequence (single-view path), FIFO."""
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    renderers = {}
+    served = []
+    ref = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref.record()
+    while pending:
+        r = pending.popleft()
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        ds, dm = registry[r.scene]
+        key = (r.scene, r.cam.width, r.cam.height)
+        if key not in renderers:
+            renderers[key] = Renderer(ds.n, r.cam.width, r.cam.height, device=device)
+        R = renderers[key]
+        img = R.render(ds, r.cam, dm, bg=r.bg)      # one host sync per frame (pair count check)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        r.image = img.clone()
+        ev.synchronize()
+        r.done = ref.elapsed_time(ev) * 1e-3
+        r.path = "plain"
+        served.append(r)
+    torch.cuda.synchronize()
+    return served
+
+
+def latency_stats(served, t_span=None):
+    lat = np.array([r.done - r.arrival for r in served]) * 1e3
+    if len(lat) == 0:
+        return {}
+    end = max(r.done for r in served)
+    start = min(r.arrival for r in served)
+    span = t_span if t_span is not None else max(end - start, 1e-9)
+    return {"requests": len(served), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "frames_per_s": len(served) / span,
+            "mpix_per_s": sum(r.cam.width * r.cam.height for r in served) / span / 1e6}
+
+
+def poisson_requests(scene_names, rate, count, seed, resolutions=((640, 480), (1280, 720), (1600, 1063), (1920, 1080)),
+                     radius=4.0):
+    """Open-loop arrivals: exponential gaps at ``rate`` req/s, random scene, pose and resolution."""
+    import mgs_data
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += rng.exponential(1.0 / rate)
+        name = scene_names[int(rng.integers(len(scene_names)))]
+        az = rng.uniform(0, 2 * math.pi)
+        el = math.radians(rng.uniform(-20.0, 40.0))
+        W, H = resolutions[int(rng.integers(len(resolutions)))]
+        eye = (radius * math.cos(el) * math.sin(az), -radius * math.sin(el), -radius * math.cos(el) * math.cos(az))
+        cam = mgs_data.look_at(eye, width=W, height=H, f=float(W))
+        out.append(Request(rid=k, scene=name, cam=cam, arrival=t))
+    return out

@@ -1,0 +1,65 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/mgs.h declares, and rejects bad arguments on the host (no kernel runs)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgs_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2603_11531_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_scope_entry_points():
+    names = declared_functions()
+    for required in ("mgs_enhance", "mgs_project", "mgs_bin", "mgs_blend_oit", "mgs_render_backward",
+                     "mgs_bin_sorted", "mgs_blend_sorted"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_string(lib):
+    assert lib.mgs_version().decode().startswith("mgs")
+    assert isinstance(lib.mgs_last_error().decode(), str)
+
+
+def test_host_side_validation(lib):
+    from paper_2603_11531_amd import _lib as L
+    nb = C.c_size_t()
+    assert lib.mgs_bin_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK and nb.value > 0
+    assert lib.mgs_bin_workspace(-1, 4, 4, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_bin_sorted_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK
+    assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
+    # invalid camera / arguments are rejected before any device work
+    cam = L.mgs_camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.near_z = 0, 10, 10.0, 10.0, 0.2
+    g = L.mgs_gaussians()
+    g.n = 0
+    proj = L.mgs_projected()
+    assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 16, 1 / 255, C.byref(proj), None) \
+        == L.MGS_ERR_INVALID_ARG
+    assert "size" in lib.mgs_last_error().decode()
+    cam.width = 10
+    assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 8, 1 / 255, C.byref(proj), None) \
+        == L.MGS_ERR_UNSUPPORTED
+    assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 16, 1.5, C.byref(proj), None) \
+        == L.MGS_ERR_INVALID_ARG
+    # n = 0 is a valid no-op
+    assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 16, 1 / 255, C.byref(proj), None) == L.MGS_OK
+    assert lib.mgs_mlp_pack(None, None, None) == L.MGS_ERR_INVALID_ARG

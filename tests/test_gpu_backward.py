@@ -1,0 +1,196 @@
+"""Backward pass (mgs_render_backward via torch.autograd) against the oracle's FP64
+autograd gradient and against finite differences of the GPU forward.
+
+Bar: per parameter tensor ||g - g*||_2 / ||g*||_2 <= 1e-3 against the oracle,
+with the MLP's gradient taken straight through the forward's bfloat16 roundings
+on both sides (the oracle runs its BF16-emulation forward).
+"""
+import numpy as np
+import pytest
+import torch
+
+import mgs_data
+import oracle as O
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+REL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11531_amd as M
+    import paper_2603_11531_amd.autograd  # noqa: F401
+    M._lib.lib()
+    return M
+
+
+def _flat_mlp(M, mlp):
+    flat = np.zeros(M._lib.MGS_MLP_PARAMS, np.float32)
+    for name, off, shape in M._lib.MLP_LAYOUT:
+        v = np.asarray(mlp[name], np.float32).reshape(-1)
+        flat[off:off + v.size] = v
+    return flat
+
+
+def gpu_grads(M, scene, cam, mlp, r, bg):
+    from paper_2603_11531_amd.autograd import render
+    params = {k: torch.tensor(np.ascontiguousarray(scene[k]), device="cuda", requires_grad=True) for k in KEYS}
+    mp = torch.tensor(_flat_mlp(M, mlp), device="cuda", requires_grad=True) if mlp is not None else None
+    img = render(params, cam, mp, bg)
+    L = (img * torch.as_tensor(r, dtype=torch.float32, device="cuda")).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    out = {k: params[k].grad.double().cpu().numpy() for k in KEYS}
+    if mp is not None:
+        out["mlp"] = mp.grad.double().cpu().numpy()
+    return out, img.detach().double().cpu()
+
+
+def oracle_grads(M, scene, cam, mlp, r, bg, bf16=True):
+    camt = O.camera_tensors(cam)
+    p = O.scene_params(scene, requires_grad=True)
+    mp = O.mlp_params(mlp, requires_grad=True) if mlp is not None else None
+    phi = m = None
+    if mp is not None:
+        act = O.activate(p)
+        _, _, P = O.camera_space(p["mean"], camt)
+        phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), mp, bf16=bf16)
+    pr = O.project(p, camt, phi, m)
+    img, _ = O.render_oit(pr, camt, np.asarray(bg))
+    (img * torch.as_tensor(r, dtype=torch.float64)).sum().backward()
+    n = scene["mean"].shape[1]
+    out = {"mean": p["mean"].grad.numpy().T, "log_scale": p["log_scale"].grad.numpy().T,
+           "quat": p["quat"].grad.numpy().T, "opacity_logit": p["opacity_logit"].grad.numpy(),
+           "sh": p["sh"].grad.numpy().reshape(n, 12).T}
+    if mp is not None:
+        flat = np.zeros(M._lib.MGS_MLP_PARAMS)
+        for name, off, shape in M._lib.MLP_LAYOUT:
+            v = mp[name].grad.numpy().reshape(-1)
+            flat[off:off + v.size] = v
+        out["mlp"] = flat
+    return out, img.detach()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _report(M, g, go):
+    for k in go:
+        say(f"  {k}: rel {_rel(g[k], go[k]):.2e}")
+    if "mlp" in go:
+        for name, off, shape in M._lib.MLP_LAYOUT:
+            sz = int(np.prod(shape)) if shape else 1
+            a, b = g["mlp"][off:off + sz], go["mlp"][off:off + sz]
+            say(f"    mlp.{name}: rel {_rel(a, b):.2e} |g*| {np.linalg.norm(b):.3e}")
+
+
+@pytest.mark.parametrize("with_mlp", [False, True])
+def test_grads_match_oracle_tiny(M, with_mlp):
+    say(f"test_grads_match_oracle_tiny mlp={with_mlp}")
+    scene = mgs_data.make_scene_uniform(50, 21, half=0.8, ls_mu=-2.4)
+    cam = mgs_data.look_at((0.0, 0.0, -4.0), width=32, height=32, f=32.0)
+    mlp = mgs_data.make_mlp(22) if with_mlp else None
+    rng = np.random.default_rng(3)
+    r = rng.normal(size=(3, 32, 32))
+    bg = (0.2, 0.4, 0.1)
+    g, img = gpu_grads(M, scene, cam, mlp, r, bg)
+    go, imgo = oracle_grads(M, scene, cam, mlp, r, bg)
+    _report(M, g, go)
+    for k in go:
+        e = _rel(g[k], go[k])
+        assert e <= REL, (k, e)
+
+
+@pytest.mark.parametrize("with_mlp", [False, True])
+def test_grads_match_oracle_small_workload(M, with_mlp):
+    say(f"test_grads_match_oracle_small_workload mlp={with_mlp}")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    mlp = mgs_data.make_mlp(1) if with_mlp else None
+    rng = np.random.default_rng(4)
+    r = rng.normal(size=(3, 128, 128))
+    bg = (0.0, 0.0, 0.0)
+    g, _ = gpu_grads(M, scene, cams[0], mlp, r, bg)
+    go, _ = oracle_grads(M, scene, cams[0], mlp, r, bg)
+    _report(M, g, go)
+    for k in go:
+        e = _rel(g[k], go[k])
+        assert e <= REL, (k, e)
+
+
+def test_grads_match_finite_differences_of_gpu_forward(M):
+    """Central differences of the GPU forward (float32, h = 1e-3) on the 50-Gaussian 32x32 scene.
+
+    With the MLP off the forward is smooth in every attribute; with the MLP on, only the
+    two head biases enter after the bfloat16 roundings, so they are the MLP parameters
+    a finite difference can probe (the rest is checked against the oracle above).
+    """
+    say("test_grads_match_finite_differences_of_gpu_forward")
+    scene = mgs_data.make_scene_uniform(50, 21, half=0.8, ls_mu=-2.4)
+    cam = mgs_data.look_at((0.0, 0.0, -4.0), width=32, height=32, f=32.0)
+    mlp = mgs_data.make_mlp(22)
+    rng = np.random.default_rng(3)
+    r = rng.normal(size=(3, 32, 32))
+    bg = (0.2, 0.4, 0.1)
+    rt = torch.as_tensor(r, dtype=torch.float64)
+
+    def loss(sc, flat):
+        ds = M.DeviceScene(sc)
+        R = M.Renderer(ds.n, 32, 32)
+        dm = M.DeviceMLP(M.DeviceMLP.unflatten(flat)) if flat is not None else None
+        img = R.render(ds, cam, dm, bg=bg).double().cpu()
+        return float((img * rt).sum()), R.decoded()["rect"].copy()
+
+    checked, bad = 0, []
+    pick = np.random.default_rng(9)
+    g, _ = gpu_grads(M, scene, cam, None, r, bg)
+    _, rect0 = loss(scene, None)
+    for k in ("mean", "log_scale", "opacity_logit", "sh", "quat"):
+        arr = scene[k]
+        for idx in pick.choice(arr.size, size=6, replace=False):
+            h = 1e-3
+            vals = []
+            for sgn in (1, -1):
+                sc = {kk: v.copy() for kk, v in scene.items()}
+                sc[k].reshape(-1)[idx] += sgn * h
+                vals.append(loss(sc, None))
+            if any(not np.array_equal(v[1], rect0) for v in vals):
+                continue
+            fd = (vals[0][0] - vals[1][0]) / (2 * h)
+            an = float(g[k].reshape(-1)[idx])
+            scale = max(abs(fd), abs(an), 0.05 * float(np.abs(g[k]).max()), 1e-3)
+            checked += 1
+            if abs(fd - an) > 3e-2 * scale:
+                bad.append((k, int(idx), fd, an))
+    gm, _ = gpu_grads(M, scene, cam, mlp, r, bg)
+    flat = _flat_mlp(M, mlp)
+    for off in (M._lib.MLP_LAYOUT[5][1], M._lib.MLP_LAYOUT[7][1]):      # b_phi, b_o
+        h = 1e-3
+        vals = []
+        for sgn in (1, -1):
+            f2 = flat.copy()
+            f2[off] += sgn * h
+            vals.append(loss(scene, f2)[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float(gm["mlp"][off])
+        checked += 1
+        if abs(fd - an) > 3e-2 * max(abs(fd), abs(an), 1e-3):
+            bad.append(("mlp", off, fd, an))
+    say(f"  checked {checked}, mismatches {bad}")
+    assert checked >= 15 and len(bad) <= 1, bad
+
+
+def test_backward_is_bit_reproducible(M):
+    say("test_backward_is_bit_reproducible")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    mlp = mgs_data.make_mlp(1)
+    r = np.random.default_rng(4).normal(size=(3, 128, 128))
+    a, _ = gpu_grads(M, scene, cams[0], mlp, r, (0, 0, 0))
+    b, _ = gpu_grads(M, scene, cams[0], mlp, r, (0, 0, 0))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k

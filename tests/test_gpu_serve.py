@@ -1,0 +1,104 @@
+"""Batched serving: every request renders the same alone and in a mixed batch,
+through graph replays with different request tables, through the continuous-
+batching server, under a tight memory budget and after a pair-capacity overflow."""
+import numpy as np
+import pytest
+import torch
+
+import mgs_data
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11531_amd as M
+    from paper_2603_11531_amd import serve
+    M._lib.lib()
+    reg = serve.SceneRegistry()
+    reg.add("a", mgs_data.make_scene_uniform(3000, 31), mgs_data.make_mlp(40))
+    reg.add("b", mgs_data.make_scene_uniform(7777, 32), None)
+    reg.add("c", mgs_data.make_scene_unbounded(20000, 33), mgs_data.make_mlp(41))
+    return M, serve, reg
+
+
+def _alone(M, reg, r):
+    ds, dm = reg[r.scene]
+    R = M.Renderer(ds.n, r.cam.width, r.cam.height)
+    img = R.render(ds, r.cam, dm, bg=r.bg).clone()
+    torch.cuda.synchronize()
+    return img
+
+
+def _reqs(serve, names, k0, res):
+    out = []
+    for k, (name, (W, H)) in enumerate(zip(names, res)):
+        cam = mgs_data.look_at((0.7 * np.sin(k), -0.3 * np.cos(k), -3.5 - 0.2 * k), width=W, height=H, f=float(W))
+        out.append(serve.Request(rid=k0 + k, scene=name, cam=cam, arrival=0.0, bg=(0.1 * k, 0.2, 0.05 * k)))
+    return out
+
+
+def test_batch_equals_alone_across_graph_replays(S):
+    M, serve, reg = S
+    say("test_batch_equals_alone_across_graph_replays")
+    slot = serve.BatchSlot(max_gaussians=200_000, max_tiles=4 * 8160, capacity=4_000_000, use_graphs=True)
+    for rep, (names, res) in enumerate([
+            (["a", "b", "c", "a"], [(96, 64), (130, 77), (200, 120), (33, 17)]),
+            (["c", "c", "b"], [(64, 64), (250, 140), (17, 33)])]):
+        reqs = _reqs(serve, names, 10 * rep, res)
+        for r in reqs:
+            r.image = torch.full((3, r.cam.height, r.cam.width), -1.0, device="cuda")
+        slot.launch(reqs, reg)
+        slot.done_event.synchronize()
+        assert not slot.overflowed()
+        assert slot.status.cpu().tolist() == [1, len(reqs)]
+        for r in reqs:
+            ref = _alone(M, reg, r)
+            assert torch.equal(r.image, ref), (rep, r.rid, float((r.image - ref).abs().max()))
+
+
+def test_server_serves_every_request_like_alone(S):
+    M, serve, reg = S
+    say("test_server_serves_every_request_like_alone")
+    srv = serve.Server(reg, max_batch=6, max_gaussians=300_000, max_tiles=6 * 2000, capacity=6_000_000, n_slots=2,
+                       use_graphs=True)
+    reqs = serve.poisson_requests(["a", "b", "c"], rate=4000.0, count=40, seed=5,
+                                  resolutions=((64, 48), (160, 90), (200, 133)))
+    served = srv.run(reqs)
+    assert len(served) == 40 and not srv.rejected
+    assert {r.path for r in served} == {"batch"}
+    st = serve.latency_stats(served)
+    say(f"  {st}")
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    for r in served:
+        assert torch.equal(r.image, _alone(M, reg, r)), r.rid
+
+
+def test_admission_rejects_what_can_never_fit_and_serves_the_rest(S):
+    M, serve, reg = S
+    say("test_admission_rejects_what_can_never_fit_and_serves_the_rest")
+    # image budget below one 200x133 frame: those requests are rejected, the others served
+    srv = serve.Server(reg, max_batch=4, max_gaussians=100_000, max_tiles=4 * 200, capacity=2_000_000, n_slots=1,
+                       image_budget_bytes=12 * 160 * 90 * 2, use_graphs=False)
+    reqs = serve.poisson_requests(["a", "b"], rate=2000.0, count=20, seed=6,
+                                  resolutions=((64, 48), (160, 90), (200, 133)))
+    served = srv.run(reqs)
+    big = [r for r in reqs if r.cam.width == 200]
+    assert len(srv.rejected) == len(big) and len(served) == len(reqs) - len(big)
+    for r in served:
+        assert torch.equal(r.image, _alone(M, reg, r)), r.rid
+
+
+def test_capacity_overflow_falls_back_to_single_view(S):
+    M, serve, reg = S
+    say("test_capacity_overflow_falls_back_to_single_view")
+    srv = serve.Server(reg, max_batch=4, max_gaussians=100_000, max_tiles=4 * 200, capacity=64, n_slots=1,
+                       use_graphs=True)
+    reqs = serve.poisson_requests(["a", "b"], rate=1000.0, count=6, seed=7, resolutions=((96, 64),))
+    served = srv.run(reqs)
+    assert len(served) == 6 and {r.path for r in served} == {"single-view retry"}
+    for r in served:
+        assert torch.equal(r.image, _alone(M, reg, r)), r.rid
