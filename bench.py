@@ -42,8 +42,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sorted", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the large-scene and training-step legs")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (a known-size kernel "
+                         "that calibrates hardware byte counters)")
     return ap.parse_args()
 
 
@@ -128,6 +132,89 @@ def serving_leg(n_requests, rate=2000.0):
             "images_identical_to_plain": bool(same), "paths": paths, "rejected": len(srv.rejected)}
 
 
+def large_leg(steps=24):
+    """3M Gaussians at 1920x1080 on a spline path: OIT vs sorted frames/s (enhance fused into project)."""
+    import torch
+
+    import mgs_data
+    import paper_2603_11531_amd as M
+    scene, cams, mlp, _ = mgs_data.make_config("large", seed=0)
+    ds, dm = M.DeviceScene(scene), M.DeviceMLP(mlp)
+    R = M.Renderer(ds.n, cams[0].width, cams[0].height)
+    out = {}
+    for sp in (False, True):
+        maxP = 0
+        for c in cams[::6]:
+            R.render(ds, c, dm, sorted_path=sp, fused=True)
+            maxP = max(maxP, R.pairs())
+        R.ensure_capacity(int(maxP * 1.3) + 4096, sorted_path=sp)
+        cs = [M._lib.make_camera(c) for c in cams]
+        for k in range(4):
+            _frame(R, ds, dm, cs[k % len(cs)], sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            _frame(R, ds, dm, cs[k % len(cs)], sp)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if R.pairs() > R.capacity:
+            raise RuntimeError("pair capacity exceeded in the large-scene leg")
+        out["sorted_fps" if sp else "oit_fps"] = round(steps / wall, 2)
+    out["oit_vs_sorted"] = round(out["oit_fps"] / out["sorted_fps"], 3)
+    out["workload"] = "3,000,000 Gaussians uniform in a ball r=10, 1920x1080, 60 spline poses, MLP on"
+    return out
+
+
+def _frame(R, ds, dm, cs, sorted_path, bg=(0.0, 0.0, 0.0)):
+    R.enhance_project(ds, cs, dm)
+    R.bin(sorted_path)
+    if sorted_path:
+        R.blend_sorted(cs, bg)
+    else:
+        R.blend_oit(cs, bg)
+
+
+def train_leg(steps=4):
+    """Differentiable training step: 500k Gaussians, 4 views at 1600x1063, L1 loss against images of a
+    perturbed copy, backward to every attribute and the MLP parameters."""
+    import numpy as np
+    import torch
+
+    import mgs_data
+    import paper_2603_11531_amd as M
+    from paper_2603_11531_amd.autograd import render
+    scene, cams, mlp, _ = mgs_data.make_config("train", seed=0)
+    target = mgs_data.perturb_scene(scene, seed=3)
+    dt, dm = M.DeviceScene(target), M.DeviceMLP(mlp)
+    targets = []
+    for c in cams:
+        R = M.Renderer(dt.n, c.width, c.height)
+        targets.append(R.render(dt, c, dm).clone())
+    keys = ("mean", "log_scale", "quat", "opacity_logit", "sh")
+    params = {k: torch.tensor(np.ascontiguousarray(scene[k]), device="cuda", requires_grad=True) for k in keys}
+    mp = dm.params.clone().requires_grad_(True)
+
+    def step():
+        for p in list(params.values()) + [mp]:
+            p.grad = None
+        loss = 0.0
+        for c, tgt in zip(cams, targets):
+            loss = loss + (render(params, c, mp) - tgt).abs().mean()
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"ms_per_step": round(1e3 * wall / steps, 3), "views_per_s": round(4 * steps / wall, 2),
+            "loss": round(float(loss), 6),
+            "workload": "500,000 Gaussians, 4 views 1600x1063, L1 vs perturbed-scene targets, fwd+bwd incl. MLP"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +229,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     log("generating the 1M-Gaussian unbounded scene ...")
     scene, cams, mlp, _ = mgs_data.make_config("unbounded", seed=0, n=args.n)
     ds = M.DeviceScene(scene)
@@ -173,21 +269,18 @@ def main():
         cs = cam_structs[k % len(cam_structs)]
         if ev is not None:
             ev[0].record(stream)
-        R.enhance(ds, cs, dm)
+        R.enhance_project(ds, cs, dm)            # Eq. 4 MLP fused with the projection
         if ev is not None:
             ev[1].record(stream)
-        R.project(ds, cs, use_mlp=True)
-        if ev is not None:
-            ev[2].record(stream)
         R.bin(sorted_path)
         if ev is not None:
-            ev[3].record(stream)
+            ev[2].record(stream)
         if sorted_path:
             R.blend_sorted(cs, bg)
         else:
             R.blend_oit(cs, bg)
         if ev is not None:
-            ev[4].record(stream)
+            ev[3].record(stream)
 
     def run(sorted_path):
         for k in range(args.warmup):
@@ -199,11 +292,11 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         # per-stage timing in a second, event-instrumented pass
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         for k in range(args.steps):
             frame(k, sorted_path, evs[k])
         torch.cuda.synchronize()
-        stages = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(4)] for k in range(args.steps)])
+        stages = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(3)] for k in range(args.steps)])
         frame_ms = stages.sum(axis=1)
         if R.pairs() > R.capacity:
             raise RuntimeError("pair capacity exceeded inside the timed loop")
@@ -217,13 +310,13 @@ def main():
         log("timing sorted ...")
         wall_s, stages_s, frame_ms_s = run(True)
         res_sorted = dict(fps=round(args.steps / wall_s, 2), ms_per_frame=round(1e3 * wall_s / args.steps, 4),
-                          stage_ms=dict(zip(["enhance", "project", "bin_sorted", "blend_sorted"],
+                          stage_ms=dict(zip(["enhance_project", "bin_sorted", "blend_sorted"],
                                             [round(float(v), 4) for v in stages_s.mean(axis=0)])))
-    blend_ms = float(stages[:, 3].mean())
+    blend_ms = float(stages[:, 2].mean())
     evals = 256.0 * mean_P
     achieved = evals * BLEND_FLOP_PER_EVAL / (blend_ms * 1e-3) / 1e12
-    proj_bytes = ds.n * (100 + 56)   # attribute reads + phi/m + 48 B record + 8 B rect
-    proj_ms = float(stages[:, 1].mean())
+    proj_bytes = ds.n * (92 + 68)    # attribute reads; record 48 + rect 8 + count 4 + phi, m 8
+    proj_ms = float(stages[:, 0].mean())
     out = {
         "metric": "FPS @1600x1063, 1M Gaussians (OIT vs sorted); p50/p99 served frame ms",
         "value": round(fps, 2),
@@ -245,9 +338,9 @@ def main():
         "mpix_per_s": round(fps * W * H / 1e6, 1),
         "frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
         "frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4),
-        "stage_ms": dict(zip(["enhance", "project", "bin", "blend_oit"],
+        "stage_ms": dict(zip(["enhance_project", "bin", "blend_oit"],
                              [round(float(v), 4) for v in stages.mean(axis=0)])),
-        "project_gbs": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
+        "enhance_project_gbs": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
         "roofline": {"bound": "alu", "kernel": "blend_kernel<oit>", "achieved": round(achieved, 2),
@@ -256,6 +349,11 @@ def main():
                      "units_per_launch": round(evals), "flop_per_unit": BLEND_FLOP_PER_EVAL,
                      "avg_launch_ms": round(blend_ms, 4)},
     }
+    if not args.no_extra:
+        log("large-scene leg ...")
+        out["large"] = large_leg()
+        log("training-step leg ...")
+        out["train"] = train_leg()
     if not args.no_serve:
         log("serving leg ...")
         del R

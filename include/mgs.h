@@ -156,6 +156,15 @@ int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
                 void *stream);
 
 /*
+ * mgs_enhance_project -- mgs_enhance followed by mgs_project in one pass over the
+ * attributes (each Gaussian is read once; the MLP runs on MFMA per 64-Gaussian
+ * wave).  Writes the same projected record as the two calls, and phi / omod
+ * (needed by mgs_render_backward).
+ */
+int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
+                        float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
  * mgs_bin_workspace -- device workspace bytes mgs_bin needs for n Gaussians,
  * a tile grid of tiles_x * tiles_y and at most `capacity` tile/Gaussian pairs.
  */
@@ -188,6 +197,20 @@ int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void
 int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
                   const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
                   float alpha_max, float *image, float *aux, void *stream);
+
+/*
+ * mgs_blend_oit_split -- mgs_blend_oit with long tile lists cut into ranges of at most
+ * 1024 Gaussians rendered by separate workgroups and merged exactly in range order
+ * (Eq. 2's sums are order-independent: N and D add, T multiplies), which balances the
+ * work of dense tiles.  Results equal mgs_blend_oit up to float32 summation order.
+ * n_pairs / capacity: as written / used by mgs_bin (nothing is drawn if n_pairs >
+ * capacity).  ws: mgs_blend_oit_split_workspace() bytes, 256-byte aligned.
+ */
+int mgs_blend_oit_split_workspace(int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes);
+int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                        const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
+                        const float bg[3], float alpha_min, float alpha_max, void *ws, size_t ws_bytes,
+                        float *image, float *aux, void *stream);
 
 /*
  * Sorted comparison path (3DGS alpha blending, Eq. 11, Appendix B).

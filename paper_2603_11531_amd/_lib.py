@@ -27,8 +27,9 @@ MLP_LAYOUT = (("W1", 0, (64, 22)), ("b1", 1408, (64,)), ("W2", 1472, (64, 64)), 
               ("w_phi", 5632, (64,)), ("b_phi", 5696, ()), ("w_o", 5697, (64,)), ("b_o", 5761, ()))
 
 EXPORTED = [
-    "mgs_last_error", "mgs_version", "mgs_mlp_pack", "mgs_enhance", "mgs_project",
-    "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_bin_sorted_workspace",
+    "mgs_last_error", "mgs_version", "mgs_mlp_pack", "mgs_enhance", "mgs_project", "mgs_enhance_project",
+    "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_blend_oit_split_workspace", "mgs_blend_oit_split",
+    "mgs_bin_sorted_workspace",
     "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch",
 ]
@@ -77,10 +78,14 @@ def load(path=LIB_PATH):
         "mgs_mlp_pack": (i32, [vp, vp, vp]),
         "mgs_enhance": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, vp]),
         "mgs_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, P(mgs_projected), vp]),
+        "mgs_enhance_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, i32, f32, P(mgs_projected), vp, vp, vp]),
         "mgs_bin_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_oit": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, vp, vp,
                                 vp]),
+        "mgs_blend_oit_split_workspace": (i32, [i32, i32, u64, P(C.c_size_t)]),
+        "mgs_blend_oit_split": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), i32, P(C.c_float), f32, f32,
+                                      vp, C.c_size_t, vp, vp, vp]),
         "mgs_bin_sorted_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin_sorted": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_sorted": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, f32,

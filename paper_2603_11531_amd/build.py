@@ -25,6 +25,9 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC,
     # packed-FP32 VALU forms are disabled on purpose (float code is emitted unpacked)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: every kernel that shares device code rounds the same
+    # way (hot loops use explicit fmaf), so a batched render equals the single-view render bit for bit
+    "-ffp-contract=off",
     "-munsafe-fp-atomics", "-Wno-unused-result",
 ]
 

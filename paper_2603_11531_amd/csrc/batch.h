@@ -39,9 +39,12 @@ __device__ __forceinline__ CamK camk_device(const mgs_camera &c) {
     for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
     k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy;
     k.W = c.width; k.H = c.height; k.near_z = c.near_z;
+    // the same rounded operations, in the same order, as the host-side make_camk (no contraction),
+    // so a batched request sees exactly the camera centre of a single-view render
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        k.campos[i] = -(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] + c.R[2 * 3 + i] * c.t[2]);
+        k.campos[i] = -__fadd_rn(__fadd_rn(__fmul_rn(c.R[0 * 3 + i], c.t[0]), __fmul_rn(c.R[1 * 3 + i], c.t[1])),
+                                 __fmul_rn(c.R[2 * 3 + i], c.t[2]));
     k.tiles_x = (c.width + MGS_TILE - 1) / MGS_TILE;
     k.tiles_y = (c.height + MGS_TILE - 1) / MGS_TILE;
     return k;
@@ -52,5 +55,11 @@ int bin_batch(const mgs_projected *proj, int64_t n_max, const BatchPlan *plan, u
               size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
               hipStream_t s);
 size_t bin_batch_workspace(int64_t n_max, uint32_t max_tiles, uint64_t capacity);
+
+// Split-tile OIT blend of a whole batch (blend.hip).
+size_t blend_split_workspace(uint32_t T, uint64_t capacity);
+int blend_split_batch(const float4 *splat, const uint32_t *offs, const uint32_t *gids, const BatchPlan *plan,
+                      const mgs_request *reqs, uint32_t max_tiles, const uint32_t *n_pairs, uint64_t capacity,
+                      float alpha_min, float alpha_max, void *ws, hipStream_t s);
 
 }  // namespace mgs

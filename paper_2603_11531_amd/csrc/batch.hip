@@ -10,7 +10,6 @@
 // same Gaussians in the same order as a single-view render, so every image is
 // bit-identical to rendering its request alone.
 #include "batch.h"
-#include "blend_math.h"
 #include "mlp_math.h"
 #include "proj_math.h"
 
@@ -101,30 +100,13 @@ batch_project_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__re
     }
 }
 
-// One workgroup per global tile: the tile of its request, into the request's image.
-__global__ void __launch_bounds__(BLEND_THREADS)
-batch_blend_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan,
-                   const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
-                   const uint32_t *__restrict__ gids, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
-                   float log2_amin, float amax) {
-    const uint32_t gt = blockIdx.x;
-    if (gt >= plan->t_total) return;                                  // block-uniform
-    if (uint64_t(*n_pairs) > capacity) return;                        // lists were not built
-    const int r = find_request(plan->tbase, plan->nreq, gt);
-    const mgs_request &q = reqs[r];
-    const uint32_t lt = gt - plan->tbase[r];
-    const uint32_t tx = plan->tiles_x[r];
-    blend_tile<false>(splat, gids, offs[gt], offs[gt + 1], int(lt % tx), int(lt / tx), q.cam.width, q.cam.height,
-                      q.bg[0], q.bg[1], q.bg[2], log2_amin, amax, 0.0f, q.image, nullptr);
-}
-
 __global__ void batch_status_kernel(const BatchPlan *__restrict__ plan, int32_t *__restrict__ status) {
     status[0] = plan->ok;
     status[1] = plan->nreq;
 }
 
 struct BatchLayout {
-    size_t plan, phi, omod, splat, rect, ntiles, offs, gids, bin, total;
+    size_t plan, phi, omod, splat, rect, ntiles, offs, gids, bin, split, total;
 };
 
 inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t capacity) {
@@ -140,6 +122,7 @@ inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t c
     L.offs = o;   o = align_up(o + (size_t(max_tiles) + 1) * 4, 256);
     L.gids = o;   o = align_up(o + cap * 4, 256);
     L.bin = o;    o = align_up(o + bin_batch_workspace(int64_t(ng), uint32_t(max_tiles), capacity), 256);
+    L.split = o;  o = align_up(o + blend_split_workspace(uint32_t(max_tiles), capacity), 256);
     L.total = o;
     return L;
 }
@@ -192,12 +175,12 @@ extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_re
     proj.splat = reinterpret_cast<float *>(splat);
     proj.rect = reinterpret_cast<uint32_t *>(rect);
     proj.n_tiles = ntiles;
-    int rc = bin_batch(&proj, max_gaussians, plan, uint32_t(max_tiles), w + L.bin, L.total - L.bin, offs, gids,
+    int rc = bin_batch(&proj, max_gaussians, plan, uint32_t(max_tiles), w + L.bin, L.split - L.bin, offs, gids,
                        capacity, n_pairs, s);
     if (rc != MGS_OK) return rc;
-    hipLaunchKernelGGL(batch_blend_kernel, dim3(unsigned(max_tiles)), dim3(BLEND_THREADS), 0, s, requests, plan,
-                       splat, offs, gids, n_pairs, capacity, log2f(alpha_min), alpha_max);
-    MGS_LAUNCH_CHECK("batch_blend_kernel");
+    rc = blend_split_batch(splat, offs, gids, plan, requests, uint32_t(max_tiles), n_pairs, capacity, alpha_min,
+                           alpha_max, w + L.split, s);
+    if (rc != MGS_OK) return rc;
     if (status) {
         hipLaunchKernelGGL(batch_status_kernel, dim3(1), dim3(1), 0, s, plan, status);
         MGS_LAUNCH_CHECK("batch_status_kernel");

@@ -27,6 +27,7 @@ constexpr int RADIX_TILE = RADIX_THREADS * RADIX_ITERS;   // 4096 keys per block
 constexpr int EXPAND_SMALL = 16;                          // pairs a lane writes on its own
 constexpr int RADIX_MAX_BITS = 8;
 constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
+constexpr int RADIX_MAX_GRID = 2048;                      // resident blocks striding over the used ones
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -258,6 +259,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
     return peers;
 }
 
+// The radix kernels run a bounded grid that strides over the logical 4096-key
+// blocks actually in use, ceil(P / 4096), read on the device; the histogram keeps
+// the capacity-sized stride `nblocks` but only its first used columns are touched.
+__device__ __forceinline__ int used_blocks(uint32_t P) { return int((uint64_t(P) + RADIX_TILE - 1) / RADIX_TILE); }
+
 // Per-block digit counts, digit-major: counts[d * nblocks + block].
 template <typename K>
 __global__ void __launch_bounds__(RADIX_THREADS)
@@ -265,14 +271,16 @@ radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_
                      int shift, int bits, uint32_t *__restrict__ counts, int nblocks) {
     __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
     const uint32_t P = *n_pairs;
+    if (uint64_t(P) > capacity) return;                                   // grid-uniform
+    const int nbu = used_blocks(P);
     const int nd = 1 << bits;
     const uint32_t mask = uint32_t(nd - 1);
-    for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
-    __syncthreads();
     const int w = threadIdx.x / 64;
     const unsigned l = lane_id();
-    if (uint64_t(P) <= capacity) {
-        const int64_t base = int64_t(blockIdx.x) * RADIX_TILE + w * (RADIX_ITERS * 64);
+    for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
+        for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+        __syncthreads();
+        const int64_t base = int64_t(blk) * RADIX_TILE + w * (RADIX_ITERS * 64);
         for (int it = 0; it < RADIX_ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
@@ -282,26 +290,31 @@ radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_
             const uint64_t peers = match_digit(d, bits, active);
             if (ok && (peers >> l) == 1ull) cnt[w][d] += uint32_t(__popcll(peers));  // highest lane of its digit
         }
+        __syncthreads();
+        for (int d = threadIdx.x; d < nd; d += RADIX_THREADS)
+            counts[int64_t(d) * nblocks + blk] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int d = threadIdx.x; d < nd; d += RADIX_THREADS)
-        counts[int64_t(d) * nblocks + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts, and its total.
 __global__ void __launch_bounds__(256)
-radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, uint32_t *__restrict__ digit_total) {
+radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, const uint32_t *__restrict__ n_pairs,
+                     uint64_t capacity, uint32_t *__restrict__ digit_total) {
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_tot;
+    const uint32_t P = *n_pairs;
+    if (uint64_t(P) > capacity) return;                                   // grid-uniform
+    const int nbu = used_blocks(P);
     uint32_t *row = counts + int64_t(blockIdx.x) * nblocks;
     uint32_t carry = 0;
     constexpr int ITEMS = 8;
-    for (int b0 = 0; b0 < nblocks; b0 += 256 * ITEMS) {
+    for (int b0 = 0; b0 < nbu; b0 += 256 * ITEMS) {
         const int i0 = b0 + threadIdx.x * ITEMS;
         uint32_t v[ITEMS], s = 0;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            v[k] = i0 + k < nblocks ? row[i0 + k] : 0u;
+            v[k] = i0 + k < nbu ? row[i0 + k] : 0u;
             s += v[k];
         }
         uint32_t pre = block_excl_scan256<uint32_t>(s, s_wsum);
@@ -310,7 +323,7 @@ radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, uint32_t *__res
         pre += carry;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            if (i0 + k < nblocks) row[i0 + k] = pre;
+            if (i0 + k < nbu) row[i0 + k] = pre;
             pre += v[k];
         }
         carry += s_tot;
@@ -333,91 +346,94 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
     __shared__ K sk[RADIX_TILE];
     __shared__ uint32_t sv[RADIX_TILE];
     const uint32_t P = *n_pairs;
-    if (uint64_t(P) > capacity) return;                                   // block-uniform
-    const int64_t blk0 = int64_t(blockIdx.x) * RADIX_TILE;
-    if (blk0 >= int64_t(P)) return;                                        // block-uniform
+    if (uint64_t(P) > capacity) return;                                   // grid-uniform
+    const int nbu = used_blocks(P);
     const int nd = 1 << bits;
     const uint32_t mask = uint32_t(nd - 1);
     const int t = threadIdx.x;
-    for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
-    {
-        const uint32_t dt = t < nd ? digit_total[t] : 0u;
-        const uint32_t ex = block_excl_scan256<uint32_t>(dt, s_wsum);      // contains __syncthreads
-        if (t < nd) s_gstart[t] = ex + colscan[int64_t(t) * nblocks + blockIdx.x];
-    }
-    __syncthreads();
     const int w = t / 64;
     const unsigned l = lane_id();
-    const int64_t base = blk0 + w * (RADIX_ITERS * 64);
-    K key[RADIX_ITERS];
-    uint32_t val[RADIX_ITERS], rank[RADIX_ITERS], dig[RADIX_ITERS];
+    const uint32_t dt = t < nd ? digit_total[t] : 0u;
+    const uint32_t dex = block_excl_scan256<uint32_t>(dt, s_wsum);          // contains __syncthreads
+    for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
+        const int64_t blk0 = int64_t(blk) * RADIX_TILE;
+        for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+        if (t < nd) s_gstart[t] = dex + colscan[int64_t(t) * nblocks + blk];
+        __syncthreads();
+        const int64_t base = blk0 + w * (RADIX_ITERS * 64);
+        K key[RADIX_ITERS];
+        uint32_t val[RADIX_ITERS], rank[RADIX_ITERS], dig[RADIX_ITERS];
 #pragma unroll
-    for (int it = 0; it < RADIX_ITERS; ++it) {
-        const int64_t idx = base + it * 64 + l;
-        const bool ok = idx < int64_t(P);
-        const uint64_t active = __ballot(ok);
-        key[it] = ok ? keys_in[idx] : K(0);
-        val[it] = ok ? vals_in[idx] : 0u;
-        const uint32_t d = ok ? digit_of(key[it], shift, mask) : 0u;
-        dig[it] = d;
-        rank[it] = 0;
-        if (active != 0) {
-            const uint64_t peers = match_digit(d, bits, active);
-            const uint32_t before = ok ? cnt[w][d] : 0u;
-            rank[it] = before + uint32_t(__popcll(peers & lanemask_lt()));
-            __builtin_amdgcn_wave_barrier();
-            if (ok && (peers >> l) == 1ull) cnt[w][d] = before + uint32_t(__popcll(peers));
-            __builtin_amdgcn_wave_barrier();
+        for (int it = 0; it < RADIX_ITERS; ++it) {
+            const int64_t idx = base + it * 64 + l;
+            const bool ok = idx < int64_t(P);
+            const uint64_t active = __ballot(ok);
+            key[it] = ok ? keys_in[idx] : K(0);
+            val[it] = ok ? vals_in[idx] : 0u;
+            const uint32_t d = ok ? digit_of(key[it], shift, mask) : 0u;
+            dig[it] = d;
+            rank[it] = 0;
+            if (active != 0) {
+                const uint64_t peers = match_digit(d, bits, active);
+                const uint32_t before = ok ? cnt[w][d] : 0u;
+                rank[it] = before + uint32_t(__popcll(peers & lanemask_lt()));
+                __builtin_amdgcn_wave_barrier();
+                if (ok && (peers >> l) == 1ull) cnt[w][d] = before + uint32_t(__popcll(peers));
+                __builtin_amdgcn_wave_barrier();
+            }
         }
-    }
-    __syncthreads();
-    uint32_t tot = 0;
-    if (t < nd) {
-        for (int ww = 0; ww < RADIX_WAVES; ++ww) {
-            const uint32_t c = cnt[ww][t];
-            cnt[ww][t] = tot;
-            tot += c;
+        __syncthreads();
+        uint32_t tot = 0;
+        if (t < nd) {
+            for (int ww = 0; ww < RADIX_WAVES; ++ww) {
+                const uint32_t c = cnt[ww][t];
+                cnt[ww][t] = tot;
+                tot += c;
+            }
         }
-    }
-    const uint32_t lex = block_excl_scan256<uint32_t>(tot, s_wsum);        // contains __syncthreads
-    if (t < nd) s_lstart[t] = lex;
-    __syncthreads();
+        const uint32_t lex = block_excl_scan256<uint32_t>(tot, s_wsum);    // contains __syncthreads
+        if (t < nd) s_lstart[t] = lex;
+        __syncthreads();
 #pragma unroll
-    for (int it = 0; it < RADIX_ITERS; ++it) {
-        const int64_t idx = base + it * 64 + l;
-        if (idx < int64_t(P)) {
-            const uint32_t lp = s_lstart[dig[it]] + cnt[w][dig[it]] + rank[it];
-            sk[lp] = key[it];
-            sv[lp] = val[it];
+        for (int it = 0; it < RADIX_ITERS; ++it) {
+            const int64_t idx = base + it * 64 + l;
+            if (idx < int64_t(P)) {
+                const uint32_t lp = s_lstart[dig[it]] + cnt[w][dig[it]] + rank[it];
+                sk[lp] = key[it];
+                sv[lp] = val[it];
+            }
         }
-    }
-    __syncthreads();
-    const int nloc = int(int64_t(P) - blk0 < RADIX_TILE ? int64_t(P) - blk0 : RADIX_TILE);
-    for (int lp = t; lp < nloc; lp += RADIX_THREADS) {
-        const K k = sk[lp];
-        const uint32_t d = digit_of(k, shift, mask);
-        const uint32_t dst = s_gstart[d] + uint32_t(lp) - s_lstart[d];
-        keys_out[dst] = k;
-        vals_out[dst] = sv[lp];
+        __syncthreads();
+        const int nloc = int(int64_t(P) - blk0 < RADIX_TILE ? int64_t(P) - blk0 : RADIX_TILE);
+        for (int lp = t; lp < nloc; lp += RADIX_THREADS) {
+            const K k = sk[lp];
+            const uint32_t d = digit_of(k, shift, mask);
+            const uint32_t dst = s_gstart[d] + uint32_t(lp) - s_lstart[d];
+            keys_out[dst] = k;
+            vals_out[dst] = sv[lp];
+        }
+        __syncthreads();
     }
 }
 
 // ----------------------------------------------------------------- tile ranges
+// offsets[u] = first pair of tile u (grid-stride over the P + 1 boundaries).
 template <typename K>
 __global__ void __launch_bounds__(256)
 tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
                    int shift, uint32_t n_tiles, uint32_t *__restrict__ offsets) {
     const uint32_t P = *n_pairs;
     if (uint64_t(P) > capacity) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i > int64_t(P)) return;
-    if (i < int64_t(P)) {
-        const int64_t t = int64_t(keys[i] >> shift);
-        const int64_t tp = i > 0 ? int64_t(keys[i - 1] >> shift) : -1;
-        for (int64_t u = tp + 1; u <= t; ++u) offsets[u] = uint32_t(i);
-    } else {
-        const int64_t tl = P > 0 ? int64_t(keys[P - 1] >> shift) : -1;
-        for (int64_t u = tl + 1; u <= int64_t(n_tiles); ++u) offsets[u] = P;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= int64_t(P);
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (i < int64_t(P)) {
+            const int64_t t = int64_t(keys[i] >> shift);
+            const int64_t tp = i > 0 ? int64_t(keys[i - 1] >> shift) : -1;
+            for (int64_t u = tp + 1; u <= t; ++u) offsets[u] = uint32_t(i);
+        } else {
+            const int64_t tl = P > 0 ? int64_t(keys[P - 1] >> shift) : -1;
+            for (int64_t u = tl + 1; u <= int64_t(n_tiles); ++u) offsets[u] = P;
+        }
     }
 }
 
@@ -495,16 +511,18 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
     }
     // 3. radix passes (digits of at most 8 bits, spread evenly)
     if (capacity > 0) {
+        const unsigned grid = unsigned(L.nblocks < RADIX_MAX_GRID ? L.nblocks : RADIX_MAX_GRID);
         int shift = 0;
         for (int p = 0; p < npass; ++p) {
             const int bits = (key_bits - shift + (npass - p) - 1) / (npass - p);
             uint32_t *vout = vbuf[(npass - 1 - p) % 2];
-            hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
+            hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(grid), dim3(RADIX_THREADS), 0, s, kin,
                                n_pairs, capacity, shift, bits, hist, L.nblocks);
             MGS_LAUNCH_CHECK("radix_upsweep_kernel");
-            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, dtot);
+            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, n_pairs,
+                               capacity, dtot);
             MGS_LAUNCH_CHECK("radix_colscan_kernel");
-            hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(L.nblocks), dim3(RADIX_THREADS), 0, s, kin,
+            hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(grid), dim3(RADIX_THREADS), 0, s, kin,
                                vin, n_pairs, capacity, shift, bits, hist, dtot, L.nblocks, kout, vout);
             MGS_LAUNCH_CHECK("radix_downsweep_kernel");
             K *tk = kin; kin = kout; kout = tk;
@@ -513,8 +531,8 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
         }
     }
     // 4. ranges
-    const uint64_t nthreads = capacity + 1;
-    hipLaunchKernelGGL((tile_ranges_kernel<K>), dim3(unsigned((nthreads + 255) / 256)), dim3(256), 0, s, kin,
+    const uint64_t rblocks = (capacity + 1 + 255) / 256;
+    hipLaunchKernelGGL((tile_ranges_kernel<K>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256), 0, s, kin,
                        n_pairs, capacity, range_shift, T, tile_offsets);
     MGS_LAUNCH_CHECK("tile_ranges_kernel");
     return MGS_OK;

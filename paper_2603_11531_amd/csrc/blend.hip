@@ -15,6 +15,7 @@
 // polynomial in the lane's offset, see quad_poly), compare/select, min, exp2,
 // and 5 FMA to accumulate N (rgb, colours pre-multiplied by w), D and T -- all
 // float32 VALU, no sort, no order.
+#include "batch.h"
 #include "blend_math.h"
 
 namespace mgs {
@@ -28,6 +29,204 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
     const int tile = blockIdx.x;
     blend_tile<SORTED>(splat, gids, offs[tile], offs[tile + 1], tile % cam.tiles_x, tile / cam.tiles_x, cam.W,
                        cam.H, bgr, bgg, bgb, log2_amin, amax, t_stop, image, aux);
+}
+
+// ---------------------------------------------------------------- split-tile OIT blend
+constexpr uint32_t SPLIT_RANGE = 1024;        // Gaussians per range of a long tile list
+constexpr int PART_FLOATS = 5 * 256;          // per-range partial sums (N rgb, D, T) x 256 pixels
+
+// Destination of one tile: a single view, or one request of a batch.
+struct TileView {
+    int tx, ty, W, H;
+    float bg[3];
+    float *image, *aux;
+};
+struct SingleViewLoc {
+    int tiles_x, W, H;
+    float bg[3];
+    float *image, *aux;
+    __device__ __forceinline__ TileView operator()(uint32_t t) const {
+        return TileView{int(t % uint32_t(tiles_x)), int(t / uint32_t(tiles_x)), W, H, {bg[0], bg[1], bg[2]}, image, aux};
+    }
+};
+struct BatchViewLoc {
+    const mgs_request *reqs;
+    const BatchPlan *plan;
+    __device__ __forceinline__ TileView operator()(uint32_t gt) const {
+        const int r = find_request(plan->tbase, plan->nreq, gt);
+        const mgs_request &q = reqs[r];
+        const uint32_t lt = gt - plan->tbase[r], tx = plan->tiles_x[r];
+        return TileView{int(lt % tx), int(lt / tx), q.cam.width, q.cam.height, {q.bg[0], q.bg[1], q.bg[2]},
+                        q.image, nullptr};
+    }
+};
+
+// Exclusive scan over a 1024-thread block (all threads call).
+__device__ __forceinline__ uint64_t block_excl_scan1024(uint64_t v, uint64_t *s_wsum /* [16] */) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(inc, o, 64);
+        if (l >= o) inc += u;
+    }
+    if (l == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int k = 0; k < w; ++k) pre += s_wsum[k];
+    __syncthreads();
+    return pre + inc - v;
+}
+
+// One block of 1024 threads: every tile gets n_ranges(L) items (item = tile | range << 24);
+// ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
+// tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
+__global__ void __launch_bounds__(1024)
+split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
+                  uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
+                  uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
+    __shared__ uint64_t s_wsum[16];
+    uint32_t T = t_count ? *t_count : t_host;
+    if (T > t_host) T = t_host;
+    if (uint64_t(*n_pairs) > capacity) T = 0;             // lists were not built: render nothing
+    uint32_t c_items = 0, c_slots = 0, c_split = 0;
+    for (uint32_t base = 0; base < T; base += 1024) {
+        const uint32_t t = base + threadIdx.x;
+        uint32_t nr = 0, m = 0;
+        if (t < T) {
+            nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
+            m = nr > 1 ? 1u : 0u;
+        }
+        const uint64_t e1 = block_excl_scan1024(uint64_t(nr) | (uint64_t(nr * m) << 32), s_wsum);
+        const uint64_t e2 = block_excl_scan1024(uint64_t(m), s_wsum);
+        const uint32_t i0 = c_items + uint32_t(e1), s0 = c_slots + uint32_t(e1 >> 32), j = c_split + uint32_t(e2);
+        for (uint32_t r = 0; r < nr; ++r) {
+            items[i0 + r] = t | (r << 24);
+            item_slot[i0 + r] = m ? s0 + r : 0xFFFFFFFFu;
+        }
+        if (m) {
+            split_tile[j] = t;
+            split_slot0[j] = s0;
+        }
+        // block totals: the last thread's exclusive prefix plus its own values
+        __shared__ uint32_t s_tot[3];
+        if (threadIdx.x == 1023) {
+            s_tot[0] = uint32_t(e1) + nr;
+            s_tot[1] = uint32_t(e1 >> 32) + nr * m;
+            s_tot[2] = uint32_t(e2) + m;
+        }
+        __syncthreads();
+        c_items += s_tot[0];
+        c_slots += s_tot[1];
+        c_split += s_tot[2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = c_items;
+        counts[1] = c_split;
+    }
+}
+
+template <typename Loc>
+__global__ void __launch_bounds__(BLEND_THREADS)
+blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
+                   const uint32_t *__restrict__ gids, const uint32_t *__restrict__ items,
+                   const uint32_t *__restrict__ item_slot, const uint32_t *__restrict__ counts, Loc loc,
+                   float log2_amin, float amax, float *__restrict__ part) {
+    const uint32_t k = blockIdx.x;
+    if (k >= counts[0]) return;                                           // block-uniform
+    const uint32_t it = items[k], t = it & 0xFFFFFFu, r = it >> 24;
+    const uint32_t start = offs[t], end = offs[t + 1];
+    const uint32_t L = end - start, rl = range_len(L, SPLIT_RANGE);
+    const TileView v = loc(t);
+    if (n_ranges(L, SPLIT_RANGE) == 1) {
+        blend_tile<false, false>(splat, gids, start, end, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin,
+                                 amax, 0.0f, v.image, v.aux);
+    } else {
+        const uint32_t s = start + r * rl, e = (end - s > rl) ? s + rl : end;
+        blend_tile<false, true>(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin, amax,
+                                0.0f, nullptr, nullptr, part + size_t(item_slot[k]) * PART_FLOATS);
+    }
+}
+
+// Merge the ranges of each split tile in range order and composite (Eq. 2).
+template <typename Loc>
+__global__ void __launch_bounds__(BLEND_THREADS)
+merge_ranges_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ split_tile,
+                    const uint32_t *__restrict__ split_slot0, const uint32_t *__restrict__ counts, Loc loc,
+                    const float *__restrict__ part) {
+    const uint32_t j = blockIdx.x;
+    if (j >= counts[1]) return;                                           // block-uniform
+    const uint32_t t = split_tile[j];
+    const uint32_t nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
+    const float *b = part + size_t(split_slot0[j]) * PART_FLOATS;
+    const int p = threadIdx.x;
+    float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
+    for (uint32_t r = 0; r < nr; ++r, b += PART_FLOATS) {
+        Nr += b[p];
+        Ng += b[256 + p];
+        Nb += b[512 + p];
+        D += b[768 + p];
+        T *= b[1024 + p];
+    }
+    const TileView v = loc(t);
+    int px, py;
+    tile_pixel(p, v.tx, v.ty, px, py);
+    composite_oit(Nr, Ng, Nb, D, T, px, py, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.image, v.aux);
+}
+
+struct SplitLayout {
+    size_t items, slot, stile, sslot, counts, part, total;
+    uint32_t max_items;
+};
+
+inline SplitLayout split_layout(uint32_t T, uint64_t capacity) {
+    SplitLayout L;
+    L.max_items = uint32_t(T + capacity / SPLIT_RANGE + 1);
+    const size_t max_slots = size_t(2 * (capacity / SPLIT_RANGE) + 2);
+    size_t o = 0;
+    L.items = o;  o = align_up(o + size_t(L.max_items) * 4, 256);
+    L.slot = o;   o = align_up(o + size_t(L.max_items) * 4, 256);
+    L.stile = o;  o = align_up(o + size_t(T) * 4 + 4, 256);
+    L.sslot = o;  o = align_up(o + size_t(T) * 4 + 4, 256);
+    L.counts = o; o = align_up(o + 16, 256);
+    L.part = o;   o = align_up(o + max_slots * PART_FLOATS * 4, 256);
+    L.total = o;
+    return L;
+}
+
+template <typename Loc>
+int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t *gids, const uint32_t *t_count,
+                       uint32_t T, const uint32_t *n_pairs, uint64_t capacity, Loc loc, float alpha_min,
+                       float alpha_max, void *ws, hipStream_t s) {
+    const SplitLayout L = split_layout(T, capacity);
+    char *w = static_cast<char *>(ws);
+    uint32_t *items = reinterpret_cast<uint32_t *>(w + L.items);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(w + L.slot);
+    uint32_t *stile = reinterpret_cast<uint32_t *>(w + L.stile);
+    uint32_t *sslot = reinterpret_cast<uint32_t *>(w + L.sslot);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(w + L.counts);
+    float *part = reinterpret_cast<float *>(w + L.part);
+    hipLaunchKernelGGL(split_plan_kernel, dim3(1), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity, items, slot,
+                       stile, sslot, counts);
+    MGS_LAUNCH_CHECK("split_plan_kernel");
+    hipLaunchKernelGGL(blend_range_kernel<Loc>, dim3(L.max_items), dim3(BLEND_THREADS), 0, s, splat, offs, gids,
+                       items, slot, counts, loc, log2f(alpha_min), alpha_max, part);
+    MGS_LAUNCH_CHECK("blend_range_kernel");
+    hipLaunchKernelGGL(merge_ranges_kernel<Loc>, dim3(T > 0 ? T : 1), dim3(BLEND_THREADS), 0, s, offs, stile, sslot,
+                       counts, loc, part);
+    MGS_LAUNCH_CHECK("merge_ranges_kernel");
+    return MGS_OK;
+}
+
+size_t blend_split_workspace(uint32_t T, uint64_t capacity) { return split_layout(T, capacity).total; }
+
+int blend_split_batch(const float4 *splat, const uint32_t *offs, const uint32_t *gids, const BatchPlan *plan,
+                      const mgs_request *reqs, uint32_t max_tiles, const uint32_t *n_pairs, uint64_t capacity,
+                      float alpha_min, float alpha_max, void *ws, hipStream_t s) {
+    return blend_split_launch(splat, offs, gids, &plan->t_total, max_tiles, n_pairs, capacity,
+                              BatchViewLoc{reqs, plan}, alpha_min, alpha_max, ws, s);
 }
 
 inline int blend_common_checks(const mgs_projected *proj, const uint32_t *offs, const uint32_t *gids,
@@ -77,4 +276,29 @@ extern "C" int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_
                        log2f(alpha_min), alpha_max, t_stop, image, nullptr);
     MGS_LAUNCH_CHECK("blend_kernel<sorted>");
     return MGS_OK;
+}
+
+extern "C" int mgs_blend_oit_split_workspace(int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes) {
+    MGS_REQUIRE(bytes && tiles_x > 0 && tiles_y > 0, "bad arguments");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    *bytes = mgs::blend_split_workspace(uint32_t(tiles_x) * uint32_t(tiles_y), capacity);
+    return MGS_OK;
+}
+
+extern "C" int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                                   const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
+                                   const float bg[3], float alpha_min, float alpha_max, void *ws, size_t ws_bytes,
+                                   float *image, float *aux, void *stream) {
+    using namespace mgs;
+    int rc;
+    if ((rc = blend_common_checks(proj, tile_offsets, gids, cam, tile, bg, alpha_min, alpha_max, image)) != MGS_OK)
+        return rc;
+    MGS_REQUIRE(n_pairs != nullptr, "n_pairs is NULL");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    const CamK k = make_camk(cam);
+    const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
+    MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= blend_split_workspace(T, capacity), "workspace too small");
+    SingleViewLoc loc{k.tiles_x, k.W, k.H, {bg[0], bg[1], bg[2]}, image, aux};
+    return blend_split_launch(reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, nullptr, T, n_pairs,
+                              capacity, loc, alpha_min, alpha_max, ws, as_stream(stream));
 }

@@ -74,11 +74,55 @@ __device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float 
 
 // Composite one 16x16 tile (tile coordinates tx, ty) from its list gids[start, end)
 // into image / aux of a W x H view.  Called by a whole 256-thread workgroup.
-template <bool SORTED>
+// Eq. 2 composite of one pixel from its sums: C = (1 - T) N / D + T c_bg (c_bg if D = 0);
+// aux (if non-NULL) receives (N/D rgb, D, T).
+__device__ __forceinline__ void composite_oit(float Nr, float Ng, float Nb, float D, float T, int px, int py, int W,
+                                              int H, float bgr, float bgg, float bgb, float *__restrict__ image,
+                                              float *__restrict__ aux) {
+    if (px >= W || py >= H) return;
+    const size_t hw = size_t(W) * H;
+    const size_t p = size_t(py) * W + px;
+    float cr, cg, cb;
+    if (D > 0.f) {
+        const float inv = 1.0f / D;
+        const float fr = Nr * inv, fg = Ng * inv, fb = Nb * inv;
+        const float f = 1.0f - T;
+        cr = fmaf(f, fr, T * bgr);
+        cg = fmaf(f, fg, T * bgg);
+        cb = fmaf(f, fb, T * bgb);
+        if (aux) {
+            aux[p] = fr; aux[hw + p] = fg; aux[2 * hw + p] = fb;
+            aux[3 * hw + p] = D; aux[4 * hw + p] = T;
+        }
+    } else {
+        cr = bgr; cg = bgg; cb = bgb;
+        if (aux) {
+            aux[p] = 0.f; aux[hw + p] = 0.f; aux[2 * hw + p] = 0.f;
+            aux[3 * hw + p] = 0.f; aux[4 * hw + p] = 1.f;
+        }
+    }
+    image[p] = cr;
+    image[hw + p] = cg;
+    image[2 * hw + p] = cb;
+}
+
+// Pixel of workgroup thread `k` in tile (tx, ty): wave k / 64 owns quadrant (w & 1, w >> 1).
+__device__ __forceinline__ void tile_pixel(int k, int tx, int ty, int &px, int &py) {
+    const int w = k >> 6, l = k & 63;
+    px = tx * 16 + (w & 1) * 8 + (l & 7);
+    py = ty * 16 + (w >> 1) * 8 + (l >> 3);
+}
+
+// Composite one 16x16 tile (tile coordinates tx, ty) from the list range gids[start, end)
+// into image / aux of a W x H view.  Called by a whole 256-thread workgroup.  With
+// PARTIAL (order-independent path only) the per-pixel sums (N rgb, D, T) of this range
+// go to part[5][256] instead, to be merged with the tile's other ranges.
+template <bool SORTED, bool PARTIAL = false>
 __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
                                            uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
                                            float bgg, float bgb, float log2_amin, float amax, float t_stop,
-                                           float *__restrict__ image, float *__restrict__ aux) {
+                                           float *__restrict__ image, float *__restrict__ aux,
+                                           float *__restrict__ part = nullptr) {
     // per quadrant and staged splat: polynomial (c0, cx, cy, cxx), (cxy, cyy, -, -) and the colour
     // (OIT: (w r, w g, w b, w); sorted: (r, g, b, 0)), one 48-byte record so a wave reads all three
     // with one address register
@@ -167,38 +211,36 @@ __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, con
         }
     }
 
-    if (px < W && py < H) {
+    if (PARTIAL) {
+        const int k = threadIdx.x;
+        part[k] = Nr;
+        part[256 + k] = Ng;
+        part[512 + k] = Nb;
+        part[768 + k] = D;
+        part[1024 + k] = T;
+    } else if (!SORTED) {
+        composite_oit(Nr, Ng, Nb, D, T, px, py, W, H, bgr, bgg, bgb, image, aux);
+    } else if (px < W && py < H) {
         const size_t hw = size_t(W) * H;
         const size_t p = size_t(py) * W + px;
-        float cr, cg, cb;
-        if (!SORTED) {
-            if (D > 0.f) {
-                const float inv = 1.0f / D;
-                const float fr = Nr * inv, fg = Ng * inv, fb = Nb * inv;
-                const float f = 1.0f - T;
-                cr = fmaf(f, fr, T * bgr);
-                cg = fmaf(f, fg, T * bgg);
-                cb = fmaf(f, fb, T * bgb);
-                if (aux) {
-                    aux[p] = fr; aux[hw + p] = fg; aux[2 * hw + p] = fb;
-                    aux[3 * hw + p] = D; aux[4 * hw + p] = T;
-                }
-            } else {
-                cr = bgr; cg = bgg; cb = bgb;
-                if (aux) {
-                    aux[p] = 0.f; aux[hw + p] = 0.f; aux[2 * hw + p] = 0.f;
-                    aux[3 * hw + p] = 0.f; aux[4 * hw + p] = 1.f;
-                }
-            }
-        } else {
-            cr = fmaf(T, bgr, Nr);
-            cg = fmaf(T, bgg, Ng);
-            cb = fmaf(T, bgb, Nb);
-        }
-        image[p] = cr;
-        image[hw + p] = cg;
-        image[2 * hw + p] = cb;
+        image[p] = fmaf(T, bgr, Nr);
+        image[hw + p] = fmaf(T, bgg, Ng);
+        image[2 * hw + p] = fmaf(T, bgb, Nb);
     }
+}
+
+// ---------------------------------------------------------------- split tiles
+// Order independence makes the per-pixel state additive (N and D add, T multiplies), so
+// a long tile list can be cut into ranges rendered by different workgroups and merged
+// exactly.  Ranges hold at most `split` Gaussians (more for extremely long lists, so a
+// tile has at most 255 ranges); item = tile | range << 24.
+__device__ __forceinline__ uint32_t range_len(uint32_t L, uint32_t split) {
+    const uint32_t m = (L + 254) / 255;
+    return split > m ? split : m;
+}
+__device__ __forceinline__ uint32_t n_ranges(uint32_t L, uint32_t split) {
+    const uint32_t r = range_len(L, split);
+    return L == 0 ? 1u : (L + r - 1) / r;
 }
 
 }  // namespace mgs

@@ -65,45 +65,42 @@ __device__ __forceinline__ void load_mlp(const uint8_t *__restrict__ packed, int
     F.bo = fbh[1];
 }
 
-// The MLP for the 64 Gaussians i0 .. i0 + 63 of g (indices >= g.n are padding), one wave;
-// outputs to phi / omod at out0 + k.  xs: this wave's LDS feature tile.
-__device__ __forceinline__ void enhance_group(const mgs_gaussians &g, const CamK &cam, int64_t i0,
-                                              const MlpFrags &F, __bf16 *xs, float *__restrict__ phi,
-                                              float *__restrict__ omod, int64_t out0) {
-    const int l = threadIdx.x & 63;
-    const int lg = l >> 4;
-    const int64_t n = g.n;
-    const int64_t i = i0 + l;
-    f32x8 f[4];
+// The 32 MLP inputs of one Gaussian: [P_i (3), s_i (3), q_i (4), Y_i (12)], zero-padded.
+__device__ __forceinline__ void lane_features(const float mu[3], const float ls[3], const float q[4],
+                                              const float sh[12], const CamK &cam, f32x8 f[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < n) {
-        const float mx = g.mean[i], my = g.mean[n + i], mz = g.mean[2 * n + i];
-        const float vx = mx - cam.campos[0], vy = my - cam.campos[1], vz = mz - cam.campos[2];
-        const float vn = rsqrtf(vx * vx + vy * vy + vz * vz);
-        float qw = g.quat[i], qx = g.quat[n + i], qy = g.quat[2 * n + i], qz = g.quat[3 * n + i];
-        const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
-        const float qi = qn2 > 0.f ? rsqrtf(qn2) : 0.f;
-        f[0][0] = vx * vn; f[0][1] = vy * vn; f[0][2] = vz * vn;
-        f[0][3] = expf(g.log_scale[i]);
-        f[0][4] = expf(g.log_scale[n + i]);
-        f[0][5] = expf(g.log_scale[2 * n + i]);
-        f[0][6] = qw * qi; f[0][7] = qx * qi;
-        f[1][0] = qy * qi; f[1][1] = qz * qi;
+    const float vx = mu[0] - cam.campos[0], vy = mu[1] - cam.campos[1], vz = mu[2] - cam.campos[2];
+    const float vn = rsqrtf(vx * vx + vy * vy + vz * vz);
+    const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const float qi = qn2 > 0.f ? rsqrtf(qn2) : 0.f;
+    f[0][0] = vx * vn; f[0][1] = vy * vn; f[0][2] = vz * vn;
+    f[0][3] = expf(ls[0]);
+    f[0][4] = expf(ls[1]);
+    f[0][5] = expf(ls[2]);
+    f[0][6] = q[0] * qi; f[0][7] = q[1] * qi;
+    f[1][0] = q[2] * qi; f[1][1] = q[3] * qi;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const float y = g.sh[k * n + i];
-            const int slot = 10 + k;
-            f[slot >> 3][slot & 7] = y;
-        }
+    for (int k = 0; k < 12; ++k) {
+        const int slot = 10 + k;
+        f[slot >> 3][slot & 7] = sh[k];
     }
+}
+
+// The MLP for the wave's 64 Gaussians (lane l holds the features of Gaussian l);
+// returns lane l's (phi, m).  xs: the wave's LDS feature tile (its first 128
+// floats are reused to hand the head outputs back to their lanes).
+__device__ __forceinline__ void mlp_wave(const f32x8 f[4], const MlpFrags &F, __bf16 *xs, float &phi_o,
+                                         float &om_o) {
+    const int l = threadIdx.x & 63;
+    const int lg = l >> 4;
     bf16x8 *row = reinterpret_cast<bf16x8 *>(xs + l * FEAT_STRIDE);
 #pragma unroll
     for (int c = 0; c < 4; ++c) row[c] = __builtin_convertvector(f[c], bf16x8);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
+    float hp[4], ho[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(xs + (nb * 16 + (l & 15)) * FEAT_STRIDE + 8 * lg);
@@ -123,15 +120,61 @@ __device__ __forceinline__ void enhance_group(const mgs_gaussians &g, const CamK
         f32x4 hz = {0.f, 0.f, 0.f, 0.f};
         f32x4 hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.AH[0], xha, hz, 0, 0, 0);
         hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.AH[1], xhb, hd, 0, 0, 0);
-        const int64_t k = nb * 16 + l;
-        if (l < 16 && i0 + k < n) {
-            phi[out0 + k] = fmaxf(hd[0] + F.bphi, 0.0f);
-            omod[out0 + k] = 1.0f / (1.0f + expf(-(hd[1] + F.bo)));
+        hp[nb] = hd[0];            // lanes 0..15 hold Gaussian nb * 16 + l
+        ho[nb] = hd[1];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float *xo = reinterpret_cast<float *>(xs);
+    if (l < 16) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            xo[nb * 16 + l] = fmaxf(hp[nb] + F.bphi, 0.0f);
+            xo[64 + nb * 16 + l] = 1.0f / (1.0f + expf(-(ho[nb] + F.bo)));
         }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    phi_o = xo[l];
+    om_o = xo[64 + l];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The MLP for the 64 Gaussians i0 .. i0 + 63 of g (indices >= g.n are padding), one wave;
+// outputs to phi / omod at out0 + k.  xs: this wave's LDS feature tile.
+__device__ __forceinline__ void enhance_group(const mgs_gaussians &g, const CamK &cam, int64_t i0,
+                                              const MlpFrags &F, __bf16 *xs, float *__restrict__ phi,
+                                              float *__restrict__ omod, int64_t out0) {
+    const int l = threadIdx.x & 63;
+    const int64_t n = g.n;
+    const int64_t i = i0 + l;
+    f32x8 f[4];
+    if (i < n) {
+        float mu[3], ls[3], q[4], sh[12];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mu[k] = g.mean[k * n + i];
+            ls[k] = g.log_scale[k * n + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = g.quat[k * n + i];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sh[k] = g.sh[k * n + i];
+        lane_features(mu, ls, q, sh, cam, f);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    float ph, om;
+    mlp_wave(f, F, xs, ph, om);
+    if (i < n) {
+        phi[out0 + l] = ph;
+        omod[out0 + l] = om;
+    }
 }
 
 }  // namespace mgs

@@ -10,6 +10,7 @@
 // cancellation of a*c - b^2, which matters for thin, elongated splats.  The
 // exponent is stored as q = A t^2 + dy^2 / c with t = dx - (b/c) dy, which is
 // the same quadratic form split into two non-negative parts.
+#include "mlp_math.h"
 #include "proj_math.h"
 
 namespace mgs {
@@ -25,7 +26,68 @@ project_kernel(mgs_gaussians g, CamK cam, const float *__restrict__ phi_in,
     store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);
 }
 
+// Enhancement MLP and projection in one pass: each wave reads its 64 Gaussians'
+// attributes once, runs the MLP on MFMA, hands every lane its own (phi, m) and
+// projects.  Same results as mgs_enhance followed by mgs_project.
+__global__ void __launch_bounds__(256)
+enhance_project_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, float alpha_min,
+                       float4 *__restrict__ splat, uint2 *__restrict__ rect_out, uint32_t *__restrict__ ntiles_out,
+                       float *__restrict__ phi_out, float *__restrict__ omod_out) {
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][64 * FEAT_STRIDE];
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int64_t n = g.n;
+    const int64_t ngroups = (n + 63) / 64;
+    MlpFrags F;
+    load_mlp(packed, l, F);
+    for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
+        const int64_t i = grp * 64 + l;
+        const bool valid = i < n;
+        GaussIn in;
+        f32x8 f[4];
+        if (valid) {
+            in = load_gauss(g, i, nullptr, nullptr);
+            lane_features(in.mu, in.ls, in.q, in.sh, cam, f);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        float ph, om;
+        mlp_wave(f, F, s_x[w], ph, om);
+        if (valid) {
+            in.phi = ph;
+            in.om = om;
+            store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);
+            phi_out[i] = ph;
+            omod_out[i] = om;
+        }
+    }
+}
+
 }  // namespace mgs
+
+extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
+                                   float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream) {
+    using namespace mgs;
+    int rc;
+    if ((rc = check_gaussians(g)) != MGS_OK) return rc;
+    if ((rc = check_camera(cam)) != MGS_OK) return rc;
+    if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
+    if (tile != MGS_TILE) return set_error(MGS_ERR_UNSUPPORTED, "tile must be %d", MGS_TILE);
+    MGS_REQUIRE(alpha_min > 0.0f && alpha_min < 1.0f, "alpha_min must be in (0, 1)");
+    MGS_REQUIRE(packed_mlp && aligned(packed_mlp, 16), "packed MLP must be non-NULL and 16-byte aligned");
+    if (g->n == 0) return MGS_OK;
+    MGS_REQUIRE(phi && omod, "phi / omod is NULL");
+    const CamK k = make_camk(cam);
+    const int64_t groups = (g->n + 63) / 64;
+    int64_t blocks = (groups + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(enhance_project_kernel, dim3(unsigned(blocks)), dim3(256), 0, as_stream(stream), *g, k,
+                       static_cast<const uint8_t *>(packed_mlp), alpha_min, reinterpret_cast<float4 *>(out->splat),
+                       reinterpret_cast<uint2 *>(out->rect), out->n_tiles, phi, omod);
+    MGS_LAUNCH_CHECK("enhance_project_kernel");
+    return MGS_OK;
+}
 
 extern "C" int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
                            const float *omod, int tile, float alpha_min, mgs_projected *out,

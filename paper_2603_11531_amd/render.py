@@ -94,6 +94,7 @@ class Renderer:
         self.gids = None
         self.ws = None
         self.ws_sorted = None
+        self.ws_split = None
         self.ensure_capacity(capacity if capacity is not None else max(1024, 4 * self.n))
 
     # -- capacity -----------------------------------------------------------
@@ -105,6 +106,11 @@ class Renderer:
             self.gids = torch.zeros(max(1, cap), dtype=torch.int32, device=self.device)
             self.ws = None
             self.ws_sorted = None
+            self.ws_split = None
+        if self.ws_split is None and not sorted_path:
+            nb = L.C.c_size_t()
+            L.check(lib.mgs_blend_oit_split_workspace(self.tiles_x, self.tiles_y, self.capacity, L.C.byref(nb)))
+            self.ws_split = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device=self.device)
         if self.ws is None and not sorted_path:
             nb = L.C.c_size_t()
             L.check(lib.mgs_bin_workspace(self.n, self.tiles_x, self.tiles_y, self.capacity, L.C.byref(nb)))
@@ -126,6 +132,12 @@ class Renderer:
         L.check(L.lib().mgs_project(L.C.byref(scene.struct), L.C.byref(cam_s), phi, om, L.MGS_TILE,
                                     alpha_min, L.C.byref(self.proj), L.stream_ptr(stream)))
 
+    def enhance_project(self, scene: DeviceScene, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None):
+        """Fused enhance + project (one read of the attributes); also fills phi / omod."""
+        L.check(L.lib().mgs_enhance_project(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
+                                            L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
+                                            L.ptr(self.omod), L.stream_ptr(stream)))
+
     def bin(self, sorted_path=False, stream=None):
         self.ensure_capacity(self.capacity, sorted_path)
         lib = L.lib()
@@ -136,9 +148,17 @@ class Renderer:
                    L.stream_ptr(stream)))
 
     def blend_oit(self, cam_s, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, want_aux=False,
-                  stream=None):
+                  stream=None, split=True):
+        """Eq. 2 composite; ``split`` (default) uses the split-tile blend that balances dense tiles."""
         if want_aux and self.aux is None:
             self.aux = torch.empty(5, self.H, self.W, dtype=torch.float32, device=self.device)
+        if split:
+            L.check(L.lib().mgs_blend_oit_split(
+                L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids), L.ptr(self.n_pairs), self.capacity,
+                L.C.byref(cam_s), L.MGS_TILE, L.bg_array(bg), alpha_min, alpha_max, L.ptr(self.ws_split),
+                self.ws_split.numel() * 4, L.ptr(self.image), L.ptr(self.aux) if want_aux else None,
+                L.stream_ptr(stream)))
+            return
         L.check(L.lib().mgs_blend_oit(L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids),
                                       L.C.byref(cam_s), L.MGS_TILE, L.bg_array(bg), alpha_min, alpha_max,
                                       L.ptr(self.image), L.ptr(self.aux) if want_aux else None,
@@ -155,13 +175,16 @@ class Renderer:
 
     # -- whole pass -----------------------------------------------------------
     def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
-               check_capacity=True, stream=None):
+               check_capacity=True, stream=None, fused=False, split=True):
         """enhance -> project -> bin -> blend.  With check_capacity the host reads the pair
         count once and re-bins with a larger capacity on overflow."""
         cam_s = L.make_camera(cam)
-        if mlp is not None:
-            self.enhance(scene, cam_s, mlp, stream)
-        self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream)
+        if mlp is not None and fused:
+            self.enhance_project(scene, cam_s, mlp, stream=stream)
+        else:
+            if mlp is not None:
+                self.enhance(scene, cam_s, mlp, stream)
+            self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream)
         self.bin(sorted_path, stream)
         if check_capacity:
             P = self.pairs()      # synchronises
@@ -171,7 +194,7 @@ class Renderer:
         if sorted_path:
             self.blend_sorted(cam_s, bg, stream=stream)
         else:
-            self.blend_oit(cam_s, bg, want_aux=want_aux, stream=stream)
+            self.blend_oit(cam_s, bg, want_aux=want_aux, stream=stream, split=split)
         return self.image
 
     # -- views for tests ---------------------------------------------------------

@@ -133,6 +133,23 @@ class BatchSlot:
         return (int(self.n_pairs.cpu()[0]) & 0xFFFFFFFF) > self.capacity
 
 
+def form_batch(queue, footprint, max_batch, max_gaussians, max_tiles, capacity, image_budget, image_in_use):
+    """FIFO admission: pop requests from the head of ``queue`` while the batch stays within
+    the request, Gaussian, tile, estimated-pair and image-memory limits.  The first request
+    of a batch is admitted on its Gaussians / tiles / memory alone (its pair estimate may
+    exceed the capacity: the slot then overflows and the request is re-rendered on the
+    single-view path).  Returns the admitted requests in arrival order."""
+    batch, n_sum, t_sum, p_sum, b_sum = [], 0, 0, 0, 0
+    while queue and len(batch) < max_batch:
+        n, t, b, p = footprint(queue[0])
+        if n_sum + n > max_gaussians or t_sum + t > max_tiles or image_in_use + b_sum + b > image_budget or \
+                (batch and p_sum + p > capacity):
+            break
+        batch.append(queue.popleft())
+        n_sum, t_sum, p_sum, b_sum = n_sum + n, t_sum + t, p_sum + p, b_sum + b
+    return batch
+
+
 class Server:
     """Open-loop continuous-batching server (see the module docstring)."""
 
@@ -216,20 +233,11 @@ class Server:
                         self.image_bytes_in_use -= 12 * r.cam.width * r.cam.height
                     served.extend(slot.requests)
             while free and queue:
-                batch, n_sum, t_sum, p_sum = [], 0, 0, 0
-                while queue and len(batch) < self.max_batch:
-                    n, t, b, p = self.footprint(queue[0])
-                    if n_sum + n > self.max_gaussians or t_sum + t > self.max_tiles or \
-                            self.image_bytes_in_use + b > self.image_budget or \
-                            (batch and p_sum + p > self.capacity):
-                        break
-                    r = queue.popleft()
+                batch = form_batch(queue, self.footprint, self.max_batch, self.max_gaussians, self.max_tiles,
+                                   self.capacity, self.image_budget, self.image_bytes_in_use)
+                for r in batch:
                     r.image = torch.empty(3, r.cam.height, r.cam.width, dtype=torch.float32, device=self.device)
-                    self.image_bytes_in_use += b
-                    n_sum += n
-                    t_sum += t
-                    p_sum += p
-                    batch.append(r)
+                    self.image_bytes_in_use += 12 * r.cam.width * r.cam.height
                 if not batch:
                     break
                 slot = free.pop()

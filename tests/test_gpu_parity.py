@@ -332,3 +332,42 @@ def _render_pixel_sorted(sub, i, j, bg):
         C += al * T * col[k]
         T *= 1 - al
     return C + T * torch.tensor(np.asarray(bg, np.float64)), flag
+
+
+def test_fused_enhance_project_equals_separate_calls(M):
+    say("test_fused_enhance_project_equals_separate_calls")
+    scene = mgs_data.make_scene_unbounded(30001, 8)
+    cam = mgs_data.circle_poses(8, 10.0, 240, 160, f=240.0)[5]
+    mlp = mgs_data.make_mlp(9)
+    ds = M.DeviceScene(scene)
+    dm = M.DeviceMLP(mlp)
+    a = M.Renderer(ds.n, cam.width, cam.height)
+    b = M.Renderer(ds.n, cam.width, cam.height)
+    ia = a.render(ds, cam, dm, fused=False).clone()
+    ib = b.render(ds, cam, dm, fused=True).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a.splat, b.splat) and torch.equal(a.n_tiles, b.n_tiles)
+    assert torch.equal(a.phi, b.phi) and torch.equal(a.omod, b.omod)
+    assert torch.equal(ia, ib)
+
+
+def test_split_tile_blend_matches_oracle_and_per_tile_blend(M):
+    """Dense tiles (lists far longer than one 1024-Gaussian range) through the split blend."""
+    say("test_split_tile_blend_matches_oracle_and_per_tile_blend")
+    scene = mgs_data.make_scene_uniform(40000, 12, ls_mu=-3.0)
+    cam = mgs_data.look_at((0.1, -0.2, -4.0), width=136, height=120, f=136.0)
+    bg = (0.2, 0.3, 0.4)
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    split_img = R.render(ds, cam, bg=bg, split=True, want_aux=True).double().cpu()
+    offs, _ = R.lists()
+    longest = int((offs[1:] - offs[:-1]).max())
+    say(f"  P={R.pairs()} longest list {longest}")
+    assert longest > 3 * 1024
+    tile_img = R.render(ds, cam, bg=bg, split=False).double().cpu()
+    assert float((split_img - tile_img).abs().max()) < 2e-6
+    pr, camt = oracle_project(scene, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), mode="binned", variants=True)
+    err, nfail = compare_oit_image(split_img, V, flagged, TOL)
+    say(f"  split vs oracle: max {err:.3e} fails {nfail} flagged {flagged}")
+    assert nfail == 0
