@@ -1,20 +1,23 @@
 // mgs_blend_oit (Eq. 2) and mgs_blend_sorted (Eq. 11): per-tile compositing.
 //
-// One 256-thread workgroup per 16x16 tile; wave w owns the 8x8 quadrant
-// (w & 1, w >> 1) and each lane one pixel of it.  The tile's Gaussians are
-// staged through LDS in batches of 256 (one coalesced 48-byte record per
-// thread).  While staging, every thread also decides, for its Gaussian, which
-// quadrants can see it: the largest alpha over a quadrant's pixel-centre
-// rectangle is found exactly (the exponent is a concave quadratic, so its
-// maximum over a rectangle is at the centre or on an edge) and quadrants where
-// it stays below alpha_min are masked out.  Each wave then walks only its own
-// Gaussians (ballot over the masks, scalar bit loop), so a wave never spends
-// VALU cycles on a splat that cannot reach its 64 pixels.
+// One 256-thread workgroup per 16x16 tile (or per range of a long tile list).  The
+// tile's Gaussians are staged through LDS in batches (one coalesced 48-byte record
+// per thread).  While staging, every thread also decides, for its Gaussian, which
+// 8x8 quadrants of the tile can see it: the largest alpha over a quadrant's
+// pixel-centre rectangle is found exactly (the exponent is a concave quadratic, so
+// its maximum over a rectangle is at the centre or on an edge) and quadrants where
+// it stays below alpha_min are masked out, so no VALU cycle is spent on a quadrant
+// that a splat cannot reach.
 //
-// Per pixel-Gaussian pair the OIT inner loop is: 5 FMA for the exponent (a
-// polynomial in the lane's offset, see quad_poly), compare/select, min, exp2,
-// and 5 FMA to accumulate N (rgb, colours pre-multiplied by w), D and T -- all
-// float32 VALU, no sort, no order.
+// Order-independent path: the four waves split the staged Gaussians, each lane
+// holds one pixel in each quadrant, and the waves' sums are merged at the end
+// (blend_tile_oit).  Per pixel-Gaussian pair the inner loop is 5 FMA for the
+// exponent (a polynomial in the pixel's offset, see quad_poly), compare/select,
+// min, exp2 and 5 FMA to accumulate N (rgb, colours pre-multiplied by w), D and T
+// -- all float32 VALU, no sort, no order.
+//
+// Sorted path: wave w owns quadrant w and walks the depth-ordered list front to
+// back with early termination (blend_tile_sorted).
 #include "batch.h"
 #include "blend_math.h"
 
@@ -27,8 +30,13 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
              float log2_amin, float amax, float t_stop, float *__restrict__ image,
              float *__restrict__ aux) {
     const int tile = blockIdx.x;
-    blend_tile<SORTED>(splat, gids, offs[tile], offs[tile + 1], tile % cam.tiles_x, tile / cam.tiles_x, cam.W,
-                       cam.H, bgr, bgg, bgb, log2_amin, amax, t_stop, image, aux);
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    if (SORTED)
+        blend_tile_sorted(splat, gids, offs[tile], offs[tile + 1], tx, ty, cam.W, cam.H, bgr, bgg, bgb, log2_amin,
+                          amax, t_stop, image);
+    else
+        blend_tile_oit(splat, gids, offs[tile], offs[tile + 1], tx, ty, cam.W, cam.H, bgr, bgg, bgb, log2_amin, amax,
+                       image, aux, nullptr);
 }
 
 // ---------------------------------------------------------------- split-tile OIT blend
@@ -140,14 +148,12 @@ blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict_
     const uint32_t start = offs[t], end = offs[t + 1];
     const uint32_t L = end - start, rl = range_len(L, SPLIT_RANGE);
     const TileView v = loc(t);
-    if (n_ranges(L, SPLIT_RANGE) == 1) {
-        blend_tile<false, false>(splat, gids, start, end, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin,
-                                 amax, 0.0f, v.image, v.aux);
-    } else {
-        const uint32_t s = start + r * rl, e = (end - s > rl) ? s + rl : end;
-        blend_tile<false, true>(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin, amax,
-                                0.0f, nullptr, nullptr, part + size_t(item_slot[k]) * PART_FLOATS);
-    }
+    // a tile with one range is composited here; a range of a split tile leaves its sums in part
+    const bool whole = n_ranges(L, SPLIT_RANGE) == 1;
+    const uint32_t s = whole ? start : start + r * rl;
+    const uint32_t e = (whole || end - s <= rl) ? end : s + rl;
+    blend_tile_oit(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin, amax, v.image,
+                   v.aux, whole ? nullptr : part + size_t(item_slot[k]) * PART_FLOATS);
 }
 
 // Merge the ranges of each split tile in range order and composite (Eq. 2).

@@ -55,11 +55,11 @@ __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, int tx, 
 constexpr int BLEND_THREADS = 256;
 constexpr int BLEND_BATCH = 128;
 
-// Exponent of a splat as a polynomial in the lane's offset (x, y) from its
-// quadrant's centre, x, y in {-3.5 .. 3.5}:
+// Exponent of a splat as a polynomial in a pixel's offset (x, y) from a centre (xc, yc)
+// (a quadrant's or a tile's):
 //   log2(alpha) = c0 + cx x + cy y + cxx x^2 + cxy x y + cyy y^2
 // (the same quadratic form as log2(o) + kA t^2 + kG dy^2, re-centred once per
-// staged splat and quadrant so the per-pixel work is five FMAs).
+// staged splat so the per-pixel work is five FMAs).
 __device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float yc, float4 &qa, float4 &qb) {
     const float kA = r1.x, beta = r1.y, kG = r1.z;
     const float u0 = xc - r0.x, v0 = yc - r0.y;
@@ -72,8 +72,6 @@ __device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float 
     qb.y = fmaf(kA * beta, beta, kG);
 }
 
-// Composite one 16x16 tile (tile coordinates tx, ty) from its list gids[start, end)
-// into image / aux of a W x H view.  Called by a whole 256-thread workgroup.
 // Eq. 2 composite of one pixel from its sums: C = (1 - T) N / D + T c_bg (c_bg if D = 0);
 // aux (if non-NULL) receives (N/D rgb, D, T).
 __device__ __forceinline__ void composite_oit(float Nr, float Ng, float Nb, float D, float T, int px, int py, int W,
@@ -113,19 +111,16 @@ __device__ __forceinline__ void tile_pixel(int k, int tx, int ty, int &px, int &
     py = ty * 16 + (w >> 1) * 8 + (l >> 3);
 }
 
-// Composite one 16x16 tile (tile coordinates tx, ty) from the list range gids[start, end)
-// into image / aux of a W x H view.  Called by a whole 256-thread workgroup.  With
-// PARTIAL (order-independent path only) the per-pixel sums (N rgb, D, T) of this range
-// go to part[5][256] instead, to be merged with the tile's other ranges.
-template <bool SORTED, bool PARTIAL = false>
-__device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
-                                           uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
-                                           float bgg, float bgb, float log2_amin, float amax, float t_stop,
-                                           float *__restrict__ image, float *__restrict__ aux,
-                                           float *__restrict__ part = nullptr) {
+// Front-to-back composite (Eq. 11) of one 16x16 tile (tile coordinates tx, ty) from its
+// depth-sorted list gids[start, end) into image of a W x H view.  Called by a whole
+// 256-thread workgroup: wave w owns quadrant (w & 1, w >> 1), lane l one pixel of it, and
+// the wave stops once every one of its pixels has transmittance below t_stop.
+__device__ __forceinline__ void blend_tile_sorted(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
+                                                  uint32_t start, uint32_t end, int tx, int ty, int W, int H,
+                                                  float bgr, float bgg, float bgb, float log2_amin, float amax,
+                                                  float t_stop, float *__restrict__ image) {
     // per quadrant and staged splat: polynomial (c0, cx, cy, cxx), (cxy, cyy, -, -) and the colour
-    // (OIT: (w r, w g, w b, w); sorted: (r, g, b, 0)), one 48-byte record so a wave reads all three
-    // with one address register
+    // (r, g, b, -), one 48-byte record so a wave reads all three with one address register
     __shared__ float4 s_rec[4][BLEND_BATCH][3];
     __shared__ uint32_t s_mask[BLEND_BATCH];
     __shared__ int s_done[4];
@@ -138,7 +133,7 @@ __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, con
     const float lx = float(l & 7) - 3.5f, ly = float(l >> 3) - 3.5f;
     const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
 
-    float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
+    float Nr = 0.f, Ng = 0.f, Nb = 0.f, T = 1.f;
     bool wave_done = false;
 
     for (uint32_t b = start; b < end; b += BLEND_BATCH) {
@@ -152,8 +147,7 @@ __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, con
                 const float4 r1 = splat[3 * size_t(g) + 1];
                 const float4 r2 = splat[3 * size_t(g) + 2];
                 mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
-                const float4 col = SORTED ? make_float4(r2.x, r2.y, r2.z, 0.f)
-                                          : make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
+                const float4 col = make_float4(r2.x, r2.y, r2.z, 0.f);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if ((mask >> q) & 1u) {
@@ -169,10 +163,10 @@ __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, con
             }
             s_mask[threadIdx.x] = mask;
         }
-        if (SORTED && l == 0) s_done[w] = wave_done ? 1 : 0;
+        if (l == 0) s_done[w] = wave_done ? 1 : 0;
         __syncthreads();
-        if (SORTED && s_done[0] && s_done[1] && s_done[2] && s_done[3]) break;
-        if (SORTED && wave_done) continue;
+        if (s_done[0] && s_done[1] && s_done[2] && s_done[3]) break;
+        if (wave_done) continue;
         const int wu = __builtin_amdgcn_readfirstlane(w);       // wave-uniform quadrant index
         const float4(*rec_w)[3] = s_rec[wu];
         for (int grp = 0; grp < BLEND_BATCH / 64; ++grp) {
@@ -188,44 +182,157 @@ __device__ __forceinline__ void blend_tile(const float4 *__restrict__ splat, con
                 e = fmaf(qa.w, lxx, e);
                 e = fmaf(qb.x, lxy, e);
                 e = fmaf(qb.y, lyy, e);
-                if (!SORTED) {
-                    const float al = e >= log2_amin ? fminf(fast_exp2(e), amax) : 0.0f;
-                    Nr = fmaf(al, cw.x, Nr);
-                    Ng = fmaf(al, cw.y, Ng);
-                    Nb = fmaf(al, cw.z, Nb);
-                    D = fmaf(al, cw.w, D);
-                    T = fmaf(-T, al, T);
-                } else {
-                    const float al = (e >= log2_amin && T >= t_stop) ? fminf(fast_exp2(e), amax) : 0.0f;
-                    const float at = al * T;
-                    Nr = fmaf(at, cw.x, Nr);
-                    Ng = fmaf(at, cw.y, Ng);
-                    Nb = fmaf(at, cw.z, Nb);
-                    T = fmaf(-T, al, T);
-                }
+                const float al = (e >= log2_amin && T >= t_stop) ? fminf(fast_exp2(e), amax) : 0.0f;
+                const float at = al * T;
+                Nr = fmaf(at, cw.x, Nr);
+                Ng = fmaf(at, cw.y, Ng);
+                Nb = fmaf(at, cw.z, Nb);
+                T = fmaf(-T, al, T);
             }
-            if (SORTED) {
-                wave_done = __ballot(T >= t_stop) == 0ull;
-                if (wave_done) break;
-            }
+            wave_done = __ballot(T >= t_stop) == 0ull;
+            if (wave_done) break;
         }
     }
 
-    if (PARTIAL) {
-        const int k = threadIdx.x;
-        part[k] = Nr;
-        part[256 + k] = Ng;
-        part[512 + k] = Nb;
-        part[768 + k] = D;
-        part[1024 + k] = T;
-    } else if (!SORTED) {
-        composite_oit(Nr, Ng, Nb, D, T, px, py, W, H, bgr, bgg, bgb, image, aux);
-    } else if (px < W && py < H) {
+    if (px < W && py < H) {
         const size_t hw = size_t(W) * H;
         const size_t p = size_t(py) * W + px;
         image[p] = fmaf(T, bgr, Nr);
         image[hw + p] = fmaf(T, bgg, Ng);
         image[2 * hw + p] = fmaf(T, bgb, Nb);
+    }
+}
+
+// Order-independent composite (Eq. 2) of one 16x16 tile (tile coordinates tx, ty) from
+// the list range gids[start, end).  Called by a whole 256-thread workgroup.
+//
+// The four waves share the range: wave w takes every fourth staged Gaussian (4k + w), and
+// each lane holds four pixels, one per 8x8 quadrant (pixel (l & 7, l >> 3) of each).  A
+// staged Gaussian is read from LDS once per wave and evaluated only on the quadrants its
+// exact quadrant test keeps, so a 40-byte broadcast read feeds up to four pixel updates.
+// The exponent is a polynomial in the pixel's offset from the tile centre (quad_poly about
+// (16 tx + 8, 16 ty + 8)); offsets are within +-7.5 px.  At the end the waves' sums are
+// merged through LDS in wave order (N and D add, T multiplies), which is exact up to
+// rounding because the composite does not depend on the order of the Gaussians.
+//
+// The result goes to thread k's pixel tile_pixel(k) (quadrant k / 64, lane k % 64): the
+// composite into image / aux of a W x H view, or, if part is non-NULL, the sums
+// (N rgb, D, T) to part[5][256] for a later merge with the tile's other ranges.
+constexpr int OIT_BATCH = 256;                  // Gaussians staged per pass, one per thread
+
+__device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
+                                               uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
+                                               float bgg, float bgb, float log2_amin, float amax,
+                                               float *__restrict__ image, float *__restrict__ aux,
+                                               float *__restrict__ part) {
+    // staged Gaussian j: (c0, cx, cy, cxx), (cxy, cyy, -, -), (w r, w g, w b, w) at s_buf[3 j ..];
+    // after the last batch the same memory holds the waves' sums for the merge
+    __shared__ float4 s_buf[4 * 4 * 5 * 64 / 4];
+    __shared__ uint32_t s_mask[OIT_BATCH];
+
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    // the lane's pixel offsets from the tile centre: x in the left / right quadrants, y in the
+    // top / bottom ones, and the products the polynomial needs
+    const float xl = float(l & 7) - 7.5f, xr = xl + 8.0f;
+    const float yt = float(l >> 3) - 7.5f, yb = yt + 8.0f;
+    const float xxl = xl * xl, xxr = xr * xr, yyt = yt * yt, yyb = yb * yb;
+    const float xy0 = xl * yt, xy1 = xr * yt, xy2 = xl * yb, xy3 = xr * yb;
+    const float tcx = float(tx * 16) + 8.0f, tcy = float(ty * 16) + 8.0f;
+
+    // per quadrant q: N rgb, D, T
+    float acc[4][5];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+        acc[q][4] = 1.f;
+    }
+
+    for (uint32_t b = start; b < end; b += OIT_BATCH) {
+        __syncthreads();
+        {
+            const uint32_t i = b + threadIdx.x;
+            uint32_t mask = 0;
+            if (i < end) {
+                const uint32_t g = gids[i];
+                const float4 r0 = splat[3 * size_t(g) + 0];
+                const float4 r1 = splat[3 * size_t(g) + 1];
+                const float4 r2 = splat[3 * size_t(g) + 2];
+                mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
+                if (mask) {
+                    float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
+                    quad_poly(r0, r1, tcx, tcy, qa, qb);
+                    s_buf[3 * threadIdx.x + 0] = qa;
+                    s_buf[3 * threadIdx.x + 1] = qb;
+                    s_buf[3 * threadIdx.x + 2] = make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
+                }
+            }
+            s_mask[threadIdx.x] = mask;
+        }
+        __syncthreads();
+        // wave w: staged Gaussians 4 k + w, k = 0 .. 63, in order; bit k of bq <=> quadrant q kept
+        const uint32_t mk = s_mask[4 * l + w];
+        const uint64_t b0 = __ballot(mk & 1u), b1 = __ballot(mk & 2u), b2 = __ballot(mk & 4u), b3 = __ballot(mk & 8u);
+        uint64_t any = b0 | b1 | b2 | b3;
+        const int wu = __builtin_amdgcn_readfirstlane(w);
+        while (any) {
+            const int k = __builtin_ctzll(any);
+            any &= any - 1;
+            const float4 *rec = s_buf + 3 * (4 * k + wu);
+            const float4 qa = rec[0];
+            const float4 qb = rec[1];
+            const float4 cw = rec[2];
+#define MGS_OIT_QUAD(q, X, Y, XX, XY, YY)                                           \
+            if ((b##q >> k) & 1ull) {                                               \
+                float e = fmaf(qa.y, X, qa.x);                                      \
+                e = fmaf(qa.z, Y, e);                                               \
+                e = fmaf(qa.w, XX, e);                                              \
+                e = fmaf(qb.x, XY, e);                                              \
+                e = fmaf(qb.y, YY, e);                                              \
+                const float al = e >= log2_amin ? fminf(fast_exp2(e), amax) : 0.0f; \
+                acc[q][0] = fmaf(al, cw.x, acc[q][0]);                              \
+                acc[q][1] = fmaf(al, cw.y, acc[q][1]);                              \
+                acc[q][2] = fmaf(al, cw.z, acc[q][2]);                              \
+                acc[q][3] = fmaf(al, cw.w, acc[q][3]);                              \
+                acc[q][4] = fmaf(-acc[q][4], al, acc[q][4]);                        \
+            }
+            MGS_OIT_QUAD(0, xl, yt, xxl, xy0, yyt)
+            MGS_OIT_QUAD(1, xr, yt, xxr, xy1, yyt)
+            MGS_OIT_QUAD(2, xl, yb, xxl, xy2, yyb)
+            MGS_OIT_QUAD(3, xr, yb, xxr, xy3, yyb)
+#undef MGS_OIT_QUAD
+        }
+    }
+
+    // merge the four waves' sums: s_sum[(w * 4 + q) * 5 + v][l]
+    float *s_sum = reinterpret_cast<float *>(s_buf);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) s_sum[((w * 4 + q) * 5 + v) * 64 + l] = acc[q][v];
+    __syncthreads();
+    // thread (w, l) now takes pixel l of quadrant w
+    float S[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) S[v] = s_sum[((0 * 4 + w) * 5 + v) * 64 + l];
+#pragma unroll
+    for (int src = 1; src < 4; ++src) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[v] += s_sum[((src * 4 + w) * 5 + v) * 64 + l];
+        S[4] *= s_sum[((src * 4 + w) * 5 + 4) * 64 + l];
+    }
+    if (part) {
+        const int k = threadIdx.x;
+        part[k] = S[0];
+        part[256 + k] = S[1];
+        part[512 + k] = S[2];
+        part[768 + k] = S[3];
+        part[1024 + k] = S[4];
+    } else {
+        int px, py;
+        tile_pixel(threadIdx.x, tx, ty, px, py);
+        composite_oit(S[0], S[1], S[2], S[3], S[4], px, py, W, H, bgr, bgg, bgb, image, aux);
     }
 }
 
