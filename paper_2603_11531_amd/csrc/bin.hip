@@ -177,10 +177,6 @@ struct TileDepthKey {
     }
 };
 
-// One block per 256 Gaussians.  The block's first pair slot comes from the scanned
-// per-block counts; inside the block a wave/LDS scan gives every Gaussian its slot.
-// Gaussians with at most EXPAND_SMALL tiles are written by their own lane (row by
-// row over the rectangle); larger ones are written by the whole wave.
 // Global tile id of tile (tx, ty) of Gaussian g's view: a single view, or a batch of views.
 struct GridMap {
     uint32_t tiles_x;
@@ -195,6 +191,10 @@ struct BatchMap {
     }
 };
 
+// One block per 256 Gaussians.  The block's first pair slot comes from the scanned
+// per-block counts; inside the block a wave/LDS scan gives every Gaussian its slot.
+// Gaussians with at most EXPAND_SMALL tiles are written by their own lane (row by
+// row over the rectangle); larger ones are written by the whole wave.
 template <typename K, typename KeyFn, typename Map>
 __global__ void __launch_bounds__(256)
 expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
@@ -278,21 +278,28 @@ radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_
     const int w = threadIdx.x / 64;
     const unsigned l = lane_id();
     for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
+        // all of the wave's loads are issued before the first digit is matched
+        const int64_t base = int64_t(blk) * RADIX_TILE + w * (RADIX_ITERS * 64);
+        uint32_t d[RADIX_ITERS];
+#pragma unroll
+        for (int it = 0; it < RADIX_ITERS; ++it) {
+            const int64_t idx = base + it * 64 + l;
+            d[it] = idx < int64_t(P) ? digit_of(keys[idx], shift, mask) : 0u;
+        }
         for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
         __syncthreads();
-        const int64_t base = int64_t(blk) * RADIX_TILE + w * (RADIX_ITERS * 64);
+#pragma unroll
         for (int it = 0; it < RADIX_ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
             const uint64_t active = __ballot(ok);
             if (active == 0) break;
-            const uint32_t d = ok ? digit_of(keys[idx], shift, mask) : 0u;
-            const uint64_t peers = match_digit(d, bits, active);
-            if (ok && (peers >> l) == 1ull) cnt[w][d] += uint32_t(__popcll(peers));  // highest lane of its digit
+            const uint64_t peers = match_digit(d[it], bits, active);
+            if (ok && (peers >> l) == 1ull) cnt[w][d[it]] += uint32_t(__popcll(peers));  // highest lane of its digit
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < nd; d += RADIX_THREADS)
-            counts[int64_t(d) * nblocks + blk] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+        for (int d2 = threadIdx.x; d2 < nd; d2 += RADIX_THREADS)
+            counts[int64_t(d2) * nblocks + blk] = cnt[0][d2] + cnt[1][d2] + cnt[2][d2] + cnt[3][d2];
         __syncthreads();
     }
 }
@@ -357,19 +364,26 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
     const uint32_t dex = block_excl_scan256<uint32_t>(dt, s_wsum);          // contains __syncthreads
     for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
         const int64_t blk0 = int64_t(blk) * RADIX_TILE;
-        for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
-        if (t < nd) s_gstart[t] = dex + colscan[int64_t(t) * nblocks + blk];
-        __syncthreads();
         const int64_t base = blk0 + w * (RADIX_ITERS * 64);
+        // all of the wave's loads are issued before the first digit is matched
         K key[RADIX_ITERS];
         uint32_t val[RADIX_ITERS], rank[RADIX_ITERS], dig[RADIX_ITERS];
 #pragma unroll
         for (int it = 0; it < RADIX_ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
-            const uint64_t active = __ballot(ok);
             key[it] = ok ? keys_in[idx] : K(0);
             val[it] = ok ? vals_in[idx] : 0u;
+        }
+        const uint32_t gcol = t < nd ? colscan[int64_t(t) * nblocks + blk] : 0u;
+        for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
+        if (t < nd) s_gstart[t] = dex + gcol;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < RADIX_ITERS; ++it) {
+            const int64_t idx = base + it * 64 + l;
+            const bool ok = idx < int64_t(P);
+            const uint64_t active = __ballot(ok);
             const uint32_t d = ok ? digit_of(key[it], shift, mask) : 0u;
             dig[it] = d;
             rank[it] = 0;

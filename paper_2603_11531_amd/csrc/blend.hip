@@ -89,6 +89,8 @@ __device__ __forceinline__ uint64_t block_excl_scan1024(uint64_t v, uint64_t *s_
 // One block of 1024 threads: every tile gets n_ranges(L) items (item = tile | range << 24);
 // ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
 // tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
+// Thread k takes a contiguous run of tiles: it totals them, one block scan gives its
+// first item / slot / split index, and a second walk over the run writes them.
 __global__ void __launch_bounds__(1024)
 split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
@@ -98,17 +100,27 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
     uint32_t T = t_count ? *t_count : t_host;
     if (T > t_host) T = t_host;
     if (uint64_t(*n_pairs) > capacity) T = 0;             // lists were not built: render nothing
+    const uint32_t per = (T + 1023) / 1024;
+    const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
     uint32_t c_items = 0, c_slots = 0, c_split = 0;
-    for (uint32_t base = 0; base < T; base += 1024) {
-        const uint32_t t = base + threadIdx.x;
-        uint32_t nr = 0, m = 0;
-        if (t < T) {
-            nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
-            m = nr > 1 ? 1u : 0u;
-        }
-        const uint64_t e1 = block_excl_scan1024(uint64_t(nr) | (uint64_t(nr * m) << 32), s_wsum);
-        const uint64_t e2 = block_excl_scan1024(uint64_t(m), s_wsum);
-        const uint32_t i0 = c_items + uint32_t(e1), s0 = c_slots + uint32_t(e1 >> 32), j = c_split + uint32_t(e2);
+    uint32_t lo = t0 < t1 ? offs[t0] : 0u;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t hi = offs[t + 1];
+        const uint32_t nr = n_ranges(hi - lo, SPLIT_RANGE);
+        const uint32_t m = nr > 1 ? 1u : 0u;
+        c_items += nr;
+        c_slots += nr * m;
+        c_split += m;
+        lo = hi;
+    }
+    const uint64_t e1 = block_excl_scan1024(uint64_t(c_items) | (uint64_t(c_slots) << 32), s_wsum);
+    const uint64_t e2 = block_excl_scan1024(uint64_t(c_split), s_wsum);
+    uint32_t i0 = uint32_t(e1), s0 = uint32_t(e1 >> 32), j = uint32_t(e2);
+    lo = t0 < t1 ? offs[t0] : 0u;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t hi = offs[t + 1];
+        const uint32_t nr = n_ranges(hi - lo, SPLIT_RANGE);
+        const bool m = nr > 1;
         for (uint32_t r = 0; r < nr; ++r) {
             items[i0 + r] = t | (r << 24);
             item_slot[i0 + r] = m ? s0 + r : 0xFFFFFFFFu;
@@ -116,23 +128,15 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         if (m) {
             split_tile[j] = t;
             split_slot0[j] = s0;
+            s0 += nr;
+            ++j;
         }
-        // block totals: the last thread's exclusive prefix plus its own values
-        __shared__ uint32_t s_tot[3];
-        if (threadIdx.x == 1023) {
-            s_tot[0] = uint32_t(e1) + nr;
-            s_tot[1] = uint32_t(e1 >> 32) + nr * m;
-            s_tot[2] = uint32_t(e2) + m;
-        }
-        __syncthreads();
-        c_items += s_tot[0];
-        c_slots += s_tot[1];
-        c_split += s_tot[2];
-        __syncthreads();
+        i0 += nr;
+        lo = hi;
     }
-    if (threadIdx.x == 0) {
-        counts[0] = c_items;
-        counts[1] = c_split;
+    if (threadIdx.x == 1023) {
+        counts[0] = i0;
+        counts[1] = j;
     }
 }
 

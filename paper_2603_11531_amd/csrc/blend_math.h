@@ -203,6 +203,11 @@ __device__ __forceinline__ void blend_tile_sorted(const float4 *__restrict__ spl
     }
 }
 
+// Staged-Gaussian flag of the order-independent blend (bits 0-3 are the quadrant mask): the
+// Gaussian's peak log2(o) is within OIT_CLAMP_MARGIN of log2(alpha_max), so the clamp may bind.
+constexpr uint32_t OIT_CLAMP = 1u << 8;
+constexpr float OIT_CLAMP_MARGIN = 1e-2f;
+
 // Order-independent composite (Eq. 2) of one 16x16 tile (tile coordinates tx, ty) from
 // the list range gids[start, end).  Called by a whole 256-thread workgroup.
 //
@@ -248,60 +253,71 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
         acc[q][4] = 1.f;
     }
 
+    // log2(o) above this: the alpha_max clamp can bind somewhere in the tile (the margin is
+    // far above the float32 error of the exponent polynomial)
+    const float log2_amax_safe = __log2f(amax) - OIT_CLAMP_MARGIN;
     for (uint32_t b = start; b < end; b += OIT_BATCH) {
         __syncthreads();
         {
             const uint32_t i = b + threadIdx.x;
-            uint32_t mask = 0;
+            uint32_t flags = 0;
             if (i < end) {
                 const uint32_t g = gids[i];
                 const float4 r0 = splat[3 * size_t(g) + 0];
                 const float4 r1 = splat[3 * size_t(g) + 1];
                 const float4 r2 = splat[3 * size_t(g) + 2];
-                mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
-                if (mask) {
+                flags = quadrant_mask(r0, r1, tx, ty, log2_amin);
+                if (flags) {
                     float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
                     quad_poly(r0, r1, tcx, tcy, qa, qb);
                     s_buf[3 * threadIdx.x + 0] = qa;
                     s_buf[3 * threadIdx.x + 1] = qb;
                     s_buf[3 * threadIdx.x + 2] = make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
+                    if (r0.z > log2_amax_safe) flags |= OIT_CLAMP;
                 }
             }
-            s_mask[threadIdx.x] = mask;
+            s_mask[threadIdx.x] = flags;
         }
         __syncthreads();
-        // wave w: staged Gaussians 4 k + w, k = 0 .. 63, in order; bit k of bq <=> quadrant q kept
+        // wave w: staged Gaussians 4 k + w, k = 0 .. 63, in order; those whose alpha can reach
+        // alpha_max are taken in a second loop, the only one that needs the clamp
         const uint32_t mk = s_mask[4 * l + w];
-        const uint64_t b0 = __ballot(mk & 1u), b1 = __ballot(mk & 2u), b2 = __ballot(mk & 4u), b3 = __ballot(mk & 8u);
-        uint64_t any = b0 | b1 | b2 | b3;
+        const uint64_t clamp = __ballot((mk & OIT_CLAMP) != 0u);
+        uint64_t any = __ballot(mk != 0u) & ~clamp;
         const int wu = __builtin_amdgcn_readfirstlane(w);
-        while (any) {
-            const int k = __builtin_ctzll(any);
-            any &= any - 1;
-            const float4 *rec = s_buf + 3 * (4 * k + wu);
-            const float4 qa = rec[0];
-            const float4 qb = rec[1];
-            const float4 cw = rec[2];
-#define MGS_OIT_QUAD(q, X, Y, XX, XY, YY)                                           \
-            if ((b##q >> k) & 1ull) {                                               \
+#define MGS_OIT_QUAD(q, X, Y, XX, XY, YY, ALPHA)                                    \
+            if (fk & (1u << q)) {                                                   \
                 float e = fmaf(qa.y, X, qa.x);                                      \
                 e = fmaf(qa.z, Y, e);                                               \
                 e = fmaf(qa.w, XX, e);                                              \
                 e = fmaf(qb.x, XY, e);                                              \
                 e = fmaf(qb.y, YY, e);                                              \
-                const float al = e >= log2_amin ? fminf(fast_exp2(e), amax) : 0.0f; \
+                const float al = e >= log2_amin ? ALPHA : 0.0f;                     \
                 acc[q][0] = fmaf(al, cw.x, acc[q][0]);                              \
                 acc[q][1] = fmaf(al, cw.y, acc[q][1]);                              \
                 acc[q][2] = fmaf(al, cw.z, acc[q][2]);                              \
                 acc[q][3] = fmaf(al, cw.w, acc[q][3]);                              \
                 acc[q][4] = fmaf(-acc[q][4], al, acc[q][4]);                        \
             }
-            MGS_OIT_QUAD(0, xl, yt, xxl, xy0, yyt)
-            MGS_OIT_QUAD(1, xr, yt, xxr, xy1, yyt)
-            MGS_OIT_QUAD(2, xl, yb, xxl, xy2, yyb)
-            MGS_OIT_QUAD(3, xr, yb, xxr, xy3, yyb)
-#undef MGS_OIT_QUAD
+#define MGS_OIT_LOOP(ALPHA)                                                         \
+        while (any) {                                                               \
+            const int k = __builtin_ctzll(any);                                     \
+            any &= any - 1;                                                         \
+            const uint32_t fk = __builtin_amdgcn_readlane(mk, k);                   \
+            const float4 *rec = s_buf + 3 * (4 * k + wu);                           \
+            const float4 qa = rec[0];                                               \
+            const float4 qb = rec[1];                                               \
+            const float4 cw = rec[2];                                               \
+            MGS_OIT_QUAD(0, xl, yt, xxl, xy0, yyt, ALPHA)                           \
+            MGS_OIT_QUAD(1, xr, yt, xxr, xy1, yyt, ALPHA)                           \
+            MGS_OIT_QUAD(2, xl, yb, xxl, xy2, yyb, ALPHA)                           \
+            MGS_OIT_QUAD(3, xr, yb, xxr, xy3, yyb, ALPHA)                           \
         }
+        MGS_OIT_LOOP(fast_exp2(e))
+        any = clamp;
+        MGS_OIT_LOOP(fminf(fast_exp2(e), amax))
+#undef MGS_OIT_LOOP
+#undef MGS_OIT_QUAD
     }
 
     // merge the four waves' sums: s_sum[(w * 4 + q) * 5 + v][l]

@@ -43,7 +43,8 @@ class Request:
     arrival: float         # seconds on the server clock
     bg: tuple = (0.0, 0.0, 0.0)
     image: torch.Tensor = None
-    done: float = None
+    start: float = None    # GPU start of the batch (or frame) that rendered it
+    done: float = None     # image ready
     path: str = ""
 
 
@@ -80,6 +81,7 @@ class BatchSlot:
         self.n_pairs = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.status = torch.zeros(2, dtype=torch.int32, device=self.device)
         self.stream = torch.cuda.Stream(device=self.device)
+        self.start_event = torch.cuda.Event(enable_timing=True)
         self.done_event = torch.cuda.Event(enable_timing=True)
         self.requests = []
         self.graph = None
@@ -114,6 +116,7 @@ class BatchSlot:
         self.requests = list(reqs)
         self.write_table(reqs, registry)
         with torch.cuda.stream(self.stream):
+            self.start_event.record(self.stream)
             if self.use_graphs:
                 if self.graph is None:
                     self._enqueue()                      # warm-up outside capture
@@ -219,15 +222,17 @@ class Server:
                     busy.remove(slot)
                     free.append(slot)
                     progressed = True
+                    t_start = ref.elapsed_time(slot.start_event) * 1e-3
                     t_done = ref.elapsed_time(slot.done_event) * 1e-3
                     if slot.overflowed():
                         for r in slot.requests:
+                            r.start = time.perf_counter() - t0
                             self._render_alone(r)
                             r.done = time.perf_counter() - t0
                             r.path = "single-view retry"
                     else:
                         for r in slot.requests:
-                            r.done = t_done
+                            r.start, r.done = t_start, t_done
                             r.path = "batch"
                     for r in slot.requests:
                         self.image_bytes_in_use -= 12 * r.cam.width * r.cam.height
@@ -279,11 +284,14 @@ def run_plain_loop(registry, requests, device="cuda"):
         if key not in renderers:
             renderers[key] = Renderer(ds.n, r.cam.width, r.cam.height, device=device)
         R = renderers[key]
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
         img = R.render(ds, r.cam, dm, bg=r.bg)      # one host sync per frame (pair count check)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         r.image = img.clone()
         ev.synchronize()
+        r.start = ref.elapsed_time(ev0) * 1e-3
         r.done = ref.elapsed_time(ev) * 1e-3
         r.path = "plain"
         served.append(r)
@@ -292,14 +300,18 @@ def run_plain_loop(registry, requests, device="cuda"):
 
 
 def latency_stats(served, t_span=None):
+    """Latency = arrival -> image ready (queueing included); service = the GPU start of the
+    request's batch (or frame) -> image ready (queueing excluded)."""
     lat = np.array([r.done - r.arrival for r in served]) * 1e3
     if len(lat) == 0:
         return {}
+    svc = np.array([r.done - r.start for r in served]) * 1e3
     end = max(r.done for r in served)
     start = min(r.arrival for r in served)
     span = t_span if t_span is not None else max(end - start, 1e-9)
     return {"requests": len(served), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "service_p50_ms": float(np.percentile(svc, 50)), "service_p99_ms": float(np.percentile(svc, 99)),
             "frames_per_s": len(served) / span,
             "mpix_per_s": sum(r.cam.width * r.cam.height for r in served) / span / 1e6}
 
