@@ -10,15 +10,20 @@ constexpr int BATCH_MAX_REQ = 64;
 // Written once per batch on the device.  Gaussians of request r occupy the global
 // index range [gbase[r], gbase[r] + n_r), each range starting on a multiple of 64 so a
 // wave-sized MLP group never mixes requests; tiles of request r are the global tile
-// ids [tbase[r], tbase[r + 1]).
+// ids [tbase[r], tbase[r + 1]) and its 8x8-tile supertiles (binning) the global ids
+// [stbase[r], stbase[r + 1]).
 struct BatchPlan {
     int32_t nreq;
     int32_t ok;            // 1 = the batch fits the workspace limits; 0 = nothing is rendered
     uint32_t n_total;      // end of the last request's (padded) Gaussian range
     uint32_t t_total;      // number of global tiles
+    uint32_t st_total;     // number of global supertiles
     uint32_t gbase[BATCH_MAX_REQ + 1];
     uint32_t tbase[BATCH_MAX_REQ + 1];
+    uint32_t stbase[BATCH_MAX_REQ + 1];
     uint32_t tiles_x[BATCH_MAX_REQ];
+    uint32_t tiles_y[BATCH_MAX_REQ];
+    uint32_t st_x[BATCH_MAX_REQ];
 };
 
 // Index r of the request whose range [base[r], base[r+1]) holds v (base[0] = 0, nreq >= 1).

@@ -23,27 +23,34 @@ __global__ void batch_plan_kernel(const mgs_request *__restrict__ reqs, const in
     int nr = *n_req;
     int ok = (nr >= 0 && nr <= BATCH_MAX_REQ) ? 1 : 0;
     if (!ok) nr = 0;
-    uint64_t g = 0, t = 0;
+    uint64_t g = 0, t = 0, st = 0;
     for (int r = 0; r < nr; ++r) {
         const mgs_request &q = reqs[r];
         const int tx = (q.cam.width + MGS_TILE - 1) / MGS_TILE, ty = (q.cam.height + MGS_TILE - 1) / MGS_TILE;
         if (q.g.n < 0 || q.cam.width <= 0 || q.cam.height <= 0 || q.cam.fx <= 0.f || q.cam.fy <= 0.f ||
             q.image == nullptr)
             ok = 0;
+        const uint32_t txu = uint32_t(tx > 0 ? tx : 1), tyu = uint32_t(ty > 0 ? ty : 1);
         plan->gbase[r] = uint32_t(g);
         plan->tbase[r] = uint32_t(t);
-        plan->tiles_x[r] = uint32_t(tx > 0 ? tx : 1);
+        plan->stbase[r] = uint32_t(st);
+        plan->tiles_x[r] = txu;
+        plan->tiles_y[r] = tyu;
+        plan->st_x[r] = (txu + 7) / 8;
         g += (uint64_t(q.g.n > 0 ? q.g.n : 0) + 63) / 64 * 64;
         t += uint64_t(tx > 0 ? tx : 0) * uint64_t(ty > 0 ? ty : 0);
+        st += uint64_t((txu + 7) / 8) * uint64_t((tyu + 7) / 8);
     }
     if (g > max_gauss || t > max_tiles) ok = 0;
-    if (!ok) { nr = 0; g = 0; t = 0; }
+    if (!ok) { nr = 0; g = 0; t = 0; st = 0; }
     plan->gbase[nr] = uint32_t(g);
     plan->tbase[nr] = uint32_t(t);
+    plan->stbase[nr] = uint32_t(st);
     plan->nreq = nr;
     plan->ok = ok;
     plan->n_total = uint32_t(g);
     plan->t_total = uint32_t(t);
+    plan->st_total = uint32_t(st);
 }
 
 // Enhancement MLP over all requests that carry one; one wave per 64-Gaussian group.

@@ -1,18 +1,19 @@
 // mgs_bin / mgs_bin_sorted: tile binning by prefix sums, with no atomics.
 //
+// Sorted comparison path (mgs_bin_sorted), the usual depth sort:
 //   1. exclusive scan of n_tiles            -> first pair slot of every Gaussian, P
-//   2. expand: each wave flattens the pairs of 64 consecutive Gaussians and
-//      writes (key, gid) for every covered tile with coalesced stores
-//   3. stable LSD radix sort on the key (digit histograms per block, a scan of
+//   2. expand: every Gaussian writes (tile << 32 | depth bits, gid) for each tile of
+//      its rectangle
+//   3. stable LSD radix sort on the 64-bit key (digit histograms per block, a scan of
 //      the digit-major histogram, stable scatter); ranks inside a wave come from
 //      ballot-matched digits, so nothing is ordered by atomics and the output is
 //      bit-identical from run to run
 //   4. tile ranges from the sorted keys
 //
-// For the order-independent path the key is the tile id alone (about 13 bits:
-// two radix passes), so each list stays in ascending Gaussian order.  The
-// sorted comparison path uses the 64-bit key (tile << 32 | depth bits), i.e.
-// the usual depth sort, which needs 32 + tile bits of radix passes.
+// Order-independent path (mgs_bin, and the batched render): no depth key and no sort
+// of the pairs.  The lists (ascending Gaussian index per tile) are built in two levels,
+// over 8x8-tile supertiles and then over the tiles of each supertile (see the comment
+// above super_count_kernel).
 #include "batch.h"
 
 namespace mgs {
@@ -29,7 +30,19 @@ constexpr int RADIX_MAX_BITS = 8;
 constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
 constexpr int RADIX_MAX_GRID = 2048;                      // resident blocks striding over the used ones
 
+constexpr int SUPER_SHIFT = 3;                            // supertile = 8 x 8 tiles (two-level binning)
+constexpr int SUPER = 1 << SUPER_SHIFT;
+constexpr int SUPER_TILES = SUPER * SUPER;
+constexpr int CHUNK = 256;                                // supertile entries per level-2 block
+constexpr int SUPER_MAX_GRID = 8192;                      // resident blocks striding over the level-2 chunks
+
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Supertiles of a rectangle of tiles (inclusive bounds packed as in mgs_projected.rect).
+__device__ __forceinline__ uint32_t n_super(uint2 r) {
+    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+    return ((x1 >> SUPER_SHIFT) - (x0 >> SUPER_SHIFT) + 1) * ((y1 >> SUPER_SHIFT) - (y0 >> SUPER_SHIFT) + 1);
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned l = lane_id();
@@ -177,25 +190,17 @@ struct TileDepthKey {
     }
 };
 
-// Global tile id of tile (tx, ty) of Gaussian g's view: a single view, or a batch of views.
+// Global tile id of tile (tx, ty) of Gaussian g's view (the expand kernel's Map interface).
 struct GridMap {
     uint32_t tiles_x;
     __device__ __forceinline__ uint32_t base(int64_t, uint32_t &tx) const { tx = tiles_x; return 0u; }
-};
-struct BatchMap {
-    const BatchPlan *plan;
-    __device__ __forceinline__ uint32_t base(int64_t g, uint32_t &tx) const {
-        const int r = find_request(plan->gbase, plan->nreq, uint32_t(g));
-        tx = plan->tiles_x[r];
-        return plan->tbase[r];
-    }
 };
 
 // One block per 256 Gaussians.  The block's first pair slot comes from the scanned
 // per-block counts; inside the block a wave/LDS scan gives every Gaussian its slot.
 // Gaussians with at most EXPAND_SMALL tiles are written by their own lane (row by
 // row over the rectangle); larger ones are written by the whole wave.
-template <typename K, typename KeyFn, typename Map>
+template <typename K, typename KeyFn, typename Map, int SHIFT = 0>
 __global__ void __launch_bounds__(256)
 expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
               const uint64_t *__restrict__ block_first, const float4 *__restrict__ splat, int64_t n,
@@ -204,7 +209,8 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
     __shared__ uint32_t s_wsum[4];
     if (uint64_t(*n_pairs) > capacity) return;          // block-uniform
     const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const uint32_t cnt = g < n ? ntiles[g] : 0u;
+    uint32_t cnt = g < n ? ntiles[g] : 0u;
+    if (SHIFT && cnt > 0) cnt = n_super(rect[g]);       // entries per supertile instead of per tile
     const uint32_t excl = block_excl_scan256<uint32_t>(cnt, s_wsum);
     const uint32_t base = uint32_t(block_first[blockIdx.x]) + excl;
     uint2 r = make_uint2(0u, 0u);
@@ -215,7 +221,8 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
         depth = splat[3 * g + 1].w;
         tbase = map.base(g, tiles_x);
     }
-    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+    const uint32_t x0 = (r.x & 0xFFFFu) >> SHIFT, y0 = (r.x >> 16) >> SHIFT;
+    const uint32_t x1 = (r.y & 0xFFFFu) >> SHIFT, y1 = (r.y >> 16) >> SHIFT;
     if (cnt > 0 && cnt <= uint32_t(EXPAND_SMALL)) {
         uint32_t p = base;
         for (uint32_t ty = y0; ty <= y1; ++ty)
@@ -451,6 +458,335 @@ tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pa
     }
 }
 
+// ----------------------------------------------------------------- two-level binning
+// The order-independent lists are built without sorting the tile/Gaussian pairs:
+//
+//   level 1  every visible Gaussian is listed once per 8x8-tile supertile its rectangle
+//            overlaps (about 1.5 entries per Gaussian against about 10 pairs), and the
+//            entries are ordered by supertile with the stable radix sort above (one
+//            8-bit pass for up to 256 supertiles); a supertile's entries stay in
+//            ascending Gaussian order;
+//   level 2  a supertile's entries are cut into chunks of CHUNK.  One pass counts,
+//            per chunk and per tile of the supertile, the entries whose rectangle
+//            covers the tile (ballots over the wave); a column scan over each
+//            supertile's chunks and a scan over the tiles give every (chunk, tile) its
+//            first slot; a second pass writes the Gaussian indices, ranked inside the
+//            chunk by the same ballots.
+//
+// Every step is a prefix sum or a ballot, so the lists are deterministic and equal to
+// the stable tile sort's: ascending Gaussian index per tile.
+
+// Supertile layout of a single view, or of a batch of views (global supertile ids).
+struct SuperGrid {
+    uint32_t tiles_x, tiles_y, st_x;
+    // global id of Gaussian g's supertile (sx, sy) (the expand kernel's Map interface)
+    __device__ __forceinline__ uint32_t base(int64_t, uint32_t &stx) const { stx = st_x; return 0u; }
+    // supertile s: the view's first global tile, its tiles per row and column, and the
+    // supertile's coordinates in the view
+    __device__ __forceinline__ void view(uint32_t s, uint32_t &tbase, uint32_t &tw, uint32_t &th, uint32_t &sx,
+                                         uint32_t &sy) const {
+        tbase = 0u; tw = tiles_x; th = tiles_y; sx = s % st_x; sy = s / st_x;
+    }
+};
+struct SuperBatch {
+    const BatchPlan *plan;
+    __device__ __forceinline__ uint32_t base(int64_t g, uint32_t &stx) const {
+        const int r = find_request(plan->gbase, plan->nreq, uint32_t(g));
+        stx = plan->st_x[r];
+        return plan->stbase[r];
+    }
+    __device__ __forceinline__ void view(uint32_t s, uint32_t &tbase, uint32_t &tw, uint32_t &th, uint32_t &sx,
+                                         uint32_t &sy) const {
+        const int r = find_request(plan->stbase, plan->nreq, s);
+        const uint32_t ls = s - plan->stbase[r];
+        tbase = plan->tbase[r]; tw = plan->tiles_x[r]; th = plan->tiles_y[r];
+        sx = ls % plan->st_x[r]; sy = ls / plan->st_x[r];
+    }
+};
+
+// Per 256 Gaussians: number of supertile entries and of tile pairs.
+__global__ void __launch_bounds__(256)
+super_count_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles, int64_t n,
+                   uint64_t *__restrict__ sums_e, uint64_t *__restrict__ sums_p) {
+    __shared__ uint64_t ws[2][4];
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const uint32_t nt = g < n ? ntiles[g] : 0u;
+    uint64_t e = nt > 0 ? n_super(rect[g]) : 0u, p = nt;
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o, 64);
+        p += __shfl_xor(p, o, 64);
+    }
+    if (lane_id() == 0) {
+        ws[0][threadIdx.x >> 6] = e;
+        ws[1][threadIdx.x >> 6] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sums_e[blockIdx.x] = ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3];
+        sums_p[blockIdx.x] = ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3];
+    }
+}
+
+// One block: exclusive scan of the entry counts in place, their total E, and the pair
+// total P (clamped to 2^32 - 1) -> n_pairs.  E is written as 0 when P > capacity, so
+// nothing after this step does any work.
+__global__ void __launch_bounds__(1024)
+super_scan_kernel(uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ sums_p, int nb, uint64_t capacity,
+                  uint32_t *__restrict__ e_total, uint32_t *__restrict__ n_pairs) {
+    __shared__ uint64_t wsum[16], wp[16];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    uint64_t ptot = 0;
+    for (int i = threadIdx.x; i < nb; i += 1024) ptot += sums_p[i];
+    for (int o = 32; o > 0; o >>= 1) ptot += __shfl_xor(ptot, o, 64);
+    if (lane_id() == 0) wp[threadIdx.x / 64] = ptot;
+    __syncthreads();
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const uint64_t v = i < nb ? sums_e[i] : 0;
+        const uint64_t inc = wave_incl_scan(v);
+        if (lane_id() == 63) wsum[threadIdx.x / 64] = inc;
+        __syncthreads();
+        uint64_t wpre = 0;
+        for (int w = 0; w < int(threadIdx.x / 64); ++w) wpre += wsum[w];
+        const uint64_t c = carry;
+        if (i < nb) sums_e[i] = c + wpre + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + wpre + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint64_t P = 0;
+        for (int w = 0; w < 16; ++w) P += wp[w];
+        const uint32_t p32 = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(P);
+        *n_pairs = p32;
+        *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(carry);
+    }
+}
+
+// Level 2 work list: supertile s has ceil(E_s / CHUNK) chunks starting at chunk sc0[s];
+// chunk c covers entries [chunk_lo[c], min(chunk_lo[c] + CHUNK, st_offs[s + 1])) of
+// supertile chunk_st[c].  One block of 1024 threads, each over a run of supertiles.
+__global__ void __launch_bounds__(1024)
+chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
+                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ sc0,
+                  uint32_t *__restrict__ chunk_st, uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
+    __shared__ uint64_t s_wsum[16];
+    uint32_t S = st_count ? *st_count : st_host;
+    if (S > st_host) S = st_host;
+    if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
+    const uint32_t per = (S + 1023) / 1024;
+    const uint32_t s0 = min(S, threadIdx.x * per), s1 = min(S, s0 + per);
+    uint32_t cnt = 0;
+    for (uint32_t s = s0; s < s1; ++s) cnt += (st_offs[s + 1] - st_offs[s] + CHUNK - 1) / CHUNK;
+    // exclusive block scan of the per-thread chunk counts
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(inc, o, 64);
+        if (l >= o) inc += u;
+    }
+    if (l == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int k = 0; k < w; ++k) pre += s_wsum[k];
+    uint32_t c = uint32_t(pre + inc - cnt);
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint32_t lo = st_offs[s], hi = st_offs[s + 1];
+        sc0[s] = c;
+        for (uint32_t e = lo; e < hi; e += CHUNK, ++c) {
+            chunk_st[c] = s;
+            chunk_lo[c] = e;
+        }
+    }
+    if (threadIdx.x == 1023) {
+        sc0[S] = c;
+        *n_chunks = c;
+    }
+}
+
+// Lane's covered tiles of its supertile as a 64-bit mask (bit ky * 8 + kx).
+__device__ __forceinline__ uint64_t cover_mask(uint2 r, uint32_t sx, uint32_t sy) {
+    const int x0 = int(r.x & 0xFFFFu) - int(sx * SUPER), y0 = int(r.x >> 16) - int(sy * SUPER);
+    const int x1 = int(r.y & 0xFFFFu) - int(sx * SUPER), y1 = int(r.y >> 16) - int(sy * SUPER);
+    const int lx0 = max(x0, 0), ly0 = max(y0, 0), lx1 = min(x1, SUPER - 1), ly1 = min(y1, SUPER - 1);
+    if (lx0 > lx1 || ly0 > ly1) return 0ull;
+    const uint64_t row = uint64_t((2u << lx1) - (1u << lx0));                    // columns lx0 .. lx1
+    const uint64_t rows = (0x0101010101010101ull << (8 * ly0)) & (~0ull >> (8 * (SUPER - 1 - ly1)));
+    return rows * row;                                                           // no carries: row < 256
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One chunk per block iteration: every wave ballots its 64 entries' cover masks per tile of
+// the union of the masks and leaves the bit masks in s_bal[w][k] (zero for other tiles).
+template <typename Geo>
+__device__ __forceinline__ void chunk_ballots(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+                                              uint32_t c, const uint32_t *__restrict__ chunk_st,
+                                              const uint32_t *__restrict__ chunk_lo,
+                                              const uint32_t *__restrict__ st_offs, const Geo &geo,
+                                              uint64_t (*s_bal)[SUPER_TILES], uint32_t &gid, uint64_t &mask,
+                                              uint32_t &s, uint32_t &tbase, uint32_t &tw, uint32_t &th,
+                                              uint32_t &sx, uint32_t &sy) {
+    const int w = threadIdx.x >> 6;
+    const unsigned l = lane_id();
+    s = chunk_st[c];
+    const uint32_t lo = chunk_lo[c], hi = min(lo + uint32_t(CHUNK), st_offs[s + 1]);
+    geo.view(s, tbase, tw, th, sx, sy);
+    const uint32_t i = lo + threadIdx.x;
+    mask = 0ull;
+    gid = 0u;
+    if (i < hi) {
+        gid = vals[i];
+        mask = cover_mask(rect[gid], sx, sy);
+    }
+    s_bal[w][l] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t any = wave_or(mask);
+    any = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(any >> 32))) << 32) |
+          uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(any)));
+    while (any) {
+        const int k = __builtin_ctzll(any);
+        any &= any - 1;
+        const uint64_t b = __ballot((mask >> k) & 1ull);
+        if (l == 0) s_bal[w][k] = b;
+    }
+}
+
+// Level-2 pass 1: per chunk and tile of its supertile, the number of covering entries.
+template <typename Geo>
+__global__ void __launch_bounds__(CHUNK)
+chunk_count_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+                   const uint32_t *__restrict__ chunk_st, const uint32_t *__restrict__ chunk_lo,
+                   const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
+                   uint32_t *__restrict__ cnt) {
+    __shared__ uint64_t s_bal[CHUNK / 64][SUPER_TILES];
+    const uint32_t nc = *n_chunks;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        uint32_t gid, s, tbase, tw, th, sx, sy;
+        uint64_t mask;
+        chunk_ballots(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, s_bal, gid, mask, s, tbase, tw, th, sx, sy);
+        __syncthreads();
+        if (threadIdx.x < SUPER_TILES) {
+            const int k = threadIdx.x;
+            cnt[size_t(c) * SUPER_TILES + k] = uint32_t(__popcll(s_bal[0][k]) + __popcll(s_bal[1][k]) +
+                                                        __popcll(s_bal[2][k]) + __popcll(s_bal[3][k]));
+        }
+        __syncthreads();
+    }
+}
+
+// Per (supertile, tile of it): exclusive scan of the chunk counts in place, and the tile's
+// total pair count -> tile_total[global tile] for every tile inside its view.
+template <typename Geo>
+__global__ void __launch_bounds__(64)
+chunk_colscan_kernel(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ sc0,
+                     const uint32_t *__restrict__ st_count, uint32_t st_host, const uint32_t *__restrict__ n_pairs,
+                     uint64_t capacity, Geo geo, uint32_t *__restrict__ tile_total) {
+    uint32_t S = st_count ? *st_count : st_host;
+    if (S > st_host) S = st_host;
+    if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
+    const unsigned l = lane_id();
+    for (uint32_t job = blockIdx.x; job < S * SUPER_TILES; job += gridDim.x) {
+        const uint32_t s = job / SUPER_TILES, k = job % SUPER_TILES;
+        uint32_t tbase, tw, th, sx, sy;
+        geo.view(s, tbase, tw, th, sx, sy);
+        const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
+        const uint32_t c0 = sc0[s], c1 = sc0[s + 1];
+        uint32_t carry = 0;
+        for (uint32_t cb = c0; cb < c1; cb += 64) {
+            const uint32_t c = cb + l;
+            const uint32_t v = c < c1 ? cnt[size_t(c) * SUPER_TILES + k] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (c < c1) cnt[size_t(c) * SUPER_TILES + k] = carry + inc - v;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (l == 0 && tx < tw && ty < th) tile_total[tbase + ty * tw + tx] = carry;
+    }
+}
+
+// One block: exclusive scan of the per-tile totals -> tile_offsets[0 .. T], skipped on
+// overflow (then only n_pairs has been written).
+__global__ void __launch_bounds__(1024)
+tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ offs) {
+    __shared__ uint64_t s_wsum[16];
+    if (uint64_t(*n_pairs) > capacity) return;                  // block-uniform
+    uint32_t T = t_count ? *t_count : t_host;
+    if (T > t_host) T = t_host;
+    const uint32_t per = (T + 1023) / 1024;
+    const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
+    uint32_t sum = 0;
+    for (uint32_t t = t0; t < t1; ++t) sum += tile_total[t];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(inc, o, 64);
+        if (l >= o) inc += u;
+    }
+    if (l == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int k = 0; k < w; ++k) pre += s_wsum[k];
+    uint32_t o = uint32_t(pre + inc - sum);
+    for (uint32_t t = t0; t < t1; ++t) {
+        offs[t] = o;
+        o += tile_total[t];
+    }
+    if (threadIdx.x == 1023) offs[T] = o;
+}
+
+// Level-2 pass 2: every entry writes its Gaussian index into the lists of the tiles it
+// covers, at the tile's first slot + the chunk's column prefix + the earlier waves' and
+// lanes' counts for that tile.
+template <typename Geo>
+__global__ void __launch_bounds__(CHUNK)
+chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+                   const uint32_t *__restrict__ chunk_st, const uint32_t *__restrict__ chunk_lo,
+                   const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
+                   const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ offs,
+                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ gids) {
+    __shared__ uint64_t s_bal[CHUNK / 64][SUPER_TILES];
+    __shared__ uint32_t s_first[CHUNK / 64][SUPER_TILES];
+    if (uint64_t(*n_pairs) > capacity) return;                  // grid-uniform
+    const uint32_t nc = *n_chunks;
+    const int w = threadIdx.x >> 6;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        uint32_t gid, s, tbase, tw, th, sx, sy;
+        uint64_t mask;
+        chunk_ballots(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, s_bal, gid, mask, s, tbase, tw, th, sx, sy);
+        __syncthreads();
+        if (threadIdx.x < SUPER_TILES) {
+            const int k = threadIdx.x;
+            const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
+            if (tx < tw && ty < th) {
+                uint32_t f = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
+#pragma unroll
+                for (int ww = 0; ww < CHUNK / 64; ++ww) {
+                    s_first[ww][k] = f;
+                    f += uint32_t(__popcll(s_bal[ww][k]));
+                }
+            }
+        }
+        __syncthreads();
+        const uint64_t lt = lanemask_lt();
+        while (mask) {
+            const int k = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            gids[s_first[w][k] + uint32_t(__popcll(s_bal[w][k] & lt))] = gid;
+        }
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------------- host side
 inline int bits_for(uint64_t v) {
     int b = 0;
@@ -552,16 +888,153 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
     return MGS_OK;
 }
 
+// Two-level order-independent binning (see the comment above super_count_kernel).
+struct Bin2Layout {
+    size_t sums_e, sums_p, etot, keys0, keys1, vals0, vals1, hist, dtot, st_offs, sc0, chunk_st, chunk_lo, nch, cnt,
+        ttot, total;
+    int nblocks;
+    uint32_t chunks_max;
+};
+
+inline Bin2Layout bin2_layout(int64_t n, uint32_t st_max, uint32_t t_max, uint64_t capacity) {
+    Bin2Layout L;
+    const size_t cap = size_t(capacity > 0 ? capacity : 1);     // entries <= pairs <= capacity
+    const int64_t nb = int64_t((cap + RADIX_TILE - 1) / RADIX_TILE);
+    L.nblocks = int(nb > 0 ? nb : 1);
+    L.chunks_max = uint32_t(cap / CHUNK + st_max + 1);
+    const size_t nsums = size_t((n + 255) / 256) + 1;
+    size_t o = 0;
+    L.sums_e = o;   o = align_up(o + nsums * 8, 256);
+    L.sums_p = o;   o = align_up(o + nsums * 8, 256);
+    L.etot = o;     o = align_up(o + 16, 256);
+    L.keys0 = o;    o = align_up(o + cap * 4, 256);
+    L.keys1 = o;    o = align_up(o + cap * 4, 256);
+    L.vals0 = o;    o = align_up(o + cap * 4, 256);
+    L.vals1 = o;    o = align_up(o + cap * 4, 256);
+    L.hist = o;     o = align_up(o + size_t(RADIX_MAX_DIGITS) * L.nblocks * 4, 256);
+    L.dtot = o;     o = align_up(o + RADIX_MAX_DIGITS * 4, 256);
+    L.st_offs = o;  o = align_up(o + (size_t(st_max) + 1) * 4, 256);
+    L.sc0 = o;      o = align_up(o + (size_t(st_max) + 1) * 4, 256);
+    L.chunk_st = o; o = align_up(o + size_t(L.chunks_max) * 4, 256);
+    L.chunk_lo = o; o = align_up(o + size_t(L.chunks_max) * 4, 256);
+    L.nch = o;      o = align_up(o + 16, 256);
+    L.cnt = o;      o = align_up(o + size_t(L.chunks_max) * SUPER_TILES * 4, 256);
+    L.ttot = o;     o = align_up(o + size_t(t_max) * 4, 256);
+    L.total = o;
+    return L;
+}
+
+// st_count / t_count: device-side supertile / tile counts (batches), NULL for a single view
+// (then st_max / T are exact).
+template <typename Geo>
+int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, const uint32_t *st_count, uint32_t T,
+              const uint32_t *t_count, void *ws, size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids,
+              uint64_t capacity, uint32_t *n_pairs, hipStream_t s) {
+    int rc;
+    MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
+    if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
+    MGS_REQUIRE(T > 0 && st_max > 0, "bad tile grid");
+    MGS_REQUIRE(tile_offsets && n_pairs, "tile_offsets / n_pairs is NULL");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity must be < 2^32 - 1");
+    MGS_REQUIRE(capacity == 0 || gids, "gids is NULL");
+    MGS_REQUIRE(ws && aligned(ws, 256), "workspace must be non-NULL and 256-byte aligned");
+    const Bin2Layout L = bin2_layout(n, st_max, T, capacity);
+    MGS_REQUIRE(ws_bytes >= L.total, "workspace too small (%zu < %zu)", ws_bytes, L.total);
+    char *w = static_cast<char *>(ws);
+    uint64_t *sums_e = reinterpret_cast<uint64_t *>(w + L.sums_e);
+    uint64_t *sums_p = reinterpret_cast<uint64_t *>(w + L.sums_p);
+    uint32_t *etot = reinterpret_cast<uint32_t *>(w + L.etot);
+    uint32_t *keys[2] = {reinterpret_cast<uint32_t *>(w + L.keys0), reinterpret_cast<uint32_t *>(w + L.keys1)};
+    uint32_t *vals[2] = {reinterpret_cast<uint32_t *>(w + L.vals0), reinterpret_cast<uint32_t *>(w + L.vals1)};
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + L.hist);
+    uint32_t *dtot = reinterpret_cast<uint32_t *>(w + L.dtot);
+    uint32_t *st_offs = reinterpret_cast<uint32_t *>(w + L.st_offs);
+    uint32_t *sc0 = reinterpret_cast<uint32_t *>(w + L.sc0);
+    uint32_t *chunk_st = reinterpret_cast<uint32_t *>(w + L.chunk_st);
+    uint32_t *chunk_lo = reinterpret_cast<uint32_t *>(w + L.chunk_lo);
+    uint32_t *nch = reinterpret_cast<uint32_t *>(w + L.nch);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(w + L.cnt);
+    uint32_t *ttot = reinterpret_cast<uint32_t *>(w + L.ttot);
+    const uint2 *rect = reinterpret_cast<const uint2 *>(proj->rect);
+    const unsigned nb256 = unsigned((n + 255) / 256);
+
+    // level 1: entry counts (and the pair total P), their scan, the entries, the supertile sort
+    if (nb256 > 0) {
+        hipLaunchKernelGGL(super_count_kernel, dim3(nb256), dim3(256), 0, s, rect, proj->n_tiles, n, sums_e, sums_p);
+        MGS_LAUNCH_CHECK("super_count_kernel");
+    }
+    hipLaunchKernelGGL(super_scan_kernel, dim3(1), dim3(1024), 0, s, sums_e, sums_p, int(nb256), capacity, etot,
+                       n_pairs);
+    MGS_LAUNCH_CHECK("super_scan_kernel");
+    if (nb256 > 0) {
+        hipLaunchKernelGGL((expand_kernel<uint32_t, TileKey, Geo, SUPER_SHIFT>), dim3(nb256), dim3(256), 0, s, rect,
+                           proj->n_tiles, sums_e, reinterpret_cast<const float4 *>(proj->splat), n, geo, n_pairs,
+                           capacity, keys[0], vals[0], TileKey());
+        MGS_LAUNCH_CHECK("expand_kernel<supertile>");
+    }
+    const int key_bits = bits_for(st_max) > 0 ? bits_for(st_max) : 1;
+    const int npass = (key_bits + RADIX_MAX_BITS - 1) / RADIX_MAX_BITS;
+    int cur = 0;
+    if (capacity > 0) {
+        const unsigned grid = unsigned(L.nblocks < RADIX_MAX_GRID ? L.nblocks : RADIX_MAX_GRID);
+        int shift = 0;
+        for (int p = 0; p < npass; ++p) {
+            const int bits = (key_bits - shift + (npass - p) - 1) / (npass - p);
+            hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t>), dim3(grid), dim3(RADIX_THREADS), 0, s, keys[cur],
+                               etot, capacity, shift, bits, hist, L.nblocks);
+            MGS_LAUNCH_CHECK("radix_upsweep_kernel");
+            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, etot,
+                               capacity, dtot);
+            MGS_LAUNCH_CHECK("radix_colscan_kernel");
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t>), dim3(grid), dim3(RADIX_THREADS), 0, s, keys[cur],
+                               vals[cur], etot, capacity, shift, bits, hist, dtot, L.nblocks, keys[cur ^ 1],
+                               vals[cur ^ 1]);
+            MGS_LAUNCH_CHECK("radix_downsweep_kernel");
+            cur ^= 1;
+            shift += bits;
+        }
+    }
+    const uint64_t rblocks = (capacity + 1 + 255) / 256;
+    hipLaunchKernelGGL((tile_ranges_kernel<uint32_t>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256), 0,
+                       s, keys[cur], etot, capacity, 0, st_max, st_offs);
+    MGS_LAUNCH_CHECK("tile_ranges_kernel<supertile>");
+
+    // level 2: chunks, per-chunk tile counts, column scans, tile offsets, the lists
+    hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs, capacity,
+                       sc0, chunk_st, chunk_lo, nch);
+    MGS_LAUNCH_CHECK("chunk_plan_kernel");
+    const unsigned cgrid = L.chunks_max < uint32_t(SUPER_MAX_GRID) ? L.chunks_max : uint32_t(SUPER_MAX_GRID);
+    hipLaunchKernelGGL((chunk_count_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st, chunk_lo,
+                       st_offs, nch, geo, cnt);
+    MGS_LAUNCH_CHECK("chunk_count_kernel");
+    const uint64_t jobs = uint64_t(st_max) * SUPER_TILES;
+    hipLaunchKernelGGL((chunk_colscan_kernel<Geo>), dim3(unsigned(jobs < 16384 ? jobs : 16384)), dim3(64), 0, s, cnt,
+                       sc0, st_count, st_max, n_pairs, capacity, geo, ttot);
+    MGS_LAUNCH_CHECK("chunk_colscan_kernel");
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, ttot, t_count, T, n_pairs, capacity, tile_offsets);
+    MGS_LAUNCH_CHECK("tile_scan_kernel");
+    if (capacity > 0) {
+        hipLaunchKernelGGL((chunk_write_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st,
+                           chunk_lo, st_offs, nch, geo, cnt, tile_offsets, n_pairs, capacity, gids);
+        MGS_LAUNCH_CHECK("chunk_write_kernel");
+    }
+    return MGS_OK;
+}
+
+inline uint32_t super_count(int tiles_x, int tiles_y) {
+    return uint32_t((tiles_x + SUPER - 1) / SUPER) * uint32_t((tiles_y + SUPER - 1) / SUPER);
+}
+
 int bin_batch(const mgs_projected *proj, int64_t n_max, const BatchPlan *plan, uint32_t max_tiles, void *ws,
               size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
               hipStream_t s) {
-    const int key_bits = bits_for(max_tiles);
-    return bin_impl<uint32_t, TileKey>(proj, n_max, BatchMap{plan}, max_tiles, ws, ws_bytes, tile_offsets, gids,
-                                       capacity, n_pairs, s, key_bits > 0 ? key_bits : 1, 0);
+    // a request has at most as many supertiles as tiles
+    return bin2_impl(proj, n_max, SuperBatch{plan}, max_tiles, &plan->st_total, max_tiles, &plan->t_total, ws,
+                     ws_bytes, tile_offsets, gids, capacity, n_pairs, s);
 }
 
-size_t bin_batch_workspace(int64_t n_max, uint32_t, uint64_t capacity) {
-    return bin_layout<uint32_t>(n_max, capacity).total;
+size_t bin_batch_workspace(int64_t n_max, uint32_t max_tiles, uint64_t capacity) {
+    return bin2_layout(n_max, max_tiles, max_tiles, capacity).total;
 }
 
 }  // namespace mgs
@@ -569,7 +1042,9 @@ size_t bin_batch_workspace(int64_t n_max, uint32_t, uint64_t capacity) {
 extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes) {
     MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
     MGS_REQUIRE(n >= 0 && tiles_x > 0 && tiles_y > 0, "bad sizes");
-    *bytes = mgs::bin_layout<uint32_t>(n, capacity).total;
+    MGS_REQUIRE(tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
+    *bytes = mgs::bin2_layout(n, mgs::super_count(tiles_x, tiles_y), uint32_t(tiles_x) * uint32_t(tiles_y), capacity)
+                 .total;
     return MGS_OK;
 }
 
@@ -577,11 +1052,10 @@ extern "C" int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int ti
                        size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
                        uint32_t *n_pairs, void *stream) {
     MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
-    const int key_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
-    return mgs::bin_impl<uint32_t, mgs::TileKey>(proj, n, mgs::GridMap{uint32_t(tiles_x)},
-                                                  uint32_t(tiles_x) * uint32_t(tiles_y), ws, ws_bytes, tile_offsets,
-                                                  gids, capacity, n_pairs, mgs::as_stream(stream),
-                                                  key_bits > 0 ? key_bits : 1, 0);
+    const uint32_t st_x = uint32_t((tiles_x + mgs::SUPER - 1) / mgs::SUPER);
+    return mgs::bin2_impl(proj, n, mgs::SuperGrid{uint32_t(tiles_x), uint32_t(tiles_y), st_x},
+                          mgs::super_count(tiles_x, tiles_y), nullptr, uint32_t(tiles_x) * uint32_t(tiles_y), nullptr,
+                          ws, ws_bytes, tile_offsets, gids, capacity, n_pairs, mgs::as_stream(stream));
 }
 
 extern "C" int mgs_bin_sorted_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity,

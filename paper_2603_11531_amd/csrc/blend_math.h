@@ -211,10 +211,12 @@ constexpr float OIT_CLAMP_MARGIN = 1e-2f;
 // Order-independent composite (Eq. 2) of one 16x16 tile (tile coordinates tx, ty) from
 // the list range gids[start, end).  Called by a whole 256-thread workgroup.
 //
-// The four waves share the range: wave w takes every fourth staged Gaussian (4k + w), and
-// each lane holds four pixels, one per 8x8 quadrant (pixel (l & 7, l >> 3) of each).  A
-// staged Gaussian is read from LDS once per wave and evaluated only on the quadrants its
-// exact quadrant test keeps, so a 40-byte broadcast read feeds up to four pixel updates.
+// The four waves share the range: wave w takes every fourth Gaussian of the list (4k + w),
+// stages 64 of them at a time in its own LDS region (one per lane) and walks them without
+// waiting for the other waves.  Each lane holds four pixels, one per 8x8 quadrant (pixel
+// (l & 7, l >> 3) of each).  A staged Gaussian is read from LDS once and evaluated only on
+// the quadrants its exact quadrant test keeps, so a 40-byte broadcast read feeds up to four
+// pixel updates.
 // The exponent is a polynomial in the pixel's offset from the tile centre (quad_poly about
 // (16 tx + 8, 16 ty + 8)); offsets are within +-7.5 px.  At the end the waves' sums are
 // merged through LDS in wave order (N and D add, T multiplies), which is exact up to
@@ -223,17 +225,16 @@ constexpr float OIT_CLAMP_MARGIN = 1e-2f;
 // The result goes to thread k's pixel tile_pixel(k) (quadrant k / 64, lane k % 64): the
 // composite into image / aux of a W x H view, or, if part is non-NULL, the sums
 // (N rgb, D, T) to part[5][256] for a later merge with the tile's other ranges.
-constexpr int OIT_BATCH = 256;                  // Gaussians staged per pass, one per thread
+constexpr int OIT_BATCH = 256;                  // list positions staged per pass by the four waves
 
 __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
                                                uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
                                                float bgg, float bgb, float log2_amin, float amax,
                                                float *__restrict__ image, float *__restrict__ aux,
                                                float *__restrict__ part) {
-    // staged Gaussian j: (c0, cx, cy, cxx), (cxy, cyy, -, -), (w r, w g, w b, w) at s_buf[3 j ..];
-    // after the last batch the same memory holds the waves' sums for the merge
+    // wave w's staged Gaussian j: (c0, cx, cy, cxx), (cxy, cyy, -, -), (w r, w g, w b, w) at
+    // s_buf[192 w + 3 j ..]; after the last batch the same memory holds the waves' sums
     __shared__ float4 s_buf[4 * 4 * 5 * 64 / 4];
-    __shared__ uint32_t s_mask[OIT_BATCH];
 
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
@@ -256,35 +257,36 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
     // log2(o) above this: the alpha_max clamp can bind somewhere in the tile (the margin is
     // far above the float32 error of the exponent polynomial)
     const float log2_amax_safe = __log2f(amax) - OIT_CLAMP_MARGIN;
+    // Each wave stages and walks its own Gaussians (list positions b + 4 l + w, l = 0 .. 63,
+    // for b = start, start + 256, ...) in its own LDS region, so the waves never wait on
+    // each other before the final merge.
+    float4 *wbuf = s_buf + w * (3 * 64);
     for (uint32_t b = start; b < end; b += OIT_BATCH) {
-        __syncthreads();
-        {
-            const uint32_t i = b + threadIdx.x;
-            uint32_t flags = 0;
-            if (i < end) {
-                const uint32_t g = gids[i];
-                const float4 r0 = splat[3 * size_t(g) + 0];
-                const float4 r1 = splat[3 * size_t(g) + 1];
-                const float4 r2 = splat[3 * size_t(g) + 2];
-                flags = quadrant_mask(r0, r1, tx, ty, log2_amin);
-                if (flags) {
-                    float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
-                    quad_poly(r0, r1, tcx, tcy, qa, qb);
-                    s_buf[3 * threadIdx.x + 0] = qa;
-                    s_buf[3 * threadIdx.x + 1] = qb;
-                    s_buf[3 * threadIdx.x + 2] = make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
-                    if (r0.z > log2_amax_safe) flags |= OIT_CLAMP;
-                }
+        const uint32_t i = b + 4 * l + w;
+        uint32_t mk = 0;
+        if (i < end) {
+            const uint32_t g = gids[i];
+            const float4 r0 = splat[3 * size_t(g) + 0];
+            const float4 r1 = splat[3 * size_t(g) + 1];
+            const float4 r2 = splat[3 * size_t(g) + 2];
+            mk = quadrant_mask(r0, r1, tx, ty, log2_amin);
+            if (mk) {
+                float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
+                quad_poly(r0, r1, tcx, tcy, qa, qb);
+                wbuf[3 * l + 0] = qa;
+                wbuf[3 * l + 1] = qb;
+                wbuf[3 * l + 2] = make_float4(r0.w * r2.x, r0.w * r2.y, r0.w * r2.z, r0.w);
+                if (r0.z > log2_amax_safe) mk |= OIT_CLAMP;
             }
-            s_mask[threadIdx.x] = flags;
         }
-        __syncthreads();
-        // wave w: staged Gaussians 4 k + w, k = 0 .. 63, in order; those whose alpha can reach
-        // alpha_max are taken in a second loop, the only one that needs the clamp
-        const uint32_t mk = s_mask[4 * l + w];
+        // the lanes' records are visible to the whole wave (LDS is in order within a wave)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // in list order; Gaussians whose alpha can reach alpha_max are taken in a second loop,
+        // the only one that needs the clamp
         const uint64_t clamp = __ballot((mk & OIT_CLAMP) != 0u);
         uint64_t any = __ballot(mk != 0u) & ~clamp;
-        const int wu = __builtin_amdgcn_readfirstlane(w);
 #define MGS_OIT_QUAD(q, X, Y, XX, XY, YY, ALPHA)                                    \
             if (fk & (1u << q)) {                                                   \
                 float e = fmaf(qa.y, X, qa.x);                                      \
@@ -304,7 +306,7 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
             const int k = __builtin_ctzll(any);                                     \
             any &= any - 1;                                                         \
             const uint32_t fk = __builtin_amdgcn_readlane(mk, k);                   \
-            const float4 *rec = s_buf + 3 * (4 * k + wu);                           \
+            const float4 *rec = wbuf + 3 * k;                                       \
             const float4 qa = rec[0];                                               \
             const float4 qb = rec[1];                                               \
             const float4 cw = rec[2];                                               \
@@ -318,6 +320,10 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
         MGS_OIT_LOOP(fminf(fast_exp2(e), amax))
 #undef MGS_OIT_LOOP
 #undef MGS_OIT_QUAD
+        // every lane's reads of this batch's records precede the next batch's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     // merge the four waves' sums: s_sum[(w * 4 + q) * 5 + v][l]
