@@ -35,6 +35,8 @@ constexpr int SUPER = 1 << SUPER_SHIFT;
 constexpr int SUPER_TILES = SUPER * SUPER;
 constexpr int CHUNK = 256;                                // supertile entries per level-2 block
 constexpr int SUPER_MAX_GRID = 8192;                      // resident blocks striding over the level-2 chunks
+constexpr int SUPER_RADIX_ITERS = 4;                      // level-1 sort: 1024 keys per block (a short sort,
+constexpr int SUPER_RADIX_TILE = RADIX_THREADS * SUPER_RADIX_ITERS;   // so more, shorter blocks)
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -269,34 +271,37 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, uint64_t a
 // The radix kernels run a bounded grid that strides over the logical 4096-key
 // blocks actually in use, ceil(P / 4096), read on the device; the histogram keeps
 // the capacity-sized stride `nblocks` but only its first used columns are touched.
-__device__ __forceinline__ int used_blocks(uint32_t P) { return int((uint64_t(P) + RADIX_TILE - 1) / RADIX_TILE); }
+template <int ITERS>
+__device__ __forceinline__ int used_blocks(uint32_t P) {
+    return int((uint64_t(P) + RADIX_THREADS * ITERS - 1) / (RADIX_THREADS * ITERS));
+}
 
 // Per-block digit counts, digit-major: counts[d * nblocks + block].
-template <typename K>
+template <typename K, int ITERS = RADIX_ITERS>
 __global__ void __launch_bounds__(RADIX_THREADS)
 radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
                      int shift, int bits, uint32_t *__restrict__ counts, int nblocks) {
     __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
     const uint32_t P = *n_pairs;
     if (uint64_t(P) > capacity) return;                                   // grid-uniform
-    const int nbu = used_blocks(P);
+    const int nbu = used_blocks<ITERS>(P);
     const int nd = 1 << bits;
     const uint32_t mask = uint32_t(nd - 1);
     const int w = threadIdx.x / 64;
     const unsigned l = lane_id();
     for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
         // all of the wave's loads are issued before the first digit is matched
-        const int64_t base = int64_t(blk) * RADIX_TILE + w * (RADIX_ITERS * 64);
-        uint32_t d[RADIX_ITERS];
+        const int64_t base = int64_t(blk) * (RADIX_THREADS * ITERS) + w * (ITERS * 64);
+        uint32_t d[ITERS];
 #pragma unroll
-        for (int it = 0; it < RADIX_ITERS; ++it) {
+        for (int it = 0; it < ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             d[it] = idx < int64_t(P) ? digit_of(keys[idx], shift, mask) : 0u;
         }
         for (int i = threadIdx.x; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += RADIX_THREADS) (&cnt[0][0])[i] = 0;
         __syncthreads();
 #pragma unroll
-        for (int it = 0; it < RADIX_ITERS; ++it) {
+        for (int it = 0; it < ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
             const uint64_t active = __ballot(ok);
@@ -312,6 +317,7 @@ radix_upsweep_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts, and its total.
+template <int ITERS = RADIX_ITERS>
 __global__ void __launch_bounds__(256)
 radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, const uint32_t *__restrict__ n_pairs,
                      uint64_t capacity, uint32_t *__restrict__ digit_total) {
@@ -319,7 +325,7 @@ radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, const uint32_t 
     __shared__ uint32_t s_tot;
     const uint32_t P = *n_pairs;
     if (uint64_t(P) > capacity) return;                                   // grid-uniform
-    const int nbu = used_blocks(P);
+    const int nbu = used_blocks<ITERS>(P);
     uint32_t *row = counts + int64_t(blockIdx.x) * nblocks;
     uint32_t carry = 0;
     constexpr int ITEMS = 8;
@@ -346,9 +352,9 @@ radix_colscan_kernel(uint32_t *__restrict__ counts, int nblocks, const uint32_t 
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one 4096-key block: ranks from ballot-matched digits, the
+// Stable scatter of one block of 256 * ITERS keys: ranks from ballot-matched digits, the
 // block's keys reordered by digit in LDS, then written out in runs (coalesced).
-template <typename K>
+template <typename K, int ITERS = RADIX_ITERS>
 __global__ void __launch_bounds__(RADIX_THREADS)
 radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
                        const uint32_t *__restrict__ n_pairs, uint64_t capacity, int shift, int bits,
@@ -357,11 +363,11 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
     __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
     __shared__ uint32_t s_lstart[RADIX_MAX_DIGITS], s_gstart[RADIX_MAX_DIGITS];
     __shared__ uint32_t s_wsum[4];
-    __shared__ K sk[RADIX_TILE];
-    __shared__ uint32_t sv[RADIX_TILE];
+    __shared__ K sk[(RADIX_THREADS * ITERS)];
+    __shared__ uint32_t sv[(RADIX_THREADS * ITERS)];
     const uint32_t P = *n_pairs;
     if (uint64_t(P) > capacity) return;                                   // grid-uniform
-    const int nbu = used_blocks(P);
+    const int nbu = used_blocks<ITERS>(P);
     const int nd = 1 << bits;
     const uint32_t mask = uint32_t(nd - 1);
     const int t = threadIdx.x;
@@ -370,13 +376,13 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
     const uint32_t dt = t < nd ? digit_total[t] : 0u;
     const uint32_t dex = block_excl_scan256<uint32_t>(dt, s_wsum);          // contains __syncthreads
     for (int blk = blockIdx.x; blk < nbu; blk += gridDim.x) {
-        const int64_t blk0 = int64_t(blk) * RADIX_TILE;
-        const int64_t base = blk0 + w * (RADIX_ITERS * 64);
+        const int64_t blk0 = int64_t(blk) * (RADIX_THREADS * ITERS);
+        const int64_t base = blk0 + w * (ITERS * 64);
         // all of the wave's loads are issued before the first digit is matched
-        K key[RADIX_ITERS];
-        uint32_t val[RADIX_ITERS], rank[RADIX_ITERS], dig[RADIX_ITERS];
+        K key[ITERS];
+        uint32_t val[ITERS], rank[ITERS], dig[ITERS];
 #pragma unroll
-        for (int it = 0; it < RADIX_ITERS; ++it) {
+        for (int it = 0; it < ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
             key[it] = ok ? keys_in[idx] : K(0);
@@ -387,7 +393,7 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
         if (t < nd) s_gstart[t] = dex + gcol;
         __syncthreads();
 #pragma unroll
-        for (int it = 0; it < RADIX_ITERS; ++it) {
+        for (int it = 0; it < ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             const bool ok = idx < int64_t(P);
             const uint64_t active = __ballot(ok);
@@ -416,7 +422,7 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
         if (t < nd) s_lstart[t] = lex;
         __syncthreads();
 #pragma unroll
-        for (int it = 0; it < RADIX_ITERS; ++it) {
+        for (int it = 0; it < ITERS; ++it) {
             const int64_t idx = base + it * 64 + l;
             if (idx < int64_t(P)) {
                 const uint32_t lp = s_lstart[dig[it]] + cnt[w][dig[it]] + rank[it];
@@ -425,7 +431,7 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
             }
         }
         __syncthreads();
-        const int nloc = int(int64_t(P) - blk0 < RADIX_TILE ? int64_t(P) - blk0 : RADIX_TILE);
+        const int nloc = int(int64_t(P) - blk0 < (RADIX_THREADS * ITERS) ? int64_t(P) - blk0 : (RADIX_THREADS * ITERS));
         for (int lp = t; lp < nloc; lp += RADIX_THREADS) {
             const K k = sk[lp];
             const uint32_t d = digit_of(k, shift, mask);
@@ -533,32 +539,30 @@ super_count_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ 
 __global__ void __launch_bounds__(1024)
 super_scan_kernel(uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ sums_p, int nb, uint64_t capacity,
                   uint32_t *__restrict__ e_total, uint32_t *__restrict__ n_pairs) {
-    __shared__ uint64_t wsum[16], wp[16];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    uint64_t ptot = 0;
-    for (int i = threadIdx.x; i < nb; i += 1024) ptot += sums_p[i];
-    for (int o = 32; o > 0; o >>= 1) ptot += __shfl_xor(ptot, o, 64);
-    if (lane_id() == 0) wp[threadIdx.x / 64] = ptot;
-    __syncthreads();
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int i = b0 + threadIdx.x;
-        const uint64_t v = i < nb ? sums_e[i] : 0;
-        const uint64_t inc = wave_incl_scan(v);
-        if (lane_id() == 63) wsum[threadIdx.x / 64] = inc;
-        __syncthreads();
-        uint64_t wpre = 0;
-        for (int w = 0; w < int(threadIdx.x / 64); ++w) wpre += wsum[w];
-        const uint64_t c = carry;
-        if (i < nb) sums_e[i] = c + wpre + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = c + wpre + inc;
-        __syncthreads();
+    __shared__ uint64_t s_wsum[16];
+    uint64_t carry = 0, ptot = 0;
+    for (int base = 0; base < nb; base += 1024 * PLAN_ITEMS) {
+        const int i0 = base + int(threadIdx.x) * PLAN_ITEMS;
+        uint64_t v[PLAN_ITEMS], sum = 0, psum = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            v[j] = i0 + j < nb ? sums_e[i0 + j] : 0u;
+            psum += i0 + j < nb ? sums_p[i0 + j] : 0u;
+            sum += v[j];
+        }
+        uint64_t tot, ptot_blk;
+        uint64_t o = block_scan1024(sum, s_wsum, &tot) + carry;
+        block_scan1024(psum, s_wsum, &ptot_blk);
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            if (i0 + j < nb) sums_e[i0 + j] = o;
+            o += v[j];
+        }
+        carry += tot;
+        ptot += ptot_blk;
     }
     if (threadIdx.x == 0) {
-        uint64_t P = 0;
-        for (int w = 0; w < 16; ++w) P += wp[w];
-        const uint32_t p32 = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(P);
+        const uint32_t p32 = ptot > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(ptot);
         *n_pairs = p32;
         *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(carry);
     }
@@ -566,43 +570,52 @@ super_scan_kernel(uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ su
 
 // Level 2 work list: supertile s has ceil(E_s / CHUNK) chunks starting at chunk sc0[s];
 // chunk c covers entries [chunk_lo[c], min(chunk_lo[c] + CHUNK, st_offs[s + 1])) of
-// supertile chunk_st[c].  One block of 1024 threads, each over a run of supertiles.
+// supertile chunk_st[c].  One block of 1024 threads; supertiles are taken PLAN_TILE at a
+// time, and the chunks of a piece are filled by all threads (binary search of the
+// supertiles' chunk prefixes in LDS).
 __global__ void __launch_bounds__(1024)
 chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ sc0,
                   uint32_t *__restrict__ chunk_st, uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
     __shared__ uint64_t s_wsum[16];
+    __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
     uint32_t S = st_count ? *st_count : st_host;
     if (S > st_host) S = st_host;
     if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
-    const uint32_t per = (S + 1023) / 1024;
-    const uint32_t s0 = min(S, threadIdx.x * per), s1 = min(S, s0 + per);
-    uint32_t cnt = 0;
-    for (uint32_t s = s0; s < s1; ++s) cnt += (st_offs[s + 1] - st_offs[s] + CHUNK - 1) / CHUNK;
-    // exclusive block scan of the per-thread chunk counts
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = cnt;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < S; base += PLAN_TILE) {
+        const uint32_t k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
+        uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t u = __shfl_up(inc, o, 64);
-        if (l >= o) inc += u;
-    }
-    if (l == 63) s_wsum[w] = inc;
-    __syncthreads();
-    uint64_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += s_wsum[k];
-    uint32_t c = uint32_t(pre + inc - cnt);
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t lo = st_offs[s], hi = st_offs[s + 1];
-        sc0[s] = c;
-        for (uint32_t e = lo; e < hi; e += CHUNK, ++c) {
-            chunk_st[c] = s;
-            chunk_lo[c] = e;
+        for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = s0 + j <= S ? st_offs[s0 + j] : 0u;
+        uint32_t nc[PLAN_ITEMS], cnt = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            nc[j] = s0 + j < S ? (o[j + 1] - o[j] + CHUNK - 1) / CHUNK : 0u;
+            cnt += nc[j];
         }
+        uint64_t tot;
+        uint32_t c = uint32_t(block_scan1024(cnt, s_wsum, &tot));
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            s_pre[k0 + j] = c;
+            if (s0 + j < S) sc0[s0 + j] = carry + c;
+            c += nc[j];
+        }
+        if (threadIdx.x == 0) s_pre[PLAN_TILE] = uint32_t(tot);
+        __syncthreads();
+        const uint32_t ns = min(uint32_t(PLAN_TILE), S - base);
+        for (uint32_t q = threadIdx.x; q < uint32_t(tot); q += 1024) {
+            const int k = upper_index(s_pre, int(ns), q);
+            chunk_st[carry + q] = base + k;
+            chunk_lo[carry + q] = st_offs[base + k] + (q - s_pre[k]) * CHUNK;
+        }
+        __syncthreads();
+        carry += uint32_t(tot);
     }
-    if (threadIdx.x == 1023) {
-        sc0[S] = c;
-        *n_chunks = c;
+    if (threadIdx.x == 0) {
+        sc0[S] = carry;
+        *n_chunks = carry;
     }
 }
 
@@ -617,25 +630,32 @@ __device__ __forceinline__ uint64_t cover_mask(uint2 r, uint32_t sx, uint32_t sy
     return rows * row;                                                           // no carries: row < 256
 }
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+// 64 x 64 bit transpose across the wave: on return lane k holds, in bit j, bit k of lane j's
+// input.  Six butterfly stages; stage s exchanges, between lanes l and l ^ s, the s-bit
+// sub-blocks whose bit index and lane index differ in bit s.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const unsigned l = lane_id();
+    const uint64_t M[6] = {0x5555555555555555ull, 0x3333333333333333ull, 0x0F0F0F0F0F0F0F0Full,
+                           0x00FF00FF00FF00FFull, 0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v |= __shfl_xor(v, o, 64);
-    return v;
+    for (int i = 0; i < 6; ++i) {
+        const int sh = 1 << i;
+        const uint32_t ylo = __shfl_xor(uint32_t(x), sh, 64), yhi = __shfl_xor(uint32_t(x >> 32), sh, 64);
+        const uint64_t y = (uint64_t(yhi) << 32) | ylo;
+        x = (l & sh) ? (((y >> sh) & M[i]) | (x & ~M[i])) : ((x & M[i]) | ((y & M[i]) << sh));
+    }
+    return x;
 }
 
-// One chunk per block iteration: every wave ballots its 64 entries' cover masks per tile of
-// the union of the masks and leaves the bit masks in s_bal[w][k] (zero for other tiles).
+// One chunk: entry threadIdx.x of the chunk (if any) and the tiles of the supertile it covers.
 template <typename Geo>
-__device__ __forceinline__ void chunk_ballots(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
-                                              uint32_t c, const uint32_t *__restrict__ chunk_st,
-                                              const uint32_t *__restrict__ chunk_lo,
-                                              const uint32_t *__restrict__ st_offs, const Geo &geo,
-                                              uint64_t (*s_bal)[SUPER_TILES], uint32_t &gid, uint64_t &mask,
-                                              uint32_t &s, uint32_t &tbase, uint32_t &tw, uint32_t &th,
-                                              uint32_t &sx, uint32_t &sy) {
-    const int w = threadIdx.x >> 6;
-    const unsigned l = lane_id();
-    s = chunk_st[c];
+__device__ __forceinline__ void chunk_entry(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+                                            uint32_t c, const uint32_t *__restrict__ chunk_st,
+                                            const uint32_t *__restrict__ chunk_lo,
+                                            const uint32_t *__restrict__ st_offs, const Geo &geo, uint32_t &gid,
+                                            uint64_t &mask, uint32_t &tbase, uint32_t &tw, uint32_t &th,
+                                            uint32_t &sx, uint32_t &sy) {
+    const uint32_t s = chunk_st[c];
     const uint32_t lo = chunk_lo[c], hi = min(lo + uint32_t(CHUNK), st_offs[s + 1]);
     geo.view(s, tbase, tw, th, sx, sy);
     const uint32_t i = lo + threadIdx.x;
@@ -645,39 +665,30 @@ __device__ __forceinline__ void chunk_ballots(const uint32_t *__restrict__ vals,
         gid = vals[i];
         mask = cover_mask(rect[gid], sx, sy);
     }
-    s_bal[w][l] = 0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint64_t any = wave_or(mask);
-    any = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(any >> 32))) << 32) |
-          uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(any)));
-    while (any) {
-        const int k = __builtin_ctzll(any);
-        any &= any - 1;
-        const uint64_t b = __ballot((mask >> k) & 1ull);
-        if (l == 0) s_bal[w][k] = b;
-    }
 }
 
-// Level-2 pass 1: per chunk and tile of its supertile, the number of covering entries.
+// Level-2 pass 1: per chunk and tile of its supertile, the number of covering entries
+// (after the wave transpose, lane k of a wave holds tile k's membership over the wave's 64
+// entries).
 template <typename Geo>
 __global__ void __launch_bounds__(CHUNK)
 chunk_count_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
                    const uint32_t *__restrict__ chunk_st, const uint32_t *__restrict__ chunk_lo,
                    const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
                    uint32_t *__restrict__ cnt) {
-    __shared__ uint64_t s_bal[CHUNK / 64][SUPER_TILES];
+    __shared__ uint32_t s_cnt[CHUNK / 64][SUPER_TILES];
     const uint32_t nc = *n_chunks;
+    const int w = threadIdx.x >> 6;
+    const unsigned l = lane_id();
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        uint32_t gid, s, tbase, tw, th, sx, sy;
+        uint32_t gid, tbase, tw, th, sx, sy;
         uint64_t mask;
-        chunk_ballots(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, s_bal, gid, mask, s, tbase, tw, th, sx, sy);
+        chunk_entry(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
+        s_cnt[w][l] = uint32_t(__popcll(wave_transpose64(mask)));
         __syncthreads();
         if (threadIdx.x < SUPER_TILES) {
             const int k = threadIdx.x;
-            cnt[size_t(c) * SUPER_TILES + k] = uint32_t(__popcll(s_bal[0][k]) + __popcll(s_bal[1][k]) +
-                                                        __popcll(s_bal[2][k]) + __popcll(s_bal[3][k]));
+            cnt[size_t(c) * SUPER_TILES + k] = s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k];
         }
         __syncthreads();
     }
@@ -721,32 +732,35 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
     if (uint64_t(*n_pairs) > capacity) return;                  // block-uniform
     uint32_t T = t_count ? *t_count : t_host;
     if (T > t_host) T = t_host;
-    const uint32_t per = (T + 1023) / 1024;
-    const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
-    uint32_t sum = 0;
-    for (uint32_t t = t0; t < t1; ++t) sum += tile_total[t];
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = sum;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < T; base += 1024 * PLAN_ITEMS) {
+        const uint32_t t0 = base + threadIdx.x * PLAN_ITEMS;
+        uint32_t v[PLAN_ITEMS], sum = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t u = __shfl_up(inc, o, 64);
-        if (l >= o) inc += u;
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            v[j] = t0 + j < T ? tile_total[t0 + j] : 0u;
+            sum += v[j];
+        }
+        uint64_t tot;
+        uint32_t o = uint32_t(block_scan1024(sum, s_wsum, &tot) + carry);
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            if (t0 + j < T) offs[t0 + j] = o;
+            o += v[j];
+        }
+        carry += tot;
     }
-    if (l == 63) s_wsum[w] = inc;
-    __syncthreads();
-    uint64_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += s_wsum[k];
-    uint32_t o = uint32_t(pre + inc - sum);
-    for (uint32_t t = t0; t < t1; ++t) {
-        offs[t] = o;
-        o += tile_total[t];
-    }
-    if (threadIdx.x == 1023) offs[T] = o;
+    if (threadIdx.x == 0) offs[T] = uint32_t(carry);
 }
 
-// Level-2 pass 2: every entry writes its Gaussian index into the lists of the tiles it
-// covers, at the tile's first slot + the chunk's column prefix + the earlier waves' and
-// lanes' counts for that tile.
+// Level-2 pass 2: the Gaussian indices go into the tile lists.  After the wave transpose,
+// lane k of wave w holds which of the wave's 64 entries cover tile k.  The chunk's output
+// for tile k is one contiguous run of the tile's list (the tile's first slot + the chunk's
+// column prefix), the waves' parts in wave order.  The runs are assembled tile by tile in
+// LDS, then copied out by consecutive threads, so the global stores are coalesced; a chunk
+// with more than CHUNK_STAGE pairs has its lanes write their runs straight to memory.
+constexpr int CHUNK_STAGE = 4096;
+
 template <typename Geo>
 __global__ void __launch_bounds__(CHUNK)
 chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
@@ -754,34 +768,65 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
                    const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
                    const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ offs,
                    const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ gids) {
-    __shared__ uint64_t s_bal[CHUNK / 64][SUPER_TILES];
-    __shared__ uint32_t s_first[CHUNK / 64][SUPER_TILES];
-    if (uint64_t(*n_pairs) > capacity) return;                  // grid-uniform
+    __shared__ uint32_t s_gid[CHUNK / 64][64];
+    __shared__ uint32_t s_cnt[CHUNK / 64][SUPER_TILES];
+    __shared__ uint32_t s_lw[CHUNK / 64][SUPER_TILES];      // local (chunk) start of wave w's part of tile k
+    __shared__ uint32_t s_lpre[SUPER_TILES + 1];            // local start of tile k's run; [64] = total
+    __shared__ uint32_t s_first[SUPER_TILES];               // global start of tile k's run
+    __shared__ uint32_t s_out[CHUNK_STAGE];
+    if (uint64_t(*n_pairs) > capacity) return;              // grid-uniform
     const uint32_t nc = *n_chunks;
     const int w = threadIdx.x >> 6;
+    const unsigned l = lane_id();
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        uint32_t gid, s, tbase, tw, th, sx, sy;
+        uint32_t gid, tbase, tw, th, sx, sy;
         uint64_t mask;
-        chunk_ballots(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, s_bal, gid, mask, s, tbase, tw, th, sx, sy);
+        chunk_entry(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
+        s_gid[w][l] = gid;
+        uint64_t col = wave_transpose64(mask);
+        s_cnt[w][l] = uint32_t(__popcll(col));
         __syncthreads();
-        if (threadIdx.x < SUPER_TILES) {
+        if (threadIdx.x < SUPER_TILES) {                        // wave 0: one lane per tile
             const int k = threadIdx.x;
             const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
-            if (tx < tw && ty < th) {
-                uint32_t f = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
+            const uint32_t ck = s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k];
+            uint32_t incl = ck;
 #pragma unroll
-                for (int ww = 0; ww < CHUNK / 64; ++ww) {
-                    s_first[ww][k] = f;
-                    f += uint32_t(__popcll(s_bal[ww][k]));
-                }
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(incl, o, 64);
+                if (k >= o) incl += u;
+            }
+            uint32_t lo = incl - ck;
+            s_lpre[k] = lo;
+            if (k == 63) s_lpre[64] = incl;
+            if (ck > 0) s_first[k] = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
+#pragma unroll
+            for (int ww = 0; ww < CHUNK / 64; ++ww) {
+                s_lw[ww][k] = lo;
+                lo += s_cnt[ww][k];
             }
         }
         __syncthreads();
-        const uint64_t lt = lanemask_lt();
-        while (mask) {
-            const int k = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            gids[s_first[w][k] + uint32_t(__popcll(s_bal[w][k] & lt))] = gid;
+        const uint32_t L = s_lpre[SUPER_TILES];
+        if (L <= uint32_t(CHUNK_STAGE)) {
+            uint32_t pos = s_lw[w][l];
+            while (col) {
+                const int j = __builtin_ctzll(col);
+                col &= col - 1;
+                s_out[pos++] = s_gid[w][j];
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < L; i += CHUNK) {
+                const int k = upper_index(s_lpre, SUPER_TILES, i);
+                gids[s_first[k] + (i - s_lpre[k])] = s_out[i];
+            }
+        } else if (col) {
+            uint32_t pos = s_first[l] + (s_lw[w][l] - s_lpre[l]);
+            while (col) {
+                const int j = __builtin_ctzll(col);
+                col &= col - 1;
+                gids[pos++] = s_gid[w][j];
+            }
         }
         __syncthreads();
     }
@@ -869,7 +914,7 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
             hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(grid), dim3(RADIX_THREADS), 0, s, kin,
                                n_pairs, capacity, shift, bits, hist, L.nblocks);
             MGS_LAUNCH_CHECK("radix_upsweep_kernel");
-            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, n_pairs,
+            hipLaunchKernelGGL(radix_colscan_kernel<>, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, n_pairs,
                                capacity, dtot);
             MGS_LAUNCH_CHECK("radix_colscan_kernel");
             hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(grid), dim3(RADIX_THREADS), 0, s, kin,
@@ -899,7 +944,7 @@ struct Bin2Layout {
 inline Bin2Layout bin2_layout(int64_t n, uint32_t st_max, uint32_t t_max, uint64_t capacity) {
     Bin2Layout L;
     const size_t cap = size_t(capacity > 0 ? capacity : 1);     // entries <= pairs <= capacity
-    const int64_t nb = int64_t((cap + RADIX_TILE - 1) / RADIX_TILE);
+    const int64_t nb = int64_t((cap + SUPER_RADIX_TILE - 1) / SUPER_RADIX_TILE);
     L.nblocks = int(nb > 0 ? nb : 1);
     L.chunks_max = uint32_t(cap / CHUNK + st_max + 1);
     const size_t nsums = size_t((n + 255) / 256) + 1;
@@ -980,13 +1025,14 @@ int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, co
         int shift = 0;
         for (int p = 0; p < npass; ++p) {
             const int bits = (key_bits - shift + (npass - p) - 1) / (npass - p);
-            hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t>), dim3(grid), dim3(RADIX_THREADS), 0, s, keys[cur],
-                               etot, capacity, shift, bits, hist, L.nblocks);
+            hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
+                               s, keys[cur], etot, capacity, shift, bits, hist, L.nblocks);
             MGS_LAUNCH_CHECK("radix_upsweep_kernel");
-            hipLaunchKernelGGL(radix_colscan_kernel, dim3(1u << bits), dim3(256), 0, s, hist, L.nblocks, etot,
-                               capacity, dtot);
+            hipLaunchKernelGGL(radix_colscan_kernel<SUPER_RADIX_ITERS>, dim3(1u << bits), dim3(256), 0, s, hist,
+                               L.nblocks, etot, capacity, dtot);
             MGS_LAUNCH_CHECK("radix_colscan_kernel");
-            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t>), dim3(grid), dim3(RADIX_THREADS), 0, s, keys[cur],
+            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
+                               s, keys[cur],
                                vals[cur], etot, capacity, shift, bits, hist, dtot, L.nblocks, keys[cur ^ 1],
                                vals[cur ^ 1]);
             MGS_LAUNCH_CHECK("radix_downsweep_kernel");

@@ -69,74 +69,72 @@ struct BatchViewLoc {
     }
 };
 
-// Exclusive scan over a 1024-thread block (all threads call).
-__device__ __forceinline__ uint64_t block_excl_scan1024(uint64_t v, uint64_t *s_wsum /* [16] */) {
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t u = __shfl_up(inc, o, 64);
-        if (l >= o) inc += u;
-    }
-    if (l == 63) s_wsum[w] = inc;
-    __syncthreads();
-    uint64_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += s_wsum[k];
-    __syncthreads();
-    return pre + inc - v;
-}
-
 // One block of 1024 threads: every tile gets n_ranges(L) items (item = tile | range << 24);
 // ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
 // tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
-// Thread k takes a contiguous run of tiles: it totals them, one block scan gives its
-// first item / slot / split index, and a second walk over the run writes them.
+// Tiles are taken PLAN_TILE at a time (PLAN_ITEMS consecutive ones per thread); after the
+// scan every thread fills items of the chunk by a binary search of the tiles' item prefixes
+// in LDS, so a tile with many ranges does not serialise its thread.
 __global__ void __launch_bounds__(1024)
 split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
                   uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
     __shared__ uint64_t s_wsum[16];
+    __shared__ uint32_t s_ipre[PLAN_TILE + 1];   // first item of each tile of the chunk (chunk-relative)
+    __shared__ uint32_t s_spre[PLAN_TILE];       // first slot of each split tile (absolute), else ~0
     uint32_t T = t_count ? *t_count : t_host;
     if (T > t_host) T = t_host;
     if (uint64_t(*n_pairs) > capacity) T = 0;             // lists were not built: render nothing
-    const uint32_t per = (T + 1023) / 1024;
-    const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
-    uint32_t c_items = 0, c_slots = 0, c_split = 0;
-    uint32_t lo = t0 < t1 ? offs[t0] : 0u;
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t hi = offs[t + 1];
-        const uint32_t nr = n_ranges(hi - lo, SPLIT_RANGE);
-        const uint32_t m = nr > 1 ? 1u : 0u;
-        c_items += nr;
-        c_slots += nr * m;
-        c_split += m;
-        lo = hi;
-    }
-    const uint64_t e1 = block_excl_scan1024(uint64_t(c_items) | (uint64_t(c_slots) << 32), s_wsum);
-    const uint64_t e2 = block_excl_scan1024(uint64_t(c_split), s_wsum);
-    uint32_t i0 = uint32_t(e1), s0 = uint32_t(e1 >> 32), j = uint32_t(e2);
-    lo = t0 < t1 ? offs[t0] : 0u;
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t hi = offs[t + 1];
-        const uint32_t nr = n_ranges(hi - lo, SPLIT_RANGE);
-        const bool m = nr > 1;
-        for (uint32_t r = 0; r < nr; ++r) {
-            items[i0 + r] = t | (r << 24);
-            item_slot[i0 + r] = m ? s0 + r : 0xFFFFFFFFu;
+    uint32_t c_items = 0, c_slots = 0, c_split = 0;       // running totals over earlier chunks
+    for (uint32_t base = 0; base < T; base += PLAN_TILE) {
+        const uint32_t k0 = threadIdx.x * PLAN_ITEMS, t0 = base + k0;
+        uint32_t o[PLAN_ITEMS + 1];
+#pragma unroll
+        for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
+        uint32_t nr[PLAN_ITEMS];
+        uint32_t ci = 0, cs = 0, cm = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            nr[j] = t0 + j < T ? n_ranges(o[j + 1] - o[j], SPLIT_RANGE) : 0u;
+            ci += nr[j];
+            cs += nr[j] > 1 ? nr[j] : 0u;
+            cm += nr[j] > 1 ? 1u : 0u;
         }
-        if (m) {
-            split_tile[j] = t;
-            split_slot0[j] = s0;
-            s0 += nr;
-            ++j;
+        uint64_t tot1, tot2;
+        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &tot1);
+        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &tot2);
+        uint32_t i0 = uint32_t(e1), s0 = c_slots + uint32_t(e1 >> 32), js = c_split + uint32_t(e2);
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            s_ipre[k0 + j] = i0;
+            s_spre[k0 + j] = nr[j] > 1 ? s0 : 0xFFFFFFFFu;
+            if (nr[j] > 1) {
+                split_tile[js] = t0 + j;
+                split_slot0[js] = s0;
+                s0 += nr[j];
+                ++js;
+            }
+            i0 += nr[j];
         }
-        i0 += nr;
-        lo = hi;
+        const uint32_t n_items = uint32_t(tot1);
+        if (threadIdx.x == 0) s_ipre[PLAN_TILE] = n_items;
+        __syncthreads();
+        const uint32_t nt = min(uint32_t(PLAN_TILE), T - base);
+        for (uint32_t it = threadIdx.x; it < n_items; it += 1024) {
+            const int k = upper_index(s_ipre, int(nt), it);
+            const uint32_t r = it - s_ipre[k];
+            items[c_items + it] = (base + k) | (r << 24);
+            item_slot[c_items + it] = s_spre[k] == 0xFFFFFFFFu ? 0xFFFFFFFFu : s_spre[k] + r;
+        }
+        __syncthreads();
+        c_items += n_items;
+        c_slots += uint32_t(tot1 >> 32);
+        c_split += uint32_t(tot2);
     }
-    if (threadIdx.x == 1023) {
-        counts[0] = i0;
-        counts[1] = j;
+    if (threadIdx.x == 0) {
+        counts[0] = c_items;
+        counts[1] = c_split;
     }
 }
 

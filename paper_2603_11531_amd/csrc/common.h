@@ -108,4 +108,43 @@ __host__ __device__ __forceinline__ float bf16_round(float f) {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Exclusive scan of one value per thread over a 1024-thread block (all threads call);
+// *total receives the block's sum in every thread.  s_wsum: 16 shared slots.
+__device__ __forceinline__ uint64_t block_scan1024(uint64_t v, uint64_t *s_wsum, uint64_t *total) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(inc, o, 64);
+        if (l >= o) inc += u;
+    }
+    if (l == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t x = s_wsum[k];
+        pre += k < w ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+// Items per thread of the single-block planning scans (each thread loads its items
+// before the scan, so one global latency covers PLAN_TILE items).
+constexpr int PLAN_ITEMS = 4;
+constexpr int PLAN_TILE = 1024 * PLAN_ITEMS;
+
+// Largest j in [0, n) with pre[j] <= v, for a non-decreasing pre with pre[0] <= v.
+__device__ __forceinline__ int upper_index(const uint32_t *pre, int n, uint32_t v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace mgs

@@ -38,6 +38,37 @@ struct MlpFrags {
     bf16x8 A1[4], A2[4][2], AH[2];
     f32x4 B1[4], B2[4];
     float bphi, bo;
+    static constexpr bool kStreamed = false;
+    __device__ __forceinline__ bf16x8 a1(int mb) const { return A1[mb]; }
+    __device__ __forceinline__ bf16x8 a2(int mb, int kc) const { return A2[mb][kc]; }
+    __device__ __forceinline__ bf16x8 ah(int kc) const { return AH[kc]; }
+    __device__ __forceinline__ f32x4 b1(int mb) const { return B1[mb]; }
+    __device__ __forceinline__ f32x4 b2(int mb) const { return B2[mb]; }
+    __device__ __forceinline__ float b_phi() const { return bphi; }
+    __device__ __forceinline__ float b_o() const { return bo; }
+};
+
+// The same fragments read from a copy of the packed MLP in LDS at each use (for kernels
+// whose other live state leaves no room for them in registers).
+struct MlpLds {
+    const uint8_t *p;    // packed MLP (MGS_MLP_PACKED_BYTES) in LDS
+    int l;               // lane
+    static constexpr bool kStreamed = true;
+    __device__ __forceinline__ bf16x8 a1(int mb) const {
+        return reinterpret_cast<const bf16x8 *>(p + PK_L1)[mb * 64 + l];
+    }
+    __device__ __forceinline__ bf16x8 a2(int mb, int kc) const {
+        return reinterpret_cast<const bf16x8 *>(p + PK_L2)[(mb * 2 + kc) * 64 + l];
+    }
+    __device__ __forceinline__ bf16x8 ah(int kc) const { return reinterpret_cast<const bf16x8 *>(p + PK_H)[kc * 64 + l]; }
+    __device__ __forceinline__ f32x4 b1(int mb) const {
+        return *reinterpret_cast<const f32x4 *>(p + PK_B1 + 4 * (16 * mb + 4 * (l >> 4)));
+    }
+    __device__ __forceinline__ f32x4 b2(int mb) const {
+        return *reinterpret_cast<const f32x4 *>(p + PK_B2 + 4 * (16 * mb + 4 * (l >> 4)));
+    }
+    __device__ __forceinline__ float b_phi() const { return reinterpret_cast<const float *>(p + PK_BH)[0]; }
+    __device__ __forceinline__ float b_o() const { return reinterpret_cast<const float *>(p + PK_BH)[1]; }
 };
 
 __device__ __forceinline__ void load_mlp(const uint8_t *__restrict__ packed, int l, MlpFrags &F) {
@@ -90,8 +121,8 @@ __device__ __forceinline__ void lane_features(const float mu[3], const float ls[
 // The MLP for the wave's 64 Gaussians (lane l holds the features of Gaussian l);
 // returns lane l's (phi, m).  xs: the wave's LDS feature tile (its first 128
 // floats are reused to hand the head outputs back to their lanes).
-__device__ __forceinline__ void mlp_wave(const f32x8 f[4], const MlpFrags &F, __bf16 *xs, float &phi_o,
-                                         float &om_o) {
+template <typename W>
+__device__ __forceinline__ void mlp_wave(const f32x8 f[4], const W &F, __bf16 *xs, float &phi_o, float &om_o) {
     const int l = threadIdx.x & 63;
     const int lg = l >> 4;
     bf16x8 *row = reinterpret_cast<bf16x8 *>(xs + l * FEAT_STRIDE);
@@ -100,39 +131,43 @@ __device__ __forceinline__ void mlp_wave(const f32x8 f[4], const MlpFrags &F, __
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float hp[4], ho[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    // Gaussians nb * 16 .. nb * 16 + 15; their head outputs land in xo[nb * 16 + l] (phi) and
+    // xo[64 + nb * 16 + l] (m), lanes 0..15.  xo overlays feature rows 0..6, which block 0 has
+    // consumed before any block writes there.
+    float *xo = reinterpret_cast<float *>(xs);
+    auto block = [&](int nb) {
         const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(xs + (nb * 16 + (l & 15)) * FEAT_STRIDE + 8 * lg);
         f32x4 h1[4];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) h1[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.A1[mb], xb, F.B1[mb], 0, 0, 0);
+        for (int mb = 0; mb < 4; ++mb) h1[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1(mb), xb, F.b1(mb), 0, 0, 0);
         const bf16x8 x2a = relu_pack(h1[0], h1[1]);
         const bf16x8 x2b = relu_pack(h1[2], h1[3]);
+        // streamed weights: keep each layer's fragment loads inside that layer
+        if constexpr (W::kStreamed) __builtin_amdgcn_sched_barrier(0);
         f32x4 h2[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
-            h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.A2[mb][0], x2a, F.B2[mb], 0, 0, 0);
-            h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.A2[mb][1], x2b, h2[mb], 0, 0, 0);
+            h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2(mb, 0), x2a, F.b2(mb), 0, 0, 0);
+            h2[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2(mb, 1), x2b, h2[mb], 0, 0, 0);
         }
         const bf16x8 xha = relu_pack(h2[0], h2[1]);
         const bf16x8 xhb = relu_pack(h2[2], h2[3]);
+        if constexpr (W::kStreamed) __builtin_amdgcn_sched_barrier(0);
         f32x4 hz = {0.f, 0.f, 0.f, 0.f};
-        f32x4 hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.AH[0], xha, hz, 0, 0, 0);
-        hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.AH[1], xhb, hd, 0, 0, 0);
-        hp[nb] = hd[0];            // lanes 0..15 hold Gaussian nb * 16 + l
-        ho[nb] = hd[1];
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float *xo = reinterpret_cast<float *>(xs);
-    if (l < 16) {
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            xo[nb * 16 + l] = fmaxf(hp[nb] + F.bphi, 0.0f);
-            xo[64 + nb * 16 + l] = 1.0f / (1.0f + expf(-(ho[nb] + F.bo)));
+        f32x4 hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ah(0), xha, hz, 0, 0, 0);
+        hd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.ah(1), xhb, hd, 0, 0, 0);
+        if (l < 16) {                                       // lanes 0..15 hold Gaussian nb * 16 + l
+            xo[nb * 16 + l] = fmaxf(hd[0] + F.b_phi(), 0.0f);
+            xo[64 + nb * 16 + l] = 1.0f / (1.0f + expf(-(hd[1] + F.b_o())));
         }
+    };
+    if constexpr (W::kStreamed) {
+        // weights come from LDS at each use: one block at a time keeps few of them live
+#pragma unroll 1
+        for (int nb = 0; nb < 4; ++nb) block(nb);
+    } else {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) block(nb);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -26,35 +26,43 @@ project_kernel(mgs_gaussians g, CamK cam, const float *__restrict__ phi_in,
     store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);
 }
 
-// Enhancement MLP and projection in one pass: each wave reads its 64 Gaussians'
-// attributes once, runs the MLP on MFMA, hands every lane its own (phi, m) and
-// projects.  Same results as mgs_enhance followed by mgs_project.
-__global__ void __launch_bounds__(256)
+// Enhancement MLP and projection in one pass: each wave builds its 64 Gaussians'
+// features, runs the MLP on MFMA (weights read from an LDS copy), hands every lane its
+// own (phi, m) and projects.  Same results as mgs_enhance followed by mgs_project.
+__global__ void __launch_bounds__(256, 4)
 enhance_project_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, float alpha_min,
                        float4 *__restrict__ splat, uint2 *__restrict__ rect_out, uint32_t *__restrict__ ntiles_out,
                        float *__restrict__ phi_out, float *__restrict__ omod_out) {
     __shared__ __attribute__((aligned(16))) __bf16 s_x[4][64 * FEAT_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint8_t s_mlp[MGS_MLP_PACKED_BYTES];
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int64_t n = g.n;
     const int64_t ngroups = (n + 63) / 64;
-    MlpFrags F;
-    load_mlp(packed, l, F);
+    // the packed MLP lives in LDS (read at each use) so the registers go to the projection
+    static_assert(MGS_MLP_PACKED_BYTES % 16 == 0, "packed MLP size");
+    for (int k = threadIdx.x; k < MGS_MLP_PACKED_BYTES / 16; k += blockDim.x)
+        reinterpret_cast<uint4 *>(s_mlp)[k] = reinterpret_cast<const uint4 *>(packed)[k];
+    __syncthreads();
+    const MlpLds F{s_mlp, l};
     for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
         const int64_t i = grp * 64 + l;
         const bool valid = i < n;
-        GaussIn in;
         f32x8 f[4];
         if (valid) {
-            in = load_gauss(g, i, nullptr, nullptr);
-            lane_features(in.mu, in.ls, in.q, in.sh, cam, f);
+            const GaussIn a = load_gauss(g, i, nullptr, nullptr);
+            lane_features(a.mu, a.ls, a.q, a.sh, cam, f);
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
         float ph, om;
         mlp_wave(f, F, s_x[w], ph, om);
+        // The projection reads the attributes again (cache hits) instead of keeping them in
+        // registers across the MLP: fewer live registers, more waves in flight.
+        __asm__ volatile("" ::: "memory");
         if (valid) {
+            GaussIn in = load_gauss(g, i, nullptr, nullptr);
             in.phi = ph;
             in.om = om;
             store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);
