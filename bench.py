@@ -281,11 +281,16 @@ def main():
 
     stream = torch.cuda.current_stream()
 
+    src = {"scene": ds}
+
     def frame(k, sorted_path, ev=None):
         cs = cam_structs[k % len(cam_structs)]
         if ev is not None:
             ev[0].record(stream)
-        R.enhance_project(ds, cs, dm)            # Eq. 4 MLP fused with the projection
+        if isinstance(src["scene"], M.DeviceNVQ):  # attributes read through the NVQ codebooks
+            R.enhance_project_nvq(src["scene"], cs, dm)
+        else:
+            R.enhance_project(src["scene"], cs, dm)  # Eq. 4 MLP fused with the projection
         if ev is not None:
             ev[1].record(stream)
         R.bin(sorted_path)
@@ -328,6 +333,26 @@ def main():
         res_sorted = dict(fps=round(args.steps / wall_s, 2), ms_per_frame=round(1e3 * wall_s / args.steps, 4),
                           stage_ms=dict(zip(["enhance_project", "bin_sorted", "blend_sorted"],
                                             [round(float(v), 4) for v in stages_s.mean(axis=0)])))
+    res_nvq = None
+    if not args.no_extra:
+        # the same positions with vector-quantised attributes (Sec. 3.3): 5 uint16 codes per
+        # Gaussian into five 1024 x 4 codebooks instead of 20 float32 attributes
+        log("timing OIT with NVQ-coded attributes ...")
+        dq = M.DeviceNVQ(mgs_data.make_nvq(scene, 7))
+        src["scene"] = dq
+        maxq = 0
+        for c in cams:
+            R.render(dq, c, dm, bg=bg)
+            maxq = max(maxq, R.pairs())
+        R.ensure_capacity(int(maxq * 1.1) + 4096)
+        wall_q, stages_q, _ = run(False)
+        src["scene"] = ds
+        res_nvq = dict(fps=round(args.steps / wall_q, 2), ms_per_frame=round(1e3 * wall_q / args.steps, 4),
+                       stage_ms=dict(zip(["enhance_project_nvq", "bin", "blend_oit"],
+                                         [round(float(v), 4) for v in stages_q.mean(axis=0)])),
+                       resident_bytes_per_gaussian=round(dq.nbytes() / dq.n, 2),
+                       float32_bytes_per_gaussian=round(ds.nbytes() / ds.n, 2))
+        del dq
     blend_ms = float(stages[:, 2].mean())
     evals = 256.0 * mean_P
     achieved = evals * BLEND_FLOP_PER_EVAL / (blend_ms * 1e-3) / 1e12
@@ -363,6 +388,7 @@ def main():
         "enhance_project_gbs": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
+        "nvq": res_nvq,
         "roofline": {"bound": "alu",
                      "kernel": "mgs_blend_oit_split (split_plan_kernel + blend_range_kernel + merge_ranges_kernel)",
                      "achieved": round(achieved, 2),

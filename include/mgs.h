@@ -165,6 +165,45 @@ int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const voi
                         float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
 
 /*
+ * Vector-quantised Gaussians (Sec. 3.3, neural vector quantization: attribute
+ * sub-vectors, each with its own codebook; five groups and 2^10 codewords per
+ * codebook in the paper's deployed configuration).  Positions stay float32.  The 20
+ * other attributes, in the order [log_scale(3), quat(4) w,x,y,z, opacity_logit,
+ * sh(12) plane 3k+ch], are five consecutive sub-vectors of four values: attribute
+ * value j of group g of Gaussian i is codebooks[(g * MGS_NVQ_CODEWORDS + codes[g * n + i]) * 4 + j].
+ * Codes are taken modulo MGS_NVQ_CODEWORDS, so no code can read outside the codebooks.
+ * Device pointers: mean [3][n] float32, codes [5][n] uint16, codebooks
+ * [5][1024][4] float32 (16-byte aligned; the caller owns all of them).
+ */
+#define MGS_NVQ_GROUPS    5
+#define MGS_NVQ_DIM       4
+#define MGS_NVQ_CODEWORDS 1024
+
+typedef struct mgs_gaussians_nvq {
+    int64_t n;
+    const float *mean;
+    const uint16_t *codes;
+    const float *codebooks;
+} mgs_gaussians_nvq;
+
+/*
+ * mgs_nvq_decode -- the codebook lookup above, written out as the float32 SoA planes
+ * of mgs_gaussians (log_scale [3][n], quat [4][n], opacity_logit [n], sh [12][n];
+ * device, caller-owned).  Bit-exact copies of the codewords.
+ */
+int mgs_nvq_decode(const mgs_gaussians_nvq *q, float *log_scale, float *quat, float *opacity_logit, float *sh,
+                   void *stream);
+
+/*
+ * mgs_enhance_project_nvq -- mgs_enhance_project reading the attributes through the
+ * codebooks (22 bytes per Gaussian from memory: mean and codes; the 80 KB of
+ * codebooks stay in cache).  Same outputs, bit for bit, as mgs_enhance_project on
+ * the decoded attributes.  packed_mlp as for mgs_enhance (required).
+ */
+int mgs_enhance_project_nvq(const mgs_gaussians_nvq *q, const mgs_camera *cam, const void *packed_mlp, int tile,
+                            float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
  * mgs_bin_workspace -- device workspace bytes mgs_bin needs for n Gaussians,
  * a tile grid of tiles_x * tiles_y and at most `capacity` tile/Gaussian pairs.
  */

@@ -28,6 +28,7 @@ __all__ = [
     "Camera", "look_at", "make_scene_uniform", "make_scene_unbounded",
     "make_scene_ball", "make_mlp", "circle_poses", "spline_poses",
     "make_config", "tiny_scene", "perturb_scene", "MLP_IN", "MLP_HIDDEN",
+    "make_nvq", "NVQ_GROUPS", "NVQ_DIM", "NVQ_CODEWORDS",
 ]
 
 MLP_IN = 22       # [P(3), s(3), q(4), Y(12)]
@@ -247,3 +248,35 @@ def make_config(name, seed=0, n=None):
         cams = circle_poses(4, 4.0, 1600, 1063, f=1600.0)
         return scene, cams, make_mlp(seed + 1), 16
     raise ValueError(f"unknown workload {name!r}")
+
+
+# ---------------------------------------------------------------------------
+# Vector-quantised scenes.  The 20 non-position attributes of a Gaussian are cut into
+# NVQ_GROUPS sub-vectors of NVQ_DIM values, each an index into its own codebook of
+# NVQ_CODEWORDS rows (see oracle/nvq.py for the layout both sides decode).
+NVQ_GROUPS = 5
+NVQ_DIM = 4
+NVQ_CODEWORDS = 1024
+
+
+def _attribute_rows(scene):
+    """(N, 20) float32 rows [log_scale(3), quat(4), opacity_logit, sh(12)] of a scene."""
+    return np.concatenate([scene["log_scale"].T, scene["quat"].T, scene["opacity_logit"][:, None],
+                           scene["sh"].T], axis=1).astype(np.float32)
+
+
+def make_nvq(scene, seed, codewords=NVQ_CODEWORDS):
+    """A vector-quantised scene with the positions of ``scene``: every codebook holds the
+    sub-vectors of ``codewords`` Gaussians of ``scene`` drawn at random (so each attribute
+    keeps the scene's distribution), and every Gaussian draws its five codes uniformly.
+    Returns dict(mean [3][N] float32, codes [5][N] uint16, codebooks [5][codewords][4] float32).
+    """
+    rng = np.random.default_rng(seed)
+    rows = _attribute_rows(scene)
+    n = rows.shape[0]
+    cb = np.empty((NVQ_GROUPS, codewords, NVQ_DIM), np.float32)
+    for g in range(NVQ_GROUPS):
+        pick = rng.integers(0, n, size=codewords)
+        cb[g] = rows[pick, g * NVQ_DIM:(g + 1) * NVQ_DIM]
+    codes = rng.integers(0, codewords, size=(NVQ_GROUPS, n)).astype(np.uint16)
+    return dict(mean=np.ascontiguousarray(scene["mean"], np.float32), codes=codes, codebooks=cb)

@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
 statement of what the render pass computes, written from the paper
 (Mobile-GS, arXiv 2603.11531): Eq. 2 and Eq. 3 (Sec. 3.1) for the
 order-independent blend, Eq. 4 for the view-dependent enhancement MLP, and
-Eq. 11 (Appendix B) for the sorted alpha-blend comparison path.  It shares no
+Eq. 11 (Appendix B) for the sorted alpha-blend comparison path, and the
+codebook decode of vector-quantised attributes (Sec. 3.3, ``oracle.nvq``).  It shares no
 code with the HIP path and imports nothing from it.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it; the product path never does.
@@ -19,3 +20,4 @@ authors' unreleased code), which is parity unpinned by nature.
 """
 from .render import *  # noqa: F401,F403
 from .render import __all__  # noqa: F401
+from . import nvq  # noqa: F401

@@ -31,8 +31,9 @@ EXPORTED = [
     "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_blend_oit_split_workspace", "mgs_blend_oit_split",
     "mgs_bin_sorted_workspace",
     "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
-    "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch",
+    "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
 ]
+MGS_NVQ_GROUPS, MGS_NVQ_DIM, MGS_NVQ_CODEWORDS = 5, 4, 1024
 
 
 class MgsError(RuntimeError):
@@ -55,6 +56,10 @@ class mgs_gaussians(C.Structure):
 class mgs_gaussians_grad(C.Structure):
     _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
                 ("opacity_logit", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class mgs_gaussians_nvq(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("codes", C.c_void_p), ("codebooks", C.c_void_p)]
 
 
 class mgs_projected(C.Structure):
@@ -90,6 +95,9 @@ def load(path=LIB_PATH):
         "mgs_bin_sorted": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_sorted": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, f32,
                                    vp, vp]),
+        "mgs_nvq_decode": (i32, [P(mgs_gaussians_nvq), vp, vp, vp, vp, vp]),
+        "mgs_enhance_project_nvq": (i32, [P(mgs_gaussians_nvq), P(mgs_camera), vp, i32, f32, P(mgs_projected), vp,
+                                          vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -150,6 +158,15 @@ def make_gaussians(scene) -> mgs_gaussians:
     g.n = int(scene["opacity_logit"].numel())
     g.mean, g.log_scale, g.quat = (ptr(scene[k]).value for k in ("mean", "log_scale", "quat"))
     g.opacity_logit, g.sh = ptr(scene["opacity_logit"]).value, ptr(scene["sh"]).value
+    return g
+
+
+def make_gaussians_nvq(q) -> mgs_gaussians_nvq:
+    """``q`` = dict of device tensors: mean [3][N] float32, codes [5][N] int16 (uint16 bits),
+    codebooks [5][1024][4] float32."""
+    g = mgs_gaussians_nvq()
+    g.n = int(q["codes"].shape[1])
+    g.mean, g.codes, g.codebooks = (ptr(q[k]).value for k in ("mean", "codes", "codebooks"))
     return g
 
 

@@ -45,6 +45,34 @@ class DeviceScene:
         return sum(v.numel() * 4 for v in self.t.values())
 
 
+class DeviceNVQ:
+    """A vector-quantised scene resident in device memory (mgs_gaussians_nvq): float32
+    positions, five uint16 codes per Gaussian and the five 1024 x 4 codebooks."""
+
+    def __init__(self, q, device="cuda"):
+        codes = np.ascontiguousarray(q["codes"], dtype=np.uint16).view(np.int16)   # torch has no uint16 ops
+        self.t = {"mean": torch.as_tensor(np.ascontiguousarray(q["mean"], dtype=np.float32)).to(device),
+                  "codes": torch.as_tensor(codes).to(device),
+                  "codebooks": torch.as_tensor(np.ascontiguousarray(q["codebooks"], dtype=np.float32)).to(device)}
+        self.n = int(self.t["codes"].shape[1])
+        self.struct = L.make_gaussians_nvq(self.t)
+
+    def nbytes(self):
+        return sum(v.numel() * v.element_size() for v in self.t.values())
+
+    def decode(self, stream=None):
+        """mgs_nvq_decode into a new DeviceScene (float32 SoA planes)."""
+        dev = self.t["mean"].device
+        planes = {"mean": self.t["mean"],
+                  "log_scale": torch.empty(3, self.n, dtype=torch.float32, device=dev),
+                  "quat": torch.empty(4, self.n, dtype=torch.float32, device=dev),
+                  "opacity_logit": torch.empty(self.n, dtype=torch.float32, device=dev),
+                  "sh": torch.empty(12, self.n, dtype=torch.float32, device=dev)}
+        L.check(L.lib().mgs_nvq_decode(L.C.byref(self.struct), L.ptr(planes["log_scale"]), L.ptr(planes["quat"]),
+                                       L.ptr(planes["opacity_logit"]), L.ptr(planes["sh"]), L.stream_ptr(stream)))
+        return DeviceScene.from_tensors(planes)
+
+
 class DeviceMLP:
     """MLP parameters on the device (one float32 array, layout of mgs.h) plus the
     packed bf16 MFMA operands that mgs_enhance reads."""
@@ -138,6 +166,12 @@ class Renderer:
                                             L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
                                             L.ptr(self.omod), L.stream_ptr(stream)))
 
+    def enhance_project_nvq(self, q: DeviceNVQ, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None):
+        """Fused enhance + project reading the attributes through the NVQ codebooks."""
+        L.check(L.lib().mgs_enhance_project_nvq(L.C.byref(q.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
+                                                L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
+                                                L.ptr(self.omod), L.stream_ptr(stream)))
+
     def bin(self, sorted_path=False, stream=None):
         self.ensure_capacity(self.capacity, sorted_path)
         lib = L.lib()
@@ -176,10 +210,15 @@ class Renderer:
     # -- whole pass -----------------------------------------------------------
     def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
                check_capacity=True, stream=None, fused=False, split=True):
-        """enhance -> project -> bin -> blend.  With check_capacity the host reads the pair
-        count once and re-bins with a larger capacity on overflow."""
+        """enhance -> project -> bin -> blend (``scene`` a DeviceScene, or a DeviceNVQ whose
+        attributes are read through its codebooks).  With check_capacity the host reads the
+        pair count once and re-bins with a larger capacity on overflow."""
         cam_s = L.make_camera(cam)
-        if mlp is not None and fused:
+        if isinstance(scene, DeviceNVQ):
+            if mlp is None:
+                raise ValueError("a vector-quantised scene renders through the fused enhance + project (needs an MLP)")
+            self.enhance_project_nvq(scene, cam_s, mlp, stream=stream)
+        elif mlp is not None and fused:
             self.enhance_project(scene, cam_s, mlp, stream=stream)
         else:
             if mlp is not None:

@@ -584,3 +584,54 @@ def test_bf16_rounding_passes_gradients_straight_through():
     assert y.tolist() == O.bf16_round(x.detach()).tolist()
     (y * torch.tensor([0.3, -1.7, 2.5], dtype=torch.float64)).sum().backward()
     assert x.grad.tolist() == [0.3, -1.7, 2.5]          # not rounded to bfloat16
+
+
+# --------------------------------------------------------------------------
+# Vector-quantised attributes (Sec. 3.3): the decode is a lookup.
+# --------------------------------------------------------------------------
+def test_nvq_decode_hand_built_codebook():
+    """Codeword value j of row b in codebook g is 1000 g + b + j / 8 (exact in float32), so
+    every decoded attribute names its group, row and slot."""
+    g_ = np.arange(5)[:, None, None]
+    b_ = np.arange(1024)[None, :, None]
+    j_ = np.arange(4)[None, None, :]
+    cb = (1000.0 * g_ + b_ + j_ / 8.0).astype(np.float32)
+    rng = np.random.default_rng(0)
+    codes = rng.integers(0, 1024, size=(5, 300)).astype(np.uint16)
+    mean = rng.normal(size=(3, 300)).astype(np.float32)
+    sc = O.nvq.decode(codes, cb, mean)
+    c = codes.astype(np.float64)
+    for a in range(3):
+        assert np.array_equal(sc["log_scale"][a], (c[0] + a / 8.0).astype(np.float32))
+    assert np.array_equal(sc["quat"][0], (c[0] + 3 / 8.0).astype(np.float32))
+    for a in range(3):
+        assert np.array_equal(sc["quat"][1 + a], (1000 + c[1] + a / 8.0).astype(np.float32))
+    assert np.array_equal(sc["opacity_logit"], (1000 + c[1] + 3 / 8.0).astype(np.float32))
+    for k in range(12):
+        g = 2 + k // 4
+        assert np.array_equal(sc["sh"][k], (1000 * g + c[g] + (k % 4) / 8.0).astype(np.float32))
+    assert np.array_equal(sc["mean"], mean)
+
+
+def test_nvq_identity_codebook_reproduces_the_scene():
+    """Codebooks holding a scene's own sub-vectors, with code = Gaussian index, decode back to
+    the scene exactly (N <= 1024)."""
+    scene = mgs_data.make_scene_uniform(700, 5)
+    rows = np.concatenate([scene["log_scale"].T, scene["quat"].T, scene["opacity_logit"][:, None],
+                           scene["sh"].T], axis=1)
+    cb = np.zeros((5, 1024, 4), np.float32)
+    for g in range(5):
+        cb[g, :700] = rows[:, 4 * g:4 * g + 4]
+    codes = np.tile(np.arange(700, dtype=np.uint16), (5, 1))
+    sc = O.nvq.decode(codes, cb, scene["mean"])
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
+        assert np.array_equal(sc[k], scene[k]), k
+
+
+def test_make_nvq_keeps_positions_and_draws_codewords_from_the_scene():
+    scene = mgs_data.make_scene_uniform(5000, 6)
+    q = mgs_data.make_nvq(scene, 7)
+    assert q["codes"].dtype == np.uint16 and q["codes"].shape == (5, 5000) and q["codes"].max() < 1024
+    assert q["codebooks"].shape == (5, 1024, 4) and np.array_equal(q["mean"], scene["mean"])
+    rows = {tuple(r) for r in np.concatenate([scene["log_scale"].T, scene["quat"].T[:, :1]], axis=1)}
+    assert all(tuple(r) in rows for r in q["codebooks"][0])
