@@ -310,7 +310,7 @@ typedef struct mgs_request {
 
 /*
  * mgs_batch_workspace -- bytes of workspace for batches of at most max_gaussians
- * Gaussians in total (each request's count rounded up to a multiple of 64),
+ * Gaussians in total (each request's count rounded up to a multiple of 256),
  * max_tiles 16x16 tiles in total, and `capacity` tile/Gaussian pairs in total.
  */
 int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uint64_t capacity, size_t *bytes);

@@ -6,10 +6,11 @@
 namespace mgs {
 
 constexpr int BATCH_MAX_REQ = 64;
+constexpr int BATCH_ALIGN = 256;       // request Gaussian ranges start on multiples of this
 
 // Written once per batch on the device.  Gaussians of request r occupy the global
-// index range [gbase[r], gbase[r] + n_r), each range starting on a multiple of 64 so a
-// wave-sized MLP group never mixes requests; tiles of request r are the global tile
+// index range [gbase[r], gbase[r] + n_r), each range starting on a multiple of
+// BATCH_ALIGN so a projection block never mixes requests; tiles of request r are the global tile
 // ids [tbase[r], tbase[r + 1]) and its 8x8-tile supertiles (binning) the global ids
 // [stbase[r], stbase[r + 1]).
 struct BatchPlan {

@@ -37,7 +37,7 @@ __global__ void batch_plan_kernel(const mgs_request *__restrict__ reqs, const in
         plan->tiles_x[r] = txu;
         plan->tiles_y[r] = tyu;
         plan->st_x[r] = (txu + 7) / 8;
-        g += (uint64_t(q.g.n > 0 ? q.g.n : 0) + 63) / 64 * 64;
+        g += (uint64_t(q.g.n > 0 ? q.g.n : 0) + BATCH_ALIGN - 1) / BATCH_ALIGN * BATCH_ALIGN;
         t += uint64_t(tx > 0 ? tx : 0) * uint64_t(ty > 0 ? ty : 0);
         st += uint64_t((txu + 7) / 8) * uint64_t((tyu + 7) / 8);
     }
@@ -53,57 +53,63 @@ __global__ void batch_plan_kernel(const mgs_request *__restrict__ reqs, const in
     plan->st_total = uint32_t(st);
 }
 
-// Enhancement MLP over all requests that carry one; one wave per 64-Gaussian group.
+// Enhancement MLP (for requests that carry one) and projection of every request's Gaussians
+// into the global index space, one 256-Gaussian block per iteration; request ranges start on
+// multiples of 256, so a block never mixes requests and one LDS copy of its request's packed
+// MLP serves the block.  Alignment padding gets n_tiles = 0; nothing past n_total is written
+// (the binning reads only the first n_total Gaussians).  Same arithmetic as the single-view
+// enhance + project, so a request renders bit-identically alone and in a batch.
 __global__ void __launch_bounds__(256)
-batch_enhance_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan,
-                     float *__restrict__ phi, float *__restrict__ omod) {
+batch_enhance_project_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan,
+                             float alpha_min, float4 *__restrict__ splat, uint2 *__restrict__ rect_out,
+                             uint32_t *__restrict__ ntiles_out) {
     __shared__ __attribute__((aligned(16))) __bf16 s_x[4][64 * FEAT_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint8_t s_mlp[MGS_MLP_PACKED_BYTES];
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int nreq = plan->nreq;
-    if (nreq == 0) return;
-    const int64_t ngroups = plan->n_total / 64;
-    MlpFrags F;
+    if (nreq == 0) return;                                             // grid-uniform
+    const uint32_t nblk = plan->n_total / BATCH_ALIGN;
     const void *loaded = nullptr;
-    for (int64_t grp = int64_t(blockIdx.x) * 4 + w; grp < ngroups; grp += int64_t(gridDim.x) * 4) {
-        const int r = find_request(plan->gbase, nreq, uint32_t(grp * 64));
+    const MlpLds F{s_mlp, l};
+    for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const uint32_t k0 = b * BATCH_ALIGN;
+        const int r = find_request(plan->gbase, nreq, k0);             // block-uniform
         const mgs_request &q = reqs[r];
-        if (q.packed_mlp == nullptr) continue;                       // wave-uniform
-        if (q.packed_mlp != loaded) {
-            load_mlp(static_cast<const uint8_t *>(q.packed_mlp), l, F);
+        const CamK cam = camk_device(q.cam);
+        const bool mlp = q.packed_mlp != nullptr;
+        if (mlp && q.packed_mlp != loaded) {
+            __syncthreads();                                           // the previous copy is no longer read
+            for (int k = threadIdx.x; k < MGS_MLP_PACKED_BYTES / 16; k += blockDim.x)
+                reinterpret_cast<uint4 *>(s_mlp)[k] = reinterpret_cast<const uint4 *>(q.packed_mlp)[k];
+            __syncthreads();
             loaded = q.packed_mlp;
         }
-        const int64_t i0 = grp * 64 - plan->gbase[r];
-        enhance_group(q.g, camk_device(q.cam), i0, F, s_x[w], phi, omod, grp * 64);
-    }
-}
-
-// Projection of every request's Gaussians into the global index space; padding and
-// unused slots up to max_gauss get n_tiles = 0.
-__global__ void __launch_bounds__(256)
-batch_project_kernel(const mgs_request *__restrict__ reqs, const BatchPlan *__restrict__ plan, int64_t max_gauss,
-                     const float *__restrict__ phi, const float *__restrict__ omod, float alpha_min,
-                     float4 *__restrict__ splat, uint2 *__restrict__ rect_out, uint32_t *__restrict__ ntiles_out) {
-    const int nreq = plan->nreq;
-    const uint32_t ntot = plan->n_total;
-    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < max_gauss;
-         k += int64_t(gridDim.x) * blockDim.x) {
-        if (k < int64_t(ntot)) {
-            const int r = find_request(plan->gbase, nreq, uint32_t(k));
-            const mgs_request &q = reqs[r];
-            const int64_t i = k - plan->gbase[r];
-            if (i < q.g.n) {
-                GaussIn in = load_gauss(q.g, i, nullptr, nullptr);
-                if (q.packed_mlp != nullptr) {
-                    in.phi = phi[k];
-                    in.om = omod[k];
-                }
-                store_proj(project_gaussian(in, camk_device(q.cam), alpha_min), k, splat, rect_out, ntiles_out);
-                continue;
+        const uint32_t k = k0 + threadIdx.x;
+        const int64_t i = int64_t(k) - plan->gbase[r];
+        const bool valid = i < q.g.n;
+        float ph = 1.0f, om = 1.0f;
+        if (mlp) {                                                     // block-uniform
+            f32x8 f[4];
+            if (valid) {
+                const GaussIn a = load_gauss(q.g, i, nullptr, nullptr);
+                lane_features(a.mu, a.ls, a.q, a.sh, cam, f);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
             }
+            mlp_wave(f, F, s_x[w], ph, om);
+            __asm__ volatile("" ::: "memory");                         // re-read the attributes below
         }
-        rect_out[k] = make_uint2(0u, 0u);
-        ntiles_out[k] = 0u;
+        if (valid) {
+            GaussIn in = load_gauss(q.g, i, nullptr, nullptr);
+            in.phi = ph;
+            in.om = om;
+            store_proj(project_gaussian(in, cam, alpha_min), k, splat, rect_out, ntiles_out);
+        } else {
+            rect_out[k] = make_uint2(0u, 0u);
+            ntiles_out[k] = 0u;
+        }
     }
 }
 
@@ -113,7 +119,7 @@ __global__ void batch_status_kernel(const BatchPlan *__restrict__ plan, int32_t 
 }
 
 struct BatchLayout {
-    size_t plan, phi, omod, splat, rect, ntiles, offs, gids, bin, split, total;
+    size_t plan, splat, rect, ntiles, offs, gids, bin, split, total;
 };
 
 inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t capacity) {
@@ -121,8 +127,6 @@ inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t c
     const size_t ng = size_t(max_gauss > 0 ? max_gauss : 1), cap = size_t(capacity > 0 ? capacity : 1);
     size_t o = 0;
     L.plan = o;   o = align_up(o + sizeof(BatchPlan), 256);
-    L.phi = o;    o = align_up(o + ng * 4, 256);
-    L.omod = o;   o = align_up(o + ng * 4, 256);
     L.splat = o;  o = align_up(o + ng * 48, 256);
     L.rect = o;   o = align_up(o + ng * 8, 256);
     L.ntiles = o; o = align_up(o + ng * 4, 256);
@@ -159,8 +163,6 @@ extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_re
     hipStream_t s = as_stream(stream);
     char *w = static_cast<char *>(ws);
     BatchPlan *plan = reinterpret_cast<BatchPlan *>(w + L.plan);
-    float *phi = reinterpret_cast<float *>(w + L.phi);
-    float *omod = reinterpret_cast<float *>(w + L.omod);
     float4 *splat = reinterpret_cast<float4 *>(w + L.splat);
     uint2 *rect = reinterpret_cast<uint2 *>(w + L.rect);
     uint32_t *ntiles = reinterpret_cast<uint32_t *>(w + L.ntiles);
@@ -170,14 +172,10 @@ extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_re
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(64), 0, s, requests, n_requests, uint64_t(max_gaussians),
                        uint64_t(max_tiles), plan);
     MGS_LAUNCH_CHECK("batch_plan_kernel");
-    const int64_t groups = (max_gaussians + 63) / 64;
-    const unsigned eblocks = unsigned(groups / 4 + 1 < 1024 ? groups / 4 + 1 : 1024);
-    hipLaunchKernelGGL(batch_enhance_kernel, dim3(eblocks), dim3(256), 0, s, requests, plan, phi, omod);
-    MGS_LAUNCH_CHECK("batch_enhance_kernel");
-    const unsigned pblocks = unsigned((max_gaussians + 255) / 256 < 8192 ? (max_gaussians + 255) / 256 : 8192);
-    hipLaunchKernelGGL(batch_project_kernel, dim3(pblocks), dim3(256), 0, s, requests, plan, max_gaussians, phi, omod,
-                       alpha_min, splat, rect, ntiles);
-    MGS_LAUNCH_CHECK("batch_project_kernel");
+    const int64_t pblk = (max_gaussians + BATCH_ALIGN - 1) / BATCH_ALIGN;
+    hipLaunchKernelGGL(batch_enhance_project_kernel, dim3(unsigned(pblk < 4096 ? pblk : 4096)), dim3(256), 0, s,
+                       requests, plan, alpha_min, splat, rect, ntiles);
+    MGS_LAUNCH_CHECK("batch_enhance_project_kernel");
     mgs_projected proj;
     proj.splat = reinterpret_cast<float *>(splat);
     proj.rect = reinterpret_cast<uint32_t *>(rect);

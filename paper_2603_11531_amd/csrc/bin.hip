@@ -207,9 +207,11 @@ __global__ void __launch_bounds__(256)
 expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
               const uint64_t *__restrict__ block_first, const float4 *__restrict__ splat, int64_t n,
               Map map, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
-              K *__restrict__ keys, uint32_t *__restrict__ vals, KeyFn keyfn) {
+              K *__restrict__ keys, uint32_t *__restrict__ vals, KeyFn keyfn,
+              const uint32_t *__restrict__ n_live = nullptr) {
     __shared__ uint32_t s_wsum[4];
     if (uint64_t(*n_pairs) > capacity) return;          // block-uniform
+    if (n_live && int64_t(*n_live) < n) n = *n_live;    // Gaussians past the live count are not read
     const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
     uint32_t cnt = g < n ? ntiles[g] : 0u;
     if (SHIFT && cnt > 0) cnt = n_super(rect[g]);       // entries per supertile instead of per tile
@@ -444,24 +446,24 @@ radix_downsweep_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict
 }
 
 // ----------------------------------------------------------------- tile ranges
-// offsets[u] = first pair of tile u (grid-stride over the P + 1 boundaries).
+// offsets[u] = first pair of tile u, for u = 0 .. n_tiles (offsets[n_tiles] = P).  Element i
+// writes the boundaries between its key and the previous one; the boundaries after the
+// last key (tiles with no pairs at the end, the sentinel) are spread over all threads.
 template <typename K>
 __global__ void __launch_bounds__(256)
 tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
                    int shift, uint32_t n_tiles, uint32_t *__restrict__ offsets) {
     const uint32_t P = *n_pairs;
     if (uint64_t(P) > capacity) return;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= int64_t(P);
-         i += int64_t(gridDim.x) * blockDim.x) {
-        if (i < int64_t(P)) {
-            const int64_t t = int64_t(keys[i] >> shift);
-            const int64_t tp = i > 0 ? int64_t(keys[i - 1] >> shift) : -1;
-            for (int64_t u = tp + 1; u <= t; ++u) offsets[u] = uint32_t(i);
-        } else {
-            const int64_t tl = P > 0 ? int64_t(keys[P - 1] >> shift) : -1;
-            for (int64_t u = tl + 1; u <= int64_t(n_tiles); ++u) offsets[u] = P;
-        }
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = tid; i < int64_t(P); i += stride) {
+        const int64_t t = int64_t(keys[i] >> shift);
+        const int64_t tp = i > 0 ? int64_t(keys[i - 1] >> shift) : -1;
+        for (int64_t u = tp + 1; u <= t; ++u) offsets[u] = uint32_t(i);
     }
+    const int64_t tl = P > 0 ? int64_t(keys[P - 1] >> shift) : -1;
+    for (int64_t u = tl + 1 + tid; u <= int64_t(n_tiles); u += stride) offsets[u] = P;
 }
 
 // ----------------------------------------------------------------- two-level binning
@@ -513,8 +515,9 @@ struct SuperBatch {
 // Per 256 Gaussians: number of supertile entries and of tile pairs.
 __global__ void __launch_bounds__(256)
 super_count_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles, int64_t n,
-                   uint64_t *__restrict__ sums_e, uint64_t *__restrict__ sums_p) {
+                   const uint32_t *__restrict__ n_live, uint64_t *__restrict__ sums_e, uint64_t *__restrict__ sums_p) {
     __shared__ uint64_t ws[2][4];
+    if (n_live && int64_t(*n_live) < n) n = *n_live;           // Gaussians past the live count are not read
     const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const uint32_t nt = g < n ? ntiles[g] : 0u;
     uint64_t e = nt > 0 ? n_super(rect[g]) : 0u, p = nt;
@@ -533,58 +536,102 @@ super_count_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ 
     }
 }
 
-// One block: exclusive scan of the entry counts in place, their total E, and the pair
-// total P (clamped to 2^32 - 1) -> n_pairs.  E is written as 0 when P > capacity, so
-// nothing after this step does any work.
+// Level-1 slots: exclusive scan of the per-256-Gaussian entry counts (in place), their total
+// E, and the pair total P (clamped to 2^32 - 1) -> n_pairs; E is written as 0 when
+// P > capacity, so nothing after this step does any work.  Chunked scan (see plan_chunks):
+// pass 1 writes the chunk totals of both counts, pass 2 the prefixes.
 __global__ void __launch_bounds__(1024)
-super_scan_kernel(uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ sums_p, int nb, uint64_t capacity,
+super_sum_kernel(const uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ sums_p, int nb,
+                 uint64_t *__restrict__ part_e, uint64_t *__restrict__ part_p) {
+    __shared__ uint64_t s_wsum[16];
+    const uint32_t nc = plan_chunks(uint64_t(nb));
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const int i0 = int(c) * PLAN_TILE + int(threadIdx.x) * PLAN_ITEMS;
+        uint64_t e = 0, p = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) {
+            e += i0 + j < nb ? sums_e[i0 + j] : 0u;
+            p += i0 + j < nb ? sums_p[i0 + j] : 0u;
+        }
+        uint64_t te, tp;
+        block_scan1024(e, s_wsum, &te);
+        block_scan1024(p, s_wsum, &tp);
+        if (threadIdx.x == 0) {
+            part_e[c] = te;
+            part_p[c] = tp;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+super_scan_kernel(uint64_t *__restrict__ sums_e, int nb, const uint64_t *__restrict__ part_e,
+                  const uint64_t *__restrict__ totals /* {E, P} */, uint64_t capacity,
                   uint32_t *__restrict__ e_total, uint32_t *__restrict__ n_pairs) {
     __shared__ uint64_t s_wsum[16];
-    uint64_t carry = 0, ptot = 0;
-    for (int base = 0; base < nb; base += 1024 * PLAN_ITEMS) {
-        const int i0 = base + int(threadIdx.x) * PLAN_ITEMS;
-        uint64_t v[PLAN_ITEMS], sum = 0, psum = 0;
+    const uint32_t nc = plan_chunks(uint64_t(nb));
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const int i0 = int(c) * PLAN_TILE + int(threadIdx.x) * PLAN_ITEMS;
+        uint64_t v[PLAN_ITEMS], sum = 0;
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             v[j] = i0 + j < nb ? sums_e[i0 + j] : 0u;
-            psum += i0 + j < nb ? sums_p[i0 + j] : 0u;
             sum += v[j];
         }
-        uint64_t tot, ptot_blk;
-        uint64_t o = block_scan1024(sum, s_wsum, &tot) + carry;
-        block_scan1024(psum, s_wsum, &ptot_blk);
+        uint64_t tot;
+        uint64_t o = block_scan1024(sum, s_wsum, &tot) + part_e[c];
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             if (i0 + j < nb) sums_e[i0 + j] = o;
             o += v[j];
         }
-        carry += tot;
-        ptot += ptot_blk;
     }
-    if (threadIdx.x == 0) {
-        const uint32_t p32 = ptot > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(ptot);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint64_t P = totals[1];
+        const uint32_t p32 = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(P);
         *n_pairs = p32;
-        *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(carry);
+        *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(totals[0]);
     }
 }
 
 // Level 2 work list: supertile s has ceil(E_s / CHUNK) chunks starting at chunk sc0[s];
 // chunk c covers entries [chunk_lo[c], min(chunk_lo[c] + CHUNK, st_offs[s + 1])) of
-// supertile chunk_st[c].  One block of 1024 threads; supertiles are taken PLAN_TILE at a
-// time, and the chunks of a piece are filled by all threads (binary search of the
-// supertiles' chunk prefixes in LDS).
-__global__ void __launch_bounds__(1024)
-chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
-                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ sc0,
-                  uint32_t *__restrict__ chunk_st, uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
-    __shared__ uint64_t s_wsum[16];
-    __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
+// supertile chunk_st[c].  Chunked scan over the supertiles: pass 1 counts each piece's
+// chunks, pass 2 writes sc0 and fills the piece's chunks (every thread, binary search of
+// the supertiles' chunk prefixes in LDS).
+__device__ __forceinline__ uint32_t live_supertiles(const uint32_t *st_count, uint32_t st_host,
+                                                    const uint32_t *n_pairs, uint64_t capacity) {
     uint32_t S = st_count ? *st_count : st_host;
     if (S > st_host) S = st_host;
-    if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < S; base += PLAN_TILE) {
-        const uint32_t k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
+    return uint64_t(*n_pairs) > capacity ? 0u : S;             // lists are not built
+}
+
+__global__ void __launch_bounds__(1024)
+chunk_sum_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
+                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint64_t *__restrict__ part) {
+    __shared__ uint64_t s_wsum[16];
+    const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(st_host); c += gridDim.x) {
+        const uint32_t s0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j)
+            if (s0 + j < S) cnt += (st_offs[s0 + j + 1] - st_offs[s0 + j] + CHUNK - 1) / CHUNK;
+        uint64_t tot;
+        block_scan1024(cnt, s_wsum, &tot);
+        if (threadIdx.x == 0) part[c] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
+                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
+                  const uint64_t *__restrict__ total, uint32_t *__restrict__ sc0, uint32_t *__restrict__ chunk_st,
+                  uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
+    __shared__ uint64_t s_wsum[16];
+    __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
+    const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(S); c += gridDim.x) {
+        const uint32_t base = c * PLAN_TILE, k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
         uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
         for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = s0 + j <= S ? st_offs[s0 + j] : 0u;
@@ -595,27 +642,28 @@ chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restri
             cnt += nc[j];
         }
         uint64_t tot;
-        uint32_t c = uint32_t(block_scan1024(cnt, s_wsum, &tot));
+        uint32_t q = uint32_t(block_scan1024(cnt, s_wsum, &tot));
+        const uint32_t first = uint32_t(part[c]);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
-            s_pre[k0 + j] = c;
-            if (s0 + j < S) sc0[s0 + j] = carry + c;
-            c += nc[j];
+            s_pre[k0 + j] = q;
+            if (s0 + j < S) sc0[s0 + j] = first + q;
+            q += nc[j];
         }
         if (threadIdx.x == 0) s_pre[PLAN_TILE] = uint32_t(tot);
         __syncthreads();
         const uint32_t ns = min(uint32_t(PLAN_TILE), S - base);
-        for (uint32_t q = threadIdx.x; q < uint32_t(tot); q += 1024) {
-            const int k = upper_index(s_pre, int(ns), q);
-            chunk_st[carry + q] = base + k;
-            chunk_lo[carry + q] = st_offs[base + k] + (q - s_pre[k]) * CHUNK;
+        for (uint32_t i = threadIdx.x; i < uint32_t(tot); i += 1024) {
+            const int k = upper_index(s_pre, int(ns), i);
+            chunk_st[first + i] = base + k;
+            chunk_lo[first + i] = st_offs[base + k] + (i - s_pre[k]) * CHUNK;
         }
         __syncthreads();
-        carry += uint32_t(tot);
     }
-    if (threadIdx.x == 0) {
-        sc0[S] = carry;
-        *n_chunks = carry;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t nct = S > 0 ? uint32_t(*total) : 0u;
+        sc0[S] = nct;
+        *n_chunks = nct;
     }
 }
 
@@ -723,18 +771,38 @@ chunk_colscan_kernel(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ sc
     }
 }
 
-// One block: exclusive scan of the per-tile totals -> tile_offsets[0 .. T], skipped on
-// overflow (then only n_pairs has been written).
+// Exclusive scan of the per-tile totals -> tile_offsets[0 .. T], skipped on overflow (then
+// only n_pairs has been written).  Chunked scan: pass 1 sums, pass 2 writes.
+__device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t t_host) {
+    const uint32_t T = t_count ? *t_count : t_host;
+    return T > t_host ? t_host : T;
+}
+
+__global__ void __launch_bounds__(1024)
+tile_sum_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                uint64_t *__restrict__ part) {
+    __shared__ uint64_t s_wsum[16];
+    const uint32_t T = live_tiles(t_count, t_host);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(t_host); c += gridDim.x) {
+        const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < PLAN_ITEMS; ++j) sum += t0 + j < T ? tile_total[t0 + j] : 0u;
+        uint64_t tot;
+        block_scan1024(sum, s_wsum, &tot);
+        if (threadIdx.x == 0) part[c] = tot;
+    }
+}
+
 __global__ void __launch_bounds__(1024)
 tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restrict__ t_count, uint32_t t_host,
-                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ offs) {
+                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
+                 uint32_t *__restrict__ offs) {
     __shared__ uint64_t s_wsum[16];
-    if (uint64_t(*n_pairs) > capacity) return;                  // block-uniform
-    uint32_t T = t_count ? *t_count : t_host;
-    if (T > t_host) T = t_host;
-    uint64_t carry = 0;
-    for (uint32_t base = 0; base < T; base += 1024 * PLAN_ITEMS) {
-        const uint32_t t0 = base + threadIdx.x * PLAN_ITEMS;
+    if (uint64_t(*n_pairs) > capacity) return;                  // grid-uniform
+    const uint32_t T = live_tiles(t_count, t_host);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
+        const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
         uint32_t v[PLAN_ITEMS], sum = 0;
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -742,15 +810,14 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
             sum += v[j];
         }
         uint64_t tot;
-        uint32_t o = uint32_t(block_scan1024(sum, s_wsum, &tot) + carry);
+        uint32_t o = uint32_t(block_scan1024(sum, s_wsum, &tot) + part[c]);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             if (t0 + j < T) offs[t0 + j] = o;
             o += v[j];
         }
-        carry += tot;
     }
-    if (threadIdx.x == 0) offs[T] = uint32_t(carry);
+    if (blockIdx.x == 0 && threadIdx.x == 0) offs[T] = *n_pairs;
 }
 
 // Level-2 pass 2: the Gaussian indices go into the tile lists.  After the wave transpose,
@@ -936,7 +1003,7 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
 // Two-level order-independent binning (see the comment above super_count_kernel).
 struct Bin2Layout {
     size_t sums_e, sums_p, etot, keys0, keys1, vals0, vals1, hist, dtot, st_offs, sc0, chunk_st, chunk_lo, nch, cnt,
-        ttot, total;
+        ttot, part_e, part_p, part_c, part_t, totals, total;
     int nblocks;
     uint32_t chunks_max;
 };
@@ -965,16 +1032,21 @@ inline Bin2Layout bin2_layout(int64_t n, uint32_t st_max, uint32_t t_max, uint64
     L.nch = o;      o = align_up(o + 16, 256);
     L.cnt = o;      o = align_up(o + size_t(L.chunks_max) * SUPER_TILES * 4, 256);
     L.ttot = o;     o = align_up(o + size_t(t_max) * 4, 256);
+    L.part_e = o;   o = align_up(o + (size_t(plan_chunks(nsums)) + 1) * 8, 256);
+    L.part_p = o;   o = align_up(o + (size_t(plan_chunks(nsums)) + 1) * 8, 256);
+    L.part_c = o;   o = align_up(o + (size_t(plan_chunks(st_max)) + 1) * 8, 256);
+    L.part_t = o;   o = align_up(o + (size_t(plan_chunks(t_max)) + 1) * 8, 256);
+    L.totals = o;   o = align_up(o + 4 * 8, 256);
     L.total = o;
     return L;
 }
 
-// st_count / t_count: device-side supertile / tile counts (batches), NULL for a single view
-// (then st_max / T are exact).
+// n_live / st_count / t_count: device-side Gaussian / supertile / tile counts (batches), NULL
+// for a single view (then n / st_max / T are exact).
 template <typename Geo>
-int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, const uint32_t *st_count, uint32_t T,
-              const uint32_t *t_count, void *ws, size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids,
-              uint64_t capacity, uint32_t *n_pairs, hipStream_t s) {
+int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo geo, uint32_t st_max,
+              const uint32_t *st_count, uint32_t T, const uint32_t *t_count, void *ws, size_t ws_bytes,
+              uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs, hipStream_t s) {
     int rc;
     MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
     if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
@@ -1000,21 +1072,33 @@ int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, co
     uint32_t *nch = reinterpret_cast<uint32_t *>(w + L.nch);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(w + L.cnt);
     uint32_t *ttot = reinterpret_cast<uint32_t *>(w + L.ttot);
+    uint64_t *part_e = reinterpret_cast<uint64_t *>(w + L.part_e);
+    uint64_t *part_p = reinterpret_cast<uint64_t *>(w + L.part_p);
+    uint64_t *part_c = reinterpret_cast<uint64_t *>(w + L.part_c);
+    uint64_t *part_t = reinterpret_cast<uint64_t *>(w + L.part_t);
+    uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);     // {E, P, chunks, -}
     const uint2 *rect = reinterpret_cast<const uint2 *>(proj->rect);
     const unsigned nb256 = unsigned((n + 255) / 256);
 
     // level 1: entry counts (and the pair total P), their scan, the entries, the supertile sort
     if (nb256 > 0) {
-        hipLaunchKernelGGL(super_count_kernel, dim3(nb256), dim3(256), 0, s, rect, proj->n_tiles, n, sums_e, sums_p);
+        hipLaunchKernelGGL(super_count_kernel, dim3(nb256), dim3(256), 0, s, rect, proj->n_tiles, n, n_live, sums_e,
+                           sums_p);
         MGS_LAUNCH_CHECK("super_count_kernel");
     }
-    hipLaunchKernelGGL(super_scan_kernel, dim3(1), dim3(1024), 0, s, sums_e, sums_p, int(nb256), capacity, etot,
-                       n_pairs);
+    const uint32_t nce = plan_chunks(nb256);
+    hipLaunchKernelGGL(super_sum_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256), part_e,
+                       part_p);
+    MGS_LAUNCH_CHECK("super_sum_kernel");
+    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_e, part_p, nce, totals, totals + 1);
+    MGS_LAUNCH_CHECK("part_scan_kernel");
+    hipLaunchKernelGGL(super_scan_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, int(nb256), part_e, totals,
+                       capacity, etot, n_pairs);
     MGS_LAUNCH_CHECK("super_scan_kernel");
     if (nb256 > 0) {
         hipLaunchKernelGGL((expand_kernel<uint32_t, TileKey, Geo, SUPER_SHIFT>), dim3(nb256), dim3(256), 0, s, rect,
                            proj->n_tiles, sums_e, reinterpret_cast<const float4 *>(proj->splat), n, geo, n_pairs,
-                           capacity, keys[0], vals[0], TileKey());
+                           capacity, keys[0], vals[0], TileKey(), n_live);
         MGS_LAUNCH_CHECK("expand_kernel<supertile>");
     }
     const int key_bits = bits_for(st_max) > 0 ? bits_for(st_max) : 1;
@@ -1046,8 +1130,15 @@ int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, co
     MGS_LAUNCH_CHECK("tile_ranges_kernel<supertile>");
 
     // level 2: chunks, per-chunk tile counts, column scans, tile offsets, the lists
-    hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs, capacity,
-                       sc0, chunk_st, chunk_lo, nch);
+    const uint32_t ncs = plan_chunks(st_max);
+    hipLaunchKernelGGL(chunk_sum_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs,
+                       capacity, part_c);
+    MGS_LAUNCH_CHECK("chunk_sum_kernel");
+    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_c, static_cast<uint64_t *>(nullptr), ncs,
+                       totals + 2, static_cast<uint64_t *>(nullptr));
+    MGS_LAUNCH_CHECK("part_scan_kernel");
+    hipLaunchKernelGGL(chunk_plan_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs,
+                       capacity, part_c, totals + 2, sc0, chunk_st, chunk_lo, nch);
     MGS_LAUNCH_CHECK("chunk_plan_kernel");
     const unsigned cgrid = L.chunks_max < uint32_t(SUPER_MAX_GRID) ? L.chunks_max : uint32_t(SUPER_MAX_GRID);
     hipLaunchKernelGGL((chunk_count_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st, chunk_lo,
@@ -1057,7 +1148,14 @@ int bin2_impl(const mgs_projected *proj, int64_t n, Geo geo, uint32_t st_max, co
     hipLaunchKernelGGL((chunk_colscan_kernel<Geo>), dim3(unsigned(jobs < 16384 ? jobs : 16384)), dim3(64), 0, s, cnt,
                        sc0, st_count, st_max, n_pairs, capacity, geo, ttot);
     MGS_LAUNCH_CHECK("chunk_colscan_kernel");
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, ttot, t_count, T, n_pairs, capacity, tile_offsets);
+    const uint32_t nct = plan_chunks(T);
+    hipLaunchKernelGGL(tile_sum_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, part_t);
+    MGS_LAUNCH_CHECK("tile_sum_kernel");
+    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_t, static_cast<uint64_t *>(nullptr), nct,
+                       static_cast<uint64_t *>(nullptr), static_cast<uint64_t *>(nullptr));
+    MGS_LAUNCH_CHECK("part_scan_kernel");
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, n_pairs, capacity,
+                       part_t, tile_offsets);
     MGS_LAUNCH_CHECK("tile_scan_kernel");
     if (capacity > 0) {
         hipLaunchKernelGGL((chunk_write_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st,
@@ -1075,8 +1173,8 @@ int bin_batch(const mgs_projected *proj, int64_t n_max, const BatchPlan *plan, u
               size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity, uint32_t *n_pairs,
               hipStream_t s) {
     // a request has at most as many supertiles as tiles
-    return bin2_impl(proj, n_max, SuperBatch{plan}, max_tiles, &plan->st_total, max_tiles, &plan->t_total, ws,
-                     ws_bytes, tile_offsets, gids, capacity, n_pairs, s);
+    return bin2_impl(proj, n_max, &plan->n_total, SuperBatch{plan}, max_tiles, &plan->st_total, max_tiles,
+                     &plan->t_total, ws, ws_bytes, tile_offsets, gids, capacity, n_pairs, s);
 }
 
 size_t bin_batch_workspace(int64_t n_max, uint32_t max_tiles, uint64_t capacity) {
@@ -1099,7 +1197,7 @@ extern "C" int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int ti
                        uint32_t *n_pairs, void *stream) {
     MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
     const uint32_t st_x = uint32_t((tiles_x + mgs::SUPER - 1) / mgs::SUPER);
-    return mgs::bin2_impl(proj, n, mgs::SuperGrid{uint32_t(tiles_x), uint32_t(tiles_y), st_x},
+    return mgs::bin2_impl(proj, n, nullptr, mgs::SuperGrid{uint32_t(tiles_x), uint32_t(tiles_y), st_x},
                           mgs::super_count(tiles_x, tiles_y), nullptr, uint32_t(tiles_x) * uint32_t(tiles_y), nullptr,
                           ws, ws_bytes, tile_offsets, gids, capacity, n_pairs, mgs::as_stream(stream));
 }

@@ -69,47 +69,76 @@ struct BatchViewLoc {
     }
 };
 
-// One block of 1024 threads: every tile gets n_ranges(L) items (item = tile | range << 24);
+// Work list of the split blend: every tile gets n_ranges(L) items (item = tile | range << 24);
 // ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
 // tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
-// Tiles are taken PLAN_TILE at a time (PLAN_ITEMS consecutive ones per thread); after the
-// scan every thread fills items of the chunk by a binary search of the tiles' item prefixes
-// in LDS, so a tile with many ranges does not serialise its thread.
-__global__ void __launch_bounds__(1024)
-split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
-                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
-                  uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
-                  uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
-    __shared__ uint64_t s_wsum[16];
-    __shared__ uint32_t s_ipre[PLAN_TILE + 1];   // first item of each tile of the chunk (chunk-relative)
-    __shared__ uint32_t s_spre[PLAN_TILE];       // first slot of each split tile (absolute), else ~0
+// Chunked scan over the tiles (see plan_chunks): pass 1 totals each chunk's items, slots
+// and split tiles; pass 2 writes them, each thread for its own PLAN_ITEMS tiles.
+__device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t t_host, const uint32_t *n_pairs,
+                                               uint64_t capacity) {
     uint32_t T = t_count ? *t_count : t_host;
     if (T > t_host) T = t_host;
-    if (uint64_t(*n_pairs) > capacity) T = 0;             // lists were not built: render nothing
-    uint32_t c_items = 0, c_slots = 0, c_split = 0;       // running totals over earlier chunks
-    for (uint32_t base = 0; base < T; base += PLAN_TILE) {
-        const uint32_t k0 = threadIdx.x * PLAN_ITEMS, t0 = base + k0;
-        uint32_t o[PLAN_ITEMS + 1];
+    return uint64_t(*n_pairs) > capacity ? 0u : T;             // lists were not built: render nothing
+}
+
+__device__ __forceinline__ void tile_ranges4(const uint32_t *offs, uint32_t t0, uint32_t T, uint32_t nr[PLAN_ITEMS],
+                                             uint32_t &ci, uint32_t &cs, uint32_t &cm) {
+    uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
-        for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
-        uint32_t nr[PLAN_ITEMS];
-        uint32_t ci = 0, cs = 0, cm = 0;
+    for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
+    ci = cs = cm = 0;
 #pragma unroll
-        for (int j = 0; j < PLAN_ITEMS; ++j) {
-            nr[j] = t0 + j < T ? n_ranges(o[j + 1] - o[j], SPLIT_RANGE) : 0u;
-            ci += nr[j];
-            cs += nr[j] > 1 ? nr[j] : 0u;
-            cm += nr[j] > 1 ? 1u : 0u;
+    for (int j = 0; j < PLAN_ITEMS; ++j) {
+        nr[j] = t0 + j < T ? n_ranges(o[j + 1] - o[j], SPLIT_RANGE) : 0u;
+        ci += nr[j];
+        cs += nr[j] > 1 ? nr[j] : 0u;
+        cm += nr[j] > 1 ? 1u : 0u;
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint64_t *__restrict__ part_is,
+                 uint64_t *__restrict__ part_m) {
+    __shared__ uint64_t s_wsum[16];
+    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(t_host); c += gridDim.x) {
+        uint32_t nr[PLAN_ITEMS], ci, cs, cm;
+        tile_ranges4(offs, c * PLAN_TILE + threadIdx.x * PLAN_ITEMS, T, nr, ci, cs, cm);
+        uint64_t t1, t2;
+        block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
+        block_scan1024(uint64_t(cm), s_wsum, &t2);
+        if (threadIdx.x == 0) {
+            part_is[c] = t1;
+            part_m[c] = t2;
         }
-        uint64_t tot1, tot2;
-        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &tot1);
-        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &tot2);
-        uint32_t i0 = uint32_t(e1), s0 = c_slots + uint32_t(e1 >> 32), js = c_split + uint32_t(e2);
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part_is,
+                  const uint64_t *__restrict__ part_m, const uint64_t *__restrict__ totals,
+                  uint32_t *__restrict__ items, uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
+                  uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
+    __shared__ uint64_t s_wsum[16];
+    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
+        const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
+        uint32_t nr[PLAN_ITEMS], ci, cs, cm;
+        tile_ranges4(offs, t0, T, nr, ci, cs, cm);
+        uint64_t t1, t2;
+        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1) + part_is[c];
+        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &t2) + part_m[c];
+        uint32_t i0 = uint32_t(e1), s0 = uint32_t(e1 >> 32), js = uint32_t(e2);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
-            s_ipre[k0 + j] = i0;
-            s_spre[k0 + j] = nr[j] > 1 ? s0 : 0xFFFFFFFFu;
-            if (nr[j] > 1) {
+            const bool m = nr[j] > 1;
+            for (uint32_t r = 0; r < nr[j]; ++r) {
+                items[i0 + r] = (t0 + j) | (r << 24);
+                item_slot[i0 + r] = m ? s0 + r : 0xFFFFFFFFu;
+            }
+            if (m) {
                 split_tile[js] = t0 + j;
                 split_slot0[js] = s0;
                 s0 += nr[j];
@@ -117,24 +146,10 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             }
             i0 += nr[j];
         }
-        const uint32_t n_items = uint32_t(tot1);
-        if (threadIdx.x == 0) s_ipre[PLAN_TILE] = n_items;
-        __syncthreads();
-        const uint32_t nt = min(uint32_t(PLAN_TILE), T - base);
-        for (uint32_t it = threadIdx.x; it < n_items; it += 1024) {
-            const int k = upper_index(s_ipre, int(nt), it);
-            const uint32_t r = it - s_ipre[k];
-            items[c_items + it] = (base + k) | (r << 24);
-            item_slot[c_items + it] = s_spre[k] == 0xFFFFFFFFu ? 0xFFFFFFFFu : s_spre[k] + r;
-        }
-        __syncthreads();
-        c_items += n_items;
-        c_slots += uint32_t(tot1 >> 32);
-        c_split += uint32_t(tot2);
     }
-    if (threadIdx.x == 0) {
-        counts[0] = c_items;
-        counts[1] = c_split;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[0] = T > 0 ? uint32_t(totals[0]) : 0u;            // items (low half of items | slots << 32)
+        counts[1] = T > 0 ? uint32_t(totals[1]) : 0u;            // split tiles
     }
 }
 
@@ -185,7 +200,7 @@ merge_ranges_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restric
 }
 
 struct SplitLayout {
-    size_t items, slot, stile, sslot, counts, part, total;
+    size_t items, slot, stile, sslot, counts, part, part_is, part_m, totals, total;
     uint32_t max_items;
 };
 
@@ -200,6 +215,9 @@ inline SplitLayout split_layout(uint32_t T, uint64_t capacity) {
     L.sslot = o;  o = align_up(o + size_t(T) * 4 + 4, 256);
     L.counts = o; o = align_up(o + 16, 256);
     L.part = o;   o = align_up(o + max_slots * PART_FLOATS * 4, 256);
+    L.part_is = o; o = align_up(o + (size_t(plan_chunks(T)) + 1) * 8, 256);
+    L.part_m = o;  o = align_up(o + (size_t(plan_chunks(T)) + 1) * 8, 256);
+    L.totals = o;  o = align_up(o + 2 * 8, 256);
     L.total = o;
     return L;
 }
@@ -216,8 +234,17 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint32_t *sslot = reinterpret_cast<uint32_t *>(w + L.sslot);
     uint32_t *counts = reinterpret_cast<uint32_t *>(w + L.counts);
     float *part = reinterpret_cast<float *>(w + L.part);
-    hipLaunchKernelGGL(split_plan_kernel, dim3(1), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity, items, slot,
-                       stile, sslot, counts);
+    uint64_t *part_is = reinterpret_cast<uint64_t *>(w + L.part_is);
+    uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
+    uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
+    const uint32_t nc = plan_chunks(T);
+    hipLaunchKernelGGL(split_sum_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
+                       part_is, part_m);
+    MGS_LAUNCH_CHECK("split_sum_kernel");
+    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_is, part_m, nc, totals, totals + 1);
+    MGS_LAUNCH_CHECK("part_scan_kernel");
+    hipLaunchKernelGGL(split_plan_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
+                       part_is, part_m, totals, items, slot, stile, sslot, counts);
     MGS_LAUNCH_CHECK("split_plan_kernel");
     hipLaunchKernelGGL(blend_range_kernel<Loc>, dim3(L.max_items), dim3(BLEND_THREADS), 0, s, splat, offs, gids,
                        items, slot, counts, loc, log2f(alpha_min), alpha_max, part);

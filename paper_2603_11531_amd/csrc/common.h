@@ -137,6 +137,41 @@ __device__ __forceinline__ uint64_t block_scan1024(uint64_t v, uint64_t *s_wsum,
 constexpr int PLAN_ITEMS = 4;
 constexpr int PLAN_TILE = 1024 * PLAN_ITEMS;
 
+// Planning scans run over chunks of PLAN_TILE items, one 1024-thread block per chunk: a
+// first pass writes every chunk's totals, part_scan_kernel turns them into exclusive chunk
+// offsets in one block, and a second pass redoes its chunk's block scan from that offset and
+// writes the outputs.  Chunks past the live item count contribute zero.
+__host__ __device__ __forceinline__ uint32_t plan_chunks(uint64_t n_items) {
+    return uint32_t((n_items + PLAN_TILE - 1) / PLAN_TILE);
+}
+inline unsigned plan_grid(uint32_t chunks) { return chunks == 0 ? 1u : (chunks < 1024u ? chunks : 1024u); }
+
+// Exclusive scan in place of a[0 .. n) (and of b, if non-NULL); the totals go to *tot_a /
+// *tot_b (if non-NULL).
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(1024)
+part_scan_kernel(uint64_t *__restrict__ a, uint64_t *__restrict__ b, uint32_t n, uint64_t *__restrict__ tot_a,
+                 uint64_t *__restrict__ tot_b) {
+    __shared__ uint64_t s_wsum[16];
+    uint64_t ca = 0, cb = 0;
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        uint64_t ta, tb;
+        const uint64_t ea = block_scan1024(i < n ? a[i] : 0u, s_wsum, &ta);
+        if (i < n) a[i] = ca + ea;
+        ca += ta;
+        if (b) {
+            const uint64_t eb = block_scan1024(i < n ? b[i] : 0u, s_wsum, &tb);
+            if (i < n) b[i] = cb + eb;
+            cb += tb;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (tot_a) *tot_a = ca;
+        if (tot_b) *tot_b = cb;
+    }
+}
+
 // Largest j in [0, n) with pre[j] <= v, for a non-decreasing pre with pre[0] <= v.
 __device__ __forceinline__ int upper_index(const uint32_t *pre, int n, uint32_t v) {
     int lo = 0, hi = n - 1;

@@ -28,7 +28,7 @@ from . import _lib as L
 from .render import ALPHA_MAX, ALPHA_MIN, DeviceMLP, DeviceScene, Renderer
 
 MAX_REQ = 64
-N_ALIGN = 64
+N_ALIGN = 256          # a request's Gaussian range in a batch starts on a multiple of this (as in the library)
 
 
 def _tiles(w, h):
