@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 BLEND_FLOP_PER_EVAL = 23
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -362,6 +363,13 @@ def main():
     traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_PROFILE))
     proj_bytes = ds.n * (92 + 68)    # attribute reads; record 48 + rect 8 + count 4 + phi, m 8
     proj_ms = float(stages[:, 0].mean())
+    # binning's algorithmic traffic: rect + n_tiles read per Gaussian, one gid written per pair,
+    # the tile offsets written
+    bin_bytes = ds.n * 12 + 4 * mean_P + 4 * (((W + 15) // 16) * ((H + 15) // 16) + 1)
+    bin_ms = float(stages[:, 1].mean())
+    # MLP arithmetic (22->64->64->2 per Gaussian, FMA = 2 flop) over the fused enhance + project
+    # time: a lower bound of what the MLP's MFMA work alone achieves
+    mlp_flop = ds.n * 2 * (22 * 64 + 64 * 64 + 64 * 2)
     out = {
         "metric": "FPS @1600x1063, 1M Gaussians (OIT vs sorted); p50/p99 served frame ms",
         "value": round(fps, 2),
@@ -386,6 +394,11 @@ def main():
         "stage_ms": dict(zip(["enhance_project", "bin", "blend_oit"],
                              [round(float(v), 4) for v in stages.mean(axis=0)])),
         "enhance_project_gbs": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
+        "enhance_project_hbm_frac": round(proj_bytes / (proj_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "bin_gbs": round(bin_bytes / (bin_ms * 1e-3) / 1e9, 1),
+        "bin_hbm_frac": round(bin_bytes / (bin_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "mlp_mfma_tflops": round(mlp_flop / (proj_ms * 1e-3) / 1e12, 2),
+        "mlp_mfma_frac": round(mlp_flop / (proj_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
         "nvq": res_nvq,

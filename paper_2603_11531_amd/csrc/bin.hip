@@ -564,32 +564,38 @@ super_sum_kernel(const uint64_t *__restrict__ sums_e, const uint64_t *__restrict
 }
 
 __global__ void __launch_bounds__(1024)
-super_scan_kernel(uint64_t *__restrict__ sums_e, int nb, const uint64_t *__restrict__ part_e,
-                  const uint64_t *__restrict__ totals /* {E, P} */, uint64_t capacity,
-                  uint32_t *__restrict__ e_total, uint32_t *__restrict__ n_pairs) {
+super_scan_kernel(uint64_t *__restrict__ sums_e, const uint64_t *__restrict__ sums_p, int nb,
+                  const uint64_t *__restrict__ part_e, const uint64_t *__restrict__ totals /* {E, P} */,
+                  uint64_t capacity, uint32_t *__restrict__ e_total, uint32_t *__restrict__ n_pairs) {
+    // part_e == NULL: one block walks every chunk with a running carry (few chunks)
     __shared__ uint64_t s_wsum[16];
     const uint32_t nc = plan_chunks(uint64_t(nb));
+    uint64_t carry = 0, ptot = 0;
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         const int i0 = int(c) * PLAN_TILE + int(threadIdx.x) * PLAN_ITEMS;
-        uint64_t v[PLAN_ITEMS], sum = 0;
+        uint64_t v[PLAN_ITEMS], sum = 0, psum = 0;
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             v[j] = i0 + j < nb ? sums_e[i0 + j] : 0u;
+            if (!part_e) psum += i0 + j < nb ? sums_p[i0 + j] : 0u;
             sum += v[j];
         }
-        uint64_t tot;
-        uint64_t o = block_scan1024(sum, s_wsum, &tot) + part_e[c];
+        uint64_t tot, ptot_c = 0;
+        uint64_t o = block_scan1024(sum, s_wsum, &tot) + (part_e ? part_e[c] : carry);
+        if (!part_e) block_scan1024(psum, s_wsum, &ptot_c);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             if (i0 + j < nb) sums_e[i0 + j] = o;
             o += v[j];
         }
+        carry += tot;
+        ptot += ptot_c;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint64_t P = totals[1];
+        const uint64_t E = part_e ? totals[0] : carry, P = part_e ? totals[1] : ptot;
         const uint32_t p32 = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(P);
         *n_pairs = p32;
-        *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(totals[0]);
+        *e_total = uint64_t(p32) > capacity ? 0u : uint32_t(E);
     }
 }
 
@@ -629,7 +635,9 @@ chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restri
                   uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
+    // part == NULL: one block walks every piece with a running carry (few pieces)
     const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
+    uint32_t carry = 0;
     for (uint32_t c = blockIdx.x; c < plan_chunks(S); c += gridDim.x) {
         const uint32_t base = c * PLAN_TILE, k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
         uint32_t o[PLAN_ITEMS + 1];
@@ -643,7 +651,7 @@ chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restri
         }
         uint64_t tot;
         uint32_t q = uint32_t(block_scan1024(cnt, s_wsum, &tot));
-        const uint32_t first = uint32_t(part[c]);
+        const uint32_t first = part ? uint32_t(part[c]) : carry;
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             s_pre[k0 + j] = q;
@@ -659,9 +667,10 @@ chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restri
             chunk_lo[first + i] = st_offs[base + k] + (i - s_pre[k]) * CHUNK;
         }
         __syncthreads();
+        carry += uint32_t(tot);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t nct = S > 0 ? uint32_t(*total) : 0u;
+        const uint32_t nct = S == 0 ? 0u : (part ? uint32_t(*total) : carry);
         sc0[S] = nct;
         *n_chunks = nct;
     }
@@ -800,7 +809,9 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
                  uint32_t *__restrict__ offs) {
     __shared__ uint64_t s_wsum[16];
     if (uint64_t(*n_pairs) > capacity) return;                  // grid-uniform
+    // part == NULL: one block walks every chunk with a running carry (few chunks)
     const uint32_t T = live_tiles(t_count, t_host);
+    uint64_t carry = 0;
     for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
         const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
         uint32_t v[PLAN_ITEMS], sum = 0;
@@ -810,12 +821,13 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
             sum += v[j];
         }
         uint64_t tot;
-        uint32_t o = uint32_t(block_scan1024(sum, s_wsum, &tot) + part[c]);
+        uint32_t o = uint32_t(block_scan1024(sum, s_wsum, &tot) + (part ? part[c] : carry));
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             if (t0 + j < T) offs[t0 + j] = o;
             o += v[j];
         }
+        carry += tot;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) offs[T] = *n_pairs;
 }
@@ -1087,13 +1099,19 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
         MGS_LAUNCH_CHECK("super_count_kernel");
     }
     const uint32_t nce = plan_chunks(nb256);
-    hipLaunchKernelGGL(super_sum_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256), part_e,
-                       part_p);
-    MGS_LAUNCH_CHECK("super_sum_kernel");
-    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_e, part_p, nce, totals, totals + 1);
-    MGS_LAUNCH_CHECK("part_scan_kernel");
-    hipLaunchKernelGGL(super_scan_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, int(nb256), part_e, totals,
-                       capacity, etot, n_pairs);
+    if (nce <= PLAN_ONE_BLOCK) {                 // few chunks: one block with a running carry
+        hipLaunchKernelGGL(super_scan_kernel, dim3(1), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), capacity,
+                           etot, n_pairs);
+    } else {
+        hipLaunchKernelGGL(super_sum_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                           part_e, part_p);
+        MGS_LAUNCH_CHECK("super_sum_kernel");
+        hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_e, part_p, nce, totals, totals + 1);
+        MGS_LAUNCH_CHECK("part_scan_kernel");
+        hipLaunchKernelGGL(super_scan_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                           part_e, totals, capacity, etot, n_pairs);
+    }
     MGS_LAUNCH_CHECK("super_scan_kernel");
     if (nb256 > 0) {
         hipLaunchKernelGGL((expand_kernel<uint32_t, TileKey, Geo, SUPER_SHIFT>), dim3(nb256), dim3(256), 0, s, rect,
@@ -1131,14 +1149,20 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
 
     // level 2: chunks, per-chunk tile counts, column scans, tile offsets, the lists
     const uint32_t ncs = plan_chunks(st_max);
-    hipLaunchKernelGGL(chunk_sum_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs,
-                       capacity, part_c);
-    MGS_LAUNCH_CHECK("chunk_sum_kernel");
-    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_c, static_cast<uint64_t *>(nullptr), ncs,
-                       totals + 2, static_cast<uint64_t *>(nullptr));
-    MGS_LAUNCH_CHECK("part_scan_kernel");
-    hipLaunchKernelGGL(chunk_plan_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs,
-                       capacity, part_c, totals + 2, sc0, chunk_st, chunk_lo, nch);
+    if (ncs <= PLAN_ONE_BLOCK) {
+        hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs, capacity,
+                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), sc0,
+                           chunk_st, chunk_lo, nch);
+    } else {
+        hipLaunchKernelGGL(chunk_sum_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max,
+                           n_pairs, capacity, part_c);
+        MGS_LAUNCH_CHECK("chunk_sum_kernel");
+        hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_c, static_cast<uint64_t *>(nullptr),
+                           ncs, totals + 2, static_cast<uint64_t *>(nullptr));
+        MGS_LAUNCH_CHECK("part_scan_kernel");
+        hipLaunchKernelGGL(chunk_plan_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max,
+                           n_pairs, capacity, part_c, totals + 2, sc0, chunk_st, chunk_lo, nch);
+    }
     MGS_LAUNCH_CHECK("chunk_plan_kernel");
     const unsigned cgrid = L.chunks_max < uint32_t(SUPER_MAX_GRID) ? L.chunks_max : uint32_t(SUPER_MAX_GRID);
     hipLaunchKernelGGL((chunk_count_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st, chunk_lo,
@@ -1149,13 +1173,18 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
                        sc0, st_count, st_max, n_pairs, capacity, geo, ttot);
     MGS_LAUNCH_CHECK("chunk_colscan_kernel");
     const uint32_t nct = plan_chunks(T);
-    hipLaunchKernelGGL(tile_sum_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, part_t);
-    MGS_LAUNCH_CHECK("tile_sum_kernel");
-    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_t, static_cast<uint64_t *>(nullptr), nct,
-                       static_cast<uint64_t *>(nullptr), static_cast<uint64_t *>(nullptr));
-    MGS_LAUNCH_CHECK("part_scan_kernel");
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, n_pairs, capacity,
-                       part_t, tile_offsets);
+    if (nct <= PLAN_ONE_BLOCK) {
+        hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, ttot, t_count, T, n_pairs, capacity,
+                           static_cast<const uint64_t *>(nullptr), tile_offsets);
+    } else {
+        hipLaunchKernelGGL(tile_sum_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, part_t);
+        MGS_LAUNCH_CHECK("tile_sum_kernel");
+        hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_t, static_cast<uint64_t *>(nullptr),
+                           nct, static_cast<uint64_t *>(nullptr), static_cast<uint64_t *>(nullptr));
+        MGS_LAUNCH_CHECK("part_scan_kernel");
+        hipLaunchKernelGGL(tile_scan_kernel, dim3(plan_grid(nct)), dim3(1024), 0, s, ttot, t_count, T, n_pairs,
+                           capacity, part_t, tile_offsets);
+    }
     MGS_LAUNCH_CHECK("tile_scan_kernel");
     if (capacity > 0) {
         hipLaunchKernelGGL((chunk_write_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st,

@@ -121,15 +121,20 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                   const uint64_t *__restrict__ part_m, const uint64_t *__restrict__ totals,
                   uint32_t *__restrict__ items, uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
+    // part_is == NULL: one block walks every chunk with running carries (few chunks)
     __shared__ uint64_t s_wsum[16];
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    uint64_t c_is = 0, c_m = 0;
     for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
         const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
         uint32_t nr[PLAN_ITEMS], ci, cs, cm;
         tile_ranges4(offs, t0, T, nr, ci, cs, cm);
         uint64_t t1, t2;
-        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1) + part_is[c];
-        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &t2) + part_m[c];
+        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1) +
+                            (part_is ? part_is[c] : c_is);
+        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &t2) + (part_is ? part_m[c] : c_m);
+        c_is += t1;
+        c_m += t2;
         uint32_t i0 = uint32_t(e1), s0 = uint32_t(e1 >> 32), js = uint32_t(e2);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -148,8 +153,8 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counts[0] = T > 0 ? uint32_t(totals[0]) : 0u;            // items (low half of items | slots << 32)
-        counts[1] = T > 0 ? uint32_t(totals[1]) : 0u;            // split tiles
+        counts[0] = T == 0 ? 0u : uint32_t(part_is ? totals[0] : c_is);   // items (low half of items | slots << 32)
+        counts[1] = T == 0 ? 0u : uint32_t(part_is ? totals[1] : c_m);    // split tiles
     }
 }
 
@@ -238,13 +243,19 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
     uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
     const uint32_t nc = plan_chunks(T);
-    hipLaunchKernelGGL(split_sum_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
-                       part_is, part_m);
-    MGS_LAUNCH_CHECK("split_sum_kernel");
-    hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_is, part_m, nc, totals, totals + 1);
-    MGS_LAUNCH_CHECK("part_scan_kernel");
-    hipLaunchKernelGGL(split_plan_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
-                       part_is, part_m, totals, items, slot, stile, sslot, counts);
+    if (nc <= PLAN_ONE_BLOCK) {                  // few chunks: one block with running carries
+        hipLaunchKernelGGL(split_plan_kernel, dim3(1), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
+                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
+                           static_cast<const uint64_t *>(nullptr), items, slot, stile, sslot, counts);
+    } else {
+        hipLaunchKernelGGL(split_sum_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs,
+                           capacity, part_is, part_m);
+        MGS_LAUNCH_CHECK("split_sum_kernel");
+        hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_is, part_m, nc, totals, totals + 1);
+        MGS_LAUNCH_CHECK("part_scan_kernel");
+        hipLaunchKernelGGL(split_plan_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs,
+                           capacity, part_is, part_m, totals, items, slot, stile, sslot, counts);
+    }
     MGS_LAUNCH_CHECK("split_plan_kernel");
     hipLaunchKernelGGL(blend_range_kernel<Loc>, dim3(L.max_items), dim3(BLEND_THREADS), 0, s, splat, offs, gids,
                        items, slot, counts, loc, log2f(alpha_min), alpha_max, part);

@@ -145,6 +145,9 @@ __host__ __device__ __forceinline__ uint32_t plan_chunks(uint64_t n_items) {
     return uint32_t((n_items + PLAN_TILE - 1) / PLAN_TILE);
 }
 inline unsigned plan_grid(uint32_t chunks) { return chunks == 0 ? 1u : (chunks < 1024u ? chunks : 1024u); }
+// Up to this many chunks a planning scan runs as one block with a running carry (one launch
+// instead of three: a launch costs a few microseconds even when it has little to do).
+constexpr uint32_t PLAN_ONE_BLOCK = 4;
 
 // Exclusive scan in place of a[0 .. n) (and of b, if non-NULL); the totals go to *tot_a /
 // *tot_b (if non-NULL).
