@@ -73,7 +73,8 @@ struct BatchViewLoc {
 // ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
 // tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
 // Chunked scan over the tiles (see plan_chunks): pass 1 totals each chunk's items, slots
-// and split tiles; pass 2 writes them, each thread for its own PLAN_ITEMS tiles.
+// and split tiles; pass 2 puts each tile's first item and slot in LDS and writes the chunk's
+// items coalesced, each thread finding the tile of its item by binary search in LDS.
 __device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t t_host, const uint32_t *n_pairs,
                                                uint64_t capacity) {
     uint32_t T = t_count ? *t_count : t_host;
@@ -115,6 +116,9 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
     }
 }
 
+static_assert(PLAN_TILE == 4096, "split_plan_kernel searches a 4096-entry table in 12 steps");
+constexpr int SPLIT_FILL_ILP = 4;                // item searches a thread keeps in flight
+
 __global__ void __launch_bounds__(1024)
 split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part_is,
@@ -123,6 +127,8 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
     // part_is == NULL: one block walks every chunk with running carries (few chunks)
     __shared__ uint64_t s_wsum[16];
+    __shared__ uint32_t s_item0[PLAN_TILE];      // chunk-relative first item of each tile
+    __shared__ uint32_t s_slot0[PLAN_TILE];      // first partial-sum slot of a split tile, else ~0
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
     uint64_t c_is = 0, c_m = 0;
     for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
@@ -130,19 +136,18 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         uint32_t nr[PLAN_ITEMS], ci, cs, cm;
         tile_ranges4(offs, t0, T, nr, ci, cs, cm);
         uint64_t t1, t2;
-        const uint64_t e1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1) +
-                            (part_is ? part_is[c] : c_is);
-        const uint64_t e2 = block_scan1024(uint64_t(cm), s_wsum, &t2) + (part_is ? part_m[c] : c_m);
+        const uint64_t x1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
+        const uint64_t x2 = block_scan1024(uint64_t(cm), s_wsum, &t2);
+        const uint64_t b1 = part_is ? part_is[c] : c_is;       // items | slots << 32 before the chunk
+        const uint64_t b2 = part_is ? part_m[c] : c_m;
         c_is += t1;
         c_m += t2;
-        uint32_t i0 = uint32_t(e1), s0 = uint32_t(e1 >> 32), js = uint32_t(e2);
+        uint32_t i0 = uint32_t(x1), s0 = uint32_t((b1 + x1) >> 32), js = uint32_t(b2 + x2);
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             const bool m = nr[j] > 1;
-            for (uint32_t r = 0; r < nr[j]; ++r) {
-                items[i0 + r] = (t0 + j) | (r << 24);
-                item_slot[i0 + r] = m ? s0 + r : 0xFFFFFFFFu;
-            }
+            s_item0[threadIdx.x * PLAN_ITEMS + j] = i0;
+            s_slot0[threadIdx.x * PLAN_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
             if (m) {
                 split_tile[js] = t0 + j;
                 split_slot0[js] = s0;
@@ -151,6 +156,31 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             }
             i0 += nr[j];
         }
+        __syncthreads();
+        // item i of the chunk belongs to its last tile whose first item is <= i (tiles with
+        // no item share the next tile's start and are never chosen); s_item0[0] = 0 <= i
+        const uint32_t n_items = uint32_t(t1), ibase = uint32_t(b1);
+        for (uint32_t i = threadIdx.x; i < n_items; i += 1024 * SPLIT_FILL_ILP) {
+            uint32_t lo[SPLIT_FILL_ILP];
+#pragma unroll
+            for (int q = 0; q < SPLIT_FILL_ILP; ++q) lo[q] = 0;
+#pragma unroll
+            for (uint32_t step = PLAN_TILE / 2; step; step >>= 1) {
+#pragma unroll
+                for (int q = 0; q < SPLIT_FILL_ILP; ++q)
+                    if (s_item0[lo[q] + step] <= i + q * 1024u) lo[q] += step;
+            }
+#pragma unroll
+            for (int q = 0; q < SPLIT_FILL_ILP; ++q) {
+                const uint32_t k = i + q * 1024u;
+                if (k < n_items) {
+                    const uint32_t r = k - s_item0[lo[q]], sl = s_slot0[lo[q]];
+                    items[ibase + k] = (c * PLAN_TILE + lo[q]) | (r << 24);
+                    item_slot[ibase + k] = sl == 0xFFFFFFFFu ? sl : sl + r;
+                }
+            }
+        }
+        __syncthreads();                         // the tables are rewritten by the next chunk
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counts[0] = T == 0 ? 0u : uint32_t(part_is ? totals[0] : c_is);   // items (low half of items | slots << 32)

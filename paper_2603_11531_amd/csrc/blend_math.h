@@ -236,7 +236,9 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
     // s_buf[192 w + 3 j ..]; after the last batch the same memory holds the waves' sums
     __shared__ float4 s_buf[4 * 4 * 5 * 64 / 4];
 
-    const int w = threadIdx.x >> 6;
+    // the wave index is uniform: held in a scalar register, the wave's LDS region address is
+    // scalar and a staged record's address costs one move per Gaussian
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     // the lane's pixel offsets from the tile centre: x in the left / right quadrants, y in the
     // top / bottom ones, and the products the polynomial needs
@@ -287,8 +289,11 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
         // the only one that needs the clamp
         const uint64_t clamp = __ballot((mk & OIT_CLAMP) != 0u);
         uint64_t any = __ballot(mk != 0u) & ~clamp;
+        // per quadrant, the staged Gaussians that reach it (tested in scalar registers)
+        const uint64_t qm0 = __ballot((mk & 1u) != 0u), qm1 = __ballot((mk & 2u) != 0u);
+        const uint64_t qm2 = __ballot((mk & 4u) != 0u), qm3 = __ballot((mk & 8u) != 0u);
 #define MGS_OIT_QUAD(q, X, Y, XX, XY, YY, ALPHA)                                    \
-            if (fk & (1u << q)) {                                                   \
+            if (qm##q & bk) {                                                       \
                 float e = fmaf(qa.y, X, qa.x);                                      \
                 e = fmaf(qa.z, Y, e);                                               \
                 e = fmaf(qa.w, XX, e);                                              \
@@ -304,8 +309,8 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
 #define MGS_OIT_LOOP(ALPHA)                                                         \
         while (any) {                                                               \
             const int k = __builtin_ctzll(any);                                     \
+            const uint64_t bk = any & (0ull - any);                                 \
             any &= any - 1;                                                         \
-            const uint32_t fk = __builtin_amdgcn_readlane(mk, k);                   \
             const float4 *rec = wbuf + 3 * k;                                       \
             const float4 qa = rec[0];                                               \
             const float4 qb = rec[1];                                               \
