@@ -29,6 +29,9 @@ CFLAGS = [
     # way (hot loops use explicit fmaf), so a batched render equals the single-view render bit for bit
     "-ffp-contract=off",
     "-munsafe-fp-atomics", "-Wno-unused-result",
+    # matrix-instruction results in ordinary VGPRs (gfx950 allows it): no copies out of AGPRs
+    # before the vector ALU can use them
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -13,41 +13,52 @@ struct Splat {
     float4 r2;   // r, g, b, o
 };
 
-// Largest log2(alpha) of a splat over the rectangle of pixel centres
-// [x0, x1] x [y0, y1] (offsets from the splat mean).
-__device__ __forceinline__ float max_log2_alpha(float4 r0, float4 r1, float x0, float x1, float y0, float y1) {
-    const float kA = r1.x, beta = r1.y, kG = r1.z;
-    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return r0.z;
-    // g(dx, dy) = kA (dx + beta dy)^2 + kG dy^2 <= 0, concave
-    float best = -INFINITY;
-    // horizontal edges: dy fixed, optimum dx = -beta dy
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dy = e ? y1 : y0;
-        const float dx = fminf(fmaxf(-beta * dy, x0), x1);
-        const float t = fmaf(beta, dy, dx);
-        best = fmaxf(best, kA * t * t + kG * dy * dy);
-    }
-    // vertical edges: dx fixed, optimum dy = -kA beta dx / (kA beta^2 + kG)
-    const float den = kA * beta * beta + kG;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dx = e ? x1 : x0;
-        const float dy = fminf(fmaxf(-kA * beta * dx / den, y0), y1);
-        const float t = fmaf(beta, dy, dx);
-        best = fmaxf(best, kA * t * t + kG * dy * dy);
-    }
-    return r0.z + best;
-}
-
-// Bit q set <=> the splat may reach quadrant q of tile (tx, ty).
+// Bit q set <=> the splat may reach quadrant q of tile (tx, ty): the largest log2(alpha) over
+// the quadrant's 8x8 pixel centres is at least thr - CULL_MARGIN.
+//
+// log2(alpha) = log2(o) + g(dx, dy) with g = kA (dx + beta dy)^2 + kG dy^2 <= 0 concave in the
+// offset from the mean, so its maximum over a rectangle is g = 0 at the mean if the mean is
+// inside, else on an edge: on a row (dy fixed) at dx = -beta dy, on a column (dx fixed) at
+// dy = -kA beta dx / (kA beta^2 + kG), each clamped to the edge.  The four quadrants are bounded
+// by four pixel-centre rows and four columns of the tile; each line's vertex is found once.
+// Only the vertex position is rounded differently from an exact division (it moves the
+// evaluated point along the edge by a relative 1e-7), far inside the margin.
 __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, int tx, int ty, float thr) {
+    const float kA = r1.x, beta = r1.y, kG = r1.z;
+    const float slope = -kA * beta * __builtin_amdgcn_rcpf(fmaf(kA * beta, beta, kG));
+    // bounding columns / rows as offsets from the mean: quadrants with (q & 1) == s span columns
+    // xs[2 s] .. xs[2 s + 1], those with (q >> 1) == s rows ys[2 s] .. ys[2 s + 1]
+    const float xa = float(tx * 16) + 0.5f - r0.x, ya = float(ty * 16) + 0.5f - r0.y;
+    const float xs[4] = {xa, xa + 7.0f, xa + 8.0f, xa + 15.0f};
+    const float ys[4] = {ya, ya + 7.0f, ya + 8.0f, ya + 15.0f};
+    // best[2 sy + sx]: largest g on the edges of quadrant (sx, sy) so far
+    float best[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {                   // row k bounds the quadrants with sy = k / 2
+        const float y = ys[k], vx = -beta * y, gy = kG * y * y;
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+            const float t = fmaf(beta, y, __builtin_amdgcn_fmed3f(vx, xs[2 * sx], xs[2 * sx + 1]));
+            best[2 * (k >> 1) + sx] = fmaxf(best[2 * (k >> 1) + sx], fmaf(kA * t, t, gy));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {                   // column k bounds the quadrants with sx = k / 2
+        const float x = xs[k], vy = slope * x;
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+            const float dy = __builtin_amdgcn_fmed3f(vy, ys[2 * sy], ys[2 * sy + 1]);
+            const float t = fmaf(beta, dy, x);
+            best[2 * sy + (k >> 1)] = fmaxf(best[2 * sy + (k >> 1)], fmaf(kA * t, t, kG * dy * dy));
+        }
+    }
+    const float need = thr - CULL_MARGIN - r0.z;    // g must reach this somewhere
     uint32_t m = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float X0 = float(tx * 16 + (q & 1) * 8) + 0.5f - r0.x;
-        const float Y0 = float(ty * 16 + (q >> 1) * 8) + 0.5f - r0.y;
-        if (max_log2_alpha(r0, r1, X0, X0 + 7.0f, Y0, Y0 + 7.0f) >= thr - CULL_MARGIN) m |= 1u << q;
+        const int sx = q & 1, sy = q >> 1;
+        const bool inside = xs[2 * sx] <= 0.0f && xs[2 * sx + 1] >= 0.0f && ys[2 * sy] <= 0.0f && ys[2 * sy + 1] >= 0.0f;
+        if ((inside ? 0.0f : best[q]) >= need) m |= 1u << q;
     }
     return m;
 }
