@@ -41,6 +41,7 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
 
 // ---------------------------------------------------------------- split-tile OIT blend
 constexpr uint32_t SPLIT_RANGE = 1024;        // Gaussians per range of a long tile list
+constexpr uint32_t MERGE_GRID = 2048;         // workgroups of the range merge
 constexpr int PART_FLOATS = 5 * 256;          // per-range partial sums (N rgb, D, T) x 256 pixels
 
 // Destination of one tile: a single view, or one request of a batch.
@@ -72,7 +73,7 @@ struct BatchViewLoc {
 // Work list of the split blend: every tile gets n_ranges(L) items (item = tile | range << 24);
 // ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
 // tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
-// Chunked scan over the tiles (see plan_chunks): pass 1 totals each chunk's items, slots
+// Chunked scan over the tiles (SPLIT_TILE tiles per chunk): pass 1 totals each chunk's items, slots
 // and split tiles; pass 2 puts each tile's first item and slot in LDS and writes the chunk's
 // items coalesced, each thread finding the tile of its item by binary search in LDS.
 __device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t t_host, const uint32_t *n_pairs,
@@ -82,19 +83,32 @@ __device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t
     return uint64_t(*n_pairs) > capacity ? 0u : T;             // lists were not built: render nothing
 }
 
-__device__ __forceinline__ void tile_ranges4(const uint32_t *offs, uint32_t t0, uint32_t T, uint32_t nr[PLAN_ITEMS],
-                                             uint32_t &ci, uint32_t &cs, uint32_t &cm) {
-    uint32_t o[PLAN_ITEMS + 1];
+// The split plan scans chunks of SPLIT_TILE tiles, SPLIT_ITEMS per thread of a 1024-thread
+// block (one chunk covers a 1920x1080 view's 8,160 tiles, so a single view needs one pass).
+constexpr int SPLIT_ITEMS = 8;
+constexpr int SPLIT_TILE = 1024 * SPLIT_ITEMS;
+__host__ __device__ __forceinline__ uint32_t split_chunks(uint64_t T) {
+    return uint32_t((T + SPLIT_TILE - 1) / SPLIT_TILE);
+}
+
+// Ranges of this thread's SPLIT_ITEMS tiles t0 .. (n_ranges <= 255: 8 bits each, tile t0 + j in
+// bits 8 j ..), and their sums: ci items, cs slots (ranges of split tiles), cm split tiles.
+__device__ __forceinline__ uint64_t tile_ranges(const uint32_t *offs, uint32_t t0, uint32_t T, uint32_t &ci,
+                                                uint32_t &cs, uint32_t &cm) {
+    uint32_t o[SPLIT_ITEMS + 1];
 #pragma unroll
-    for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
+    for (int j = 0; j <= SPLIT_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
     ci = cs = cm = 0;
+    uint64_t packed = 0;
 #pragma unroll
-    for (int j = 0; j < PLAN_ITEMS; ++j) {
-        nr[j] = t0 + j < T ? n_ranges(o[j + 1] - o[j], SPLIT_RANGE) : 0u;
-        ci += nr[j];
-        cs += nr[j] > 1 ? nr[j] : 0u;
-        cm += nr[j] > 1 ? 1u : 0u;
+    for (int j = 0; j < SPLIT_ITEMS; ++j) {
+        const uint32_t nr = t0 + j < T ? n_ranges(o[j + 1] - o[j], SPLIT_RANGE) : 0u;
+        packed |= uint64_t(nr) << (8 * j);
+        ci += nr;
+        cs += nr > 1 ? nr : 0u;
+        cm += nr > 1 ? 1u : 0u;
     }
+    return packed;
 }
 
 __global__ void __launch_bounds__(1024)
@@ -103,9 +117,9 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
                  uint64_t *__restrict__ part_m) {
     __shared__ uint64_t s_wsum[16];
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
-    for (uint32_t c = blockIdx.x; c < plan_chunks(t_host); c += gridDim.x) {
-        uint32_t nr[PLAN_ITEMS], ci, cs, cm;
-        tile_ranges4(offs, c * PLAN_TILE + threadIdx.x * PLAN_ITEMS, T, nr, ci, cs, cm);
+    for (uint32_t c = blockIdx.x; c < split_chunks(t_host); c += gridDim.x) {
+        uint32_t ci, cs, cm;
+        tile_ranges(offs, c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS, T, ci, cs, cm);
         uint64_t t1, t2;
         block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
         block_scan1024(uint64_t(cm), s_wsum, &t2);
@@ -116,7 +130,7 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
     }
 }
 
-static_assert(PLAN_TILE == 4096, "split_plan_kernel searches a 4096-entry table in 12 steps");
+static_assert(SPLIT_TILE == 8192, "split_plan_kernel searches an 8192-entry table in 13 steps");
 constexpr int SPLIT_FILL_ILP = 4;                // item searches a thread keeps in flight
 
 __global__ void __launch_bounds__(1024)
@@ -127,14 +141,14 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
     // part_is == NULL: one block walks every chunk with running carries (few chunks)
     __shared__ uint64_t s_wsum[16];
-    __shared__ uint32_t s_item0[PLAN_TILE];      // chunk-relative first item of each tile
-    __shared__ uint32_t s_slot0[PLAN_TILE];      // first partial-sum slot of a split tile, else ~0
+    __shared__ uint32_t s_item0[SPLIT_TILE];     // chunk-relative first item of each tile
+    __shared__ uint32_t s_slot0[SPLIT_TILE];     // first partial-sum slot of a split tile, else ~0
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
     uint64_t c_is = 0, c_m = 0;
-    for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
-        const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
-        uint32_t nr[PLAN_ITEMS], ci, cs, cm;
-        tile_ranges4(offs, t0, T, nr, ci, cs, cm);
+    for (uint32_t c = blockIdx.x; c < split_chunks(T); c += gridDim.x) {
+        const uint32_t t0 = c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS;
+        uint32_t ci, cs, cm;
+        const uint64_t nr = tile_ranges(offs, t0, T, ci, cs, cm);
         uint64_t t1, t2;
         const uint64_t x1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
         const uint64_t x2 = block_scan1024(uint64_t(cm), s_wsum, &t2);
@@ -144,17 +158,18 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         c_m += t2;
         uint32_t i0 = uint32_t(x1), s0 = uint32_t((b1 + x1) >> 32), js = uint32_t(b2 + x2);
 #pragma unroll
-        for (int j = 0; j < PLAN_ITEMS; ++j) {
-            const bool m = nr[j] > 1;
-            s_item0[threadIdx.x * PLAN_ITEMS + j] = i0;
-            s_slot0[threadIdx.x * PLAN_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
+        for (int j = 0; j < SPLIT_ITEMS; ++j) {
+            const uint32_t nj = uint32_t(nr >> (8 * j)) & 0xFFu;
+            const bool m = nj > 1;
+            s_item0[threadIdx.x * SPLIT_ITEMS + j] = i0;
+            s_slot0[threadIdx.x * SPLIT_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
             if (m) {
                 split_tile[js] = t0 + j;
                 split_slot0[js] = s0;
-                s0 += nr[j];
+                s0 += nj;
                 ++js;
             }
-            i0 += nr[j];
+            i0 += nj;
         }
         __syncthreads();
         // item i of the chunk belongs to its last tile whose first item is <= i (tiles with
@@ -164,8 +179,8 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             uint32_t lo[SPLIT_FILL_ILP];
 #pragma unroll
             for (int q = 0; q < SPLIT_FILL_ILP; ++q) lo[q] = 0;
-#pragma unroll
-            for (uint32_t step = PLAN_TILE / 2; step; step >>= 1) {
+#pragma unroll 1
+            for (uint32_t step = SPLIT_TILE / 2; step; step >>= 1) {
 #pragma unroll
                 for (int q = 0; q < SPLIT_FILL_ILP; ++q)
                     if (s_item0[lo[q] + step] <= i + q * 1024u) lo[q] += step;
@@ -175,7 +190,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                 const uint32_t k = i + q * 1024u;
                 if (k < n_items) {
                     const uint32_t r = k - s_item0[lo[q]], sl = s_slot0[lo[q]];
-                    items[ibase + k] = (c * PLAN_TILE + lo[q]) | (r << 24);
+                    items[ibase + k] = (c * SPLIT_TILE + lo[q]) | (r << 24);
                     item_slot[ibase + k] = sl == 0xFFFFFFFFu ? sl : sl + r;
                 }
             }
@@ -214,24 +229,25 @@ __global__ void __launch_bounds__(BLEND_THREADS)
 merge_ranges_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ split_tile,
                     const uint32_t *__restrict__ split_slot0, const uint32_t *__restrict__ counts, Loc loc,
                     const float *__restrict__ part) {
-    const uint32_t j = blockIdx.x;
-    if (j >= counts[1]) return;                                           // block-uniform
-    const uint32_t t = split_tile[j];
-    const uint32_t nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
-    const float *b = part + size_t(split_slot0[j]) * PART_FLOATS;
-    const int p = threadIdx.x;
-    float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
-    for (uint32_t r = 0; r < nr; ++r, b += PART_FLOATS) {
-        Nr += b[p];
-        Ng += b[256 + p];
-        Nb += b[512 + p];
-        D += b[768 + p];
-        T *= b[1024 + p];
+    const uint32_t n_split = counts[1];
+    for (uint32_t j = blockIdx.x; j < n_split; j += gridDim.x) {         // block-uniform
+        const uint32_t t = split_tile[j];
+        const uint32_t nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
+        const float *b = part + size_t(split_slot0[j]) * PART_FLOATS;
+        const int p = threadIdx.x;
+        float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
+        for (uint32_t r = 0; r < nr; ++r, b += PART_FLOATS) {
+            Nr += b[p];
+            Ng += b[256 + p];
+            Nb += b[512 + p];
+            D += b[768 + p];
+            T *= b[1024 + p];
+        }
+        const TileView v = loc(t);
+        int px, py;
+        tile_pixel(p, v.tx, v.ty, px, py);
+        composite_oit(Nr, Ng, Nb, D, T, px, py, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.image, v.aux);
     }
-    const TileView v = loc(t);
-    int px, py;
-    tile_pixel(p, v.tx, v.ty, px, py);
-    composite_oit(Nr, Ng, Nb, D, T, px, py, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.image, v.aux);
 }
 
 struct SplitLayout {
@@ -250,8 +266,8 @@ inline SplitLayout split_layout(uint32_t T, uint64_t capacity) {
     L.sslot = o;  o = align_up(o + size_t(T) * 4 + 4, 256);
     L.counts = o; o = align_up(o + 16, 256);
     L.part = o;   o = align_up(o + max_slots * PART_FLOATS * 4, 256);
-    L.part_is = o; o = align_up(o + (size_t(plan_chunks(T)) + 1) * 8, 256);
-    L.part_m = o;  o = align_up(o + (size_t(plan_chunks(T)) + 1) * 8, 256);
+    L.part_is = o; o = align_up(o + (size_t(split_chunks(T)) + 1) * 8, 256);
+    L.part_m = o;  o = align_up(o + (size_t(split_chunks(T)) + 1) * 8, 256);
     L.totals = o;  o = align_up(o + 2 * 8, 256);
     L.total = o;
     return L;
@@ -272,7 +288,7 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint64_t *part_is = reinterpret_cast<uint64_t *>(w + L.part_is);
     uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
     uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
-    const uint32_t nc = plan_chunks(T);
+    const uint32_t nc = split_chunks(T);
     if (nc <= PLAN_ONE_BLOCK) {                  // few chunks: one block with running carries
         hipLaunchKernelGGL(split_plan_kernel, dim3(1), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
                            static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
@@ -290,8 +306,9 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     hipLaunchKernelGGL(blend_range_kernel<Loc>, dim3(L.max_items), dim3(BLEND_THREADS), 0, s, splat, offs, gids,
                        items, slot, counts, loc, log2f(alpha_min), alpha_max, part);
     MGS_LAUNCH_CHECK("blend_range_kernel");
-    hipLaunchKernelGGL(merge_ranges_kernel<Loc>, dim3(T > 0 ? T : 1), dim3(BLEND_THREADS), 0, s, offs, stile, sslot,
-                       counts, loc, part);
+    // split tiles are at most T; a bounded grid walks them (most tiles are not split)
+    hipLaunchKernelGGL(merge_ranges_kernel<Loc>, dim3(T == 0 ? 1u : (T < MERGE_GRID ? T : MERGE_GRID)),
+                       dim3(BLEND_THREADS), 0, s, offs, stile, sslot, counts, loc, part);
     MGS_LAUNCH_CHECK("merge_ranges_kernel");
     return MGS_OK;
 }

@@ -384,8 +384,10 @@ __device__ __forceinline__ uint32_t range_len(uint32_t L, uint32_t split) {
     return split > m ? split : m;
 }
 __device__ __forceinline__ uint32_t n_ranges(uint32_t L, uint32_t split) {
-    const uint32_t r = range_len(L, split);
-    return L == 0 ? 1u : (L + r - 1) / r;
+    if (L == 0) return 1u;
+    if (L <= 255u * split) return (L + split - 1) / split;
+    const uint32_t r = (L + 254) / 255;          // longer lists: ranges of ceil(L / 255)
+    return (L + r - 1) / r;
 }
 
 }  // namespace mgs
