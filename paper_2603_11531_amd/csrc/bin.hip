@@ -37,6 +37,8 @@ constexpr int CHUNK = 256;                                // supertile entries p
 constexpr int SUPER_MAX_GRID = 8192;                      // resident blocks striding over the level-2 chunks
 constexpr int SUPER_RADIX_ITERS = 4;                      // level-1 sort: 1024 keys per block (a short sort,
 constexpr int SUPER_RADIX_TILE = RADIX_THREADS * SUPER_RADIX_ITERS;   // so more, shorter blocks)
+// supertiles up to which the plan takes the supertile ranges from the sort's digit totals
+constexpr int ST_FROM_DIGITS = 256;
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -629,20 +631,36 @@ chunk_sum_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restric
 }
 
 __global__ void __launch_bounds__(1024)
-chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
+chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
                   const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
                   const uint64_t *__restrict__ total, uint32_t *__restrict__ sc0, uint32_t *__restrict__ chunk_st,
-                  uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks) {
+                  uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks,
+                  const uint32_t *__restrict__ digit_total, uint32_t *st_offs_out) {
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
+    __shared__ uint32_t s_offs[ST_FROM_DIGITS + 1];
     // part == NULL: one block walks every piece with a running carry (few pieces)
     const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
+    // digit_total != NULL (one block, S <= ST_FROM_DIGITS): the supertile sort took a single
+    // radix pass over the whole supertile id, so its digit totals are the supertiles' entry
+    // counts; their exclusive scan is st_offs, written here instead of by a pass over the keys
+    if (digit_total) {
+        uint64_t tot;
+        const uint32_t v = threadIdx.x < S ? digit_total[threadIdx.x] : 0u;
+        const uint32_t pre = uint32_t(block_scan1024(v, s_wsum, &tot));
+        if (threadIdx.x <= S && threadIdx.x <= uint32_t(ST_FROM_DIGITS)) {
+            s_offs[threadIdx.x] = threadIdx.x < S ? pre : uint32_t(tot);
+            st_offs_out[threadIdx.x] = threadIdx.x < S ? pre : uint32_t(tot);
+        }
+        __syncthreads();
+    }
+    const uint32_t *offs_in = digit_total ? s_offs : st_offs;
     uint32_t carry = 0;
     for (uint32_t c = blockIdx.x; c < plan_chunks(S); c += gridDim.x) {
         const uint32_t base = c * PLAN_TILE, k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
         uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
-        for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = s0 + j <= S ? st_offs[s0 + j] : 0u;
+        for (int j = 0; j <= PLAN_ITEMS; ++j) o[j] = s0 + j <= S ? offs_in[s0 + j] : 0u;
         uint32_t nc[PLAN_ITEMS], cnt = 0;
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -664,7 +682,7 @@ chunk_plan_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restri
         for (uint32_t i = threadIdx.x; i < uint32_t(tot); i += 1024) {
             const int k = upper_index(s_pre, int(ns), i);
             chunk_st[first + i] = base + k;
-            chunk_lo[first + i] = st_offs[base + k] + (i - s_pre[k]) * CHUNK;
+            chunk_lo[first + i] = offs_in[base + k] + (i - s_pre[k]) * CHUNK;
         }
         __syncthreads();
         carry += uint32_t(tot);
@@ -860,6 +878,15 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         uint32_t gid, tbase, tw, th, sx, sy;
         uint64_t mask;
+        // wave 0, one lane per tile of the supertile: the tile's list start plus this chunk's
+        // slot in it, loaded before the entries so the two memory latencies overlap
+        uint32_t first = 0u;
+        if (threadIdx.x < SUPER_TILES) {
+            geo.view(chunk_st[c], tbase, tw, th, sx, sy);
+            const int k = threadIdx.x;
+            const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
+            if (tx < tw && ty < th) first = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
+        }
         chunk_entry(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
         s_gid[w][l] = gid;
         uint64_t col = wave_transpose64(mask);
@@ -867,7 +894,6 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
         __syncthreads();
         if (threadIdx.x < SUPER_TILES) {                        // wave 0: one lane per tile
             const int k = threadIdx.x;
-            const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
             const uint32_t ck = s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k];
             uint32_t incl = ck;
 #pragma unroll
@@ -878,7 +904,7 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
             uint32_t lo = incl - ck;
             s_lpre[k] = lo;
             if (k == 63) s_lpre[64] = incl;
-            if (ck > 0) s_first[k] = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
+            if (ck > 0) s_first[k] = first;
 #pragma unroll
             for (int ww = 0; ww < CHUNK / 64; ++ww) {
                 s_lw[ww][k] = lo;
@@ -1142,17 +1168,23 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
             shift += bits;
         }
     }
-    const uint64_t rblocks = (capacity + 1 + 255) / 256;
-    hipLaunchKernelGGL((tile_ranges_kernel<uint32_t>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256), 0,
-                       s, keys[cur], etot, capacity, 0, st_max, st_offs);
-    MGS_LAUNCH_CHECK("tile_ranges_kernel<supertile>");
+    // supertile ranges: from the sort's digit totals when one radix pass covered the whole id
+    // (the plan scans them), else from the sorted keys
+    const uint32_t ncs = plan_chunks(st_max);
+    const bool from_digits = capacity > 0 && npass == 1 && st_max <= uint32_t(ST_FROM_DIGITS) && ncs <= PLAN_ONE_BLOCK;
+    if (!from_digits) {
+        const uint64_t rblocks = (capacity + 1 + 255) / 256;
+        hipLaunchKernelGGL((tile_ranges_kernel<uint32_t>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256),
+                           0, s, keys[cur], etot, capacity, 0, st_max, st_offs);
+        MGS_LAUNCH_CHECK("tile_ranges_kernel<supertile>");
+    }
 
     // level 2: chunks, per-chunk tile counts, column scans, tile offsets, the lists
-    const uint32_t ncs = plan_chunks(st_max);
     if (ncs <= PLAN_ONE_BLOCK) {
         hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs, capacity,
                            static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), sc0,
-                           chunk_st, chunk_lo, nch);
+                           chunk_st, chunk_lo, nch, from_digits ? dtot : static_cast<const uint32_t *>(nullptr),
+                           st_offs);
     } else {
         hipLaunchKernelGGL(chunk_sum_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max,
                            n_pairs, capacity, part_c);
@@ -1161,7 +1193,8 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
                            ncs, totals + 2, static_cast<uint64_t *>(nullptr));
         MGS_LAUNCH_CHECK("part_scan_kernel");
         hipLaunchKernelGGL(chunk_plan_kernel, dim3(plan_grid(ncs)), dim3(1024), 0, s, st_offs, st_count, st_max,
-                           n_pairs, capacity, part_c, totals + 2, sc0, chunk_st, chunk_lo, nch);
+                           n_pairs, capacity, part_c, totals + 2, sc0, chunk_st, chunk_lo, nch,
+                           static_cast<const uint32_t *>(nullptr), st_offs);
     }
     MGS_LAUNCH_CHECK("chunk_plan_kernel");
     const unsigned cgrid = L.chunks_max < uint32_t(SUPER_MAX_GRID) ? L.chunks_max : uint32_t(SUPER_MAX_GRID);

@@ -93,6 +93,16 @@ __host__ __device__ __forceinline__ uint32_t split_chunks(uint64_t T) {
 
 // Ranges of this thread's SPLIT_ITEMS tiles t0 .. (n_ranges <= 255: 8 bits each, tile t0 + j in
 // bits 8 j ..), and their sums: ci items, cs slots (ranges of split tiles), cm split tiles.
+// One chunk's items, slots and split tiles packed for a single block scan: items and slots
+// are at most SPLIT_TILE * 255 < 2^21 each, split tiles at most SPLIT_TILE.
+static_assert(uint64_t(SPLIT_TILE) * 255 < (1ull << 21), "split plan packing");
+__device__ __forceinline__ uint64_t split_pack(uint32_t ci, uint32_t cs, uint32_t cm) {
+    return uint64_t(ci) | (uint64_t(cs) << 21) | (uint64_t(cm) << 42);
+}
+__device__ __forceinline__ uint32_t split_items(uint64_t v) { return uint32_t(v) & 0x1FFFFFu; }
+__device__ __forceinline__ uint32_t split_slots(uint64_t v) { return uint32_t(v >> 21) & 0x1FFFFFu; }
+__device__ __forceinline__ uint32_t split_tiles(uint64_t v) { return uint32_t(v >> 42); }
+
 __device__ __forceinline__ uint64_t tile_ranges(const uint32_t *offs, uint32_t t0, uint32_t T, uint32_t &ci,
                                                 uint32_t &cs, uint32_t &cm) {
     uint32_t o[SPLIT_ITEMS + 1];
@@ -120,12 +130,11 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
     for (uint32_t c = blockIdx.x; c < split_chunks(t_host); c += gridDim.x) {
         uint32_t ci, cs, cm;
         tile_ranges(offs, c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS, T, ci, cs, cm);
-        uint64_t t1, t2;
-        block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
-        block_scan1024(uint64_t(cm), s_wsum, &t2);
+        uint64_t t;
+        block_scan1024(split_pack(ci, cs, cm), s_wsum, &t);
         if (threadIdx.x == 0) {
-            part_is[c] = t1;
-            part_m[c] = t2;
+            part_is[c] = split_items(t) | (uint64_t(split_slots(t)) << 32);
+            part_m[c] = split_tiles(t);
         }
     }
 }
@@ -149,14 +158,14 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         const uint32_t t0 = c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS;
         uint32_t ci, cs, cm;
         const uint64_t nr = tile_ranges(offs, t0, T, ci, cs, cm);
-        uint64_t t1, t2;
-        const uint64_t x1 = block_scan1024(uint64_t(ci) | (uint64_t(cs) << 32), s_wsum, &t1);
-        const uint64_t x2 = block_scan1024(uint64_t(cm), s_wsum, &t2);
+        uint64_t t;
+        const uint64_t x = block_scan1024(split_pack(ci, cs, cm), s_wsum, &t);
         const uint64_t b1 = part_is ? part_is[c] : c_is;       // items | slots << 32 before the chunk
         const uint64_t b2 = part_is ? part_m[c] : c_m;
-        c_is += t1;
-        c_m += t2;
-        uint32_t i0 = uint32_t(x1), s0 = uint32_t((b1 + x1) >> 32), js = uint32_t(b2 + x2);
+        const uint32_t t1 = split_items(t);
+        c_is += t1 | (uint64_t(split_slots(t)) << 32);
+        c_m += split_tiles(t);
+        uint32_t i0 = split_items(x), s0 = uint32_t(b1 >> 32) + split_slots(x), js = uint32_t(b2) + split_tiles(x);
 #pragma unroll
         for (int j = 0; j < SPLIT_ITEMS; ++j) {
             const uint32_t nj = uint32_t(nr >> (8 * j)) & 0xFFu;

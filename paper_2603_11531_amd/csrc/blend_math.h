@@ -281,9 +281,9 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
             const uint32_t g = gids[i];
             const float4 r0 = splat[3 * size_t(g) + 0];
             const float4 r1 = splat[3 * size_t(g) + 1];
-            const float4 r2 = splat[3 * size_t(g) + 2];
             mk = quadrant_mask(r0, r1, tx, ty, log2_amin);
             if (mk) {
+                const float4 r2 = splat[3 * size_t(g) + 2];   // colour, only for a kept Gaussian
                 float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
                 quad_poly(r0, r1, tcx, tcy, qa, qb);
                 wbuf[3 * l + 0] = qa;
