@@ -166,10 +166,22 @@ def enhance(x, mlp, bf16=False):
 # --------------------------------------------------------------------------
 # Step 5 -- depth-aware weight (Eq. 3).
 # --------------------------------------------------------------------------
-def depth_weight(phi, d, s):
-    """w = phi^2 + phi / d^2 + exp(s_max / d); s_max = largest activated scale."""
+# Eq. 3 and the two ablations of it in the paper's ablation table (Table 3): "without
+# depth" read as d = 1 in Eq. 3, "without scale" as Eq. 3 without its exp(s_max / d) term.
+WEIGHT_EQ3, WEIGHT_NO_DEPTH, WEIGHT_NO_SCALE = 0, 1, 2
+
+
+def depth_weight(phi, d, s, mode=WEIGHT_EQ3):
+    """w = phi^2 + phi / d^2 + exp(s_max / d); s_max = largest activated scale (Eq. 3),
+    or an ablation: mode WEIGHT_NO_DEPTH puts d = 1, WEIGHT_NO_SCALE drops the last term."""
     s_max = s.max(dim=1).values
-    return phi * phi + phi / (d * d) + torch.exp(s_max / d)
+    if mode == WEIGHT_EQ3:
+        return phi * phi + phi / (d * d) + torch.exp(s_max / d)
+    if mode == WEIGHT_NO_DEPTH:
+        return phi * phi + phi + torch.exp(s_max)
+    if mode == WEIGHT_NO_SCALE:
+        return phi * phi + phi / (d * d)
+    raise ValueError(f"unknown weight mode {mode}")
 
 
 # --------------------------------------------------------------------------
@@ -196,7 +208,7 @@ def ewa_cov2d(x_c, Sigma, cam):
     return cov
 
 
-def project(params, cam, phi=None, m=None, tile=16):
+def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3):
     """Per-Gaussian preprocessing: everything the per-pixel blend needs.
 
     Returns float64 tensors: mean2d (N,2), cov2d (N,2,2), conic (N,3) =
@@ -218,7 +230,7 @@ def project(params, cam, phi=None, m=None, tile=16):
     if m is None:
         m = torch.ones(n, dtype=DT)
     o_eff = act["o"] * m
-    w = depth_weight(phi, d, act["s"])
+    w = depth_weight(phi, d, act["s"], weight_mode)
     front = d > cam["near"]
     # Keep the projection finite for culled points (they never reach the blend).
     d_safe = torch.where(front, d, torch.ones_like(d))
@@ -551,7 +563,7 @@ def mlp_params(mlp, requires_grad=False):
 
 
 def render(scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), bf16=False, mode="brute", tile=16,
-           params=None, mparams=None, sorted_path=False):
+           params=None, mparams=None, sorted_path=False, weight_mode=WEIGHT_EQ3):
     """Enhance -> project -> (bin) -> blend for one view; returns (image, aux, proj)."""
     camt = camera_tensors(cam)
     p = scene_params(scene) if params is None else params
@@ -562,11 +574,11 @@ def render(scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), bf16=False, mode="brute", t
         _, _, P = camera_space(p["mean"], camt)
         x = mlp_features(P, act["s"], act["q"], p["sh"])
         phi, m = enhance(x, mp, bf16=bf16)
-    proj = project(p, camt, phi, m, tile)
+    proj = project(p, camt, phi, m, tile, weight_mode)
     if sorted_path:
         return render_sorted(proj, camt, bg), None, proj
     img, aux = render_oit(proj, camt, bg, mode=mode)
     return img, aux, proj
 
 
-__all__ += ["scene_params", "mlp_params", "bf16_round"]
+__all__ += ["scene_params", "mlp_params", "bf16_round", "WEIGHT_EQ3", "WEIGHT_NO_DEPTH", "WEIGHT_NO_SCALE"]

@@ -107,6 +107,48 @@ def test_depth_weight_closed_form():
     assert np.allclose(w.numpy(), exp, rtol=1e-15, atol=0)
 
 
+def test_weight_ablations_drop_exactly_their_dependence():
+    """Table 3's Eq. 3 ablations: "without depth" leaves w independent of the camera distance,
+    "without scale" independent of the Gaussians' scales; Eq. 3 itself depends on both."""
+    scene = mgs_data.make_scene_uniform(300, 11)
+    p = O.scene_params(scene)
+    near, far = (O.camera_tensors(mgs_data.look_at((0.0, 0.0, -z), width=64, height=64)) for z in (4.0, 6.5))
+    with torch.no_grad():
+        w = {(m, c): O.project(p, cam, weight_mode=m)["w"] for m in (0, 1, 2) for c, cam in (("n", near), ("f", far))}
+    assert torch.equal(w[(O.WEIGHT_NO_DEPTH, "n")], w[(O.WEIGHT_NO_DEPTH, "f")])
+    assert not torch.allclose(w[(O.WEIGHT_EQ3, "n")], w[(O.WEIGHT_EQ3, "f")])
+    assert not torch.allclose(w[(O.WEIGHT_NO_SCALE, "n")], w[(O.WEIGHT_NO_SCALE, "f")])
+    big = dict(scene)
+    big["log_scale"] = scene["log_scale"] + np.float32(0.7)
+    pb = O.scene_params(big)
+    with torch.no_grad():
+        wb = {m: O.project(pb, near, weight_mode=m)["w"] for m in (0, 2)}
+    assert torch.equal(wb[O.WEIGHT_NO_SCALE], w[(O.WEIGHT_NO_SCALE, "n")])
+    assert not torch.allclose(wb[O.WEIGHT_EQ3], w[(O.WEIGHT_EQ3, "n")])
+    # the three differ pairwise on the same view
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        assert not torch.allclose(w[(a, "n")], w[(b, "n")])
+
+
+def test_weight_eq3_at_unit_depth_is_the_no_depth_ablation():
+    """Every Gaussian on the plane z = 0 seen from (0, 0, -1): d = 1, where Eq. 3 and its
+    "without depth" reading coincide; the "without scale" one is 1 (= exp 0) lower."""
+    scene = mgs_data.make_scene_uniform(200, 12, half=0.3)
+    scene = dict(scene)
+    mean = scene["mean"].copy()
+    mean[2] = 0.0
+    scene["mean"] = mean
+    p = O.scene_params(scene)
+    cam = O.camera_tensors(mgs_data.look_at((0.0, 0.0, -1.0), width=64, height=64))
+    with torch.no_grad():
+        d = O.camera_space(p["mean"], cam)[1]
+        assert torch.equal(d, torch.ones_like(d))
+        w0, w1, w2 = (O.project(p, cam, weight_mode=m)["w"] for m in (0, 1, 2))
+    assert torch.equal(w0, w1)
+    s_max = O.activate(p)["s"].max(dim=1).values
+    assert torch.allclose(w0 - w2, torch.exp(s_max), rtol=1e-14, atol=0)
+
+
 # ---------------------------------------------------------------- EWA projection
 def test_ewa_closed_form_on_axis():
     f, z = 100.0, 5.0
