@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Camera", "look_at", "make_scene_uniform", "make_scene_unbounded",
     "make_scene_ball", "make_mlp", "circle_poses", "spline_poses",
-    "make_config", "tiny_scene", "perturb_scene", "MLP_IN", "MLP_HIDDEN",
+    "make_config", "tiny_scene", "perturb_scene", "MLP_IN", "MLP_HIDDEN", "make_mlp_f", "MLP_F_WIDTHS",
     "make_nvq", "NVQ_GROUPS", "NVQ_DIM", "NVQ_CODEWORDS",
 ]
 
@@ -172,6 +172,26 @@ def make_mlp(seed, hidden=MLP_HIDDEN, n_in=MLP_IN):
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return dict(W1=f32(W1), b1=f32(np.zeros(hidden)), W2=f32(W2), b2=f32(np.zeros(hidden)),
                 w_phi=f32(w_phi), b_phi=np.float32(1.0), w_o=f32(w_o), b_o=np.float32(2.0))
+
+
+MLP_F_WIDTHS = (256, 128, 64)   # the appendix's MLP_f hidden layers
+
+
+def make_mlp_f(seed, widths=MLP_F_WIDTHS, n_in=MLP_IN):
+    """He-normal FP32 master weights of an MLP with ReLU hidden layers of the given widths
+    (keys W1, b1, W2, b2, ...); heads as make_mlp (phi near 1, opacity factor near sigma(2))."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    out, prev = {}, n_in
+    for k, h in enumerate(widths, start=1):
+        out[f"W{k}"] = f32(rng.normal(0, math.sqrt(2.0 / prev), size=(h, prev)))
+        out[f"b{k}"] = f32(0.05 * rng.normal(size=h))
+        prev = h
+    out["w_phi"] = f32(0.1 * rng.normal(0, math.sqrt(2.0 / prev), size=prev))
+    out["b_phi"] = np.float32(1.0)
+    out["w_o"] = f32(rng.normal(0, math.sqrt(2.0 / prev), size=prev))
+    out["b_o"] = np.float32(2.0)
+    return out
 
 
 def circle_poses(n_poses, radius, width, height, f=None, elevation_deg=0.0):

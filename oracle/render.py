@@ -142,24 +142,28 @@ def bf16_round(x):
 
 
 def enhance(x, mlp, bf16=False):
-    """F = MLP_f(x) (two ReLU layers), phi = ReLU(MLP_phi(F)), m = sigmoid(MLP_o(F)).
+    """F = MLP_f(x), phi = ReLU(MLP_phi(F)), m = sigmoid(MLP_o(F)) (Eq. 4).
 
-    ``mlp`` holds float64 tensors W1 (64,22), b1, W2 (64,64), b2, w_phi (64,),
-    b_phi, w_o (64,), b_o.  With ``bf16`` the inputs of every product (x, the
-    weights, the hidden activations and F) are rounded to bfloat16 first and the
-    products are summed in float64, standing in for BF16-in / FP32-accumulate.
+    MLP_f is the chain of ReLU layers W1, b1, W2, b2, ... (every ``Wk`` present, in
+    order): two layers of 64 (the benchmark shape) or the appendix's three of 256, 128
+    and 64.  ``mlp`` holds float64 tensors Wk (h_k, h_{k-1}), bk, w_phi (h_L,), b_phi,
+    w_o (h_L,), b_o.  With ``bf16`` the inputs of every product (x, the weights, the
+    hidden activations and F) are rounded to bfloat16 first and the products are
+    summed in float64, standing in for BF16-in / FP32-accumulate.
     """
-    W1, W2, wp, wo = mlp["W1"], mlp["W2"], mlp["w_phi"], mlp["w_o"]
+    h = bf16_round(x) if bf16 else x
+    k = 1
+    while f"W{k}" in mlp:
+        W = bf16_round(mlp[f"W{k}"]) if bf16 else mlp[f"W{k}"]
+        h = torch.relu(h @ W.T + mlp[f"b{k}"])
+        if bf16:
+            h = bf16_round(h)
+        k += 1
+    wp, wo = mlp["w_phi"], mlp["w_o"]
     if bf16:
-        x, W1, W2, wp, wo = bf16_round(x), bf16_round(W1), bf16_round(W2), bf16_round(wp), bf16_round(wo)
-    h1 = torch.relu(x @ W1.T + mlp["b1"])
-    if bf16:
-        h1 = bf16_round(h1)
-    F = torch.relu(h1 @ W2.T + mlp["b2"])
-    if bf16:
-        F = bf16_round(F)
-    phi = torch.relu(F @ wp + mlp["b_phi"])
-    m = torch.sigmoid(F @ wo + mlp["b_o"])
+        wp, wo = bf16_round(wp), bf16_round(wo)
+    phi = torch.relu(h @ wp + mlp["b_phi"])
+    m = torch.sigmoid(h @ wo + mlp["b_o"])
     return phi, m
 
 

@@ -548,6 +548,45 @@ def test_mlp_hidden_permutation_and_init():
     assert float((m3 - 1 / (1 + math.exp(-2.0))).abs().max()) < 1e-15
 
 
+def test_mlp_f_256_128_64_matches_a_loop_over_neurons():
+    """The appendix's MLP_f (ReLU layers of 256, 128, 64) against plain Python loops over
+    the neurons of every layer for a few Gaussians (brute force, independent of the matrix
+    products)."""
+    mlp = mgs_data.make_mlp_f(21)
+    mp = O.mlp_params(mlp)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(3, 22))
+    phi, m = O.enhance(torch.tensor(x), mp)
+    for g in range(3):
+        h = [float(v) for v in x[g]]
+        for k in (1, 2, 3):
+            W, b = mlp[f"W{k}"].astype(np.float64), mlp[f"b{k}"].astype(np.float64)
+            h = [max(0.0, sum(W[i][j] * h[j] for j in range(len(h))) + b[i]) for i in range(W.shape[0])]
+        assert len(h) == 64
+        zp = sum(float(mlp["w_phi"][i]) * h[i] for i in range(64)) + float(mlp["b_phi"])
+        zo = sum(float(mlp["w_o"][i]) * h[i] for i in range(64)) + float(mlp["b_o"])
+        assert abs(float(phi[g]) - max(0.0, zp)) < 1e-12
+        assert abs(float(m[g]) - 1.0 / (1.0 + math.exp(-zo))) < 1e-12
+
+
+def test_mlp_identity_layer_leaves_the_output_unchanged():
+    """A third hidden layer that is the identity (on ReLU outputs, which are >= 0) gives the
+    two-layer network's result: the layers are chained in order, each exactly once."""
+    mp = _mlp64()
+    rng = np.random.default_rng(2)
+    x = torch.tensor(rng.normal(size=(30, 22)))
+    phi, m = O.enhance(x, mp)
+    deep = dict(mp)
+    deep["W3"] = torch.eye(64, dtype=torch.float64)
+    deep["b3"] = torch.zeros(64, dtype=torch.float64)
+    phi3, m3 = O.enhance(x, deep)
+    assert torch.equal(phi, phi3) and torch.equal(m, m3)
+    # ... and a non-identity third layer changes it
+    deep["W3"] = torch.eye(64, dtype=torch.float64).roll(1, dims=0) * 0.5
+    phi4, _ = O.enhance(x, deep)
+    assert not torch.allclose(phi, phi4)
+
+
 def test_bf16_rounding_is_round_to_nearest_even():
     v = torch.tensor([1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 1 + 2 ** -8 + 2 ** -20, 3.0],
                      dtype=torch.float64)
