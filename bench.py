@@ -290,8 +290,10 @@ def main():
             ev[0].record(stream)
         if isinstance(src["scene"], M.DeviceNVQ):  # attributes read through the NVQ codebooks
             R.enhance_project_nvq(src["scene"], cs, dm)
-        else:
-            R.enhance_project(src["scene"], cs, dm)  # Eq. 4 MLP fused with the projection
+        elif src.get("mlp_f") is not None:        # the appendix's MLP_f 256-128-64, fused
+            R.enhance_project_mlp_f(src["scene"], cs, src["mlp_f"])
+        else:  # Eq. 4 MLP fused with the projection; Eq. 3 weight or one of its ablations
+            R.enhance_project(src["scene"], cs, dm, weight_mode=src.get("weight_mode", M._lib.MGS_WEIGHT_EQ3))
         if ev is not None:
             ev[1].record(stream)
         R.bin(sorted_path)
@@ -354,6 +356,51 @@ def main():
                        resident_bytes_per_gaussian=round(dq.nbytes() / dq.n, 2),
                        float32_bytes_per_gaussian=round(ds.nbytes() / ds.n, 2))
         del dq
+    res_weight = None
+    if not args.no_extra:
+        # Table 3's ablations of Eq. 3 (the same frames with another per-Gaussian weight)
+        # interleaved repeats, median per mode: the differences are within run-to-run noise
+        modes = (("eq3", M._lib.MGS_WEIGHT_EQ3), ("no_depth", M._lib.MGS_WEIGHT_NO_DEPTH),
+                 ("no_scale", M._lib.MGS_WEIGHT_NO_SCALE))
+        walls = {name: [] for name, _ in modes}
+        ep_ms = {name: [] for name, _ in modes}
+        log("timing OIT with Eq. 3 and its two ablations (3 interleaved repeats) ...")
+        for _ in range(3):
+            for name, mode in modes:
+                src["weight_mode"] = mode
+                wall_w, stages_w, _ = run(False)
+                walls[name].append(wall_w)
+                ep_ms[name].append(float(stages_w[:, 0].mean()))
+        src["weight_mode"] = M._lib.MGS_WEIGHT_EQ3
+        med = {name: float(np.median(v)) for name, v in walls.items()}
+        res_weight = {name: dict(fps=round(args.steps / med[name], 2), vs_eq3=round(med["eq3"] / med[name], 3),
+                                 enhance_project_ms=round(float(np.median(ep_ms[name])), 4))
+                      for name, _ in modes}
+        # the paper's FPS ratios for the same ablations (Table 3, another device), for context
+        res_weight["paper_vs_eq3"] = dict(no_depth=round(1167 / 1125, 3), no_scale=round(1171 / 1125, 3))
+    res_mlpf = None
+    if not args.no_extra:
+        # the appendix's enhancement network MLP_f (ReLU layers 256, 128, 64), fused with the
+        # projection: ~93 kFLOP per Gaussian, a matrix-core-bound stage
+        log("timing OIT with MLP_f 256-128-64 ...")
+        dmf = M.DeviceMLPF(mgs_data.make_mlp_f(1))
+        maxf = 0
+        for c in cams:
+            R.render(ds, c, dmf, bg=bg)
+            maxf = max(maxf, R.pairs())
+        R.ensure_capacity(int(maxf * 1.1) + 4096)
+        src["mlp_f"] = dmf
+        wall_f, stages_f, _ = run(False)
+        src["mlp_f"] = None
+        ep_f = float(stages_f[:, 0].mean())
+        flop_f = ds.n * 2.0 * (22 * 256 + 256 * 128 + 128 * 64 + 64 * 2)
+        res_mlpf = dict(fps=round(args.steps / wall_f, 2), ms_per_frame=round(1e3 * wall_f / args.steps, 4),
+                        stage_ms=dict(zip(["enhance_project_mlp_f", "bin", "blend_oit"],
+                                          [round(float(v), 4) for v in stages_f.mean(axis=0)])),
+                        flop_per_gaussian=int(flop_f / ds.n),
+                        mfma_tflops=round(flop_f / (ep_f * 1e-3) / 1e12, 2),
+                        mfma_frac=round(flop_f / (ep_f * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4))
+        del dmf
     blend_ms = float(stages[:, 2].mean())
     evals = 256.0 * mean_P
     achieved = evals * BLEND_FLOP_PER_EVAL / (blend_ms * 1e-3) / 1e12
@@ -402,6 +449,8 @@ def main():
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
         "nvq": res_nvq,
+        "weighting_ablations": res_weight,
+        "mlp_f": res_mlpf,
         "roofline": {"bound": "alu",
                      "kernel": "mgs_blend_oit_split (split_plan_kernel + blend_range_kernel + merge_ranges_kernel)",
                      "achieved": round(achieved, 2),

@@ -51,6 +51,13 @@ extern "C" {
 /* Floats per projected Gaussian record ("splat"), see mgs_projected. */
 #define MGS_SPLAT_FLOATS 12
 
+/* Per-Gaussian blending weight w (mgs_project_weighted / mgs_enhance_project_weighted):
+ * Eq. 3, or the two ablations of it in the paper's ablation table (Table 3), read as
+ * d = 1 ("without depth") and the exp(s_max / d) term dropped ("without scale"). */
+#define MGS_WEIGHT_EQ3       0      /* w = phi^2 + phi/d^2 + exp(s_max/d)                */
+#define MGS_WEIGHT_NO_DEPTH  1      /* w = phi^2 + phi + exp(s_max)                      */
+#define MGS_WEIGHT_NO_SCALE  2      /* w = phi^2 + phi/d^2                               */
+
 /* Pinhole camera.  R is row-major world->camera (rows: right, down, forward). */
 typedef struct mgs_camera {
     float   R[9];
@@ -129,6 +136,44 @@ const char *mgs_version(void);
 int mgs_mlp_pack(const float *params, void *packed, void *stream);
 
 /*
+ * The appendix's enhancement network MLP_f: ReLU hidden layers of 256, 128 and 64 neurons
+ * (Additional Implementation Details), with the inputs x and the phi / opacity heads of
+ * Eq. 4 above.  Parameters: one float32 array of MGS_MLPF_PARAMS values, row-major:
+ *   W1 [256][22], b1 [256], W2 [128][256], b2 [128], W3 [64][128], b3 [64],
+ *   w_phi [64], b_phi, w_o [64], b_o  (offsets MGS_MLPF_OFF_*).
+ */
+#define MGS_MLPF_OFF_W1    0
+#define MGS_MLPF_OFF_B1    5632
+#define MGS_MLPF_OFF_W2    5888
+#define MGS_MLPF_OFF_B2    38656
+#define MGS_MLPF_OFF_W3    38784
+#define MGS_MLPF_OFF_B3    46976
+#define MGS_MLPF_OFF_WPHI  47040
+#define MGS_MLPF_OFF_BPHI  47104
+#define MGS_MLPF_OFF_WO    47105
+#define MGS_MLPF_OFF_BO    47169
+#define MGS_MLPF_PARAMS    47170
+/* Bytes of the packed MLP_f written by mgs_mlp_f_pack (bf16 MFMA operands + float32 biases). */
+#define MGS_MLPF_PACKED_BYTES 104208
+
+/*
+ * mgs_mlp_f_pack -- MLP_f parameters (device, MGS_MLPF_PARAMS floats) -> packed operands
+ * for mgs_enhance_project_mlp_f (`packed`: MGS_MLPF_PACKED_BYTES bytes of device memory,
+ * 16-byte aligned).  Weights are rounded to bfloat16 (nearest-even), biases stay float32.
+ */
+int mgs_mlp_f_pack(const float *params, void *packed, void *stream);
+
+/*
+ * mgs_enhance_project_mlp_f -- mgs_enhance_project with MLP_f in place of the two-layer
+ * network: per Gaussian phi and omod from MLP_f (bfloat16 products, float32
+ * accumulation), then the projection of mgs_project.  Same outputs and argument rules as
+ * mgs_enhance_project; `packed_mlp_f` from mgs_mlp_f_pack.  The backward pass
+ * (mgs_render_backward) differentiates the two-layer network only.
+ */
+int mgs_enhance_project_mlp_f(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp_f, int tile,
+                              float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
  * mgs_enhance -- view-dependent enhancement, Eq. 4 (Sec. 3.1).
  * For every Gaussian: P_i = (mu - t_v)/|mu - t_v| with t_v the camera centre,
  * s = exp(log_scale), r = normalised quaternion, Y = SH coefficients; runs the
@@ -156,6 +201,16 @@ int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
                 void *stream);
 
 /*
+ * mgs_project_weighted -- mgs_project with the weight w of weight_mode (MGS_WEIGHT_*,
+ * the Eq. 3 ablations of Table 3); mgs_project is weight_mode = MGS_WEIGHT_EQ3.  Every
+ * other output is the same.  An unknown weight_mode is MGS_ERR_INVALID_ARG.  The
+ * backward pass (mgs_render_backward) differentiates Eq. 3 only.
+ */
+int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
+                         const float *omod, int tile, float alpha_min, int weight_mode,
+                         mgs_projected *out, void *stream);
+
+/*
  * mgs_enhance_project -- mgs_enhance followed by mgs_project in one pass over the
  * attributes (each Gaussian is read once; the MLP runs on MFMA per 64-Gaussian
  * wave).  Writes the same projected record as the two calls, and phi / omod
@@ -163,6 +218,14 @@ int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
  */
 int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
                         float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
+ * mgs_enhance_project_weighted -- mgs_enhance_project with the weight of weight_mode
+ * (MGS_WEIGHT_*, as mgs_project_weighted).
+ */
+int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp,
+                                 int tile, float alpha_min, int weight_mode, mgs_projected *out, float *phi,
+                                 float *omod, void *stream);
 
 /*
  * Vector-quantised Gaussians (Sec. 3.3, neural vector quantization: attribute

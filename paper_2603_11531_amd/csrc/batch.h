@@ -53,6 +53,7 @@ __device__ __forceinline__ CamK camk_device(const mgs_camera &c) {
                                  __fmul_rn(c.R[2 * 3 + i], c.t[2]));
     k.tiles_x = (c.width + MGS_TILE - 1) / MGS_TILE;
     k.tiles_y = (c.height + MGS_TILE - 1) / MGS_TILE;
+    k.weight_mode = MGS_WEIGHT_EQ3;
     return k;
 }
 

@@ -39,7 +39,12 @@ struct CamK {
     float near_z;
     float campos[3];   // t_v = -R^T t
     int tiles_x, tiles_y;
+    int weight_mode;   // MGS_WEIGHT_*: Eq. 3 or one of its ablations
 };
+
+inline bool valid_weight_mode(int m) {
+    return m == MGS_WEIGHT_EQ3 || m == MGS_WEIGHT_NO_DEPTH || m == MGS_WEIGHT_NO_SCALE;
+}
 
 inline CamK make_camk(const mgs_camera *c) {
     CamK k;
@@ -51,6 +56,7 @@ inline CamK make_camk(const mgs_camera *c) {
         k.campos[i] = -(c->R[0 * 3 + i] * c->t[0] + c->R[1 * 3 + i] * c->t[1] + c->R[2 * 3 + i] * c->t[2]);
     k.tiles_x = (c->width + MGS_TILE - 1) / MGS_TILE;
     k.tiles_y = (c->height + MGS_TILE - 1) / MGS_TILE;
+    k.weight_mode = MGS_WEIGHT_EQ3;
     return k;
 }
 

@@ -21,14 +21,24 @@ __host__ __device__ __forceinline__ int perm_neuron(int kc, int g, int j) {
     return 16 * (2 * kc + (j >> 2)) + 4 * g + (j & 3);
 }
 
+// ReLU then bf16 of (lo, hi).  Converted first, then clamped as signed 16-bit integers (a
+// negative bf16, -0 included, has the sign bit set): the same bits as converting max(x, 0),
+// one conversion per pair of values and one packed integer max per pair.
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ i16x2 relu_bf16x2(float a, float b) {
+    const bf16x2 c = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    return __builtin_elementwise_max(__builtin_bit_cast(i16x2, c), i16x2{0, 0});
+}
 __device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
-    f32x8 v;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        v[i] = fmaxf(lo[i], 0.0f);
-        v[i + 4] = fmaxf(hi[i], 0.0f);
-    }
-    return __builtin_convertvector(v, bf16x8);
+    bf16x8 r;
+    i16x2 *u = reinterpret_cast<i16x2 *>(&r);
+    u[0] = relu_bf16x2(lo[0], lo[1]);
+    u[1] = relu_bf16x2(lo[2], lo[3]);
+    u[2] = relu_bf16x2(hi[0], hi[1]);
+    u[3] = relu_bf16x2(hi[2], hi[3]);
+    return r;
 }
 
 constexpr int FEAT_STRIDE = 40;   // bf16 per LDS row (32 + 8 padding)

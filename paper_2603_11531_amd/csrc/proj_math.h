@@ -100,8 +100,17 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
     if (f.s[1] > f.smax) { f.smax = f.s[1]; f.kmax = 1; }
     if (f.s[2] > f.smax) { f.smax = f.s[2]; f.kmax = 2; }
     f.phi = in.phi;
-    f.esd = expf(f.smax / f.z);
-    f.w = in.phi * in.phi + in.phi / (f.z * f.z) + f.esd;
+    // Eq. 3, or its ablations without the depth (d = 1) or without the scale term
+    if (cam.weight_mode == MGS_WEIGHT_NO_DEPTH) {
+        f.esd = expf(f.smax);
+        f.w = in.phi * in.phi + in.phi + f.esd;
+    } else if (cam.weight_mode == MGS_WEIGHT_NO_SCALE) {
+        f.esd = 0.0f;
+        f.w = in.phi * in.phi + in.phi / (f.z * f.z);
+    } else {
+        f.esd = expf(f.smax / f.z);
+        f.w = in.phi * in.phi + in.phi / (f.z * f.z) + f.esd;
+    }
 
     const float limx = FRUSTUM_CLAMP * (0.5f * cam.W) / cam.fx;
     const float limy = FRUSTUM_CLAMP * (0.5f * cam.H) / cam.fy;

@@ -142,10 +142,12 @@ inline NvqSource nvq_source(const mgs_gaussians_nvq *q) {
 
 }  // namespace mgs
 
-extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
-                                   float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream) {
+extern "C" int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_camera *cam,
+                                            const void *packed_mlp, int tile, float alpha_min, int weight_mode,
+                                            mgs_projected *out, float *phi, float *omod, void *stream) {
     using namespace mgs;
     int rc;
+    MGS_REQUIRE(valid_weight_mode(weight_mode), "unknown weight_mode %d", weight_mode);
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;
     if ((rc = check_camera(cam)) != MGS_OK) return rc;
     if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
@@ -154,7 +156,8 @@ extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam
     MGS_REQUIRE(packed_mlp && aligned(packed_mlp, 16), "packed MLP must be non-NULL and 16-byte aligned");
     if (g->n == 0) return MGS_OK;
     MGS_REQUIRE(phi && omod, "phi / omod is NULL");
-    const CamK k = make_camk(cam);
+    CamK k = make_camk(cam);
+    k.weight_mode = weight_mode;
     const int64_t groups = (g->n + 63) / 64;
     int64_t blocks = (groups + 3) / 4;
     if (blocks > 2048) blocks = 2048;
@@ -166,24 +169,37 @@ extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam
     return MGS_OK;
 }
 
-extern "C" int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
-                           const float *omod, int tile, float alpha_min, mgs_projected *out,
-                           void *stream) {
+extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
+                                   float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream) {
+    return mgs_enhance_project_weighted(g, cam, packed_mlp, tile, alpha_min, MGS_WEIGHT_EQ3, out, phi, omod, stream);
+}
+
+extern "C" int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
+                                    const float *omod, int tile, float alpha_min, int weight_mode,
+                                    mgs_projected *out, void *stream) {
     using namespace mgs;
     int rc;
+    MGS_REQUIRE(valid_weight_mode(weight_mode), "unknown weight_mode %d", weight_mode);
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;
     if ((rc = check_camera(cam)) != MGS_OK) return rc;
     if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
     if (tile != MGS_TILE) return set_error(MGS_ERR_UNSUPPORTED, "tile must be %d", MGS_TILE);
     MGS_REQUIRE(alpha_min > 0.0f && alpha_min < 1.0f, "alpha_min must be in (0, 1)");
     if (g->n == 0) return MGS_OK;
-    const CamK k = make_camk(cam);
+    CamK k = make_camk(cam);
+    k.weight_mode = weight_mode;
     const unsigned blocks = unsigned((g->n + 255) / 256);
     hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, as_stream(stream), *g, k, phi, omod,
                        alpha_min, reinterpret_cast<float4 *>(out->splat),
                        reinterpret_cast<uint2 *>(out->rect), out->n_tiles);
     MGS_LAUNCH_CHECK("project_kernel");
     return MGS_OK;
+}
+
+extern "C" int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
+                           const float *omod, int tile, float alpha_min, mgs_projected *out,
+                           void *stream) {
+    return mgs_project_weighted(g, cam, phi, omod, tile, alpha_min, MGS_WEIGHT_EQ3, out, stream);
 }
 
 extern "C" int mgs_nvq_decode(const mgs_gaussians_nvq *q, float *log_scale, float *quat, float *opacity_logit,

@@ -97,6 +97,22 @@ class DeviceMLP:
                 for name, off, shape in L.MLP_LAYOUT}
 
 
+class DeviceMLPF:
+    """The appendix's MLP_f (hidden layers 256, 128, 64) on the device: parameters in the
+    mgs.h layout plus the packed bf16 operands that mgs_enhance_project_mlp_f reads."""
+
+    def __init__(self, mlp, device="cuda"):
+        flat = np.zeros(L.MGS_MLPF_PARAMS, np.float32)
+        for name, off, shape in L.MLPF_LAYOUT:
+            v = np.asarray(mlp[name], np.float32).reshape(-1)
+            if v.size != max(1, int(np.prod(shape))):
+                raise ValueError(f"MLP_f parameter {name}: {v.size} values, layout wants shape {shape}")
+            flat[off:off + v.size] = v
+        self.params = torch.as_tensor(flat).to(device)
+        self.packed = torch.empty(L.MGS_MLPF_PACKED_BYTES // 4, dtype=torch.float32, device=device)
+        L.check(L.lib().mgs_mlp_f_pack(L.ptr(self.params), L.ptr(self.packed), None))
+
+
 class Renderer:
     """Reusable buffers for one (N, W, H) shape; one call per stage or ``render``."""
 
@@ -154,17 +170,35 @@ class Renderer:
         L.check(L.lib().mgs_enhance(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
                                     L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
 
-    def project(self, scene: DeviceScene, cam_s, use_mlp=False, alpha_min=ALPHA_MIN, stream=None):
+    def project(self, scene: DeviceScene, cam_s, use_mlp=False, alpha_min=ALPHA_MIN, stream=None,
+                weight_mode=L.MGS_WEIGHT_EQ3):
         phi = L.ptr(self.phi) if use_mlp else None
         om = L.ptr(self.omod) if use_mlp else None
-        L.check(L.lib().mgs_project(L.C.byref(scene.struct), L.C.byref(cam_s), phi, om, L.MGS_TILE,
-                                    alpha_min, L.C.byref(self.proj), L.stream_ptr(stream)))
+        if weight_mode == L.MGS_WEIGHT_EQ3:
+            L.check(L.lib().mgs_project(L.C.byref(scene.struct), L.C.byref(cam_s), phi, om, L.MGS_TILE,
+                                        alpha_min, L.C.byref(self.proj), L.stream_ptr(stream)))
+        else:
+            L.check(L.lib().mgs_project_weighted(L.C.byref(scene.struct), L.C.byref(cam_s), phi, om, L.MGS_TILE,
+                                                 alpha_min, int(weight_mode), L.C.byref(self.proj),
+                                                 L.stream_ptr(stream)))
 
-    def enhance_project(self, scene: DeviceScene, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None):
+    def enhance_project(self, scene: DeviceScene, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None,
+                        weight_mode=L.MGS_WEIGHT_EQ3):
         """Fused enhance + project (one read of the attributes); also fills phi / omod."""
-        L.check(L.lib().mgs_enhance_project(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
-                                            L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
-                                            L.ptr(self.omod), L.stream_ptr(stream)))
+        if weight_mode == L.MGS_WEIGHT_EQ3:
+            L.check(L.lib().mgs_enhance_project(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
+                                                L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
+                                                L.ptr(self.omod), L.stream_ptr(stream)))
+        else:
+            L.check(L.lib().mgs_enhance_project_weighted(
+                L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed), L.MGS_TILE, alpha_min,
+                int(weight_mode), L.C.byref(self.proj), L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
+
+    def enhance_project_mlp_f(self, scene: DeviceScene, cam_s, mlp: DeviceMLPF, alpha_min=ALPHA_MIN, stream=None):
+        """Fused MLP_f (256-128-64) enhancement + projection; also fills phi / omod."""
+        L.check(L.lib().mgs_enhance_project_mlp_f(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
+                                                  L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
+                                                  L.ptr(self.omod), L.stream_ptr(stream)))
 
     def enhance_project_nvq(self, q: DeviceNVQ, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None):
         """Fused enhance + project reading the attributes through the NVQ codebooks."""
@@ -209,21 +243,28 @@ class Renderer:
 
     # -- whole pass -----------------------------------------------------------
     def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
-               check_capacity=True, stream=None, fused=False, split=True):
+               check_capacity=True, stream=None, fused=False, split=True, weight_mode=L.MGS_WEIGHT_EQ3):
         """enhance -> project -> bin -> blend (``scene`` a DeviceScene, or a DeviceNVQ whose
         attributes are read through its codebooks).  With check_capacity the host reads the
-        pair count once and re-bins with a larger capacity on overflow."""
+        pair count once and re-bins with a larger capacity on overflow.  ``weight_mode``
+        selects Eq. 3 or one of its ablations (MGS_WEIGHT_*)."""
         cam_s = L.make_camera(cam)
         if isinstance(scene, DeviceNVQ):
             if mlp is None:
                 raise ValueError("a vector-quantised scene renders through the fused enhance + project (needs an MLP)")
+            if weight_mode != L.MGS_WEIGHT_EQ3:
+                raise ValueError("the vector-quantised path computes the Eq. 3 weight only")
             self.enhance_project_nvq(scene, cam_s, mlp, stream=stream)
+        elif isinstance(mlp, DeviceMLPF):
+            if weight_mode != L.MGS_WEIGHT_EQ3:
+                raise ValueError("the MLP_f path computes the Eq. 3 weight only")
+            self.enhance_project_mlp_f(scene, cam_s, mlp, stream=stream)
         elif mlp is not None and fused:
-            self.enhance_project(scene, cam_s, mlp, stream=stream)
+            self.enhance_project(scene, cam_s, mlp, stream=stream, weight_mode=weight_mode)
         else:
             if mlp is not None:
                 self.enhance(scene, cam_s, mlp, stream)
-            self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream)
+            self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream, weight_mode=weight_mode)
         self.bin(sorted_path, stream)
         if check_capacity:
             P = self.pairs()      # synchronises

@@ -20,7 +20,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_project(scene, cam, mlp=None, bf16=False, tile=16):
+def oracle_project(scene, cam, mlp=None, bf16=False, tile=16, weight_mode=O.WEIGHT_EQ3):
     camt = O.camera_tensors(cam)
     p = O.scene_params(scene)
     phi = m = None
@@ -29,7 +29,7 @@ def oracle_project(scene, cam, mlp=None, bf16=False, tile=16):
         _, _, P = O.camera_space(p["mean"], camt)
         phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp), bf16=bf16)
     with torch.no_grad():
-        return O.project(p, camt, phi, m, tile), camt
+        return O.project(p, camt, phi, m, tile, weight_mode), camt
 
 
 def compare_oit_image(gpu_img, variants, flagged, tol):

@@ -58,6 +58,15 @@ def test_host_side_validation(lib):
     cam.width = 10
     assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 8, 1 / 255, C.byref(proj), None) \
         == L.MGS_ERR_UNSUPPORTED
+    # weight modes: the three of include/mgs.h pass the host checks (n = 0: nothing to launch),
+    # anything else is rejected
+    for mode in (L.MGS_WEIGHT_EQ3, L.MGS_WEIGHT_NO_DEPTH, L.MGS_WEIGHT_NO_SCALE):
+        assert lib.mgs_project_weighted(C.byref(g), C.byref(cam), None, None, 16, 1 / 255, mode, C.byref(proj),
+                                        None) == L.MGS_OK
+    for mode in (-1, 3):
+        assert lib.mgs_project_weighted(C.byref(g), C.byref(cam), None, None, 16, 1 / 255, mode, C.byref(proj),
+                                        None) == L.MGS_ERR_INVALID_ARG
+        assert "weight_mode" in lib.mgs_last_error().decode()
     assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 16, 1.5, C.byref(proj), None) \
         == L.MGS_ERR_INVALID_ARG
     # n = 0 is a valid no-op
