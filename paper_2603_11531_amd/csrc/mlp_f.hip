@@ -33,7 +33,18 @@ constexpr int MF_L3 = 81920;         // [2 m tiles][8 k steps]   W3, inputs perm
 constexpr int MF_H = 98304;          // [4 k steps]              rows 0 = w_phi, 1 = w_o
 constexpr int MF_B1 = 102400, MF_B2 = 103424, MF_B3 = 103936, MF_BH = 104192;
 static_assert(MF_BH + 8 <= MGS_MLPF_PACKED_BYTES && MGS_MLPF_PACKED_BYTES % 16 == 0, "packed MLP_f size");
-constexpr int MF_THREADS = 512;
+#ifndef MGS_MLPF_NT
+#define MGS_MLPF_NT 2
+#endif
+#ifndef MGS_MLPF_THREADS
+#define MGS_MLPF_THREADS 512
+#endif
+// 32-Gaussian N tiles per MLP pass, and the workgroup size (one workgroup per CU).  Measured on
+// the 1M-Gaussian workload: NT = 2 with 512 threads (238 VGPRs, two waves per SIMD) 117 us;
+// NT = 1 with 1024 threads (128 VGPRs, four waves per SIMD, twice the LDS weight traffic) 127 us;
+// NT = 1 with 768 threads 130 us.
+constexpr int MF_NT = MGS_MLPF_NT;
+constexpr int MF_THREADS = MGS_MLPF_THREADS;
 
 // Input neuron of the next layer fed by K step ks, lane half h, slot e of a B fragment made
 // from registers 8 s .. 8 s + 7 of an accumulator (see the header comment).
@@ -107,17 +118,12 @@ __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(MF_THREADS)
-enhance_project_mlpf_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, float alpha_min,
-                            float4 *__restrict__ splat, uint2 *__restrict__ rect_out,
-                            uint32_t *__restrict__ ntiles_out, float *__restrict__ phi_out,
-                            float *__restrict__ omod_out) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_w[MGS_MLPF_PACKED_BYTES];
-    __shared__ float s_xo[MF_THREADS / 64][128];
-    for (int k = threadIdx.x; k < MGS_MLPF_PACKED_BYTES / 16; k += blockDim.x)
-        reinterpret_cast<uint4 *>(s_w)[k] = reinterpret_cast<const uint4 *>(packed)[k];
-    __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, c = l & 31;
+// MLP_f for the 32 NT Gaussians g0 + 32 nt + c (nt < NT) of a wave; (phi, m) of Gaussian
+// g0 + k - base go to xo[k] and xo[64 + k] (k = 32 nt + c + o, o the pass offset).
+template <int NT>
+__device__ __forceinline__ void mlpf_pass(const mgs_gaussians &g, const CamK &cam, int64_t g0, int o,
+                                          const uint8_t *s_w, float *xo) {
+    const int l = threadIdx.x & 63, h = l >> 5, c = l & 31;
     const bf16x8 *A1 = reinterpret_cast<const bf16x8 *>(s_w + MF_L1) + l;
     const bf16x8 *A2 = reinterpret_cast<const bf16x8 *>(s_w + MF_L2) + l;
     const bf16x8 *A3 = reinterpret_cast<const bf16x8 *>(s_w + MF_L3) + l;
@@ -126,102 +132,136 @@ enhance_project_mlpf_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict
     const float *b2 = reinterpret_cast<const float *>(s_w + MF_B2);
     const float *b3 = reinterpret_cast<const float *>(s_w + MF_B3);
     const float *bh = reinterpret_cast<const float *>(s_w + MF_BH);
-    const int64_t n = g.n, ngroups = (n + 63) / 64;
-    const int wpb = MF_THREADS / 64;
-    for (int64_t grp = int64_t(blockIdx.x) * wpb + w; grp < ngroups; grp += int64_t(gridDim.x) * wpb) {
-        // B fragments of the first layer: features 16 s + 8 h .. + 7 of Gaussian 32 nt + c
-        bf16x8 x[2][2];
+    const int64_t n = g.n;
+    // B fragments of the first layer: features 16 s + 8 h .. + 7 of Gaussian g0 + 32 nt + c
+    bf16x8 x[NT][2];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int64_t i = grp * 64 + 32 * nt + c;
-            f32x8 f[4];
-            if (i < n) {
-                const GaussIn a = load_gauss(g, i, nullptr, nullptr);
-                lane_features(a.mu, a.ls, a.q, a.sh, cam, f);
-            } else {
+    for (int nt = 0; nt < NT; ++nt) {
+        const int64_t i = g0 + 32 * nt + c;
+        f32x8 f[4];
+        if (i < n) {
+            const GaussIn a = load_gauss(g, i, nullptr, nullptr);
+            lane_features(a.mu, a.ls, a.q, a.sh, cam, f);
+        } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) f[q] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
-            }
-            // lane half h takes features 16 s + 8 h .. + 7 (a select, not a dynamic register index)
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                f32x8 y;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) y[e] = h ? f[2 * s + 1][e] : f[2 * s][e];
-                x[nt][s] = __builtin_convertvector(y, bf16x8);
-            }
+            for (int q = 0; q < 4; ++q) f[q] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
-        // layers 1 and 2: each 32-neuron tile of layer 1 feeds two K steps of layer 2 at once
-        f32x16 acc2[4][2];
+        // lane half h takes features 16 s + 8 h .. + 7 (a select, not a dynamic register index)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc2[mt][0] = acc2[mt][1] = bias_tile(b2 + 32 * mt, h);
+        for (int s = 0; s < 2; ++s) {
+            f32x8 y;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) y[e] = h ? f[2 * s + 1][e] : f[2 * s][e];
+            x[nt][s] = __builtin_convertvector(y, bf16x8);
+        }
+    }
+    // layers 1 and 2: each 32-neuron tile of layer 1 feeds two K steps of layer 2 at once
+    f32x16 acc2[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const f32x16 b = bias_tile(b2 + 32 * mt, h);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc2[mt][nt] = b;
+    }
 #pragma unroll 1
-        for (int t = 0; t < 8; ++t) {
-            f32x16 h1[2];
-            h1[0] = h1[1] = bias_tile(b1 + 32 * t, h);
+    for (int t = 0; t < 8; ++t) {
+        __asm__ volatile("" ::: "memory");
+        const f32x16 b = bias_tile(b1 + 32 * t, h);
+        f32x16 h1[NT];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const bf16x8 a = A1[(2 * t + s) * 64];
+        for (int nt = 0; nt < NT; ++nt) h1[nt] = mfma32(A1[(2 * t) * 64], x[nt][0], b);
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) h1[nt] = mfma32(a, x[nt][s], h1[nt]);
+        for (int nt = 0; nt < NT; ++nt) h1[nt] = mfma32(A1[(2 * t + 1) * 64], x[nt][1], h1[nt]);
+        bf16x8 p[NT][2];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) p[nt][s] = relu_half(h1[nt], s);
+        // K step s outer: the accumulators are updated in turn, so no instruction waits on the
+        // one just issued
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const bf16x8 a = A2[(16 * mt + 2 * t + s) * 64];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc2[mt][nt] = mfma32(a, p[nt][s], acc2[mt][nt]);
             }
-            bf16x8 p[2][2];
+    }
+    // layer 3
+    bf16x8 x3[NT][8];
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int s = 0; s < 2; ++s) p[nt][s] = relu_half(h1[nt], s);
-            // K step s outer: the eight accumulators are updated in turn, so no instruction
-            // waits on the one just issued
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int nt = 0; nt < NT; ++nt) x3[nt][2 * mt + s] = relu_half(acc2[mt][nt], s);
+    f32x16 acc3[2][NT];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    const bf16x8 a = A2[(16 * mt + 2 * t + s) * 64];
+    for (int mt = 0; mt < 2; ++mt) {
+        const f32x16 b = bias_tile(b3 + 32 * mt, h);
 #pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) acc2[mt][nt] = mfma32(a, p[nt][s], acc2[mt][nt]);
-                }
+        for (int nt = 0; nt < NT; ++nt) acc3[mt][nt] = b;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const bf16x8 a = A3[(8 * mt + ks) * 64];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc3[mt][nt] = mfma32(a, x3[nt][ks], acc3[mt][nt]);
         }
-        // layer 3
-        bf16x8 x3[2][8];
+    // heads: row 0 phi, row 1 m
+    bf16x8 xh[NT][4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) x3[nt][2 * mt + s] = relu_half(acc2[mt][nt], s);
-        f32x16 acc3[2][2];
+            for (int nt = 0; nt < NT; ++nt) xh[nt][2 * mt + s] = relu_half(acc3[mt][nt], s);
+    f32x16 hd[NT];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) acc3[mt][0] = acc3[mt][1] = bias_tile(b3 + 32 * mt, h);
+    for (int nt = 0; nt < NT; ++nt) hd[nt] = f32x16{};
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
+    for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 a = AH[ks * 64];
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-                const bf16x8 a = A3[(8 * mt + ks) * 64];
+        for (int nt = 0; nt < NT; ++nt) hd[nt] = mfma32(a, xh[nt][ks], hd[nt]);
+    }
+    // (phi, m) of Gaussian 32 nt + c sit in lane c (h = 0), registers 0 and 1
+    if (h == 0) {
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) acc3[mt][nt] = mfma32(a, x3[nt][ks], acc3[mt][nt]);
-            }
-        // heads: row 0 phi, row 1 m
-        bf16x8 xh[2][4];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) xh[nt][2 * mt + s] = relu_half(acc3[mt][nt], s);
-        f32x16 hd[2] = {};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const bf16x8 a = AH[ks * 64];
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) hd[nt] = mfma32(a, xh[nt][ks], hd[nt]);
+        for (int nt = 0; nt < NT; ++nt) {
+            xo[o + 32 * nt + c] = fmaxf(hd[nt][0] + bh[0], 0.0f);
+            xo[64 + o + 32 * nt + c] = 1.0f / (1.0f + expf(-(hd[nt][1] + bh[1])));
         }
-        // (phi, m) of Gaussian 32 nt + c sit in lane c (h = 0), registers 0 and 1
-        if (h == 0) {
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                s_xo[w][32 * nt + c] = fmaxf(hd[nt][0] + bh[0], 0.0f);
-                s_xo[w][64 + 32 * nt + c] = 1.0f / (1.0f + expf(-(hd[nt][1] + bh[1])));
-            }
+    }
+}
+
+// A wave takes 64 Gaussians per task: MLP_f in 2 / NT passes of 32 NT Gaussians (NT = 2: each
+// weight fragment read from LDS feeds two matrix instructions; NT = 1: half the accumulator
+// registers, more waves per SIMD), then one projection per lane.
+template <int NT, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+enhance_project_mlpf_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, float alpha_min,
+                            float4 *__restrict__ splat, uint2 *__restrict__ rect_out,
+                            uint32_t *__restrict__ ntiles_out, float *__restrict__ phi_out,
+                            float *__restrict__ omod_out) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_w[MGS_MLPF_PACKED_BYTES];
+    __shared__ float s_xo[THREADS / 64][128];
+    for (int k = threadIdx.x; k < MGS_MLPF_PACKED_BYTES / 16; k += blockDim.x)
+        reinterpret_cast<uint4 *>(s_w)[k] = reinterpret_cast<const uint4 *>(packed)[k];
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t n = g.n, ngroups = (n + 63) / 64;
+    const int wpb = THREADS / 64;
+    for (int64_t grp = int64_t(blockIdx.x) * wpb + w; grp < ngroups; grp += int64_t(gridDim.x) * wpb) {
+#pragma unroll 1
+        for (int o = 0; o < 64; o += 32 * NT) {
+            // weights and biases are read from LDS at each use: keep the compiler from hoisting
+            // those loads out of the loops into (spilled) registers
+            __asm__ volatile("" ::: "memory");
+            mlpf_pass<NT>(g, cam, grp * 64 + o, o, s_w, s_xo[w]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -274,8 +314,8 @@ extern "C" int mgs_enhance_project_mlp_f(const mgs_gaussians *g, const mgs_camer
     const int64_t groups = (g->n + 63) / 64, per_block = MF_THREADS / 64;
     int64_t blocks = (groups + per_block - 1) / per_block;
     if (blocks > cus) blocks = cus;
-    hipLaunchKernelGGL(enhance_project_mlpf_kernel, dim3(unsigned(blocks)), dim3(MF_THREADS), 0, as_stream(stream),
-                       *g, k, static_cast<const uint8_t *>(packed_mlp_f), alpha_min,
+    hipLaunchKernelGGL((enhance_project_mlpf_kernel<MF_NT, MF_THREADS>), dim3(unsigned(blocks)), dim3(MF_THREADS), 0,
+                       as_stream(stream), *g, k, static_cast<const uint8_t *>(packed_mlp_f), alpha_min,
                        reinterpret_cast<float4 *>(out->splat), reinterpret_cast<uint2 *>(out->rect), out->n_tiles,
                        phi, omod);
     MGS_LAUNCH_CHECK("enhance_project_mlpf_kernel");
