@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Camera", "look_at", "make_scene_uniform", "make_scene_unbounded",
     "make_scene_ball", "make_mlp", "circle_poses", "spline_poses",
-    "make_config", "tiny_scene", "perturb_scene", "MLP_IN", "MLP_HIDDEN", "make_mlp_f", "MLP_F_WIDTHS",
+    "make_config", "tiny_scene", "perturb_scene", "MLP_IN", "MLP_HIDDEN", "make_mlp_f", "MLP_F_WIDTHS", "with_sh_degree",
     "make_nvq", "NVQ_GROUPS", "NVQ_DIM", "NVQ_CODEWORDS",
 ]
 
@@ -172,6 +172,26 @@ def make_mlp(seed, hidden=MLP_HIDDEN, n_in=MLP_IN):
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return dict(W1=f32(W1), b1=f32(np.zeros(hidden)), W2=f32(W2), b2=f32(np.zeros(hidden)),
                 w_phi=f32(w_phi), b_phi=np.float32(1.0), w_o=f32(w_o), b_o=np.float32(2.0))
+
+
+def with_sh_degree(scene, degree, seed, sd_high=0.1):
+    """Copy of a first-order-SH scene with SH of ``degree`` (0..3): degree 0 keeps the DC
+    coefficient of each channel; degrees 2 and 3 append coefficients N(0, sd_high) drawn from
+    their own stream (so the lower-order ones stay those of the input).  SH planes stay
+    coefficient-major (plane 3 k + channel)."""
+    if degree not in (0, 1, 2, 3):
+        raise ValueError("SH degree must be 0..3")
+    out = dict(scene)
+    sh = np.asarray(scene["sh"])
+    n = sh.shape[1]
+    K = (degree + 1) ** 2
+    if K <= 4:
+        out["sh"] = np.ascontiguousarray(sh[:3 * K], dtype=np.float32)
+    else:
+        rng = np.random.default_rng([seed, 2])
+        extra = rng.normal(0.0, sd_high, size=(3 * (K - 4), n))
+        out["sh"] = np.ascontiguousarray(np.concatenate([sh, extra], axis=0), dtype=np.float32)
+    return out
 
 
 MLP_F_WIDTHS = (256, 128, 64)   # the appendix's MLP_f hidden layers

@@ -30,7 +30,7 @@ import torch
 __all__ = [
     "ALPHA_MIN", "ALPHA_MAX", "DILATION", "JAC_CLAMP", "T_STOP", "SH_C0", "SH_C1",
     "AMBIG_LOG", "to64", "quat_to_rotmat", "activate", "camera_space", "sh1_color",
-    "mlp_features", "enhance", "depth_weight", "ewa_cov2d", "project", "bin_lists",
+    "mlp_features", "sh_basis", "sh_color", "enhance", "depth_weight", "ewa_cov2d", "project", "bin_lists",
     "bin_lists_bruteforce", "bin_lists_sorted", "pixel_grid", "eval_pixels_oit", "render_oit",
     "render_sorted", "render", "camera_tensors", "oit_pixel_variants",
 ]
@@ -123,12 +123,52 @@ def sh1_color(P, sh):
     return torch.clamp(c, min=0.0)
 
 
+def sh_basis(P, degree):
+    """Orthonormal real SH up to ``degree`` (0..3) at unit directions P: (N, (degree+1)^2),
+    coefficient l^2 + l + m for order m = -l..l, with the sign (-1)^m on odd m (the l = 1 terms
+    are then -C1 y, C1 z, -C1 x, as in sh1_color)."""
+    x, y, z = P[:, 0], P[:, 1], P[:, 2]
+    one = torch.ones_like(x)
+    out = [SH_C0 * one]
+    if degree >= 1:
+        out += [-SH_C1 * y, SH_C1 * z, -SH_C1 * x]
+    if degree >= 2:
+        a, b, c = 0.5 * math.sqrt(15 / math.pi), 0.25 * math.sqrt(5 / math.pi), 0.25 * math.sqrt(15 / math.pi)
+        out += [a * x * y, -a * y * z, b * (3 * z * z - 1), -a * x * z, c * (x * x - y * y)]
+    if degree >= 3:
+        a = 0.25 * math.sqrt(35 / (2 * math.pi))
+        b = 0.5 * math.sqrt(105 / math.pi)
+        c = 0.25 * math.sqrt(21 / (2 * math.pi))
+        d = 0.25 * math.sqrt(7 / math.pi)
+        e = 0.25 * math.sqrt(105 / math.pi)
+        out += [-a * y * (3 * x * x - y * y), b * x * y * z, -c * y * (5 * z * z - 1), d * z * (5 * z * z - 3),
+                -c * x * (5 * z * z - 1), e * z * (x * x - y * y), -a * x * (x * x - 3 * y * y)]
+    return torch.stack(out, dim=1)
+
+
+SH_DEGREE_OF = {1: 0, 4: 1, 9: 2, 16: 3}
+
+
+def sh_color(P, sh):
+    """c = max(0, 1/2 + sum_k Y_k(P) sh_k) for sh (N, K, 3), K = (degree+1)^2 of degree 0..3
+    (Table 3's SH-order variants); degree 1 is sh1_color itself."""
+    K = sh.shape[1]
+    if K == 4:
+        return sh1_color(P, sh)
+    Y = sh_basis(P, SH_DEGREE_OF[K])
+    return torch.clamp(0.5 + (Y[:, :, None] * sh).sum(dim=1), min=0.0)
+
+
 # --------------------------------------------------------------------------
 # Step 4 -- neural view-dependent enhancement (Eq. 4).
 # --------------------------------------------------------------------------
 def mlp_features(P, s, q, sh):
-    """MLP input [P_i, s_i, r_i, Y_i]: 3 + 3 + 4 + 12 = 22 values per Gaussian."""
-    return torch.cat([P, s, q, sh.reshape(sh.shape[0], 12)], dim=1)
+    """MLP input [P_i, s_i, r_i, Y_i]: 3 + 3 + 4 + 12 = 22 values per Gaussian.  Y_i is the
+    degree <= 1 block of the SH coefficients (the first four of each channel; zeros for a
+    degree-0 model)."""
+    n, K = sh.shape[0], sh.shape[1]
+    Y = sh[:, :4] if K >= 4 else torch.cat([sh, torch.zeros(n, 4 - K, 3, dtype=sh.dtype)], dim=1)
+    return torch.cat([P, s, q, Y.reshape(n, 12)], dim=1)
 
 
 def bf16_round(x):
@@ -227,7 +267,7 @@ def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3):
     """
     act = activate(params)
     x_c, d, P = camera_space(params["mean"], cam)
-    color = sh1_color(P, params["sh"])
+    color = sh_color(P, params["sh"])
     n = d.shape[0]
     if phi is None:
         phi = torch.ones(n, dtype=DT)
@@ -558,7 +598,8 @@ def scene_params(scene, requires_grad=False):
              log_scale=to64(np.asarray(scene["log_scale"]).T, requires_grad),
              quat=to64(np.asarray(scene["quat"]).T, requires_grad),
              opacity_logit=to64(scene["opacity_logit"], requires_grad),
-             sh=to64(np.asarray(scene["sh"]).T.reshape(n, 4, 3), requires_grad))
+             sh=to64(np.asarray(scene["sh"]).T.reshape(n, np.asarray(scene["sh"]).shape[0] // 3, 3),
+                     requires_grad))
     return p
 
 

@@ -97,6 +97,66 @@ def test_sh1_color_axes():
     assert float(O.sh1_color(P[:1], neg).max()) == 0.0
 
 
+# ---------------------------------------------------------------- SH orders 0-3 (Table 3 variants)
+def _unit_dirs(n, seed):
+    P = np.random.default_rng(seed).normal(size=(n, 3))
+    return P / np.linalg.norm(P, axis=1, keepdims=True)
+
+
+def test_sh_basis_is_the_real_harmonics_of_scipy_with_odd_m_negated():
+    """Degrees 0..3 against scipy's complex harmonics turned real (standard real form, no
+    Condon-Shortley phase), times (-1)^m on odd m: the convention that gives -C1 y, C1 z, -C1 x."""
+    from scipy.special import sph_harm_y
+    P = _unit_dirs(40, 3)
+    theta, phi = np.arccos(P[:, 2]), np.arctan2(P[:, 1], P[:, 0])
+    Y = O.sh_basis(torch.tensor(P), 3).numpy()
+    for l in range(4):
+        for m in range(-l, l + 1):
+            if m > 0:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, m, theta, phi).real
+            elif m < 0:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, -m, theta, phi).imag
+            else:
+                ref = sph_harm_y(l, 0, theta, phi).real
+            sign = -1.0 if m % 2 else 1.0
+            assert np.allclose(Y[:, l * l + l + m], sign * ref, atol=1e-12, rtol=0), (l, m)
+
+
+def test_sh_basis_is_orthonormal_on_the_sphere():
+    """Gauss-Legendre in cos(theta) x uniform phi (exact for these polynomial degrees)."""
+    from scipy.special import roots_legendre
+    u, wu = roots_legendre(12)
+    ph = np.arange(24) * (2 * math.pi / 24)
+    ct, pp = np.meshgrid(u, ph, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    P = np.stack([st * np.cos(pp), st * np.sin(pp), ct], -1).reshape(-1, 3)
+    w = (wu[:, None] * np.full(24, 2 * math.pi / 24)[None]).reshape(-1)
+    Y = O.sh_basis(torch.tensor(P), 3).numpy()
+    G = (Y * w[:, None]).T @ Y
+    assert np.allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_color_of_every_order_and_the_features_it_feeds():
+    rng = np.random.default_rng(4)
+    P = torch.tensor(_unit_dirs(30, 5))
+    sh3 = torch.tensor(rng.normal(0, 0.3, size=(30, 16, 3)))
+    # order 1 through the general basis is sh1_color; order 3 by an explicit sum per coefficient
+    Y = O.sh_basis(P, 3)
+    c1 = torch.clamp(0.5 + sum(Y[:, k, None] * sh3[:, k] for k in range(4)), min=0.0)
+    assert torch.allclose(O.sh1_color(P, sh3[:, :4]), c1, atol=1e-14)
+    c3 = torch.clamp(0.5 + sum(Y[:, k, None] * sh3[:, k] for k in range(16)), min=0.0)
+    assert torch.allclose(O.sh_color(P, sh3), c3, atol=1e-14)
+    c0 = O.sh_color(P, sh3[:, :1])
+    assert torch.allclose(c0, torch.clamp(0.5 + O.SH_C0 * sh3[:, 0], min=0.0).expand(30, 3), atol=1e-15)
+    # the MLP sees the degree <= 1 block: equal for orders 1-3, zero-padded for order 0
+    s = torch.ones(30, 3, dtype=torch.float64)
+    q = torch.ones(30, 4, dtype=torch.float64)
+    f1 = O.mlp_features(P, s, q, sh3[:, :4])
+    assert torch.equal(O.mlp_features(P, s, q, sh3), f1) and torch.equal(O.mlp_features(P, s, q, sh3[:, :9]), f1)
+    f0 = O.mlp_features(P, s, q, sh3[:, :1])
+    assert torch.equal(f0[:, :13], f1[:, :13]) and float(f0[:, 13:].abs().max()) == 0.0
+
+
 # ---------------------------------------------------------------- weight (Eq. 3)
 def test_depth_weight_closed_form():
     phi = torch.tensor([1.0, 0.0, 2.5], dtype=torch.float64)
