@@ -378,6 +378,28 @@ def main():
                       for name, _ in modes}
         # the paper's FPS ratios for the same ablations (Table 3, another device), for context
         res_weight["paper_vs_eq3"] = dict(no_depth=round(1167 / 1125, 3), no_scale=round(1171 / 1125, 3))
+    res_sh = None
+    if not args.no_extra:
+        # Table 3's SH-order variants: the same Gaussians with colour SH of order 0, 2 or 3
+        # (3, 27, 48 SH floats per Gaussian against 12)
+        res_sh = {}
+        for deg in (0, 2, 3):
+            log(f"timing OIT with SH order {deg} ...")
+            dsd = M.DeviceScene(mgs_data.with_sh_degree(scene, deg, 0))
+            maxd = 0
+            for c in cams:
+                R.render(dsd, c, dm, bg=bg)
+                maxd = max(maxd, R.pairs())
+            R.ensure_capacity(int(maxd * 1.1) + 4096)
+            src["scene"] = dsd
+            wall_d, stages_d, _ = run(False)
+            res_sh[str(deg)] = dict(fps=round(args.steps / wall_d, 2), vs_order1=round(wall / wall_d, 3),
+                                    enhance_project_ms=round(float(stages_d[:, 0].mean()), 4),
+                                    bytes_per_gaussian=round(dsd.nbytes() / dsd.n, 1))
+            del dsd
+        src["scene"] = ds
+        # the paper's FPS for the same variants (Table 3, another device), for context
+        res_sh["paper_fps"] = {"0": 1219, "1": 1125, "2": 917, "3": 841}
     res_mlpf = None
     if not args.no_extra:
         # the appendix's enhancement network MLP_f (ReLU layers 256, 128, 64), fused with the
@@ -451,6 +473,7 @@ def main():
         "nvq": res_nvq,
         "weighting_ablations": res_weight,
         "mlp_f": res_mlpf,
+        "sh_orders": res_sh,
         "roofline": {"bound": "alu",
                      "kernel": "mgs_blend_oit_split (split_plan_kernel + blend_range_kernel + merge_ranges_kernel)",
                      "achieved": round(achieved, 2),

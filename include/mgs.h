@@ -220,6 +220,18 @@ int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const voi
                         float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
 
 /*
+ * mgs_enhance_project_sh -- mgs_enhance_project for a scene whose colour is real SH of order
+ * sh_degree (0..3; Table 3's SH-order variants): g->sh holds 3 (sh_degree + 1)^2 planes,
+ * plane 3 k + channel, k = l^2 + l + m (orders m = -l..l, sign (-1)^m on odd m, as the
+ * first-order terms above).  Colour c = max(0, 1/2 + sum_k Y_k(P) sh_k); the MLP input Y_i is
+ * the order <= 1 block (zeros for order 0).  sh_degree 1 is mgs_enhance_project.  Other
+ * arguments and outputs as mgs_enhance_project; sh_degree outside 0..3 is MGS_ERR_INVALID_ARG.
+ * The backward pass (mgs_render_backward) is first-order only.
+ */
+int mgs_enhance_project_sh(const mgs_gaussians *g, int sh_degree, const mgs_camera *cam, const void *packed_mlp,
+                           int tile, float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
  * mgs_enhance_project_weighted -- mgs_enhance_project with the weight of weight_mode
  * (MGS_WEIGHT_*, as mgs_project_weighted).
  */

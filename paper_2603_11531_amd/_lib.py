@@ -33,6 +33,7 @@ EXPORTED = [
     "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
+    "mgs_enhance_project_sh",
 ]
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
 MLPF_LAYOUT = (("W1", 0, (256, 22)), ("b1", 5632, (256,)), ("W2", 5888, (128, 256)), ("b2", 38656, (128,)),
@@ -92,6 +93,8 @@ def load(path=LIB_PATH):
         "mgs_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, P(mgs_projected), vp]),
         "mgs_enhance_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, i32, f32, P(mgs_projected), vp, vp, vp]),
         "mgs_mlp_f_pack": (i32, [vp, vp, vp]),
+        "mgs_enhance_project_sh": (i32, [P(mgs_gaussians), i32, P(mgs_camera), vp, i32, f32, P(mgs_projected), vp,
+                                         vp, vp]),
         "mgs_enhance_project_mlp_f": (i32, [P(mgs_gaussians), P(mgs_camera), vp, i32, f32, P(mgs_projected), vp, vp,
                                             vp]),
         "mgs_project_weighted": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, i32, P(mgs_projected),

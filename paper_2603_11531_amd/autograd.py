@@ -23,6 +23,8 @@ class MGSRender(torch.autograd.Function):
         dev = mean.device
         scene = DeviceScene.from_tensors(dict(mean=mean.detach(), log_scale=log_scale.detach(), quat=quat.detach(),
                                               opacity_logit=opacity_logit.detach(), sh=sh.detach()))
+        if scene.sh_degree != 1:
+            raise ValueError("the backward pass differentiates first-order SH only")
         R = Renderer(scene.n, cam.width, cam.height, device=dev)
         cam_s = L.make_camera(cam)
         use_mlp = mlp_params is not None

@@ -16,6 +16,7 @@ constexpr float FRUSTUM_CLAMP = 1.3f;
 struct GaussIn {
     float mu[3], ls[3], q[4], logit, sh[12];
     float phi, om;
+    float cext[3];            // SH terms above first order, added before the colour clamp (0 for SH1)
 };
 
 struct GaussFwd {
@@ -57,6 +58,7 @@ __device__ __forceinline__ GaussIn load_gauss(const mgs_gaussians &g, int64_t i,
     for (int k = 0; k < 12; ++k) in.sh[k] = g.sh[k * n + i];
     in.phi = phi_in ? phi_in[i] : 1.0f;
     in.om = om_in ? om_in[i] : 1.0f;
+    in.cext[0] = in.cext[1] = in.cext[2] = 0.0f;
     return in;
 }
 
@@ -91,7 +93,8 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         f.cpre[ch] = 0.5f + SH_C0 * in.sh[ch] +
-                     SH_C1 * (-f.P[1] * in.sh[3 + ch] + f.P[2] * in.sh[6 + ch] - f.P[0] * in.sh[9 + ch]);
+                     SH_C1 * (-f.P[1] * in.sh[3 + ch] + f.P[2] * in.sh[6 + ch] - f.P[0] * in.sh[9 + ch]) +
+                     in.cext[ch];
         f.col[ch] = fmaxf(0.0f, f.cpre[ch]);
     }
 

@@ -59,6 +59,56 @@ struct NvqSource {
         }
         in.phi = 1.0f;
         in.om = 1.0f;
+        in.cext[0] = in.cext[1] = in.cext[2] = 0.0f;
+        return in;
+    }
+};
+
+// Float32 SoA planes with SH of order DEG (0, 2 or 3; 3 (DEG + 1)^2 planes, plane 3 k + channel):
+// the MLP and the first-order colour see the order <= 1 block (zeros for order 0), the terms of
+// order 2 and 3 go to cext.  Real SH with the sign (-1)^m on odd m, as for order 1.
+template <int DEG>
+struct SoaShSource {
+    mgs_gaussians g;
+    float campos[3];
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    __device__ __forceinline__ int64_t count() const { return g.n; }
+    __device__ __forceinline__ GaussIn load(int64_t i) const {
+        const int64_t n = g.n;
+        GaussIn in;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            in.mu[k] = g.mean[k * n + i];
+            in.ls[k] = g.log_scale[k * n + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in.q[k] = g.quat[k * n + i];
+        in.logit = g.opacity_logit[i];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) in.sh[k] = k < 3 * K ? g.sh[k * n + i] : 0.0f;
+        in.phi = 1.0f;
+        in.om = 1.0f;
+        in.cext[0] = in.cext[1] = in.cext[2] = 0.0f;
+        if constexpr (DEG >= 2) {
+            const float vx = in.mu[0] - campos[0], vy = in.mu[1] - campos[1], vz = in.mu[2] - campos[2];
+            const float vi = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+            const float x = vx * vi, y = vy * vi, z = vz * vi;
+            float Y[K > 4 ? K - 4 : 1];
+            const float a2 = 1.0925484305920792f, b2 = 0.31539156525252005f, c2 = 0.5462742152960396f;
+            Y[0] = a2 * x * y; Y[1] = -a2 * y * z; Y[2] = b2 * (3.0f * z * z - 1.0f); Y[3] = -a2 * x * z;
+            Y[4] = c2 * (x * x - y * y);
+            if constexpr (DEG >= 3) {
+                const float a3 = 0.5900435899266435f, b3 = 2.890611442640554f, c3 = 0.4570457994644658f;
+                const float d3 = 0.3731763325901154f, e3 = 1.445305721320277f;
+                Y[5] = -a3 * y * (3.0f * x * x - y * y); Y[6] = b3 * x * y * z; Y[7] = -c3 * y * (5.0f * z * z - 1.0f);
+                Y[8] = d3 * z * (5.0f * z * z - 3.0f); Y[9] = -c3 * x * (5.0f * z * z - 1.0f);
+                Y[10] = e3 * z * (x * x - y * y); Y[11] = -a3 * x * (x * x - 3.0f * y * y);
+            }
+#pragma unroll
+            for (int k = 4; k < K; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) in.cext[ch] += Y[k - 4] * g.sh[(3 * k + ch) * n + i];
+        }
         return in;
     }
 };
@@ -172,6 +222,41 @@ extern "C" int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_ca
 extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, int tile,
                                    float alpha_min, mgs_projected *out, float *phi, float *omod, void *stream) {
     return mgs_enhance_project_weighted(g, cam, packed_mlp, tile, alpha_min, MGS_WEIGHT_EQ3, out, phi, omod, stream);
+}
+
+extern "C" int mgs_enhance_project_sh(const mgs_gaussians *g, int sh_degree, const mgs_camera *cam,
+                                      const void *packed_mlp, int tile, float alpha_min, mgs_projected *out,
+                                      float *phi, float *omod, void *stream) {
+    using namespace mgs;
+    int rc;
+    MGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree %d outside 0..3", sh_degree);
+    if (sh_degree == 1) return mgs_enhance_project(g, cam, packed_mlp, tile, alpha_min, out, phi, omod, stream);
+    if ((rc = check_gaussians(g)) != MGS_OK) return rc;
+    if ((rc = check_camera(cam)) != MGS_OK) return rc;
+    if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
+    if (tile != MGS_TILE) return set_error(MGS_ERR_UNSUPPORTED, "tile must be %d", MGS_TILE);
+    MGS_REQUIRE(alpha_min > 0.0f && alpha_min < 1.0f, "alpha_min must be in (0, 1)");
+    MGS_REQUIRE(packed_mlp && aligned(packed_mlp, 16), "packed MLP must be non-NULL and 16-byte aligned");
+    if (g->n == 0) return MGS_OK;
+    MGS_REQUIRE(phi && omod, "phi / omod is NULL");
+    const CamK k = make_camk(cam);
+    const int64_t groups = (g->n + 63) / 64;
+    int64_t blocks = (groups + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    auto launch = [&](auto src) {
+        hipLaunchKernelGGL(enhance_project_kernel<decltype(src)>, dim3(unsigned(blocks)), dim3(256), 0,
+                           as_stream(stream), src, k, static_cast<const uint8_t *>(packed_mlp), alpha_min,
+                           reinterpret_cast<float4 *>(out->splat), reinterpret_cast<uint2 *>(out->rect),
+                           out->n_tiles, phi, omod);
+    };
+    if (sh_degree == 0)
+        launch(SoaShSource<0>{*g, {k.campos[0], k.campos[1], k.campos[2]}});
+    else if (sh_degree == 2)
+        launch(SoaShSource<2>{*g, {k.campos[0], k.campos[1], k.campos[2]}});
+    else
+        launch(SoaShSource<3>{*g, {k.campos[0], k.campos[1], k.campos[2]}});
+    MGS_LAUNCH_CHECK("enhance_project_kernel<sh>");
+    return MGS_OK;
 }
 
 extern "C" int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,

@@ -27,17 +27,29 @@ class DeviceScene:
 
     KEYS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
 
+    # SH planes (3 per coefficient) -> SH order
+    SH_DEGREE = {3: 0, 12: 1, 27: 2, 48: 3}
+
     def __init__(self, scene, device="cuda"):
         self.t = {k: torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.float32)).to(device)
                   for k in self.KEYS}
         self.n = int(self.t["opacity_logit"].numel())
+        self.sh_degree = self._degree(self.t["sh"])
         self.struct = L.make_gaussians(self.t)
+
+    @classmethod
+    def _degree(cls, sh):
+        planes = int(sh.shape[0]) if sh.dim() == 2 else 12
+        if planes not in cls.SH_DEGREE:
+            raise ValueError(f"{planes} SH planes: expected 3 (d + 1)^2 for an order d in 0..3")
+        return cls.SH_DEGREE[planes]
 
     @classmethod
     def from_tensors(cls, tensors):
         obj = cls.__new__(cls)
         obj.t = {k: tensors[k].contiguous() for k in cls.KEYS}
         obj.n = int(obj.t["opacity_logit"].numel())
+        obj.sh_degree = cls._degree(obj.t["sh"])
         obj.struct = L.make_gaussians(obj.t)
         return obj
 
@@ -185,7 +197,13 @@ class Renderer:
     def enhance_project(self, scene: DeviceScene, cam_s, mlp: DeviceMLP, alpha_min=ALPHA_MIN, stream=None,
                         weight_mode=L.MGS_WEIGHT_EQ3):
         """Fused enhance + project (one read of the attributes); also fills phi / omod."""
-        if weight_mode == L.MGS_WEIGHT_EQ3:
+        if scene.sh_degree != 1:
+            if weight_mode != L.MGS_WEIGHT_EQ3:
+                raise ValueError("SH orders other than 1 are projected with the Eq. 3 weight only")
+            L.check(L.lib().mgs_enhance_project_sh(L.C.byref(scene.struct), scene.sh_degree, L.C.byref(cam_s),
+                                                   L.ptr(mlp.packed), L.MGS_TILE, alpha_min, L.C.byref(self.proj),
+                                                   L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
+        elif weight_mode == L.MGS_WEIGHT_EQ3:
             L.check(L.lib().mgs_enhance_project(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
                                                 L.MGS_TILE, alpha_min, L.C.byref(self.proj), L.ptr(self.phi),
                                                 L.ptr(self.omod), L.stream_ptr(stream)))
@@ -256,12 +274,14 @@ class Renderer:
                 raise ValueError("the vector-quantised path computes the Eq. 3 weight only")
             self.enhance_project_nvq(scene, cam_s, mlp, stream=stream)
         elif isinstance(mlp, DeviceMLPF):
-            if weight_mode != L.MGS_WEIGHT_EQ3:
-                raise ValueError("the MLP_f path computes the Eq. 3 weight only")
+            if weight_mode != L.MGS_WEIGHT_EQ3 or scene.sh_degree != 1:
+                raise ValueError("the MLP_f path computes first-order SH and the Eq. 3 weight only")
             self.enhance_project_mlp_f(scene, cam_s, mlp, stream=stream)
-        elif mlp is not None and fused:
+        elif mlp is not None and (fused or scene.sh_degree != 1):
             self.enhance_project(scene, cam_s, mlp, stream=stream, weight_mode=weight_mode)
         else:
+            if scene.sh_degree != 1:
+                raise ValueError("SH orders other than 1 render through the fused enhance + project (needs an MLP)")
             if mlp is not None:
                 self.enhance(scene, cam_s, mlp, stream)
             self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream, weight_mode=weight_mode)

@@ -56,6 +56,8 @@ class SceneRegistry:
 
     def add(self, name, scene, mlp=None, device="cuda"):
         ds = scene if isinstance(scene, DeviceScene) else DeviceScene(scene, device)
+        if ds.sh_degree != 1:
+            raise ValueError("the batched renderer takes first-order SH scenes")
         dm = mlp if (mlp is None or isinstance(mlp, DeviceMLP)) else DeviceMLP(mlp, device)
         self.scenes[name] = (ds, dm)
 

@@ -67,6 +67,10 @@ def test_host_side_validation(lib):
         assert lib.mgs_project_weighted(C.byref(g), C.byref(cam), None, None, 16, 1 / 255, mode, C.byref(proj),
                                         None) == L.MGS_ERR_INVALID_ARG
         assert "weight_mode" in lib.mgs_last_error().decode()
+    for deg in (-1, 4):
+        assert lib.mgs_enhance_project_sh(C.byref(g), deg, C.byref(cam), None, 16, 1 / 255, C.byref(proj), None,
+                                          None, None) == L.MGS_ERR_INVALID_ARG
+        assert "sh_degree" in lib.mgs_last_error().decode()
     assert lib.mgs_project(C.byref(g), C.byref(cam), None, None, 16, 1.5, C.byref(proj), None) \
         == L.MGS_ERR_INVALID_ARG
     # n = 0 is a valid no-op
