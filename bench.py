@@ -232,6 +232,70 @@ def train_leg(steps=4):
             "workload": "500,000 Gaussians, 4 views 1600x1063, L1 vs perturbed-scene targets, fwd+bwd incl. MLP"}
 
 
+def counter_figures(profsum, proj_ms, bin_ms, blend_ms):
+    """Hardware-counter figures per stage from the committed rocprofv3 summaries of this
+    workload (profiles/), each only while its kernels' sources are unchanged (else null):
+    HBM bytes per launch and the GB/s they mean at this run's stage time; for the blend the
+    VALU and LDS instruction rates per CU per clock (the published FP32 peak is 2 wave-wide FMA
+    instructions per CU per clock); for enhance + project the fraction of time the matrix cores
+    were busy."""
+    out = {}
+    cus, xcds = 256, 8
+    for name, fname, group, ms in (("enhance_project", "enhance_project_1m_counters.txt", "enhance_project", proj_ms),
+                                   ("bin", "bin_1m_1600x1063_counters.txt", "bin", bin_ms),
+                                   ("blend", TRAFFIC_PROFILE, "blend", blend_ms)):
+        r = profsum.read_summary(os.path.join(ROOT, "profiles", fname), profsum.SOURCES[group])
+        if r is None:
+            out[name] = None
+            continue
+        traffic, sq = r
+        fig = {"hbm_bytes_per_launch": round(traffic), "hbm_gbs": round(traffic / (ms * 1e-3) / 1e9, 1),
+               "hbm_frac": round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        main_k = {"enhance_project": "enhance_project_kernel<mgs::SoaSource>",
+                  "blend": "blend_range_kernel<mgs::SingleViewLoc>"}.get(name)
+        cyc = sq.get((main_k, "GRBM_GUI_ACTIVE")) if main_k else None
+        if cyc:
+            cu_clk = cus * cyc / xcds
+            if name == "blend":
+                v = sq.get((main_k, "SQ_INSTS_VALU"), 0.0) / cu_clk
+                fig.update(valu_instr_per_cu_clk=round(v, 3), valu_issue_frac=round(v / 2.0, 3),
+                           lds_instr_per_cu_clk=round(sq.get((main_k, "SQ_INSTS_LDS"), 0.0) / cu_clk, 4))
+            else:
+                busy = sq.get((main_k, "SQ_VALU_MFMA_BUSY_CYCLES"))
+                if busy is not None:
+                    fig["mfma_busy_frac"] = round(busy / (4 * cu_clk), 4)
+        out[name] = fig
+    return out
+
+
+def measured_peaks(torch, dev):
+    """This device's achieved HBM copy bandwidth (1 GiB device-to-device copy) and BF16 GEMM
+    rate (rocBLAS/hipBLASLt through torch, 8192^3), beside the published peaks."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    x = torch.randn(8192, 8192, dtype=torch.bfloat16, device=dev)
+    y = torch.randn(8192, 8192, dtype=torch.bfloat16, device=dev)
+    torch.matmul(x, y)
+    e0.record()
+    for _ in range(10):
+        torch.matmul(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    gemm = 10 * 2.0 * 8192 ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y
+    return {"hbm_copy_gbs": round(copy_gbs, 1), "hbm_published_gbs": PEAK_HBM_GBS,
+            "bf16_gemm_tflops": round(gemm, 1), "bf16_published_tflops": PEAK_BF16_MFMA_TFLOPS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -439,6 +503,8 @@ def main():
     # MLP arithmetic (22->64->64->2 per Gaussian, FMA = 2 flop) over the fused enhance + project
     # time: a lower bound of what the MLP's MFMA work alone achieves
     mlp_flop = ds.n * 2 * (22 * 64 + 64 * 64 + 64 * 2)
+    counters = counter_figures(profsum, proj_ms, bin_ms, blend_ms)
+    peaks = measured_peaks(torch, dev)
     out = {
         "metric": "FPS @1600x1063, 1M Gaussians (OIT vs sorted); p50/p99 served frame ms",
         "value": round(fps, 2),
@@ -468,6 +534,8 @@ def main():
         "bin_hbm_frac": round(bin_bytes / (bin_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "mlp_mfma_tflops": round(mlp_flop / (proj_ms * 1e-3) / 1e12, 2),
         "mlp_mfma_frac": round(mlp_flop / (proj_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
+        "counters": counters,
+        "peaks_measured": peaks,
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
         "nvq": res_nvq,

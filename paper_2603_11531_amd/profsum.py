@@ -28,8 +28,13 @@ from collections import OrderedDict
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 
-# sources whose code the order-independent blend kernel is built from
-BLEND_SOURCES = ("blend.hip", "blend_math.h", "batch.h", "common.h")
+# sources each profiled kernel group is built from (a summary is valid while they hash the same)
+SOURCES = {
+    "blend": ("blend.hip", "blend_math.h", "batch.h", "common.h"),
+    "enhance_project": ("project.hip", "proj_math.h", "mlp_math.h", "common.h"),
+    "bin": ("bin.hip", "batch.h", "common.h"),
+}
+BLEND_SOURCES = SOURCES["blend"]
 
 
 def source_hash(files=BLEND_SOURCES):
@@ -69,9 +74,9 @@ def _pick(agg, kernel_substr, counter):
     return vals
 
 
-def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd):
+def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd, group="blend"):
     """kernels: the kernels one launch of the measured entry point runs (name substrings);
-    their per-dispatch means are summed."""
+    their per-dispatch means are summed.  sq_csv: one counter CSV or a list of them."""
     fa, wa = _counters(fetch_csv), _counters(write_csv)
     calib_kib = calib_mib * 1024.0
     # the calibration copy is the largest copy dispatch of the run
@@ -81,7 +86,7 @@ def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd):
     kw = calib_kib / cw
     out = [f"command (one run per counter group): {cmd}",
            f"kernels: {', '.join(kernels)}",
-           f"source_sha256: {source_hash()}",
+           f"source_sha256: {source_hash(SOURCES[group])}",
            f"calibration copy: {calib_mib:g} MiB read + {calib_mib:g} MiB written; FETCH_SIZE read {cf:.1f} KiB, "
            f"WRITE_SIZE read {cw:.1f} KiB -> scale factors fetch {kf:.4f}, write {kw:.4f}"]
     total = 0.0
@@ -97,7 +102,9 @@ def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd):
                 f"scaled {wm * kw / 1024:.1f} MiB"]
     out.append(f"traffic_bytes_per_launch: {total:.0f}")
     if sq_csv:
-        sa = _counters(sq_csv)
+        sa = OrderedDict()
+        for path in ([sq_csv] if isinstance(sq_csv, str) else sq_csv):
+            sa.update(_counters(path))
         out.append("")
         out.append("SQ / GRBM counters per dispatch (mean over dispatches; GRBM_GUI_ACTIVE summed over XCDs):")
         for kernel in kernels:
@@ -107,20 +114,36 @@ def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd):
     return "\n".join(out) + "\n"
 
 
-def read_traffic(path, files=BLEND_SOURCES):
-    """traffic_bytes_per_launch from a pmc summary, or None if it is missing or the kernel's
-    sources changed since the counters were taken."""
+def read_summary(path, files=BLEND_SOURCES):
+    """(traffic_bytes_per_launch, {(kernel, counter): mean per dispatch}) of a pmc summary, or
+    None if it is missing or the kernels' sources changed since the counters were taken."""
     try:
         lines = open(path).read().splitlines()
     except OSError:
         return None
-    kv = dict(l.split(": ", 1) for l in lines if ": " in l)
+    kv = dict(l.split(": ", 1) for l in lines if ": " in l and not l.startswith(" "))
     if kv.get("source_sha256") != source_hash(files):
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        traffic = float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+    sq = {}
+    for l in lines:
+        f = l.split()
+        if l.startswith("  ") and len(f) == 3 and f[1].isupper():
+            try:
+                sq[(f[0], f[1])] = float(f[2])
+            except ValueError:
+                pass
+    return traffic, sq
+
+
+def read_traffic(path, files=BLEND_SOURCES):
+    """traffic_bytes_per_launch from a pmc summary, or None if it is missing or the kernel's
+    sources changed since the counters were taken."""
+    r = read_summary(path, files)
+    return None if r is None else r[0]
 
 
 def main(argv=None):
@@ -132,7 +155,8 @@ def main(argv=None):
     p = sub.add_parser("pmc")
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
-    p.add_argument("--sq", default=None)
+    p.add_argument("--sq", default=None, help="comma-separated counter CSVs of SQ / GRBM passes")
+    p.add_argument("--group", default="blend", choices=sorted(SOURCES))
     p.add_argument("--kernel", required=True, help="comma-separated kernel name substrings")
     p.add_argument("--calib-mib", type=float, required=True)
     p.add_argument("--cmd", required=True)
@@ -140,7 +164,8 @@ def main(argv=None):
     if a.mode == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
     else:
-        sys.stdout.write(pmc(a.fetch, a.write, a.sq, a.kernel.split(","), a.calib_mib, a.cmd))
+        sys.stdout.write(pmc(a.fetch, a.write, a.sq.split(",") if a.sq else None, a.kernel.split(","), a.calib_mib,
+                             a.cmd, a.group))
 
 
 if __name__ == "__main__":

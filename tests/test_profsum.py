@@ -36,3 +36,15 @@ def test_traffic_is_dropped_when_sources_change(tmp_path):
     p.write_text("source_sha256: 0000000000000000\ntraffic_bytes_per_launch: 1234\n")
     assert profsum.read_traffic(str(p)) is None
     assert profsum.read_traffic(str(tmp_path / "missing.txt")) is None
+
+
+def test_summary_counters_are_parsed_back(tmp_path):
+    p = tmp_path / "s.txt"
+    p.write_text(f"source_sha256: {profsum.source_hash(profsum.SOURCES['bin'])}\ntraffic_bytes_per_launch: 10\n\n"
+                 "SQ / GRBM counters per dispatch (mean over dispatches):\n"
+                 "  chunk_write_kernel     SQ_INSTS_VALU                    123.0\n"
+                 "  chunk_write_kernel     GRBM_GUI_ACTIVE                  800.0\n")
+    traffic, sq = profsum.read_summary(str(p), profsum.SOURCES["bin"])
+    assert traffic == 10.0
+    assert sq == {("chunk_write_kernel", "SQ_INSTS_VALU"): 123.0, ("chunk_write_kernel", "GRBM_GUI_ACTIVE"): 800.0}
+    assert profsum.read_summary(str(p), profsum.SOURCES["blend"]) is None
