@@ -10,7 +10,7 @@ plain device-to-device copy of known size that ``bench.py --calib-copy-mib`` run
 
     python -m paper_2603_11531_amd.profsum pmc --fetch <f>/p_counter_collection.csv \
         --write <w>/p_counter_collection.csv [--sq <s>/p_counter_collection.csv] \
-        --kernel split_plan_kernel,blend_range_kernel,merge_ranges_kernel --calib-mib 1024 \
+        --kernel "split_plan_kernel;blend_range_kernel;merge_ranges_kernel" --calib-mib 1024 \
         --cmd "<command>"
 
 The pmc summary records a hash of the kernel's sources; ``bench.py`` reports the
@@ -110,7 +110,7 @@ def pmc(fetch_csv, write_csv, sq_csv, kernels, calib_mib, cmd, group="blend"):
         for kernel in kernels:
             for (k, c), vs in sa.items():
                 if kernel in k:
-                    out.append(f"  {kernel:22s} {c:22s} {sum(vs) / len(vs):16.1f}")
+                    out.append(f"  {kernel.replace(' ', ''):22s} {c:22s} {sum(vs) / len(vs):16.1f}")
     return "\n".join(out) + "\n"
 
 
@@ -157,14 +157,14 @@ def main(argv=None):
     p.add_argument("--write", required=True)
     p.add_argument("--sq", default=None, help="comma-separated counter CSVs of SQ / GRBM passes")
     p.add_argument("--group", default="blend", choices=sorted(SOURCES))
-    p.add_argument("--kernel", required=True, help="comma-separated kernel name substrings")
+    p.add_argument("--kernel", required=True, help="';'-separated kernel name substrings")
     p.add_argument("--calib-mib", type=float, required=True)
     p.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.mode == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
     else:
-        sys.stdout.write(pmc(a.fetch, a.write, a.sq.split(",") if a.sq else None, a.kernel.split(","), a.calib_mib,
+        sys.stdout.write(pmc(a.fetch, a.write, a.sq.split(",") if a.sq else None, a.kernel.split(";"), a.calib_mib,
                              a.cmd, a.group))
 
 
