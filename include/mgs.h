@@ -294,6 +294,7 @@ int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, si
  * caller detects the overflow from n_pairs after synchronising (this keeps
  * the call free of host synchronisation).
  * ws/ws_bytes: workspace of at least mgs_bin_workspace() bytes, 256-byte aligned.
+ * MGS_ERR_INVALID_ARG for a grid of 2^20 or more 8x8-tile supertiles.
  */
 int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
             size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
@@ -386,7 +387,8 @@ typedef struct mgs_request {
 /*
  * mgs_batch_workspace -- bytes of workspace for batches of at most max_gaussians
  * Gaussians in total (each request's count rounded up to a multiple of 256),
- * max_tiles 16x16 tiles in total, and `capacity` tile/Gaussian pairs in total.
+ * max_tiles 16x16 tiles in total (1 .. 2^20 - 1), and `capacity` tile/Gaussian pairs
+ * in total.
  */
 int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uint64_t capacity, size_t *bytes);
 

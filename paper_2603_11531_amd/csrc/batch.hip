@@ -143,7 +143,7 @@ inline BatchLayout batch_layout(int64_t max_gauss, int64_t max_tiles, uint64_t c
 extern "C" int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uint64_t capacity, size_t *bytes) {
     MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
     MGS_REQUIRE(max_gaussians > 0 && max_gaussians < (int64_t(1) << 31), "max_gaussians out of range");
-    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 24), "max_tiles out of range");
+    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 20), "max_tiles out of range");
     MGS_REQUIRE(capacity > 0 && capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
     *bytes = mgs::batch_layout(max_gaussians, max_tiles, capacity).total;
     return MGS_OK;
@@ -155,7 +155,7 @@ extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_re
     using namespace mgs;
     MGS_REQUIRE(requests && n_requests && n_pairs, "requests / n_requests / n_pairs is NULL");
     MGS_REQUIRE(max_gaussians > 0 && max_gaussians < (int64_t(1) << 31), "max_gaussians out of range");
-    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 24), "max_tiles out of range");
+    MGS_REQUIRE(max_tiles > 0 && max_tiles < (int64_t(1) << 20), "max_tiles out of range");
     MGS_REQUIRE(capacity > 0 && capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
     MGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f && alpha_max > alpha_min && alpha_max < 1.f, "bad alpha range");
     const BatchLayout L = batch_layout(max_gaussians, max_tiles, capacity);

@@ -204,6 +204,25 @@ struct GridMap {
 // per-block counts; inside the block a wave/LDS scan gives every Gaussian its slot.
 // Gaussians with at most EXPAND_SMALL tiles are written by their own lane (row by
 // row over the rectangle); larger ones are written by the whole wave.
+// Key of a list entry.  Per tile (SHIFT = 0): keyfn(tile, depth).  Per supertile (SHIFT > 0):
+// the supertile id above the entry's tile rectangle inside that supertile, 3 bits per corner
+// coordinate (lx0 | ly0 << 3 | lx1 << 6 | ly1 << 9): the sort orders by the id alone
+// (ST_KEY_SHIFT up) and the level-2 passes read the rectangle from the key instead of
+// gathering the Gaussian's rectangle by index.
+constexpr int ST_KEY_SHIFT = 12;
+template <int SHIFT, typename KeyFn>
+__device__ __forceinline__ auto entry_key(const KeyFn &keyfn, uint32_t id, float depth, uint2 r, uint32_t sx,
+                                          uint32_t sy) {
+    if constexpr (SHIFT == 0) {
+        return keyfn(id, depth);
+    } else {
+        const uint32_t ox = sx << SHIFT, oy = sy << SHIFT, last = (1u << SHIFT) - 1u;
+        const uint32_t lx0 = max(r.x & 0xFFFFu, ox) - ox, ly0 = max(r.x >> 16, oy) - oy;
+        const uint32_t lx1 = min((r.y & 0xFFFFu) - ox, last), ly1 = min((r.y >> 16) - oy, last);
+        return uint32_t((id << ST_KEY_SHIFT) | lx0 | (ly0 << 3) | (lx1 << 6) | (ly1 << 9));
+    }
+}
+
 template <typename K, typename KeyFn, typename Map, int SHIFT = 0>
 __global__ void __launch_bounds__(256)
 expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles,
@@ -233,7 +252,7 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
         uint32_t p = base;
         for (uint32_t ty = y0; ty <= y1; ++ty)
             for (uint32_t tx = x0; tx <= x1; ++tx, ++p) {
-                keys[p] = keyfn(tbase + ty * tiles_x + tx, depth);
+                keys[p] = entry_key<SHIFT>(keyfn, tbase + ty * tiles_x + tx, depth, r, tx, ty);
                 vals[p] = uint32_t(g);
             }
     }
@@ -246,11 +265,12 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
         const uint32_t xj = __shfl(x0, j, 64), yj = __shfl(y0, j, 64), x1j = __shfl(x1, j, 64);
         const float dj = __shfl(depth, j, 64);
         const uint32_t tbj = __shfl(tbase, j, 64), txj = __shfl(tiles_x, j, 64);
+        const uint2 rj = make_uint2(__shfl(r.x, j, 64), __shfl(r.y, j, 64));
         const uint32_t gj = uint32_t(g - l + j);
         const uint32_t wdt = x1j - xj + 1;
         for (uint32_t p = l; p < cj; p += 64) {
             const uint32_t ty = yj + p / wdt, tx = xj + p % wdt;
-            keys[bj + p] = keyfn(tbj + ty * txj + tx, dj);
+            keys[bj + p] = entry_key<SHIFT>(keyfn, tbj + ty * txj + tx, dj, rj, tx, ty);
             vals[bj + p] = gj;
         }
     }
@@ -475,7 +495,9 @@ tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_pa
 //            overlaps (about 1.5 entries per Gaussian against about 10 pairs), and the
 //            entries are ordered by supertile with the stable radix sort above (one
 //            8-bit pass for up to 256 supertiles); a supertile's entries stay in
-//            ascending Gaussian order;
+//            ascending Gaussian order.  An entry's key carries, below the supertile id,
+//            the part of the Gaussian's tile rectangle inside that supertile, so level 2
+//            reads keys and values in order and gathers nothing by Gaussian index;
 //   level 2  a supertile's entries are cut into chunks of CHUNK.  One pass counts,
 //            per chunk and per tile of the supertile, the entries whose rectangle
 //            covers the tile (ballots over the wave); a column scan over each
@@ -694,12 +716,11 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
     }
 }
 
-// Lane's covered tiles of its supertile as a 64-bit mask (bit ky * 8 + kx).
-__device__ __forceinline__ uint64_t cover_mask(uint2 r, uint32_t sx, uint32_t sy) {
-    const int x0 = int(r.x & 0xFFFFu) - int(sx * SUPER), y0 = int(r.x >> 16) - int(sy * SUPER);
-    const int x1 = int(r.y & 0xFFFFu) - int(sx * SUPER), y1 = int(r.y >> 16) - int(sy * SUPER);
-    const int lx0 = max(x0, 0), ly0 = max(y0, 0), lx1 = min(x1, SUPER - 1), ly1 = min(y1, SUPER - 1);
-    if (lx0 > lx1 || ly0 > ly1) return 0ull;
+// An entry's covered tiles of its supertile as a 64-bit mask (bit ky * 8 + kx), from the
+// local rectangle in the low bits of its level-1 key (never empty: the entry exists because
+// the rectangle overlaps the supertile).
+__device__ __forceinline__ uint64_t local_mask(uint32_t key) {
+    const uint32_t lx0 = key & 7u, ly0 = (key >> 3) & 7u, lx1 = (key >> 6) & 7u, ly1 = (key >> 9) & 7u;
     const uint64_t row = uint64_t((2u << lx1) - (1u << lx0));                    // columns lx0 .. lx1
     const uint64_t rows = (0x0101010101010101ull << (8 * ly0)) & (~0ull >> (8 * (SUPER - 1 - ly1)));
     return rows * row;                                                           // no carries: row < 256
@@ -724,7 +745,7 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
 
 // One chunk: entry threadIdx.x of the chunk (if any) and the tiles of the supertile it covers.
 template <typename Geo>
-__device__ __forceinline__ void chunk_entry(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+__device__ __forceinline__ void chunk_entry(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ keys,
                                             uint32_t c, const uint32_t *__restrict__ chunk_st,
                                             const uint32_t *__restrict__ chunk_lo,
                                             const uint32_t *__restrict__ st_offs, const Geo &geo, uint32_t &gid,
@@ -738,7 +759,7 @@ __device__ __forceinline__ void chunk_entry(const uint32_t *__restrict__ vals, c
     gid = 0u;
     if (i < hi) {
         gid = vals[i];
-        mask = cover_mask(rect[gid], sx, sy);
+        mask = local_mask(keys[i]);
     }
 }
 
@@ -747,7 +768,7 @@ __device__ __forceinline__ void chunk_entry(const uint32_t *__restrict__ vals, c
 // entries).
 template <typename Geo>
 __global__ void __launch_bounds__(CHUNK)
-chunk_count_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+chunk_count_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ keys,
                    const uint32_t *__restrict__ chunk_st, const uint32_t *__restrict__ chunk_lo,
                    const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
                    uint32_t *__restrict__ cnt) {
@@ -758,7 +779,7 @@ chunk_count_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         uint32_t gid, tbase, tw, th, sx, sy;
         uint64_t mask;
-        chunk_entry(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
+        chunk_entry(vals, keys, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
         s_cnt[w][l] = uint32_t(__popcll(wave_transpose64(mask)));
         __syncthreads();
         if (threadIdx.x < SUPER_TILES) {
@@ -860,7 +881,7 @@ constexpr int CHUNK_STAGE = 4096;
 
 template <typename Geo>
 __global__ void __launch_bounds__(CHUNK)
-chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ rect,
+chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ keys,
                    const uint32_t *__restrict__ chunk_st, const uint32_t *__restrict__ chunk_lo,
                    const uint32_t *__restrict__ st_offs, const uint32_t *__restrict__ n_chunks, Geo geo,
                    const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ offs,
@@ -887,7 +908,7 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint2 *__restrict__ 
             const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
             if (tx < tw && ty < th) first = offs[tbase + ty * tw + tx] + cbase[size_t(c) * SUPER_TILES + k];
         }
-        chunk_entry(vals, rect, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
+        chunk_entry(vals, keys, c, chunk_st, chunk_lo, st_offs, geo, gid, mask, tbase, tw, th, sx, sy);
         s_gid[w][l] = gid;
         uint64_t col = wave_transpose64(mask);
         s_cnt[w][l] = uint32_t(__popcll(col));
@@ -1089,6 +1110,7 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
     if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
     MGS_REQUIRE(T > 0 && st_max > 0, "bad tile grid");
+    MGS_REQUIRE(st_max < (1u << (32 - ST_KEY_SHIFT)), "more than 2^%d supertiles", 32 - ST_KEY_SHIFT);
     MGS_REQUIRE(tile_offsets && n_pairs, "tile_offsets / n_pairs is NULL");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity must be < 2^32 - 1");
     MGS_REQUIRE(capacity == 0 || gids, "gids is NULL");
@@ -1150,9 +1172,9 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     int cur = 0;
     if (capacity > 0) {
         const unsigned grid = unsigned(L.nblocks < RADIX_MAX_GRID ? L.nblocks : RADIX_MAX_GRID);
-        int shift = 0;
+        int shift = ST_KEY_SHIFT;                        // the local rectangle below the id is not sorted
         for (int p = 0; p < npass; ++p) {
-            const int bits = (key_bits - shift + (npass - p) - 1) / (npass - p);
+            const int bits = (key_bits - (shift - ST_KEY_SHIFT) + (npass - p) - 1) / (npass - p);
             hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
                                s, keys[cur], etot, capacity, shift, bits, hist, L.nblocks);
             MGS_LAUNCH_CHECK("radix_upsweep_kernel");
@@ -1175,7 +1197,7 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     if (!from_digits) {
         const uint64_t rblocks = (capacity + 1 + 255) / 256;
         hipLaunchKernelGGL((tile_ranges_kernel<uint32_t>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256),
-                           0, s, keys[cur], etot, capacity, 0, st_max, st_offs);
+                           0, s, keys[cur], etot, capacity, ST_KEY_SHIFT, st_max, st_offs);
         MGS_LAUNCH_CHECK("tile_ranges_kernel<supertile>");
     }
 
@@ -1198,8 +1220,8 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     }
     MGS_LAUNCH_CHECK("chunk_plan_kernel");
     const unsigned cgrid = L.chunks_max < uint32_t(SUPER_MAX_GRID) ? L.chunks_max : uint32_t(SUPER_MAX_GRID);
-    hipLaunchKernelGGL((chunk_count_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st, chunk_lo,
-                       st_offs, nch, geo, cnt);
+    hipLaunchKernelGGL((chunk_count_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], keys[cur], chunk_st,
+                       chunk_lo, st_offs, nch, geo, cnt);
     MGS_LAUNCH_CHECK("chunk_count_kernel");
     const uint64_t jobs = uint64_t(st_max) * SUPER_TILES;
     hipLaunchKernelGGL((chunk_colscan_kernel<Geo>), dim3(unsigned(jobs < 16384 ? jobs : 16384)), dim3(64), 0, s, cnt,
@@ -1220,7 +1242,7 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     }
     MGS_LAUNCH_CHECK("tile_scan_kernel");
     if (capacity > 0) {
-        hipLaunchKernelGGL((chunk_write_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], rect, chunk_st,
+        hipLaunchKernelGGL((chunk_write_kernel<Geo>), dim3(cgrid), dim3(CHUNK), 0, s, vals[cur], keys[cur], chunk_st,
                            chunk_lo, st_offs, nch, geo, cnt, tile_offsets, n_pairs, capacity, gids);
         MGS_LAUNCH_CHECK("chunk_write_kernel");
     }
@@ -1249,6 +1271,7 @@ extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t c
     MGS_REQUIRE(bytes != nullptr, "bytes is NULL");
     MGS_REQUIRE(n >= 0 && tiles_x > 0 && tiles_y > 0, "bad sizes");
     MGS_REQUIRE(tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
+    MGS_REQUIRE(mgs::super_count(tiles_x, tiles_y) < (1u << (32 - mgs::ST_KEY_SHIFT)), "too many supertiles");
     *bytes = mgs::bin2_layout(n, mgs::super_count(tiles_x, tiles_y), uint32_t(tiles_x) * uint32_t(tiles_y), capacity)
                  .total;
     return MGS_OK;
