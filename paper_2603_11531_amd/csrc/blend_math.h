@@ -252,11 +252,9 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     // the lane's pixel offsets from the tile centre: x in the left / right quadrants, y in the
-    // top / bottom ones, and the products the polynomial needs
+    // top / bottom ones
     const float xl = float(l & 7) - 7.5f, xr = xl + 8.0f;
     const float yt = float(l >> 3) - 7.5f, yb = yt + 8.0f;
-    const float xxl = xl * xl, xxr = xr * xr, yyt = yt * yt, yyb = yb * yb;
-    const float xy0 = xl * yt, xy1 = xr * yt, xy2 = xl * yb, xy3 = xr * yb;
     const float tcx = float(tx * 16) + 8.0f, tcy = float(ty * 16) + 8.0f;
 
     // per quadrant q: N rgb, D, T
@@ -296,20 +294,28 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // in list order; Gaussians whose alpha can reach alpha_max are taken in a second loop,
-        // the only one that needs the clamp
+        // Gaussians whose alpha can reach alpha_max are taken last, in the only loop that needs
+        // the clamp.  The others are walked by quadrant pattern: one loop per pattern a convex
+        // footprint usually has (one quadrant, two side by side, all four) evaluates exactly
+        // those quadrants with no per-Gaussian tests; the rare rest (three quadrants, diagonals)
+        // go through a loop that tests each quadrant.
         const uint64_t clamp = __ballot((mk & OIT_CLAMP) != 0u);
-        uint64_t any = __ballot(mk != 0u) & ~clamp;
+        const uint32_t mq = mk & 15u;
+        constexpr uint32_t OWN_LOOP = (1u << 1) | (1u << 2) | (1u << 4) | (1u << 8) | (1u << 3) | (1u << 12) |
+                                      (1u << 5) | (1u << 10) | (1u << 15);
+        uint64_t any = __ballot(mq != 0u && ((OWN_LOOP >> mq) & 1u) == 0u) & ~clamp;
         // per quadrant, the staged Gaussians that reach it (tested in scalar registers)
         const uint64_t qm0 = __ballot((mk & 1u) != 0u), qm1 = __ballot((mk & 2u) != 0u);
         const uint64_t qm2 = __ballot((mk & 4u) != 0u), qm3 = __ballot((mk & 8u) != 0u);
-#define MGS_OIT_QUAD(q, X, Y, XX, XY, YY, ALPHA)                                    \
-            if (qm##q & bk) {                                                       \
-                float e = fmaf(qa.y, X, qa.x);                                      \
-                e = fmaf(qa.z, Y, e);                                               \
-                e = fmaf(qa.w, XX, e);                                              \
-                e = fmaf(qb.x, XY, e);                                              \
-                e = fmaf(qb.y, YY, e);                                              \
+// The exponent c0 + cx x + cy y + cxx x^2 + cxy x y + cyy y^2 is evaluated as
+// P(y) + x (R(y) + cxx x), P(y) = c0 + y (cy + cyy y), R(y) = cx + cxy y: the two quadrants
+// of a row share y, so P and R are computed once for both (3 FMA) and each pixel costs 2.
+#define MGS_OIT_ROWTERMS(Y)                                                         \
+            const float P = fmaf(fmaf(qb.y, Y, qa.z), Y, qa.x);                     \
+            const float R = fmaf(qb.x, Y, qa.y);
+#define MGS_OIT_EVAL(q, X, ALPHA)                                                   \
+            {                                                                       \
+                const float e = fmaf(fmaf(qa.w, X, R), X, P);                       \
                 const float al = e >= log2_amin ? ALPHA : 0.0f;                     \
                 acc[q][0] = fmaf(al, cw.x, acc[q][0]);                              \
                 acc[q][1] = fmaf(al, cw.y, acc[q][1]);                              \
@@ -317,25 +323,47 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
                 acc[q][3] = fmaf(al, cw.w, acc[q][3]);                              \
                 acc[q][4] = fmaf(-acc[q][4], al, acc[q][4]);                        \
             }
-#define MGS_OIT_LOOP(ALPHA)                                                         \
-        while (any) {                                                               \
-            const int k = __builtin_ctzll(any);                                     \
-            const uint64_t bk = any & (0ull - any);                                 \
-            any &= any - 1;                                                         \
+// staged Gaussians of SET in list order, their record in qa, qb, cw
+#define MGS_OIT_WALK(SET, BODY)                                                     \
+        for (uint64_t set = (SET); set; set &= set - 1) {                           \
+            const int k = __builtin_ctzll(set);                                     \
             const float4 *rec = wbuf + 3 * k;                                       \
             const float4 qa = rec[0];                                               \
             const float4 qb = rec[1];                                               \
             const float4 cw = rec[2];                                               \
-            MGS_OIT_QUAD(0, xl, yt, xxl, xy0, yyt, ALPHA)                           \
-            MGS_OIT_QUAD(1, xr, yt, xxr, xy1, yyt, ALPHA)                           \
-            MGS_OIT_QUAD(2, xl, yb, xxl, xy2, yyb, ALPHA)                           \
-            MGS_OIT_QUAD(3, xr, yb, xxr, xy3, yyb, ALPHA)                           \
+            BODY                                                                    \
         }
-        MGS_OIT_LOOP(fast_exp2(e))
-        any = clamp;
-        MGS_OIT_LOOP(fminf(fast_exp2(e), amax))
-#undef MGS_OIT_LOOP
-#undef MGS_OIT_QUAD
+#define MGS_OIT_PATTERN(M, BODY) MGS_OIT_WALK(__ballot(mq == (M)) & ~clamp, BODY)
+#define MGS_OIT_TOP(BODY) { MGS_OIT_ROWTERMS(yt) BODY }
+#define MGS_OIT_BOTTOM(BODY) { MGS_OIT_ROWTERMS(yb) BODY }
+#define MGS_OIT_EXP fast_exp2(e)
+        MGS_OIT_PATTERN(1u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(2u, MGS_OIT_TOP(MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(4u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(8u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(3u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP) MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(12u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP) MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(5u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP)) MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(10u, MGS_OIT_TOP(MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)) MGS_OIT_BOTTOM(MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
+        MGS_OIT_PATTERN(15u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP) MGS_OIT_EVAL(1, xr, MGS_OIT_EXP))
+                                 MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP) MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
+#undef MGS_OIT_EXP
+#define MGS_OIT_TESTED(q, X, ALPHA) if ((qm##q >> k) & 1u) MGS_OIT_EVAL(q, X, ALPHA)
+#define MGS_OIT_ANY(ALPHA)                                                          \
+        if (((qm0 | qm1) >> k) & 1u)                                                \
+            MGS_OIT_TOP(MGS_OIT_TESTED(0, xl, ALPHA) MGS_OIT_TESTED(1, xr, ALPHA))   \
+        if (((qm2 | qm3) >> k) & 1u)                                                \
+            MGS_OIT_BOTTOM(MGS_OIT_TESTED(2, xl, ALPHA) MGS_OIT_TESTED(3, xr, ALPHA))
+        MGS_OIT_WALK(any, MGS_OIT_ANY(fast_exp2(e)))
+        MGS_OIT_WALK(clamp, MGS_OIT_ANY(fminf(fast_exp2(e), amax)))
+#undef MGS_OIT_ANY
+#undef MGS_OIT_TESTED
+#undef MGS_OIT_BOTTOM
+#undef MGS_OIT_TOP
+#undef MGS_OIT_PATTERN
+#undef MGS_OIT_WALK
+#undef MGS_OIT_EVAL
+#undef MGS_OIT_ROWTERMS
         // every lane's reads of this batch's records precede the next batch's writes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
