@@ -11,10 +11,10 @@
 //
 // Order-independent path: the four waves split the staged Gaussians, each lane
 // holds one pixel in each quadrant, and the waves' sums are merged at the end
-// (blend_tile_oit).  Per pixel-Gaussian pair the inner loop is 5 FMA for the
-// exponent (a polynomial in the pixel's offset, see quad_poly), compare/select,
-// min, exp2 and 5 FMA to accumulate N (rgb, colours pre-multiplied by w), D and T
-// -- all float32 VALU, no sort, no order.
+// (blend_tile_oit).  Per pixel-Gaussian pair the inner loop is 2 FMA for the
+// exponent (a polynomial in the pixel's offset, see quad_poly, with 3 more FMA per
+// row of quadrants), compare/select, exp2 and 5 FMA to accumulate N (rgb, colours
+// pre-multiplied by w), D and T -- all float32 VALU, no sort, no order.
 //
 // Sorted path: wave w owns quadrant w and walks the depth-ordered list front to
 // back with early termination (blend_tile_sorted).
