@@ -875,8 +875,9 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
 // lane k of wave w holds which of the wave's 64 entries cover tile k.  The chunk's output
 // for tile k is one contiguous run of the tile's list (the tile's first slot + the chunk's
 // column prefix), the waves' parts in wave order.  The runs are assembled tile by tile in
-// LDS, then copied out by consecutive threads, so the global stores are coalesced; a chunk
-// with more than CHUNK_STAGE pairs has its lanes write their runs straight to memory.
+// LDS (with each pair's tile in a byte map), then copied out by consecutive threads, so the
+// global stores are coalesced; a chunk with more than CHUNK_STAGE pairs has its lanes write
+// their runs straight to memory.
 constexpr int CHUNK_STAGE = 4096;
 
 template <typename Geo>
@@ -892,6 +893,7 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
     __shared__ uint32_t s_lpre[SUPER_TILES + 1];            // local start of tile k's run; [64] = total
     __shared__ uint32_t s_first[SUPER_TILES];               // global start of tile k's run
     __shared__ uint32_t s_out[CHUNK_STAGE];
+    __shared__ uint8_t s_tile[CHUNK_STAGE];                 // tile of each staged pair
     if (uint64_t(*n_pairs) > capacity) return;              // grid-uniform
     const uint32_t nc = *n_chunks;
     const int w = threadIdx.x >> 6;
@@ -935,15 +937,32 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
         __syncthreads();
         const uint32_t L = s_lpre[SUPER_TILES];
         if (L <= uint32_t(CHUNK_STAGE)) {
+            // up to four of the lane's entries per step, their LDS reads in flight together
+            // (an index past the last entry reads entry 63 and is not stored)
             uint32_t pos = s_lw[w][l];
             while (col) {
-                const int j = __builtin_ctzll(col);
+                const int j0 = __builtin_ctzll(col);
                 col &= col - 1;
-                s_out[pos++] = s_gid[w][j];
+                const bool h1 = col != 0ull;
+                const int j1 = __builtin_ctzll(col | (1ull << 63));
+                col &= col - 1;
+                const bool h2 = col != 0ull;
+                const int j2 = __builtin_ctzll(col | (1ull << 63));
+                col &= col - 1;
+                const bool h3 = col != 0ull;
+                const int j3 = __builtin_ctzll(col | (1ull << 63));
+                col &= col - 1;
+                const uint32_t g0 = s_gid[w][j0], g1 = s_gid[w][j1], g2 = s_gid[w][j2], g3 = s_gid[w][j3];
+                s_out[pos] = g0;
+                s_tile[pos] = uint8_t(l);
+                if (h1) { s_out[pos + 1] = g1; s_tile[pos + 1] = uint8_t(l); }
+                if (h2) { s_out[pos + 2] = g2; s_tile[pos + 2] = uint8_t(l); }
+                if (h3) { s_out[pos + 3] = g3; s_tile[pos + 3] = uint8_t(l); }
+                pos += 1u + uint32_t(h1) + uint32_t(h2) + uint32_t(h3);
             }
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < L; i += CHUNK) {
-                const int k = upper_index(s_lpre, SUPER_TILES, i);
+                const int k = s_tile[i];
                 gids[s_first[k] + (i - s_lpre[k])] = s_out[i];
             }
         } else if (col) {
