@@ -141,6 +141,7 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
 
 static_assert(SPLIT_TILE == 8192, "split_plan_kernel searches an 8192-entry table in 13 steps");
 constexpr int SPLIT_FILL_ILP = 4;                // item searches a thread keeps in flight
+constexpr unsigned SPLIT_REPLICAS = 16;          // blocks of a single-pass plan, each writing a share of the items
 
 __global__ void __launch_bounds__(1024)
 split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
@@ -148,13 +149,18 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                   const uint64_t *__restrict__ part_m, const uint64_t *__restrict__ totals,
                   uint32_t *__restrict__ items, uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
-    // part_is == NULL: one block walks every chunk with running carries (few chunks)
+    // part_is == NULL (few chunks): every block walks every chunk with running carries and
+    // writes every grid-th 1024 items of each
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_item0[SPLIT_TILE];     // chunk-relative first item of each tile
     __shared__ uint32_t s_slot0[SPLIT_TILE];     // first partial-sum slot of a split tile, else ~0
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
     uint64_t c_is = 0, c_m = 0;
-    for (uint32_t c = blockIdx.x; c < split_chunks(T); c += gridDim.x) {
+    const bool replicated = part_is == nullptr;
+    const bool writer = !replicated || blockIdx.x == 0;     // writes the split-tile table and counts
+    const uint32_t fill0 = replicated ? blockIdx.x * 1024u : 0u;
+    const uint32_t fill_stride = 1024u * (replicated ? gridDim.x : 1u);
+    for (uint32_t c = replicated ? 0u : blockIdx.x; c < split_chunks(T); c += replicated ? 1u : gridDim.x) {
         const uint32_t t0 = c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS;
         uint32_t ci, cs, cm;
         const uint64_t nr = tile_ranges(offs, t0, T, ci, cs, cm);
@@ -172,9 +178,11 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             const bool m = nj > 1;
             s_item0[threadIdx.x * SPLIT_ITEMS + j] = i0;
             s_slot0[threadIdx.x * SPLIT_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
-            if (m) {
+            if (m && writer) {
                 split_tile[js] = t0 + j;
                 split_slot0[js] = s0;
+            }
+            if (m) {
                 s0 += nj;
                 ++js;
             }
@@ -184,7 +192,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         // item i of the chunk belongs to its last tile whose first item is <= i (tiles with
         // no item share the next tile's start and are never chosen); s_item0[0] = 0 <= i
         const uint32_t n_items = uint32_t(t1), ibase = uint32_t(b1);
-        for (uint32_t i = threadIdx.x; i < n_items; i += 1024 * SPLIT_FILL_ILP) {
+        for (uint32_t i = fill0 + threadIdx.x; i < n_items; i += fill_stride * SPLIT_FILL_ILP) {
             uint32_t lo[SPLIT_FILL_ILP];
 #pragma unroll
             for (int q = 0; q < SPLIT_FILL_ILP; ++q) lo[q] = 0;
@@ -192,11 +200,11 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             for (uint32_t step = SPLIT_TILE / 2; step; step >>= 1) {
 #pragma unroll
                 for (int q = 0; q < SPLIT_FILL_ILP; ++q)
-                    if (s_item0[lo[q] + step] <= i + q * 1024u) lo[q] += step;
+                    if (s_item0[lo[q] + step] <= i + q * fill_stride) lo[q] += step;
             }
 #pragma unroll
             for (int q = 0; q < SPLIT_FILL_ILP; ++q) {
-                const uint32_t k = i + q * 1024u;
+                const uint32_t k = i + q * fill_stride;
                 if (k < n_items) {
                     const uint32_t r = k - s_item0[lo[q]], sl = s_slot0[lo[q]];
                     items[ibase + k] = (c * SPLIT_TILE + lo[q]) | (r << 24);
@@ -298,9 +306,9 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
     uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
     const uint32_t nc = split_chunks(T);
-    if (nc <= PLAN_ONE_BLOCK) {                  // few chunks: one block with running carries
-        hipLaunchKernelGGL(split_plan_kernel, dim3(1), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
-                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
+    if (nc <= PLAN_ONE_BLOCK) {                  // few chunks: replicated blocks with running carries
+        hipLaunchKernelGGL(split_plan_kernel, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T, n_pairs,
+                           capacity, static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
                            static_cast<const uint64_t *>(nullptr), items, slot, stile, sslot, counts);
     } else {
         hipLaunchKernelGGL(split_sum_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs,
