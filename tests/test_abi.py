@@ -44,6 +44,15 @@ def test_host_side_validation(lib):
     nb = C.c_size_t()
     assert lib.mgs_bin_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK and nb.value > 0
     assert lib.mgs_bin_workspace(-1, 4, 4, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
+    # supertile ids share a 32-bit key with a 12-bit tile rectangle: at most 2^20 - 1 supertiles
+    # of 8x8 tiles (65535 tiles across = 8192 supertiles; 8192 x 128 = 2^20 is the first grid over)
+    assert lib.mgs_bin_workspace(100, 65535, 8 * 128, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_bin_workspace(100, 65535, 8 * 127, 1000, C.byref(nb)) == L.MGS_OK
+    pz = L.mgs_projected()
+    assert lib.mgs_bin(C.byref(pz), 0, 65535, 8 * 128, None, 0, None, None, 0, None, None) == L.MGS_ERR_INVALID_ARG
+    assert "supertiles" in lib.mgs_last_error().decode()
+    assert lib.mgs_batch_workspace(1000, (1 << 20) - 1, 1000, C.byref(nb)) == L.MGS_OK
+    assert lib.mgs_batch_workspace(1000, 1 << 20, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_bin_sorted_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK
     assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
     # invalid camera / arguments are rejected before any device work
