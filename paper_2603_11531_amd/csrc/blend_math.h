@@ -70,7 +70,7 @@ constexpr int BLEND_BATCH = 128;
 // (a quadrant's or a tile's):
 //   log2(alpha) = c0 + cx x + cy y + cxx x^2 + cxy x y + cyy y^2
 // (the same quadratic form as log2(o) + kA t^2 + kG dy^2, re-centred once per
-// staged splat so the per-pixel work is five FMAs).
+// staged splat so the per-pixel work is a few FMAs).
 __device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float yc, float4 &qa, float4 &qb) {
     const float kA = r1.x, beta = r1.y, kG = r1.z;
     const float u0 = xc - r0.x, v0 = yc - r0.y;

@@ -186,6 +186,25 @@ def test_empty_and_degenerate_scenes(M):
     assert nfail == 0, err
 
 
+@pytest.mark.parametrize("logit", [8.0, 4.1])
+def test_opaque_gaussians_match_oracle(M, logit):
+    """Every Gaussian in the blend's clamped loop: opacity above alpha_max (logit 8, the clamp
+    binds near the centres) or just under it (logit 4.1: o = 0.9837, within the loop's margin
+    of 0.99 but never clamped), against the oracle's min(a, alpha_max), over the quadrant
+    patterns a mix of sizes produces."""
+    say(f"test_opaque_gaussians_match_oracle[{logit}]")
+    scene = mgs_data.make_scene_uniform(700, 12, ls_mu=-2.6)
+    scene["opacity_logit"][:] = logit
+    cam = mgs_data.look_at((0.1, 0.3, -3.0), width=120, height=88, f=110.0)
+    bg = (0.2, 0.1, 0.4)
+    R, img = _render_gpu(M, scene, cam, bg=bg)
+    pr, camt = oracle_project(scene, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), variants=True)
+    err, nfail = compare_oit_image(img, V, flagged, TOL)
+    say(f"  max err {err:.3e}, fails {nfail}, P={R.pairs()}")
+    assert nfail == 0 and R.pairs() > 0
+
+
 def test_render_is_bit_reproducible(M):
     say("test_render_is_bit_reproducible")
     scene, cams, _, _ = mgs_data.make_config("small", seed=0)
