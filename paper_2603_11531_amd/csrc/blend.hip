@@ -221,7 +221,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
 }
 
 template <typename Loc>
-__global__ void __launch_bounds__(BLEND_THREADS, 6)
+__global__ void __launch_bounds__(BLEND_THREADS, 7)
 blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
                    const uint32_t *__restrict__ gids, const uint32_t *__restrict__ items,
                    const uint32_t *__restrict__ item_slot, const uint32_t *__restrict__ counts, Loc loc,
