@@ -41,7 +41,11 @@ __device__ __forceinline__ bf16x8 relu_pack(f32x4 lo, f32x4 hi) {
     return r;
 }
 
-constexpr int FEAT_STRIDE = 40;   // bf16 per LDS row (32 + 8 padding)
+// LDS feature tile: 64 rows of 32 bf16 (64 bytes), the four 16-byte chunks of row r stored
+// in the order c ^ ((r >> 2) & 3), so 16 consecutive rows' chunk c (the MFMA operand reads) and
+// 16 consecutive rows written whole both fall in distinct banks.
+constexpr int FEAT_STRIDE = 32;
+__device__ __forceinline__ int feat_chunk(int row, int c) { return c ^ ((row >> 2) & 3); }
 
 // Weight fragments and biases of one packed MLP, held in registers by a wave.
 struct MlpFrags {
@@ -137,16 +141,17 @@ __device__ __forceinline__ void mlp_wave(const f32x8 f[4], const W &F, __bf16 *x
     const int lg = l >> 4;
     bf16x8 *row = reinterpret_cast<bf16x8 *>(xs + l * FEAT_STRIDE);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) row[c] = __builtin_convertvector(f[c], bf16x8);
+    for (int c = 0; c < 4; ++c) row[feat_chunk(l, c)] = __builtin_convertvector(f[c], bf16x8);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // Gaussians nb * 16 .. nb * 16 + 15; their head outputs land in xo[nb * 16 + l] (phi) and
-    // xo[64 + nb * 16 + l] (m), lanes 0..15.  xo overlays feature rows 0..6, which block 0 has
+    // xo[64 + nb * 16 + l] (m), lanes 0..15.  xo overlays feature rows 0..7, which block 0 has
     // consumed before any block writes there.
     float *xo = reinterpret_cast<float *>(xs);
     auto block = [&](int nb) {
-        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(xs + (nb * 16 + (l & 15)) * FEAT_STRIDE + 8 * lg);
+        const int xr = nb * 16 + (l & 15);
+        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(xs + xr * FEAT_STRIDE + 8 * feat_chunk(xr, lg));
         f32x4 h1[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) h1[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1(mb), xb, F.b1(mb), 0, 0, 0);
