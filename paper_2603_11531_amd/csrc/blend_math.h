@@ -336,18 +336,23 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
 #define MGS_OIT_PATTERN(M, BODY) MGS_OIT_WALK(__ballot(mq == (M)) & ~clamp, BODY)
 #define MGS_OIT_TOP(BODY) { MGS_OIT_ROWTERMS(yt) BODY }
 #define MGS_OIT_BOTTOM(BODY) { MGS_OIT_ROWTERMS(yb) BODY }
-#define MGS_OIT_EXP fast_exp2(e)
-        MGS_OIT_PATTERN(1u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(2u, MGS_OIT_TOP(MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(4u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(8u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(3u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP) MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(12u, MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP) MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(5u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP)) MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(10u, MGS_OIT_TOP(MGS_OIT_EVAL(1, xr, MGS_OIT_EXP)) MGS_OIT_BOTTOM(MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
-        MGS_OIT_PATTERN(15u, MGS_OIT_TOP(MGS_OIT_EVAL(0, xl, MGS_OIT_EXP) MGS_OIT_EVAL(1, xr, MGS_OIT_EXP))
-                                 MGS_OIT_BOTTOM(MGS_OIT_EVAL(2, xl, MGS_OIT_EXP) MGS_OIT_EVAL(3, xr, MGS_OIT_EXP)))
-#undef MGS_OIT_EXP
+#define MGS_OIT_Q0 MGS_OIT_EVAL(0, xl, fast_exp2(e))
+#define MGS_OIT_Q1 MGS_OIT_EVAL(1, xr, fast_exp2(e))
+#define MGS_OIT_Q2 MGS_OIT_EVAL(2, xl, fast_exp2(e))
+#define MGS_OIT_Q3 MGS_OIT_EVAL(3, xr, fast_exp2(e))
+        MGS_OIT_PATTERN(1u, MGS_OIT_TOP(MGS_OIT_Q0))
+        MGS_OIT_PATTERN(2u, MGS_OIT_TOP(MGS_OIT_Q1))
+        MGS_OIT_PATTERN(4u, MGS_OIT_BOTTOM(MGS_OIT_Q2))
+        MGS_OIT_PATTERN(8u, MGS_OIT_BOTTOM(MGS_OIT_Q3))
+        MGS_OIT_PATTERN(3u, MGS_OIT_TOP(MGS_OIT_Q0 MGS_OIT_Q1))
+        MGS_OIT_PATTERN(12u, MGS_OIT_BOTTOM(MGS_OIT_Q2 MGS_OIT_Q3))
+        MGS_OIT_PATTERN(5u, MGS_OIT_TOP(MGS_OIT_Q0) MGS_OIT_BOTTOM(MGS_OIT_Q2))
+        MGS_OIT_PATTERN(10u, MGS_OIT_TOP(MGS_OIT_Q1) MGS_OIT_BOTTOM(MGS_OIT_Q3))
+        MGS_OIT_PATTERN(15u, MGS_OIT_TOP(MGS_OIT_Q0 MGS_OIT_Q1) MGS_OIT_BOTTOM(MGS_OIT_Q2 MGS_OIT_Q3))
+#undef MGS_OIT_Q3
+#undef MGS_OIT_Q2
+#undef MGS_OIT_Q1
+#undef MGS_OIT_Q0
 #define MGS_OIT_TESTED(q, X, ALPHA) if ((qm##q >> k) & 1u) MGS_OIT_EVAL(q, X, ALPHA)
 #define MGS_OIT_ANY(ALPHA)                                                          \
         if (((qm0 | qm1) >> k) & 1u)                                                \
