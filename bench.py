@@ -52,14 +52,13 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
-    """FP64 oracle on the host cores: full enhance + project + lists for one pose,
-    OIT blend on a random sample of tiles, scaled to a whole frame."""
+def _oracle_binned_sample(scene, cams, mlp, n_tiles_sample, seed=0):
+    """FP64 oracle, pose 0: full enhance + project + lists, then the OIT blend of a random
+    sample of non-empty tiles.  Returns (pre-pass s, sample blend s, sampled, non-empty, W, H)."""
     import numpy as np
     import torch
 
     import oracle as O
-    threads = torch.get_num_threads()
     cam = cams[0]
     t0 = time.perf_counter()
     camt = O.camera_tensors(cam)
@@ -67,7 +66,10 @@ def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
     with torch.no_grad():
         act = O.activate(p)
         _, _, P = O.camera_space(p["mean"], camt)
-        phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp))
+        if mlp is not None:
+            phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp))
+        else:
+            phi = m = None
         proj = O.project(p, camt, phi, m)
         offs, gids = O.bin_lists(proj["rect"], proj["n_tiles"], proj["tiles_x"], proj["tiles_y"])
     t_pre = time.perf_counter() - t0
@@ -84,13 +86,47 @@ def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
             jj = torch.arange(ty * 16, min(H, ty * 16 + 16), dtype=torch.float64) + 0.5
             pix = torch.stack(torch.meshgrid(jj, ii, indexing="ij")[::-1], -1).reshape(-1, 2)
             O.eval_pixels_oit(pix, proj, gids[int(offs[t]):int(offs[t + 1])])
-    t_blend_sample = time.perf_counter() - t1
-    t_frame = t_pre + t_blend_sample * (len(nonempty) / max(1, len(sample)))
+    return t_pre, time.perf_counter() - t1, len(sample), len(nonempty), W, H
+
+
+def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
+    """FP64 oracle on the host cores: full enhance + project + lists for one pose,
+    OIT blend on a random sample of tiles, scaled to a whole frame."""
+    import torch
+    threads = torch.get_num_threads()
+    t_pre, t_blend_sample, n_s, n_ne, _, _ = _oracle_binned_sample(scene, cams, mlp, n_tiles_sample, seed)
+    t_frame = t_pre + t_blend_sample * (n_ne / max(1, n_s))
     return {"value": round(1.0 / t_frame, 6), "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 torch-CPU oracle, pose 0 of the 1M-Gaussian 1600x1063 workload: enhance + "
                        f"project + tile lists for all Gaussians ({t_pre:.1f} s), OIT blend of "
-                       f"{len(sample)} random non-empty tiles ({t_blend_sample:.1f} s) scaled to all "
-                       f"{len(nonempty)} non-empty tiles; s/frame = {t_frame:.1f}")}
+                       f"{n_s} random non-empty tiles ({t_blend_sample:.1f} s) scaled to all "
+                       f"{n_ne} non-empty tiles; s/frame = {t_frame:.1f}")}
+
+
+def oracle_timings(n_tiles_sample=400):
+    """The FP64 oracle on the other workloads: brute force (every pixel against every Gaussian)
+    on the 2,000-Gaussian 128x128 view, and the binned oracle on pose 0 of the 3M-Gaussian
+    1920x1080 workload (a tile sample scaled to the frame, as for cpu_baseline)."""
+    import numpy as np
+    import torch
+
+    import mgs_data
+    import oracle as O
+    out = {"cores": torch.get_num_threads()}
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    t0 = time.perf_counter()
+    camt = O.camera_tensors(cams[0])
+    with torch.no_grad():
+        proj = O.project(O.scene_params(scene), camt)
+        O.render_oit(proj, camt, np.zeros(3), mode="brute")
+    t = time.perf_counter() - t0
+    out["brute_2k_128x128"] = {"s_per_frame": round(t, 4), "mpix_per_s": round(128 * 128 / t / 1e6, 4)}
+    scene, cams, mlp, _ = mgs_data.make_config("large", seed=0)
+    t_pre, t_bs, n_s, n_ne, W, H = _oracle_binned_sample(scene, cams, mlp, n_tiles_sample)
+    t = t_pre + t_bs * (n_ne / max(1, n_s))
+    out["binned_3m_1920x1080"] = {"s_per_frame": round(t, 2), "mpix_per_s": round(W * H / t / 1e6, 5),
+                                  "sample": f"{n_s} of {n_ne} non-empty tiles, pre-pass {t_pre:.1f} s"}
+    return out
 
 
 SERVE_SIZES = (200_000, 400_000, 600_000, 800_000, 1_000_000, 1_500_000, 2_000_000, 2_500_000)
@@ -565,6 +601,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams, mlp)
+        log("timing the CPU oracle on the other workloads ...")
+        out["oracle_timings"] = oracle_timings()
     print(json.dumps(out), flush=True)
 
 
