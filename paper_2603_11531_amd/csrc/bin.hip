@@ -1129,7 +1129,7 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     MGS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "n out of range");
     if ((rc = check_projected(proj, n)) != MGS_OK) return rc;
     MGS_REQUIRE(T > 0 && st_max > 0, "bad tile grid");
-    MGS_REQUIRE(st_max < (1u << (32 - ST_KEY_SHIFT)), "more than 2^%d supertiles", 32 - ST_KEY_SHIFT);
+    MGS_REQUIRE(st_max < (1u << (32 - ST_KEY_SHIFT)), "2^%d or more supertiles", 32 - ST_KEY_SHIFT);
     MGS_REQUIRE(tile_offsets && n_pairs, "tile_offsets / n_pairs is NULL");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity must be < 2^32 - 1");
     MGS_REQUIRE(capacity == 0 || gids, "gids is NULL");
