@@ -335,7 +335,7 @@ def measured_peaks(torch, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding of the "
+        print(json.dumps({"error": "the renderer runs on one GPU; --gpus must be 1 (multi-GPU sharding of the "
                                    "additive OIT partial sums is a documented design, not built)"}))
         sys.exit(2)
     import numpy as np
