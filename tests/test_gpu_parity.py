@@ -403,6 +403,32 @@ def test_fused_enhance_project_equals_separate_calls(M):
     assert torch.equal(ia, ib)
 
 
+def test_split_tile_longer_than_255_full_ranges(M):
+    """One tile with more than 255 x 1024 Gaussians: its list is cut into 255 ranges of
+    ceil(L / 255) > 1024 (the long-list rule of the split plan), merged in order."""
+    say("test_split_tile_longer_than_255_full_ranges")
+    scene = mgs_data.make_scene_uniform(270_000, 21, half=0.5, ls_mu=-4.5)
+    cam = mgs_data.look_at((0.0, 0.0, -4.0), width=16, height=16, f=16.0)
+    bg = (0.1, 0.2, 0.3)
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height, capacity=ds.n)
+    split_img = R.render(ds, cam, bg=bg, split=True).double().cpu()
+    offs, _ = R.lists()
+    L = int(offs[1] - offs[0])
+    say(f"  one tile, list length {L}")
+    assert L > 255 * 1024
+    tile_img = R.render(ds, cam, bg=bg, split=False).double().cpu()
+    # 270k-term float32 sums in two different orders (255 ranges vs four waves)
+    d = float((split_img - tile_img).abs().max())
+    say(f"  split vs per-tile blend: {d:.3e}")
+    assert d < TOL
+    pr, camt = oracle_project(scene, cam)
+    ref, aux, V, flagged = O.render_oit(pr, camt, np.array(bg), mode="binned", variants=True)
+    err, nfail = compare_oit_image(split_img, V, flagged, TOL)
+    say(f"  split vs oracle: max {err:.3e} fails {nfail} flagged {flagged}")
+    assert nfail == 0
+
+
 def test_split_tile_blend_matches_oracle_and_per_tile_blend(M):
     """Dense tiles (lists far longer than one 1024-Gaussian range) through the split blend."""
     say("test_split_tile_blend_matches_oracle_and_per_tile_blend")
