@@ -309,8 +309,10 @@ extern "C" int mgs_enhance_project_mlp_f(const mgs_gaussians *g, const mgs_camer
     MGS_REQUIRE(phi && omod, "phi / omod is NULL");
     const CamK k = make_camk(cam);
     // one workgroup per CU holds the network in LDS; the grid strides over 64-Gaussian groups
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;                                  // the grid size only; any positive count is correct
     const int64_t groups = (g->n + 63) / 64, per_block = MF_THREADS / 64;
     int64_t blocks = (groups + per_block - 1) / per_block;
     if (blocks > cus) blocks = cus;
