@@ -20,7 +20,7 @@ stand-ins for the paper's Mip-NeRF 360 / Tanks&Temples / Deep Blending scenes).
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 

@@ -22,7 +22,6 @@ Steps, in the paper's order:
 from __future__ import annotations
 
 import math
-from typing import Optional
 
 import numpy as np
 import torch

@@ -6,7 +6,6 @@ capacity of the tile lists (the only data-dependent size of the pass).
 """
 from __future__ import annotations
 
-import math
 
 import numpy as np
 import torch

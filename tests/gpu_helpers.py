@@ -11,7 +11,6 @@ import sys
 import numpy as np
 import torch
 
-import mgs_data
 import oracle as O
 
 
