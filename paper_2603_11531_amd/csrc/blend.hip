@@ -70,9 +70,10 @@ struct BatchViewLoc {
     }
 };
 
-// Work list of the split blend: every tile gets n_ranges(L) items (item = tile | range << 24);
-// ranges of split tiles (n_ranges > 1) also get a partial-sum slot.  counts = {items, split
-// tiles}; split_tile[j] / split_slot0[j] = tile and first slot of the j-th split tile.
+// Work list of the split blend: every tile gets n_ranges(L) items (item = tile | range << 24,
+// so at most 2^24 - 1 tiles); ranges of split tiles (n_ranges > 1) also get a partial-sum slot.
+// counts = {items, split tiles}; split_tile[j] = tile | n_ranges << 24 and split_slot0[j] = first
+// slot of the j-th split tile.
 // Chunked scan over the tiles (SPLIT_TILE tiles per chunk): pass 1 totals each chunk's items, slots
 // and split tiles; pass 2 puts each tile's first item and slot in LDS and writes the chunk's
 // items coalesced, each thread finding the tile of its item by binary search in LDS.
@@ -179,7 +180,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             s_item0[threadIdx.x * SPLIT_ITEMS + j] = i0;
             s_slot0[threadIdx.x * SPLIT_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
             if (m && writer) {
-                split_tile[js] = t0 + j;
+                split_tile[js] = (t0 + j) | (nj << 24);          // the merge needs no list offsets
                 split_slot0[js] = s0;
             }
             if (m) {
@@ -243,13 +244,11 @@ blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict_
 // Merge the ranges of each split tile in range order and composite (Eq. 2).
 template <typename Loc>
 __global__ void __launch_bounds__(BLEND_THREADS)
-merge_ranges_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ split_tile,
-                    const uint32_t *__restrict__ split_slot0, const uint32_t *__restrict__ counts, Loc loc,
-                    const float *__restrict__ part) {
+merge_ranges_kernel(const uint32_t *__restrict__ split_tile, const uint32_t *__restrict__ split_slot0,
+                    const uint32_t *__restrict__ counts, Loc loc, const float *__restrict__ part) {
     const uint32_t n_split = counts[1];
     for (uint32_t j = blockIdx.x; j < n_split; j += gridDim.x) {         // block-uniform
-        const uint32_t t = split_tile[j];
-        const uint32_t nr = n_ranges(offs[t + 1] - offs[t], SPLIT_RANGE);
+        const uint32_t st = split_tile[j], t = st & 0xFFFFFFu, nr = st >> 24;
         const float *b = part + size_t(split_slot0[j]) * PART_FLOATS;
         const int p = threadIdx.x;
         float Nr = 0.f, Ng = 0.f, Nb = 0.f, D = 0.f, T = 1.f;
@@ -325,7 +324,7 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     MGS_LAUNCH_CHECK("blend_range_kernel");
     // split tiles are at most T; a bounded grid walks them (most tiles are not split)
     hipLaunchKernelGGL(merge_ranges_kernel<Loc>, dim3(T == 0 ? 1u : (T < MERGE_GRID ? T : MERGE_GRID)),
-                       dim3(BLEND_THREADS), 0, s, offs, stile, sslot, counts, loc, part);
+                       dim3(BLEND_THREADS), 0, s, stile, sslot, counts, loc, part);
     MGS_LAUNCH_CHECK("merge_ranges_kernel");
     return MGS_OK;
 }
@@ -390,6 +389,7 @@ extern "C" int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_
 
 extern "C" int mgs_blend_oit_split_workspace(int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes) {
     MGS_REQUIRE(bytes && tiles_x > 0 && tiles_y > 0, "bad arguments");
+    MGS_REQUIRE(uint64_t(tiles_x) * uint64_t(tiles_y) < (uint64_t(1) << 24), "2^24 or more tiles");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
     *bytes = mgs::blend_split_workspace(uint32_t(tiles_x) * uint32_t(tiles_y), capacity);
     return MGS_OK;
@@ -406,6 +406,7 @@ extern "C" int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *ti
     MGS_REQUIRE(n_pairs != nullptr, "n_pairs is NULL");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
     const CamK k = make_camk(cam);
+    MGS_REQUIRE(uint64_t(k.tiles_x) * uint64_t(k.tiles_y) < (uint64_t(1) << 24), "2^24 or more tiles");
     const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
     MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= blend_split_workspace(T, capacity), "workspace too small");
     SingleViewLoc loc{k.tiles_x, k.W, k.H, {bg[0], bg[1], bg[2]}, image, aux};

@@ -52,6 +52,9 @@ def test_host_side_validation(lib):
     assert lib.mgs_bin(C.byref(pz), 0, 65535, 8 * 128, None, 0, None, None, 0, None, None) == L.MGS_ERR_INVALID_ARG
     assert "supertiles" in lib.mgs_last_error().decode()
     assert lib.mgs_batch_workspace(1000, (1 << 20) - 1, 1000, C.byref(nb)) == L.MGS_OK
+    # the split blend's work items hold a 24-bit tile id
+    assert lib.mgs_blend_oit_split_workspace(4096, 4095, 1000, C.byref(nb)) == L.MGS_OK
+    assert lib.mgs_blend_oit_split_workspace(4096, 4096, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_batch_workspace(1000, 1 << 20, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_bin_sorted_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK
     assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
