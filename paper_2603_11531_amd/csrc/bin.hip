@@ -39,6 +39,7 @@ constexpr int SUPER_RADIX_ITERS = 4;                      // level-1 sort: 1024 
 constexpr int SUPER_RADIX_TILE = RADIX_THREADS * SUPER_RADIX_ITERS;   // so more, shorter blocks)
 // supertiles up to which the plan takes the supertile ranges from the sort's digit totals
 constexpr int ST_FROM_DIGITS = 256;
+constexpr unsigned PLAN_REPLICAS = 8;                    // blocks of a single-pass chunk plan
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -661,8 +662,11 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
     __shared__ uint32_t s_offs[ST_FROM_DIGITS + 1];
-    // part == NULL: one block walks every piece with a running carry (few pieces)
+    // part == NULL (few pieces): every block walks every piece with a running carry and writes
+    // every grid-th 1024 chunk entries; block 0 writes the per-supertile outputs
     const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
+    const bool replicated = part == nullptr;
+    const bool writer = !replicated || blockIdx.x == 0;
     // digit_total != NULL (one block, S <= ST_FROM_DIGITS): the supertile sort took a single
     // radix pass over the whole supertile id, so its digit totals are the supertiles' entry
     // counts; their exclusive scan is st_offs, written here instead of by a pass over the keys
@@ -672,13 +676,14 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
         const uint32_t pre = uint32_t(block_scan1024(v, s_wsum, &tot));
         if (threadIdx.x <= S && threadIdx.x <= uint32_t(ST_FROM_DIGITS)) {
             s_offs[threadIdx.x] = threadIdx.x < S ? pre : uint32_t(tot);
-            st_offs_out[threadIdx.x] = threadIdx.x < S ? pre : uint32_t(tot);
+            if (writer) st_offs_out[threadIdx.x] = threadIdx.x < S ? pre : uint32_t(tot);
         }
         __syncthreads();
     }
     const uint32_t *offs_in = digit_total ? s_offs : st_offs;
     uint32_t carry = 0;
-    for (uint32_t c = blockIdx.x; c < plan_chunks(S); c += gridDim.x) {
+    const uint32_t fill0 = replicated ? blockIdx.x * 1024u : 0u, fill_step = 1024u * (replicated ? gridDim.x : 1u);
+    for (uint32_t c = replicated ? 0u : blockIdx.x; c < plan_chunks(S); c += replicated ? 1u : gridDim.x) {
         const uint32_t base = c * PLAN_TILE, k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
         uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
@@ -695,13 +700,13 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             s_pre[k0 + j] = q;
-            if (s0 + j < S) sc0[s0 + j] = first + q;
+            if (writer && s0 + j < S) sc0[s0 + j] = first + q;
             q += nc[j];
         }
         if (threadIdx.x == 0) s_pre[PLAN_TILE] = uint32_t(tot);
         __syncthreads();
         const uint32_t ns = min(uint32_t(PLAN_TILE), S - base);
-        for (uint32_t i = threadIdx.x; i < uint32_t(tot); i += 1024) {
+        for (uint32_t i = fill0 + threadIdx.x; i < uint32_t(tot); i += fill_step) {
             const int k = upper_index(s_pre, int(ns), i);
             chunk_st[first + i] = base + k;
             chunk_lo[first + i] = offs_in[base + k] + (i - s_pre[k]) * CHUNK;
@@ -1222,8 +1227,8 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
 
     // level 2: chunks, per-chunk tile counts, column scans, tile offsets, the lists
     if (ncs <= PLAN_ONE_BLOCK) {
-        hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs, capacity,
-                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), sc0,
+        hipLaunchKernelGGL(chunk_plan_kernel, dim3(PLAN_REPLICAS), dim3(1024), 0, s, st_offs, st_count, st_max, n_pairs,
+                           capacity, static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), sc0,
                            chunk_st, chunk_lo, nch, from_digits ? dtot : static_cast<const uint32_t *>(nullptr),
                            st_offs);
     } else {
