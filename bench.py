@@ -383,25 +383,26 @@ def main():
 
     src = {"scene": ds}
 
-    def frame(k, sorted_path, ev=None):
+    def frame(k, sorted_path, ev=None, Rx=None):
+        Rx = R if Rx is None else Rx
         cs = cam_structs[k % len(cam_structs)]
         if ev is not None:
             ev[0].record(stream)
         if isinstance(src["scene"], M.DeviceNVQ):  # attributes read through the NVQ codebooks
-            R.enhance_project_nvq(src["scene"], cs, dm)
+            Rx.enhance_project_nvq(src["scene"], cs, dm)
         elif src.get("mlp_f") is not None:        # the appendix's MLP_f 256-128-64, fused
-            R.enhance_project_mlp_f(src["scene"], cs, src["mlp_f"])
+            Rx.enhance_project_mlp_f(src["scene"], cs, src["mlp_f"])
         else:  # Eq. 4 MLP fused with the projection; Eq. 3 weight or one of its ablations
-            R.enhance_project(src["scene"], cs, dm, weight_mode=src.get("weight_mode", M._lib.MGS_WEIGHT_EQ3))
+            Rx.enhance_project(src["scene"], cs, dm, weight_mode=src.get("weight_mode", M._lib.MGS_WEIGHT_EQ3))
         if ev is not None:
             ev[1].record(stream)
-        R.bin(sorted_path)
+        Rx.bin(sorted_path)
         if ev is not None:
             ev[2].record(stream)
         if sorted_path:
-            R.blend_sorted(cs, bg)
+            Rx.blend_sorted(cs, bg)
         else:
-            R.blend_oit(cs, bg)
+            Rx.blend_oit(cs, bg)
         if ev is not None:
             ev[3].record(stream)
 
@@ -425,6 +426,31 @@ def main():
             raise RuntimeError("pair capacity exceeded inside the timed loop")
         return wall, stages, frame_ms
 
+    def run_pipelined(sorted_path, n_streams=2):
+        """Frames on n_streams streams (frame k on stream k % n, each with its own buffers):
+        one frame's latency-bound binning overlaps another frame's blend."""
+        Rs = [R] + [M.Renderer(ds.n, W, H) for _ in range(n_streams - 1)]
+        for Rx in Rs[1:]:
+            Rx.ensure_capacity(R.capacity)
+            Rx.ensure_capacity(R.capacity, sorted_path=True)
+        streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        torch.cuda.synchronize()
+        for k in range(args.warmup):
+            with torch.cuda.stream(streams[k % n_streams]):
+                frame(k, sorted_path, Rx=Rs[k % n_streams])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            with torch.cuda.stream(streams[k % n_streams]):
+                frame(k, sorted_path, Rx=Rs[k % n_streams])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for Rx in Rs:
+            if Rx.pairs() > Rx.capacity:
+                raise RuntimeError("pair capacity exceeded inside the timed loop")
+        del Rs
+        return wall
+
     log("timing OIT ...")
     wall, stages, frame_ms = run(False)
     fps = args.steps / wall
@@ -435,6 +461,12 @@ def main():
         res_sorted = dict(fps=round(args.steps / wall_s, 2), ms_per_frame=round(1e3 * wall_s / args.steps, 4),
                           stage_ms=dict(zip(["enhance_project", "bin_sorted", "blend_sorted"],
                                             [round(float(v), 4) for v in stages_s.mean(axis=0)])))
+    log("timing OIT (and sorted) with consecutive frames on two streams ...")
+    wall_p = run_pipelined(False)
+    res_pipe = dict(streams=2, fps=round(args.steps / wall_p, 2))
+    if not args.no_sorted:
+        wall_ps = run_pipelined(True)
+        res_pipe.update(sorted_fps=round(args.steps / wall_ps, 2), oit_vs_sorted=round(wall_ps / wall_p, 3))
     res_nvq = None
     if not args.no_extra:
         # the same positions with vector-quantised attributes (Sec. 3.3): 5 uint16 codes per
@@ -573,6 +605,7 @@ def main():
         "peaks_measured": peaks,
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
+        "two_streams": res_pipe,
         "nvq": res_nvq,
         "weighting_ablations": res_weight,
         "mlp_f": res_mlpf,
