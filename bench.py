@@ -469,7 +469,7 @@ def main():
         res_pipe.update(sorted_fps=round(args.steps / wall_ps, 2), oit_vs_sorted=round(wall_ps / wall_p, 3))
     res_nvq = None
     if not args.no_extra:
-        # the same positions with vector-quantised attributes (Sec. 3.3): 5 uint16 codes per
+        # the same positions with vector-quantised attributes (Sec. 3.2): 5 uint16 codes per
         # Gaussian into five 1024 x 4 codebooks instead of 20 float32 attributes
         log("timing OIT with NVQ-coded attributes ...")
         dq = M.DeviceNVQ(mgs_data.make_nvq(scene, 7))

@@ -240,7 +240,7 @@ int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, 
                                  float *omod, void *stream);
 
 /*
- * Vector-quantised Gaussians (Sec. 3.3, neural vector quantization: attribute
+ * Vector-quantised Gaussians (Sec. 3.2, neural vector quantization: attribute
  * sub-vectors, each with its own codebook; five groups and 2^10 codewords per
  * codebook in the paper's deployed configuration).  Positions stay float32.  The 20
  * other attributes, in the order [log_scale(3), quat(4) w,x,y,z, opacity_logit,

@@ -14,7 +14,7 @@ Everything it returns is plain numpy float32/int arrays:
 * mlp: FP32 master weights of the view-dependent enhancement MLP (Eq. 4):
   22 -> 64 -> 64 -> {phi, opacity} heads.
 
-Distributions follow the workload recipes listed in the design doc (synthetic
+Distributions follow the workload recipes of the generators below (synthetic
 stand-ins for the paper's Mip-NeRF 360 / Tanks&Temples / Deep Blending scenes).
 """
 from __future__ import annotations

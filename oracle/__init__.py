@@ -5,13 +5,13 @@ statement of what the render pass computes, written from the paper
 (Mobile-GS, arXiv 2603.11531): Eq. 2 and Eq. 3 (Sec. 3.1) for the
 order-independent blend, Eq. 4 for the view-dependent enhancement MLP, and
 Eq. 11 (Appendix B) for the sorted alpha-blend comparison path, and the
-codebook decode of vector-quantised attributes (Sec. 3.3, ``oracle.nvq``).  It shares no
+codebook decode of vector-quantised attributes (Sec. 3.2, ``oracle.nvq``).  It shares no
 code with the HIP path and imports nothing from it.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it; the product path never does.
 
-Every function states the passage it follows; readings of silent or
-ambiguous points are listed in DESIGN.md ("Readings").
+Every function states the passage it follows; where the paper is silent or
+ambiguous, the reading taken is stated beside the code that applies it.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, invariants, textbook special cases or brute force,

@@ -1,6 +1,6 @@
 """Decode of vector-quantised Gaussian attributes (test infrastructure; a lookup, so exact).
 
-Neural vector quantization (Sec. 3.3, and the implementation details in the appendix):
+Neural vector quantization (Sec. 3.2, and the implementation details in the appendix):
 the per-Gaussian attribute vector is cut into K sub-vectors, each quantised with its own
 codebook of B codewords; the deployed renderer keeps only the codes and the codebooks
 (the group MLPs that refine the codewords are applied once, to the codebooks, so the

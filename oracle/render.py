@@ -211,12 +211,16 @@ def enhance(x, mlp, bf16=False):
 # --------------------------------------------------------------------------
 # Eq. 3 and the two ablations of it in the paper's ablation table (Table 3): "without
 # depth" read as d = 1 in Eq. 3, "without scale" as Eq. 3 without its exp(s_max / d) term.
-WEIGHT_EQ3, WEIGHT_NO_DEPTH, WEIGHT_NO_SCALE = 0, 1, 2
+# WEIGHT_SORTFREE is the weighting function of the SortFreeGS composite the paper starts
+# from (Eq. 1, Sec. 2): w(d_i) = exp(-sigma_i d_i^beta_i), with per-Gaussian sigma_i, beta_i.
+WEIGHT_EQ3, WEIGHT_NO_DEPTH, WEIGHT_NO_SCALE, WEIGHT_SORTFREE = 0, 1, 2, 3
 
 
-def depth_weight(phi, d, s, mode=WEIGHT_EQ3):
+def depth_weight(phi, d, s, mode=WEIGHT_EQ3, sortfree=None):
     """w = phi^2 + phi / d^2 + exp(s_max / d); s_max = largest activated scale (Eq. 3),
-    or an ablation: mode WEIGHT_NO_DEPTH puts d = 1, WEIGHT_NO_SCALE drops the last term."""
+    or an ablation: mode WEIGHT_NO_DEPTH puts d = 1, WEIGHT_NO_SCALE drops the last term;
+    or mode WEIGHT_SORTFREE: w = exp(-sigma d^beta) (Eq. 1) with ``sortfree`` = (sigma, beta),
+    two (N,) tensors (phi and the scale play no part)."""
     s_max = s.max(dim=1).values
     if mode == WEIGHT_EQ3:
         return phi * phi + phi / (d * d) + torch.exp(s_max / d)
@@ -224,6 +228,11 @@ def depth_weight(phi, d, s, mode=WEIGHT_EQ3):
         return phi * phi + phi + torch.exp(s_max)
     if mode == WEIGHT_NO_SCALE:
         return phi * phi + phi / (d * d)
+    if mode == WEIGHT_SORTFREE:
+        if sortfree is None:
+            raise ValueError("WEIGHT_SORTFREE needs (sigma, beta)")
+        sigma, beta = sortfree
+        return torch.exp(-sigma * d ** beta)
     raise ValueError(f"unknown weight mode {mode}")
 
 
@@ -251,14 +260,15 @@ def ewa_cov2d(x_c, Sigma, cam):
     return cov
 
 
-def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3):
+def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3, sortfree=None):
     """Per-Gaussian preprocessing: everything the per-pixel blend needs.
 
     Returns float64 tensors: mean2d (N,2), cov2d (N,2,2), conic (N,3) =
     (A, B, C) of Sigma'^-1, color (N,3), o_eff (N,), w (N,), depth (N,), and
     integer results: visible (N,) bool, rect (N,4) int64 = (tx0, ty0, tx1, ty1)
     inclusive tile coordinates, n_tiles (N,) int64.  Culled Gaussians have
-    n_tiles = 0 and rect = 0.
+    n_tiles = 0 and rect = 0.  ``weight_mode`` / ``sortfree`` select w (depth_weight);
+    with tile = 1 the rect is the pixel range itself.
 
     Culling: depth <= near; o_eff < alpha_min; an empty pixel range.  The rect is
     the set of tiles touched by the pixel centres inside the exact bounding box
@@ -273,8 +283,10 @@ def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3):
     if m is None:
         m = torch.ones(n, dtype=DT)
     o_eff = act["o"] * m
-    w = depth_weight(phi, d, act["s"], weight_mode)
     front = d > cam["near"]
+    # culled points get depth 1 in the weight (keeps d^beta real; they never reach the blend)
+    w = depth_weight(phi, torch.where(front, d, torch.ones_like(d)) if weight_mode == WEIGHT_SORTFREE else d,
+                     act["s"], weight_mode, sortfree)
     # Keep the projection finite for culled points (they never reach the blend).
     d_safe = torch.where(front, d, torch.ones_like(d))
     x_safe = torch.cat([x_c[:, :2], d_safe[:, None]], dim=1)
@@ -429,20 +441,30 @@ def eval_pixels_oit(pix, proj, idx, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, tr
     return N, D, T, cnt, amb_list, n_amb
 
 
-def _composite(N, D, T, bg):
-    """C = (1 - T) N / D + T c_bg, and C = c_bg where no Gaussian contributes."""
+def _composite(N, D, T, bg, w_bg=None):
+    """C = (1 - T) N / D + T c_bg, and C = c_bg where no Gaussian contributes (Eq. 2).
+
+    With ``w_bg`` (a float >= 0) the SortFreeGS composite of Eq. 1 instead:
+    C = (c_bg w_bg + N) / (w_bg + D), T unused, and C = c_bg where w_bg + D = 0.
+    F = N / D (0 where D = 0) is returned in both cases."""
     has = D > 0
     Dsafe = torch.where(has, D, torch.ones_like(D))
-    F = N / Dsafe[:, None]
+    F = torch.where(has[:, None], N / Dsafe[:, None], torch.zeros_like(N))
+    if w_bg is not None:
+        den = D + w_bg
+        pos = den > 0
+        C = (N + w_bg * bg[None, :]) / torch.where(pos, den, torch.ones_like(den))[:, None]
+        return torch.where(pos[:, None], C, bg[None, :].expand_as(C)), F
     C = (1.0 - T)[:, None] * F + T[:, None] * bg[None, :]
     return torch.where(has[:, None], C, bg[None, :].expand_as(C)), F
 
 
-def oit_pixel_variants(N, D, T, amb_list, bg):
+def oit_pixel_variants(N, D, T, amb_list, bg, w_bg=None):
     """Images for every way the (at most two) ambiguous pairs of a pixel may fall.
 
     Returns (4, n_pix, 3): variant v toggles ambiguous pair k when bit k of v
     is set (pixels with fewer ambiguous pairs repeat their nominal result).
+    ``w_bg``: composite of Eq. 1 instead of Eq. 2 (see _composite).
     """
     outs = []
     for v in range(4):
@@ -457,14 +479,14 @@ def oit_pixel_variants(N, D, T, amb_list, bg):
                               torch.where(tog, e["one_minus"], torch.ones_like(e["one_minus"])))
             Tv = Tv * fac
         Dv = torch.where(Dv.abs() < 1e-12, torch.zeros_like(Dv), Dv)
-        C, _ = _composite(Nv, Dv, Tv, bg)
+        C, _ = _composite(Nv, Dv, Tv, bg, w_bg)
         outs.append(C)
     return torch.stack(outs)
 
 
 def render_oit(proj, cam, bg, mode="brute", lists=None, chunk=1 << 22, variants=False,
-               alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX):
-    """Image (3, H, W) of Eq. 2.
+               alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, w_bg=None):
+    """Image (3, H, W) of Eq. 2 (or, with ``w_bg``, of Eq. 1's composite).
 
     ``mode='brute'`` evaluates every pixel against every visible Gaussian;
     ``mode='binned'`` evaluates each tile's pixels against that tile's list
@@ -523,12 +545,12 @@ def render_oit(proj, cam, bg, mode="brute", lists=None, chunk=1 << 22, variants=
             run(pidx, g)
     else:
         raise ValueError(mode)
-    C, F = _composite(N, D, T, bg)
+    C, F = _composite(N, D, T, bg, w_bg)
     img = C.T.reshape(3, H, W)
     aux = torch.cat([F.T, D[None], T[None]], dim=0).reshape(5, H, W)
     if not variants:
         return img, aux
-    V = oit_pixel_variants(N, D, T, amb_store, bg)      # (4, n_pix, 3)
+    V = oit_pixel_variants(N, D, T, amb_store, bg, w_bg)      # (4, n_pix, 3)
     V = V.permute(0, 2, 1).reshape(4, 3, H, W)
     flagged = int((n_amb > 2).sum())
     return img, aux, V, flagged
@@ -607,8 +629,9 @@ def mlp_params(mlp, requires_grad=False):
 
 
 def render(scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), bf16=False, mode="brute", tile=16,
-           params=None, mparams=None, sorted_path=False, weight_mode=WEIGHT_EQ3):
-    """Enhance -> project -> (bin) -> blend for one view; returns (image, aux, proj)."""
+           params=None, mparams=None, sorted_path=False, weight_mode=WEIGHT_EQ3, sortfree=None, w_bg=None):
+    """Enhance -> project -> (bin) -> blend for one view; returns (image, aux, proj).
+    ``sortfree`` = (sigma, beta) arrays and ``w_bg`` select Eq. 1 (with WEIGHT_SORTFREE)."""
     camt = camera_tensors(cam)
     p = scene_params(scene) if params is None else params
     phi = m = None
@@ -618,11 +641,14 @@ def render(scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), bf16=False, mode="brute", t
         _, _, P = camera_space(p["mean"], camt)
         x = mlp_features(P, act["s"], act["q"], p["sh"])
         phi, m = enhance(x, mp, bf16=bf16)
-    proj = project(p, camt, phi, m, tile, weight_mode)
+    if sortfree is not None:
+        sortfree = tuple(to64(np.asarray(v)) for v in sortfree)
+    proj = project(p, camt, phi, m, tile, weight_mode, sortfree)
     if sorted_path:
         return render_sorted(proj, camt, bg), None, proj
-    img, aux = render_oit(proj, camt, bg, mode=mode)
+    img, aux = render_oit(proj, camt, bg, mode=mode, w_bg=w_bg)
     return img, aux, proj
 
 
-__all__ += ["scene_params", "mlp_params", "bf16_round", "WEIGHT_EQ3", "WEIGHT_NO_DEPTH", "WEIGHT_NO_SCALE"]
+__all__ += ["scene_params", "mlp_params", "bf16_round", "WEIGHT_EQ3", "WEIGHT_NO_DEPTH", "WEIGHT_NO_SCALE",
+            "WEIGHT_SORTFREE"]

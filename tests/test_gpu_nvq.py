@@ -1,4 +1,4 @@
-"""Vector-quantised attributes (Sec. 3.3): the codebook decode and the fused enhance +
+"""Vector-quantised attributes (Sec. 3.2): the codebook decode and the fused enhance +
 project that reads through the codebooks, against the oracle's decode (bit-exact), the
 float32 path on the decoded attributes (bit-exact) and the FP64 oracle image."""
 import numpy as np

@@ -728,7 +728,7 @@ def test_bf16_rounding_passes_gradients_straight_through():
 
 
 # --------------------------------------------------------------------------
-# Vector-quantised attributes (Sec. 3.3): the decode is a lookup.
+# Vector-quantised attributes (Sec. 3.2): the decode is a lookup.
 # --------------------------------------------------------------------------
 def test_nvq_decode_hand_built_codebook():
     """Codeword value j of row b in codebook g is 1000 g + b + j / 8 (exact in float32), so
