@@ -57,6 +57,10 @@ extern "C" {
 #define MGS_WEIGHT_EQ3       0      /* w = phi^2 + phi/d^2 + exp(s_max/d)                */
 #define MGS_WEIGHT_NO_DEPTH  1      /* w = phi^2 + phi + exp(s_max)                      */
 #define MGS_WEIGHT_NO_SCALE  2      /* w = phi^2 + phi/d^2                               */
+/* The weighting function of the SortFreeGS composite the paper builds on (Eq. 1, Sec. 2):
+ * w = exp(-sigma_i d^beta_i) with per-Gaussian sigma_i, beta_i; selected only through
+ * mgs_project_sortfree / mgs_enhance_project_sortfree, which take the two arrays. */
+#define MGS_WEIGHT_SORTFREE  3      /* w = exp(-sigma_i d^beta_i)                        */
 
 /* Pinhole camera.  R is row-major world->camera (rows: right, down, forward). */
 typedef struct mgs_camera {
@@ -240,6 +244,24 @@ int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, 
                                  float *omod, void *stream);
 
 /*
+ * SortFreeGS weighting (Eq. 1, Sec. 2), the sort-free composite the paper compares its own
+ * against:  C = (c_bg w_bg + sum_i c_i alpha_i w(d_i)) / (w_bg + sum_i alpha_i w(d_i)),
+ * w(d_i) = exp(-sigma_i d_i^beta_i), d_i the camera depth.  It has no transmittance term.
+ *
+ * mgs_project_sortfree -- mgs_project with w = exp(-sigma_i d_i^beta_i) in the splat record's
+ * weight slot (MGS_WEIGHT_SORTFREE); sigma, beta: device float32 [n] (required for n > 0).
+ * phi plays no part in this weight; omod (NULL -> 1) still modulates the opacity.
+ * mgs_enhance_project_sortfree -- the same after the enhancement MLP (phi / omod written as
+ * by mgs_enhance_project; only omod enters the record).  Other arguments and errors as
+ * mgs_project / mgs_enhance_project.  mgs_render_backward does not differentiate Eq. 1.
+ */
+int mgs_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const float *omod, const float *sigma,
+                         const float *beta, int tile, float alpha_min, mgs_projected *out, void *stream);
+int mgs_enhance_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp,
+                                 const float *sigma, const float *beta, int tile, float alpha_min,
+                                 mgs_projected *out, float *phi, float *omod, void *stream);
+
+/*
  * Vector-quantised Gaussians (Sec. 3.2, neural vector quantization: attribute
  * sub-vectors, each with its own codebook; five groups and 2^10 codewords per
  * codebook in the paper's deployed configuration).  Positions stay float32.  The 20
@@ -328,6 +350,23 @@ int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *tile_offsets,
                         const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
                         const float bg[3], float alpha_min, float alpha_max, void *ws, size_t ws_bytes,
                         float *image, float *aux, void *stream);
+
+/*
+ * mgs_blend_sortfree / mgs_blend_sortfree_split -- mgs_blend_oit / mgs_blend_oit_split with
+ * the composite of Eq. 1 (Sec. 2) in place of Eq. 2's:  C = (bg w_bg + N) / (w_bg + D), with
+ * N = sum alpha w c and D = sum alpha w over the same contributors (a >= alpha_min, alpha
+ * clamped at alpha_max); C = bg where w_bg + D = 0.  w_bg >= 0 (a host float), otherwise
+ * MGS_ERR_INVALID_ARG.  The weights are those of the projected records (normally from
+ * mgs_project_sortfree).  aux, when non-NULL, receives (N/D rgb, D, T) as for Eq. 2.  Every
+ * other argument, workspace and rule is that of the Eq. 2 call.
+ */
+int mgs_blend_sortfree(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                       const mgs_camera *cam, int tile, const float bg[3], float w_bg, float alpha_min,
+                       float alpha_max, float *image, float *aux, void *stream);
+int mgs_blend_sortfree_split(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                             const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
+                             const float bg[3], float w_bg, float alpha_min, float alpha_max, void *ws,
+                             size_t ws_bytes, float *image, float *aux, void *stream);
 
 /*
  * Sorted comparison path (3DGS alpha blending, Eq. 11, Appendix B).

@@ -174,6 +174,15 @@ def make_mlp(seed, hidden=MLP_HIDDEN, n_in=MLP_IN):
                 w_phi=f32(w_phi), b_phi=np.float32(1.0), w_o=f32(w_o), b_o=np.float32(2.0))
 
 
+def make_sortfree_params(n, seed, sigma_range=(0.02, 0.6), beta_range=(0.5, 1.8)):
+    """Per-Gaussian (sigma, beta) of the SortFreeGS weighting function w = exp(-sigma d^beta)
+    (Eq. 1): float32 arrays drawn uniformly in the given ranges (sigma first, then beta)."""
+    rng = np.random.default_rng(seed)
+    sigma = rng.uniform(*sigma_range, n).astype(np.float32)
+    beta = rng.uniform(*beta_range, n).astype(np.float32)
+    return sigma, beta
+
+
 def with_sh_degree(scene, degree, seed, sd_high=0.1):
     """Copy of a first-order-SH scene with SH of ``degree`` (0..3): degree 0 keeps the DC
     coefficient of each channel; degrees 2 and 3 append coefficients N(0, sd_high) drawn from

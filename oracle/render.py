@@ -28,10 +28,10 @@ import torch
 
 __all__ = [
     "ALPHA_MIN", "ALPHA_MAX", "DILATION", "JAC_CLAMP", "T_STOP", "SH_C0", "SH_C1",
-    "AMBIG_LOG", "to64", "quat_to_rotmat", "activate", "camera_space", "sh1_color",
+    "AMBIG_LOG", "DEPTH_KEY_ULPS", "POS_ULPS", "to64", "quat_to_rotmat", "activate", "camera_space", "sh1_color",
     "mlp_features", "sh_basis", "sh_color", "enhance", "depth_weight", "ewa_cov2d", "project", "bin_lists",
     "bin_lists_bruteforce", "bin_lists_sorted", "pixel_grid", "eval_pixels_oit", "render_oit",
-    "render_sorted", "render", "camera_tensors", "oit_pixel_variants",
+    "render_sorted", "render", "camera_tensors", "oit_pixel_variants", "ambiguous_gaussians",
 ]
 
 DT = torch.float64
@@ -45,6 +45,8 @@ T_STOP = 1e-4             # sorted path only: stop once transmittance drops belo
 SH_C0 = 0.5 / math.sqrt(math.pi)                  # real SH, l=0
 SH_C1 = math.sqrt(3.0) / (2.0 * math.sqrt(math.pi))  # real SH, l=1
 AMBIG_LOG = 1e-4          # |ln(a / alpha_min)| below this -> the pair's inclusion is ambiguous
+POS_ULPS = 4.0            # float32 error bound of a screen mean, in 2^-24 x the magnitude of its terms
+DEPTH_KEY_ULPS = 8.0      # sorted path: float32 error bound of a depth key, in 2^-24 x magnitude
 
 
 def to64(a, requires_grad=False):
@@ -316,8 +318,18 @@ def project(params, cam, phi=None, m=None, tile=16, weight_mode=WEIGHT_EQ3, sort
         rect = torch.where(vis[:, None], rect, torch.zeros_like(rect))
         n_tiles = torch.where(vis, (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1),
                               torch.zeros_like(rect[:, 0]))
+    # magnitude of the terms of d = R_z . mu + t_z (scales the float32 error of a depth key)
+    mu_abs = params["mean"].detach().abs()
+    depth_mag = (mu_abs @ cam["R"][2].abs()) + abs(float(cam["t"][2]))
+    # float32 error bound of the screen mean f x_c / d + c per axis: POS_ULPS units of 2^-24 times
+    # the magnitude of its terms (x_c = R_x . mu + t_x summed in magnitude, then the offset c)
+    with torch.no_grad():
+        dabs = d_safe.detach().abs()
+        mag_x = cam["fx"] * ((mu_abs @ cam["R"][0].abs()) + abs(float(cam["t"][0]))) / dabs + abs(cam["cx"])
+        mag_y = cam["fy"] * ((mu_abs @ cam["R"][1].abs()) + abs(float(cam["t"][1]))) / dabs + abs(cam["cy"])
+        pos_err = POS_ULPS * 2.0 ** -24 * torch.maximum(mag_x, mag_y)
     return dict(mean2d=mean2d, cov2d=cov, conic=conic, color=color, o_eff=o_eff, w=w,
-                depth=d, visible=vis, rect=rect, n_tiles=n_tiles, phi=phi, m=m,
+                depth=d, depth_mag=depth_mag, pos_err=pos_err, visible=vis, rect=rect, n_tiles=n_tiles, phi=phi, m=m,
                 tiles_x=(cam["W"] + tile - 1) // tile, tiles_y=(cam["H"] + tile - 1) // tile,
                 tile=tile)
 
@@ -401,13 +413,31 @@ def _alpha(pix, mean2d, conic, o_eff):
     return o_eff[None, :] * torch.exp(-0.5 * q)
 
 
+def _ambiguous(pix, proj, idx, a, alpha_min):
+    """Pairs whose side of the alpha cut a float32 evaluation may not reproduce (n_pix, n_g):
+    |ln(a / alpha_min)| < AMBIG_LOG + |grad_pixel ln a|_1 pos_err, where ln a moves by
+    |A dx| per pixel of screen-mean error and pos_err bounds that error for the Gaussian
+    (proj["pos_err"], zero when absent)."""
+    band = AMBIG_LOG
+    pos = proj.get("pos_err")
+    near = (a > alpha_min * math.exp(-0.05)) & (a < alpha_min * math.exp(0.05))
+    if pos is None or not bool(near.any()):
+        return (a > alpha_min * math.exp(-band)) & (a < alpha_min * math.exp(band))
+    conic, mean2d = proj["conic"][idx].detach(), proj["mean2d"][idx].detach()
+    dx = pix[:, 0:1] - mean2d[None, :, 0]
+    dy = pix[:, 1:2] - mean2d[None, :, 1]
+    grad = (conic[None, :, 0] * dx + conic[None, :, 1] * dy).abs() + (conic[None, :, 1] * dx + conic[None, :, 2] * dy).abs()
+    width = band + grad * pos[idx].detach()[None, :]
+    return near & (torch.log(a / alpha_min).abs() < width)
+
+
 def eval_pixels_oit(pix, proj, idx, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, track_ambiguous=False):
     """Sums of Eq. 2 for the pixels ``pix`` over the Gaussians ``idx``.
 
     Returns N (n_pix,3) = sum c alpha w, D = sum alpha w, T = prod(1 - alpha) over
     the contributors (alpha >= alpha_min, alpha clamped at alpha_max), and the
     contributor count.  With ``track_ambiguous`` also returns, per pixel, up to
-    two ambiguous pairs (|ln(a/alpha_min)| < AMBIG_LOG) as their contributions
+    two ambiguous pairs (see _ambiguous) as their contributions
     (c a w, a w, 1 - a, nominally_in) and the number of ambiguous pairs.
     """
     idx = torch.as_tensor(idx, dtype=torch.int64)
@@ -425,20 +455,60 @@ def eval_pixels_oit(pix, proj, idx, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, tr
     if not track_ambiguous:
         return N, D, T, cnt
     with torch.no_grad():
-        amb = (torch.log(torch.clamp(a, min=1e-300) / alpha_min).abs() < AMBIG_LOG)
+        amb = _ambiguous(pix, proj, idx, a.detach(), alpha_min)
         n_amb = amb.sum(dim=1)
-        al_raw = torch.clamp(a, max=alpha_max)
-        amb_list = []
-        score = amb.to(torch.int64) * torch.arange(amb.shape[1], 0, -1)[None, :]
-        for _ in range(2):
+        n = a.shape[0]
+        amb_list = [dict(has=torch.zeros(n, dtype=torch.bool), cw=torch.zeros(n, 3, dtype=DT),
+                         aw=torch.zeros(n, dtype=DT), one_minus=torch.ones(n, dtype=DT),
+                         nominal=torch.zeros(n, dtype=torch.bool)) for _ in range(2)]
+        rows = torch.nonzero(n_amb > 0).reshape(-1)       # the pixels with an ambiguous pair
+        if rows.numel() == 0:
+            return N, D, T, cnt, amb_list, n_amb
+        a_r, inc_r = a[rows], inc[rows]
+        al_raw = torch.clamp(a_r, max=alpha_max)
+        # the first two ambiguous pairs of each such pixel, in list order
+        score = amb[rows].to(torch.int64) * torch.arange(a.shape[1], 0, -1)[None, :]
+        for k in range(2):
             j = torch.argmax(score, dim=1)
             has = score.gather(1, j[:, None])[:, 0] > 0
             alj = al_raw.gather(1, j[:, None])[:, 0]
             wj = w[j]
-            amb_list.append(dict(has=has, cw=color[j] * (alj * wj)[:, None], aw=alj * wj,
-                                 one_minus=1.0 - alj, nominal=inc.gather(1, j[:, None])[:, 0]))
+            e = amb_list[k]
+            e["has"][rows] = has
+            e["cw"][rows] = color[j] * (alj * wj)[:, None]
+            e["aw"][rows] = alj * wj
+            e["one_minus"][rows] = 1.0 - alj
+            e["nominal"][rows] = inc_r.gather(1, j[:, None])[:, 0]
             score = score.scatter(1, j[:, None], 0)
     return N, D, T, cnt, amb_list, n_amb
+
+
+def ambiguous_gaussians(proj, cam, lists=None, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX):
+    """Gaussians with at least one pixel pair whose side of a cut float32 may not reproduce:
+    the alpha_min cut (see _ambiguous) or the alpha_max clamp (same band around alpha_max).
+    The render of such a Gaussian's pixels is admissible either way, and its gradient has a
+    term (the pair's) that float32 may include or not.  Per tile over the tile lists (by
+    default the oracle's own).  Returns a bool tensor (N,)."""
+    W, H = cam["W"], cam["H"]
+    if lists is None:
+        lists = bin_lists(proj["rect"], proj["n_tiles"], proj["tiles_x"], proj["tiles_y"])
+    offs, gids = (torch.as_tensor(np.asarray(v), dtype=torch.int64) for v in lists)
+    pix = pixel_grid(W, H)
+    B = proj["tile"]
+    out = torch.zeros(proj["o_eff"].shape[0], dtype=torch.bool)
+    with torch.no_grad():
+        for t in range(proj["tiles_x"] * proj["tiles_y"]):
+            g = gids[offs[t]:offs[t + 1]]
+            if g.numel() == 0:
+                continue
+            tx, ty = t % proj["tiles_x"], t // proj["tiles_x"]
+            ii = torch.arange(tx * B, min(W, tx * B + B))
+            jj = torch.arange(ty * B, min(H, ty * B + B))
+            pp = pix[(jj[:, None] * W + ii[None, :]).reshape(-1)]
+            a = _alpha(pp, proj["mean2d"][g].detach(), proj["conic"][g].detach(), proj["o_eff"][g].detach())
+            amb = _ambiguous(pp, proj, g, a, alpha_min) | _ambiguous(pp, proj, g, a, alpha_max)
+            out[g[amb.any(0)]] = True
+    return out
 
 
 def _composite(N, D, T, bg, w_bg=None):
@@ -516,13 +586,19 @@ def render_oit(proj, cam, bg, mode="brute", lists=None, chunk=1 << 22, variants=
             n_, d_, t_, _, amb, na = res
             for k in range(2):
                 for key in ("has", "cw", "aw", "one_minus", "nominal"):
-                    amb_store[k][key] = amb_store[k][key].index_put((pix_idx,), amb[k][key])
-            n_amb = n_amb.index_put((pix_idx,), na)
+                    amb_store[k][key][pix_idx] = amb[k][key]
+            n_amb[pix_idx] = na
         else:
             n_, d_, t_, _ = res
-        N = N.index_put((pix_idx,), n_)
-        D = D.index_put((pix_idx,), d_)
-        T = T.index_put((pix_idx,), t_)
+        if n_.requires_grad or d_.requires_grad or t_.requires_grad:
+            # out of place, so autograd sees each tile's sums as a separate input
+            N = N.index_put((pix_idx,), n_)
+            D = D.index_put((pix_idx,), d_)
+            T = T.index_put((pix_idx,), t_)
+        else:
+            N[pix_idx] = n_
+            D[pix_idx] = d_
+            T[pix_idx] = t_
 
     if mode == "brute":
         gidx = torch.nonzero(proj["visible"]).reshape(-1)
@@ -559,8 +635,43 @@ def render_oit(proj, cam, bg, mode="brute", lists=None, chunk=1 << 22, variants=
 # --------------------------------------------------------------------------
 # Step 9 -- sorted front-to-back alpha blending, the comparison path (Eq. 11).
 # --------------------------------------------------------------------------
+def _sorted_pixels(pix, proj, order, bg, alpha_min, alpha_max, t_stop, want_flags):
+    """Eq. 11 for the pixels ``pix`` over the Gaussians ``order`` (already in (depth, index)
+    order): returns the colours (n_pix, 3) and, with ``want_flags``, the fragility flags."""
+    a = _alpha(pix, proj["mean2d"][order], proj["conic"][order], proj["o_eff"][order])
+    inc = a >= alpha_min
+    al = torch.where(inc, torch.clamp(a, max=alpha_max), torch.zeros_like(a))
+    one_m = 1.0 - al
+    Tin = torch.cumprod(torch.cat([torch.ones(pix.shape[0], 1, dtype=DT), one_m[:, :-1]], 1), 1)
+    live = Tin >= t_stop
+    contrib = (al * Tin * live) @ proj["color"][order]
+    Tfin = torch.prod(torch.where(live, one_m, torch.ones_like(one_m)), dim=1)
+    out = contrib + Tfin[:, None] * bg[None, :]
+    if not want_flags:
+        return out, None
+    with torch.no_grad():
+        dep = proj["depth"][order].detach()
+        amb = _ambiguous(pix, proj, order, a, alpha_min).any(1)
+        near_stop = ((Tin / t_stop - 1.0).abs() < 1e-3).any(1)
+        # Depth ties a float32 sort key cannot order: two contributors composited before the
+        # stop whose depths differ by no more than the float32 evaluation error of the key,
+        # bounded by DEPTH_KEY_ULPS units of 2^-24 times the magnitude of the terms of
+        # d = R_z . mu + t_z (proj["depth_mag"]).  Contributors behind the stop do not count.
+        mag = proj["depth_mag"][order].detach()
+        live_c = inc & (Tin >= t_stop * (1.0 - 1e-3))
+        # ``order`` is ascending in depth, so each live contributor's predecessor among the live
+        # ones is the running maximum of the live depths before it
+        prev, pidx = torch.cummax(torch.where(live_c, dep[None, :].expand_as(a), torch.full_like(a, -math.inf)), 1)
+        prev, pidx = prev[:, :-1], pidx[:, :-1]
+        gap = dep[None, 1:] - prev
+        tol = DEPTH_KEY_ULPS * 2.0 ** -24 * (mag[None, 1:] + mag[pidx])
+        tie = (live_c[:, 1:] & torch.isfinite(prev) & (gap <= tol)).any(1)
+        flags = amb | near_stop | tie
+    return out, flags
+
+
 def render_sorted(proj, cam, bg, chunk=1 << 21, alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX,
-                  t_stop=T_STOP, return_flags=False):
+                  t_stop=T_STOP, return_flags=False, mode="brute", lists=None):
     """C = sum_k c_k alpha_k T_k + T_K c_bg over contributors sorted by (depth, index).
 
     T_k = prod_{j<k}(1 - alpha_j).  A contributor is composited only while the
@@ -569,40 +680,51 @@ def render_sorted(proj, cam, bg, chunk=1 << 21, alpha_min=ALPHA_MIN, alpha_max=A
     float32 implementation may legitimately order or stop differently (near
     depth ties among contributors, transmittance within 0.1% of t_stop, or an
     ambiguous alpha cut).
+
+    ``mode='brute'`` sorts every visible Gaussian for every pixel; ``mode='binned'``
+    evaluates each tile's pixels over that tile's list only (``lists`` = (tile_offsets,
+    gids), by default the oracle's own), sorted by (depth, index): the same result,
+    since a Gaussian outside a tile's list has alpha < alpha_min on all its pixels.
     """
     W, H = cam["W"], cam["H"]
     bg = torch.as_tensor(np.asarray(bg, np.float64), dtype=DT)
-    gidx = torch.nonzero(proj["visible"]).reshape(-1)
-    # depth order, ties by Gaussian index (stable sort of an index-ordered array)
-    order = gidx[torch.sort(proj["depth"][gidx].detach(), stable=True).indices]
     pix = pixel_grid(W, H)
     n_pix = pix.shape[0]
-    out = torch.zeros(n_pix, 3, dtype=DT)
+    out = bg[None, :].repeat(n_pix, 1)
     flags = torch.zeros(n_pix, dtype=torch.bool)
-    step = max(1, chunk // max(1, len(order)))
-    dep = proj["depth"][order].detach()
-    for p0 in range(0, n_pix, step):
-        pi = torch.arange(p0, min(n_pix, p0 + step))
-        a = _alpha(pix[pi], proj["mean2d"][order], proj["conic"][order], proj["o_eff"][order])
-        inc = a >= alpha_min
-        al = torch.where(inc, torch.clamp(a, max=alpha_max), torch.zeros_like(a))
-        one_m = 1.0 - al
-        Tin = torch.cumprod(torch.cat([torch.ones(len(pi), 1, dtype=DT), one_m[:, :-1]], 1), 1)
-        live = Tin >= t_stop
-        contrib = (al * Tin * live) @ proj["color"][order]
-        Tfin = torch.prod(torch.where(live, one_m, torch.ones_like(one_m)), dim=1)
-        out[pi] = contrib + Tfin[:, None] * bg[None, :]
-        if return_flags:
-            with torch.no_grad():
-                amb = (torch.log(torch.clamp(a, min=1e-300) / alpha_min).abs() < AMBIG_LOG).any(1)
-                near_stop = ((Tin / t_stop - 1.0).abs() < 1e-3).any(1)
-                dd = dep[None, :].expand_as(a)
-                big = torch.where(inc, dd, torch.full_like(dd, float("inf")))
-                srt = torch.sort(big, dim=1).values
-                gap = (srt[:, 1:] - srt[:, :-1]).abs()
-                fin = torch.isfinite(srt[:, 1:])
-                tie = ((gap <= 1e-6 * srt[:, 1:].abs()) & fin).any(1)
-                flags[pi] = amb | near_stop | tie
+    if mode == "brute":
+        gidx = torch.nonzero(proj["visible"]).reshape(-1)
+        # depth order, ties by Gaussian index (stable sort of an index-ordered array)
+        order = gidx[torch.sort(proj["depth"][gidx].detach(), stable=True).indices]
+        step = max(1, chunk // max(1, len(order)))
+        for p0 in range(0, n_pix, step):
+            pi = torch.arange(p0, min(n_pix, p0 + step))
+            o, f = _sorted_pixels(pix[pi], proj, order, bg, alpha_min, alpha_max, t_stop, return_flags)
+            out[pi] = o
+            if return_flags:
+                flags[pi] = f
+    elif mode == "binned":
+        if lists is None:
+            lists = bin_lists(proj["rect"], proj["n_tiles"], proj["tiles_x"], proj["tiles_y"])
+        offs, gids = (torch.as_tensor(np.asarray(v), dtype=torch.int64) for v in lists)
+        B = proj["tile"]
+        depth = proj["depth"].detach()
+        for t in range(proj["tiles_x"] * proj["tiles_y"]):
+            g = gids[offs[t]:offs[t + 1]]
+            if g.numel() == 0:
+                continue
+            g = torch.sort(g).values                                   # index order, then
+            order = g[torch.sort(depth[g], stable=True).indices]      # stable by depth
+            tx, ty = t % proj["tiles_x"], t // proj["tiles_x"]
+            ii = torch.arange(tx * B, min(W, tx * B + B))
+            jj = torch.arange(ty * B, min(H, ty * B + B))
+            pidx = (jj[:, None] * W + ii[None, :]).reshape(-1)
+            o, f = _sorted_pixels(pix[pidx], proj, order, bg, alpha_min, alpha_max, t_stop, return_flags)
+            out[pidx] = o
+            if return_flags:
+                flags[pidx] = f
+    else:
+        raise ValueError(mode)
     img = out.T.reshape(3, H, W)
     if return_flags:
         return img, flags.reshape(H, W)

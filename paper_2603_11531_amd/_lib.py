@@ -33,14 +33,15 @@ EXPORTED = [
     "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
-    "mgs_enhance_project_sh",
+    "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
+    "mgs_blend_sortfree_split",
 ]
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
 MLPF_LAYOUT = (("W1", 0, (256, 22)), ("b1", 5632, (256,)), ("W2", 5888, (128, 256)), ("b2", 38656, (128,)),
                ("W3", 38784, (64, 128)), ("b3", 46976, (64,)), ("w_phi", 47040, (64,)), ("b_phi", 47104, ()),
                ("w_o", 47105, (64,)), ("b_o", 47169, ()))
 MGS_MLPF_PARAMS, MGS_MLPF_PACKED_BYTES = 47170, 104208
-MGS_WEIGHT_EQ3, MGS_WEIGHT_NO_DEPTH, MGS_WEIGHT_NO_SCALE = 0, 1, 2
+MGS_WEIGHT_EQ3, MGS_WEIGHT_NO_DEPTH, MGS_WEIGHT_NO_SCALE, MGS_WEIGHT_SORTFREE = 0, 1, 2, 3
 MGS_NVQ_GROUPS, MGS_NVQ_DIM, MGS_NVQ_CODEWORDS = 5, 4, 1024
 
 
@@ -101,6 +102,14 @@ def load(path=LIB_PATH):
                                        vp]),
         "mgs_enhance_project_weighted": (i32, [P(mgs_gaussians), P(mgs_camera), vp, i32, f32, i32,
                                                P(mgs_projected), vp, vp, vp]),
+        "mgs_project_sortfree": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, i32, f32, P(mgs_projected),
+                                       vp]),
+        "mgs_enhance_project_sortfree": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, i32, f32,
+                                               P(mgs_projected), vp, vp, vp]),
+        "mgs_blend_sortfree": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, f32, vp,
+                                     vp, vp]),
+        "mgs_blend_sortfree_split": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), i32, P(C.c_float), f32,
+                                           f32, f32, vp, C.c_size_t, vp, vp, vp]),
         "mgs_bin_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_oit": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, vp, vp,

@@ -26,7 +26,7 @@ namespace mgs {
 template <bool SORTED>
 __global__ void __launch_bounds__(BLEND_THREADS)
 blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
-             const uint32_t *__restrict__ gids, CamK cam, float bgr, float bgg, float bgb,
+             const uint32_t *__restrict__ gids, CamK cam, float bgr, float bgg, float bgb, float wbg,
              float log2_amin, float amax, float t_stop, float *__restrict__ image,
              float *__restrict__ aux) {
     const int tile = blockIdx.x;
@@ -35,8 +35,8 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
         blend_tile_sorted(splat, gids, offs[tile], offs[tile + 1], tx, ty, cam.W, cam.H, bgr, bgg, bgb, log2_amin,
                           amax, t_stop, image);
     else
-        blend_tile_oit(splat, gids, offs[tile], offs[tile + 1], tx, ty, cam.W, cam.H, bgr, bgg, bgb, log2_amin, amax,
-                       image, aux, nullptr);
+        blend_tile_oit(splat, gids, offs[tile], offs[tile + 1], tx, ty, cam.W, cam.H, bgr, bgg, bgb, wbg, log2_amin,
+                       amax, image, aux, nullptr);
 }
 
 // ---------------------------------------------------------------- split-tile OIT blend
@@ -45,17 +45,21 @@ constexpr uint32_t MERGE_GRID = 2048;         // workgroups of the range merge
 constexpr int PART_FLOATS = 5 * 256;          // per-range partial sums (N rgb, D, T) x 256 pixels
 
 // Destination of one tile: a single view, or one request of a batch.
+// wbg: EQ2_COMPOSITE, or the background weight of Eq. 1's composite.
 struct TileView {
     int tx, ty, W, H;
     float bg[3];
+    float wbg;
     float *image, *aux;
 };
 struct SingleViewLoc {
     int tiles_x, W, H;
     float bg[3];
+    float wbg;
     float *image, *aux;
     __device__ __forceinline__ TileView operator()(uint32_t t) const {
-        return TileView{int(t % uint32_t(tiles_x)), int(t / uint32_t(tiles_x)), W, H, {bg[0], bg[1], bg[2]}, image, aux};
+        return TileView{int(t % uint32_t(tiles_x)), int(t / uint32_t(tiles_x)), W, H, {bg[0], bg[1], bg[2]}, wbg,
+                        image, aux};
     }
 };
 struct BatchViewLoc {
@@ -66,7 +70,7 @@ struct BatchViewLoc {
         const mgs_request &q = reqs[r];
         const uint32_t lt = gt - plan->tbase[r], tx = plan->tiles_x[r];
         return TileView{int(lt % tx), int(lt / tx), q.cam.width, q.cam.height, {q.bg[0], q.bg[1], q.bg[2]},
-                        q.image, nullptr};
+                        EQ2_COMPOSITE, q.image, nullptr};
     }
 };
 
@@ -237,8 +241,8 @@ blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict_
     const bool whole = n_ranges(L, SPLIT_RANGE) == 1;
     const uint32_t s = whole ? start : start + r * rl;
     const uint32_t e = (whole || end - s <= rl) ? end : s + rl;
-    blend_tile_oit(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], log2_amin, amax, v.image,
-                   v.aux, whole ? nullptr : part + size_t(item_slot[k]) * PART_FLOATS);
+    blend_tile_oit(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.wbg, log2_amin, amax,
+                   v.image, v.aux, whole ? nullptr : part + size_t(item_slot[k]) * PART_FLOATS);
 }
 
 // Merge the ranges of each split tile in range order and composite (Eq. 2).
@@ -262,7 +266,7 @@ merge_ranges_kernel(const uint32_t *__restrict__ split_tile, const uint32_t *__r
         const TileView v = loc(t);
         int px, py;
         tile_pixel(p, v.tx, v.ty, px, py);
-        composite_oit(Nr, Ng, Nb, D, T, px, py, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.image, v.aux);
+        composite_oit(Nr, Ng, Nb, D, T, px, py, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.wbg, v.image, v.aux);
     }
 }
 
@@ -354,20 +358,58 @@ inline int blend_common_checks(const mgs_projected *proj, const uint32_t *offs, 
 
 }  // namespace mgs
 
-extern "C" int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
-                             const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
+namespace mgs {
+
+// One workgroup per tile, Eq. 2 (wbg = EQ2_COMPOSITE) or Eq. 1 composite.
+inline int blend_whole_tiles(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                             const mgs_camera *cam, int tile, const float bg[3], float wbg, float alpha_min,
                              float alpha_max, float *image, float *aux, void *stream) {
-    using namespace mgs;
     int rc;
     if ((rc = blend_common_checks(proj, tile_offsets, gids, cam, tile, bg, alpha_min, alpha_max, image)) != MGS_OK)
         return rc;
     const CamK k = make_camk(cam);
     const unsigned ntiles = unsigned(k.tiles_x) * unsigned(k.tiles_y);
     hipLaunchKernelGGL(blend_kernel<false>, dim3(ntiles), dim3(BLEND_THREADS), 0, as_stream(stream),
-                       reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, k, bg[0], bg[1], bg[2],
+                       reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, k, bg[0], bg[1], bg[2], wbg,
                        log2f(alpha_min), alpha_max, 0.0f, image, aux);
     MGS_LAUNCH_CHECK("blend_kernel<oit>");
     return MGS_OK;
+}
+
+// Split tile lists, Eq. 2 (wbg = EQ2_COMPOSITE) or Eq. 1 composite.
+inline int blend_split_single(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                              const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
+                              const float bg[3], float wbg, float alpha_min, float alpha_max, void *ws,
+                              size_t ws_bytes, float *image, float *aux, void *stream) {
+    int rc;
+    if ((rc = blend_common_checks(proj, tile_offsets, gids, cam, tile, bg, alpha_min, alpha_max, image)) != MGS_OK)
+        return rc;
+    MGS_REQUIRE(n_pairs != nullptr, "n_pairs is NULL");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    const CamK k = make_camk(cam);
+    MGS_REQUIRE(uint64_t(k.tiles_x) * uint64_t(k.tiles_y) < (uint64_t(1) << 24), "2^24 or more tiles");
+    const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
+    MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= blend_split_workspace(T, capacity), "workspace too small");
+    SingleViewLoc loc{k.tiles_x, k.W, k.H, {bg[0], bg[1], bg[2]}, wbg, image, aux};
+    return blend_split_launch(reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, nullptr, T, n_pairs,
+                              capacity, loc, alpha_min, alpha_max, ws, as_stream(stream));
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                             const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
+                             float alpha_max, float *image, float *aux, void *stream) {
+    return mgs::blend_whole_tiles(proj, tile_offsets, gids, cam, tile, bg, mgs::EQ2_COMPOSITE, alpha_min, alpha_max,
+                                  image, aux, stream);
+}
+
+extern "C" int mgs_blend_sortfree(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                                  const mgs_camera *cam, int tile, const float bg[3], float w_bg, float alpha_min,
+                                  float alpha_max, float *image, float *aux, void *stream) {
+    MGS_REQUIRE(w_bg >= 0.0f && w_bg < INFINITY, "w_bg must be finite and >= 0");
+    return mgs::blend_whole_tiles(proj, tile_offsets, gids, cam, tile, bg, w_bg, alpha_min, alpha_max, image, aux,
+                                  stream);
 }
 
 extern "C" int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
@@ -382,7 +424,7 @@ extern "C" int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_
     const unsigned ntiles = unsigned(k.tiles_x) * unsigned(k.tiles_y);
     hipLaunchKernelGGL(blend_kernel<true>, dim3(ntiles), dim3(BLEND_THREADS), 0, as_stream(stream),
                        reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, k, bg[0], bg[1], bg[2],
-                       log2f(alpha_min), alpha_max, t_stop, image, nullptr);
+                       EQ2_COMPOSITE, log2f(alpha_min), alpha_max, t_stop, image, nullptr);
     MGS_LAUNCH_CHECK("blend_kernel<sorted>");
     return MGS_OK;
 }
@@ -399,17 +441,16 @@ extern "C" int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *ti
                                    const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
                                    const float bg[3], float alpha_min, float alpha_max, void *ws, size_t ws_bytes,
                                    float *image, float *aux, void *stream) {
-    using namespace mgs;
-    int rc;
-    if ((rc = blend_common_checks(proj, tile_offsets, gids, cam, tile, bg, alpha_min, alpha_max, image)) != MGS_OK)
-        return rc;
-    MGS_REQUIRE(n_pairs != nullptr, "n_pairs is NULL");
-    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
-    const CamK k = make_camk(cam);
-    MGS_REQUIRE(uint64_t(k.tiles_x) * uint64_t(k.tiles_y) < (uint64_t(1) << 24), "2^24 or more tiles");
-    const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
-    MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= blend_split_workspace(T, capacity), "workspace too small");
-    SingleViewLoc loc{k.tiles_x, k.W, k.H, {bg[0], bg[1], bg[2]}, image, aux};
-    return blend_split_launch(reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, nullptr, T, n_pairs,
-                              capacity, loc, alpha_min, alpha_max, ws, as_stream(stream));
+    return mgs::blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, mgs::EQ2_COMPOSITE,
+                                   alpha_min, alpha_max, ws, ws_bytes, image, aux, stream);
+}
+
+extern "C" int mgs_blend_sortfree_split(const mgs_projected *proj, const uint32_t *tile_offsets,
+                                        const uint32_t *gids, const uint32_t *n_pairs, uint64_t capacity,
+                                        const mgs_camera *cam, int tile, const float bg[3], float w_bg,
+                                        float alpha_min, float alpha_max, void *ws, size_t ws_bytes, float *image,
+                                        float *aux, void *stream) {
+    MGS_REQUIRE(w_bg >= 0.0f && w_bg < INFINITY, "w_bg must be finite and >= 0");
+    return mgs::blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, w_bg, alpha_min,
+                                   alpha_max, ws, ws_bytes, image, aux, stream);
 }

@@ -83,16 +83,35 @@ __device__ __forceinline__ void quad_poly(float4 r0, float4 r1, float xc, float 
     qb.y = fmaf(kA * beta, beta, kG);
 }
 
-// Eq. 2 composite of one pixel from its sums: C = (1 - T) N / D + T c_bg (c_bg if D = 0);
-// aux (if non-NULL) receives (N/D rgb, D, T).
+// Background weight that selects Eq. 2's composite (any w_bg >= 0 selects Eq. 1's).
+constexpr float EQ2_COMPOSITE = -1.0f;
+
+// Composite of one pixel from its sums.  Eq. 2 (wbg < 0): C = (1 - T) N / D + T c_bg (c_bg if
+// D = 0).  Eq. 1 (wbg >= 0): C = (c_bg wbg + N) / (wbg + D) (c_bg if wbg + D = 0).
+// aux (if non-NULL) receives (N/D rgb, D, T) in both cases.
 __device__ __forceinline__ void composite_oit(float Nr, float Ng, float Nb, float D, float T, int px, int py, int W,
-                                              int H, float bgr, float bgg, float bgb, float *__restrict__ image,
-                                              float *__restrict__ aux) {
+                                              int H, float bgr, float bgg, float bgb, float wbg,
+                                              float *__restrict__ image, float *__restrict__ aux) {
     if (px >= W || py >= H) return;
     const size_t hw = size_t(W) * H;
     const size_t p = size_t(py) * W + px;
     float cr, cg, cb;
-    if (D > 0.f) {
+    if (wbg >= 0.f) {
+        const float den = wbg + D;
+        if (den > 0.f) {
+            const float inv = 1.0f / den;
+            cr = fmaf(wbg, bgr, Nr) * inv;
+            cg = fmaf(wbg, bgg, Ng) * inv;
+            cb = fmaf(wbg, bgb, Nb) * inv;
+        } else {
+            cr = bgr; cg = bgg; cb = bgb;
+        }
+        if (aux) {
+            const float inv = D > 0.f ? 1.0f / D : 0.0f;
+            aux[p] = Nr * inv; aux[hw + p] = Ng * inv; aux[2 * hw + p] = Nb * inv;
+            aux[3 * hw + p] = D; aux[4 * hw + p] = T;
+        }
+    } else if (D > 0.f) {
         const float inv = 1.0f / D;
         const float fr = Nr * inv, fg = Ng * inv, fb = Nb * inv;
         const float f = 1.0f - T;
@@ -234,13 +253,14 @@ constexpr float OIT_CLAMP_MARGIN = 1e-2f;
 // rounding because the composite does not depend on the order of the Gaussians.
 //
 // The result goes to thread k's pixel tile_pixel(k) (quadrant k / 64, lane k % 64): the
-// composite into image / aux of a W x H view, or, if part is non-NULL, the sums
+// composite (Eq. 2, or Eq. 1 for wbg >= 0) into image / aux of a W x H view, or, if part is
+// non-NULL, the sums
 // (N rgb, D, T) to part[5][256] for a later merge with the tile's other ranges.
 constexpr int OIT_BATCH = 256;                  // list positions staged per pass by the four waves
 
 __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat, const uint32_t *__restrict__ gids,
                                                uint32_t start, uint32_t end, int tx, int ty, int W, int H, float bgr,
-                                               float bgg, float bgb, float log2_amin, float amax,
+                                               float bgg, float bgb, float wbg, float log2_amin, float amax,
                                                float *__restrict__ image, float *__restrict__ aux,
                                                float *__restrict__ part) {
     // wave w's staged Gaussian j: (c0, cx, cy, cxx), (cxy, cyy, -, -), (w r, w g, w b, w) at
@@ -403,7 +423,7 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
     } else {
         int px, py;
         tile_pixel(threadIdx.x, tx, ty, px, py);
-        composite_oit(S[0], S[1], S[2], S[3], S[4], px, py, W, H, bgr, bgg, bgb, image, aux);
+        composite_oit(S[0], S[1], S[2], S[3], S[4], px, py, W, H, bgr, bgg, bgb, wbg, image, aux);
     }
 }
 

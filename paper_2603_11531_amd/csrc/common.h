@@ -39,7 +39,7 @@ struct CamK {
     float near_z;
     float campos[3];   // t_v = -R^T t
     int tiles_x, tiles_y;
-    int weight_mode;   // MGS_WEIGHT_*: Eq. 3 or one of its ablations
+    int weight_mode;   // MGS_WEIGHT_*: Eq. 3, one of its ablations, or Eq. 1's weight
 };
 
 inline bool valid_weight_mode(int m) {

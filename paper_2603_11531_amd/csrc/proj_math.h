@@ -17,6 +17,7 @@ struct GaussIn {
     float mu[3], ls[3], q[4], logit, sh[12];
     float phi, om;
     float cext[3];            // SH terms above first order, added before the colour clamp (0 for SH1)
+    float wsig = 0.0f, wbeta = 1.0f;   // sigma_i, beta_i of the Eq. 1 weight (MGS_WEIGHT_SORTFREE only)
 };
 
 struct GaussFwd {
@@ -103,13 +104,18 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
     if (f.s[1] > f.smax) { f.smax = f.s[1]; f.kmax = 1; }
     if (f.s[2] > f.smax) { f.smax = f.s[2]; f.kmax = 2; }
     f.phi = in.phi;
-    // Eq. 3, or its ablations without the depth (d = 1) or without the scale term
+    // Eq. 3, its ablations without the depth (d = 1) or without the scale term, or Eq. 1
     if (cam.weight_mode == MGS_WEIGHT_NO_DEPTH) {
         f.esd = expf(f.smax);
         f.w = in.phi * in.phi + in.phi + f.esd;
     } else if (cam.weight_mode == MGS_WEIGHT_NO_SCALE) {
         f.esd = 0.0f;
         f.w = in.phi * in.phi + in.phi / (f.z * f.z);
+    } else if (cam.weight_mode == MGS_WEIGHT_SORTFREE) {
+        // Eq. 1's weighting function w(d) = exp(-sigma d^beta); d > near_z > 0 for every
+        // Gaussian that reaches the blend (culled ones use z = 1)
+        f.esd = 0.0f;
+        f.w = expf(-in.wsig * powf(f.z, in.wbeta));
     } else {
         f.esd = expf(f.smax / f.z);
         f.w = in.phi * in.phi + in.phi / (f.z * f.z) + f.esd;

@@ -15,14 +15,20 @@
 
 namespace mgs {
 
+// sig_in / beta_in: the Eq. 1 weight's sigma_i, beta_i (read only for MGS_WEIGHT_SORTFREE).
 __global__ void __launch_bounds__(256)
 project_kernel(mgs_gaussians g, CamK cam, const float *__restrict__ phi_in,
-               const float *__restrict__ omod_in, float alpha_min,
+               const float *__restrict__ omod_in, const float *__restrict__ sig_in,
+               const float *__restrict__ beta_in, float alpha_min,
                float4 *__restrict__ splat, uint2 *__restrict__ rect_out,
                uint32_t *__restrict__ ntiles_out) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
-    const GaussIn in = load_gauss(g, i, phi_in, omod_in);
+    GaussIn in = load_gauss(g, i, phi_in, omod_in);
+    if (cam.weight_mode == MGS_WEIGHT_SORTFREE) {
+        in.wsig = sig_in[i];
+        in.wbeta = beta_in[i];
+    }
     store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);
 }
 
@@ -32,6 +38,18 @@ struct SoaSource {
     mgs_gaussians g;
     __device__ __forceinline__ int64_t count() const { return g.n; }
     __device__ __forceinline__ GaussIn load(int64_t i) const { return load_gauss(g, i, nullptr, nullptr); }
+};
+// Float32 SoA planes plus the per-Gaussian sigma_i, beta_i of the Eq. 1 weight.
+struct SoaSortfreeSource {
+    mgs_gaussians g;
+    const float *sigma, *beta;
+    __device__ __forceinline__ int64_t count() const { return g.n; }
+    __device__ __forceinline__ GaussIn load(int64_t i) const {
+        GaussIn in = load_gauss(g, i, nullptr, nullptr);
+        in.wsig = sigma[i];
+        in.wbeta = beta[i];
+        return in;
+    }
 };
 struct NvqSource {
     int64_t n;
@@ -275,9 +293,58 @@ extern "C" int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *ca
     k.weight_mode = weight_mode;
     const unsigned blocks = unsigned((g->n + 255) / 256);
     hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, as_stream(stream), *g, k, phi, omod,
-                       alpha_min, reinterpret_cast<float4 *>(out->splat),
-                       reinterpret_cast<uint2 *>(out->rect), out->n_tiles);
+                       static_cast<const float *>(nullptr), static_cast<const float *>(nullptr), alpha_min,
+                       reinterpret_cast<float4 *>(out->splat), reinterpret_cast<uint2 *>(out->rect), out->n_tiles);
     MGS_LAUNCH_CHECK("project_kernel");
+    return MGS_OK;
+}
+
+extern "C" int mgs_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const float *omod,
+                                    const float *sigma, const float *beta, int tile, float alpha_min,
+                                    mgs_projected *out, void *stream) {
+    using namespace mgs;
+    int rc;
+    if ((rc = check_gaussians(g)) != MGS_OK) return rc;
+    if ((rc = check_camera(cam)) != MGS_OK) return rc;
+    if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
+    if (tile != MGS_TILE) return set_error(MGS_ERR_UNSUPPORTED, "tile must be %d", MGS_TILE);
+    MGS_REQUIRE(alpha_min > 0.0f && alpha_min < 1.0f, "alpha_min must be in (0, 1)");
+    if (g->n == 0) return MGS_OK;
+    MGS_REQUIRE(sigma && beta, "sigma / beta is NULL");
+    CamK k = make_camk(cam);
+    k.weight_mode = MGS_WEIGHT_SORTFREE;
+    const unsigned blocks = unsigned((g->n + 255) / 256);
+    hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, as_stream(stream), *g, k,
+                       static_cast<const float *>(nullptr), omod, sigma, beta, alpha_min,
+                       reinterpret_cast<float4 *>(out->splat), reinterpret_cast<uint2 *>(out->rect), out->n_tiles);
+    MGS_LAUNCH_CHECK("project_kernel<sortfree>");
+    return MGS_OK;
+}
+
+extern "C" int mgs_enhance_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp,
+                                            const float *sigma, const float *beta, int tile, float alpha_min,
+                                            mgs_projected *out, float *phi, float *omod, void *stream) {
+    using namespace mgs;
+    int rc;
+    if ((rc = check_gaussians(g)) != MGS_OK) return rc;
+    if ((rc = check_camera(cam)) != MGS_OK) return rc;
+    if ((rc = check_projected(out, g->n)) != MGS_OK) return rc;
+    if (tile != MGS_TILE) return set_error(MGS_ERR_UNSUPPORTED, "tile must be %d", MGS_TILE);
+    MGS_REQUIRE(alpha_min > 0.0f && alpha_min < 1.0f, "alpha_min must be in (0, 1)");
+    MGS_REQUIRE(packed_mlp && aligned(packed_mlp, 16), "packed MLP must be non-NULL and 16-byte aligned");
+    if (g->n == 0) return MGS_OK;
+    MGS_REQUIRE(phi && omod, "phi / omod is NULL");
+    MGS_REQUIRE(sigma && beta, "sigma / beta is NULL");
+    CamK k = make_camk(cam);
+    k.weight_mode = MGS_WEIGHT_SORTFREE;
+    const int64_t groups = (g->n + 63) / 64;
+    int64_t blocks = (groups + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(enhance_project_kernel<SoaSortfreeSource>, dim3(unsigned(blocks)), dim3(256), 0,
+                       as_stream(stream), SoaSortfreeSource{*g, sigma, beta}, k,
+                       static_cast<const uint8_t *>(packed_mlp), alpha_min, reinterpret_cast<float4 *>(out->splat),
+                       reinterpret_cast<uint2 *>(out->rect), out->n_tiles, phi, omod);
+    MGS_LAUNCH_CHECK("enhance_project_kernel<sortfree>");
     return MGS_OK;
 }
 

@@ -211,6 +211,23 @@ class Renderer:
                 L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed), L.MGS_TILE, alpha_min,
                 int(weight_mode), L.C.byref(self.proj), L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
 
+    def project_sortfree(self, scene: DeviceScene, cam_s, sigma, beta, mlp=None, alpha_min=ALPHA_MIN, stream=None,
+                         fused=True):
+        """Projection with Eq. 1's weight exp(-sigma d^beta) (sigma, beta: device float32 [N]);
+        with ``mlp`` its opacity head modulates o (the fused enhance + project, or with
+        ``fused=False`` mgs_enhance followed by mgs_project_sortfree)."""
+        if mlp is None or not fused:
+            if mlp is not None:
+                self.enhance(scene, cam_s, mlp, stream)
+            L.check(L.lib().mgs_project_sortfree(L.C.byref(scene.struct), L.C.byref(cam_s),
+                                                 L.ptr(self.omod) if mlp is not None else None, L.ptr(sigma),
+                                                 L.ptr(beta), L.MGS_TILE, alpha_min, L.C.byref(self.proj),
+                                                 L.stream_ptr(stream)))
+        else:
+            L.check(L.lib().mgs_enhance_project_sortfree(
+                L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed), L.ptr(sigma), L.ptr(beta), L.MGS_TILE,
+                alpha_min, L.C.byref(self.proj), L.ptr(self.phi), L.ptr(self.omod), L.stream_ptr(stream)))
+
     def enhance_project_mlp_f(self, scene: DeviceScene, cam_s, mlp: DeviceMLPF, alpha_min=ALPHA_MIN, stream=None):
         """Fused MLP_f (256-128-64) enhancement + projection; also fills phi / omod."""
         L.check(L.lib().mgs_enhance_project_mlp_f(L.C.byref(scene.struct), L.C.byref(cam_s), L.ptr(mlp.packed),
@@ -233,10 +250,23 @@ class Renderer:
                    L.stream_ptr(stream)))
 
     def blend_oit(self, cam_s, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, want_aux=False,
-                  stream=None, split=True):
-        """Eq. 2 composite; ``split`` (default) uses the split-tile blend that balances dense tiles."""
+                  stream=None, split=True, w_bg=None):
+        """Eq. 2 composite (Eq. 1's with a background weight ``w_bg``); ``split`` (default) uses the
+        split-tile blend that balances dense tiles."""
         if want_aux and self.aux is None:
             self.aux = torch.empty(5, self.H, self.W, dtype=torch.float32, device=self.device)
+        if w_bg is not None:
+            aux = L.ptr(self.aux) if want_aux else None
+            if split:
+                L.check(L.lib().mgs_blend_sortfree_split(
+                    L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids), L.ptr(self.n_pairs),
+                    self.capacity, L.C.byref(cam_s), L.MGS_TILE, L.bg_array(bg), float(w_bg), alpha_min, alpha_max,
+                    L.ptr(self.ws_split), self.ws_split.numel() * 4, L.ptr(self.image), aux, L.stream_ptr(stream)))
+            else:
+                L.check(L.lib().mgs_blend_sortfree(
+                    L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids), L.C.byref(cam_s), L.MGS_TILE,
+                    L.bg_array(bg), float(w_bg), alpha_min, alpha_max, L.ptr(self.image), aux, L.stream_ptr(stream)))
+            return
         if split:
             L.check(L.lib().mgs_blend_oit_split(
                 L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids), L.ptr(self.n_pairs), self.capacity,
@@ -260,13 +290,21 @@ class Renderer:
 
     # -- whole pass -----------------------------------------------------------
     def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
-               check_capacity=True, stream=None, fused=False, split=True, weight_mode=L.MGS_WEIGHT_EQ3):
+               check_capacity=True, stream=None, fused=False, split=True, weight_mode=L.MGS_WEIGHT_EQ3,
+               sortfree=None, w_bg=None):
         """enhance -> project -> bin -> blend (``scene`` a DeviceScene, or a DeviceNVQ whose
         attributes are read through its codebooks).  With check_capacity the host reads the
         pair count once and re-bins with a larger capacity on overflow.  ``weight_mode``
-        selects Eq. 3 or one of its ablations (MGS_WEIGHT_*)."""
+        selects Eq. 3 or one of its ablations (MGS_WEIGHT_*); ``sortfree`` = (sigma, beta)
+        device arrays with ``w_bg`` selects Eq. 1 (SortFreeGS weight and composite)."""
         cam_s = L.make_camera(cam)
-        if isinstance(scene, DeviceNVQ):
+        if (sortfree is None) != (w_bg is None):
+            raise ValueError("Eq. 1 needs both sortfree=(sigma, beta) and w_bg")
+        if sortfree is not None:
+            if sorted_path or not isinstance(scene, DeviceScene) or scene.sh_degree != 1 or isinstance(mlp, DeviceMLPF):
+                raise ValueError("Eq. 1 renders float32 first-order-SH scenes on the order-independent path")
+            self.project_sortfree(scene, cam_s, sortfree[0], sortfree[1], mlp=mlp, stream=stream, fused=fused)
+        elif isinstance(scene, DeviceNVQ):
             if mlp is None:
                 raise ValueError("a vector-quantised scene renders through the fused enhance + project (needs an MLP)")
             if weight_mode != L.MGS_WEIGHT_EQ3:
@@ -293,7 +331,7 @@ class Renderer:
         if sorted_path:
             self.blend_sorted(cam_s, bg, stream=stream)
         else:
-            self.blend_oit(cam_s, bg, want_aux=want_aux, stream=stream, split=split)
+            self.blend_oit(cam_s, bg, want_aux=want_aux, stream=stream, split=split, w_bg=w_bg)
         return self.image
 
     # -- views for tests ---------------------------------------------------------

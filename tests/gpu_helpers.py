@@ -19,16 +19,48 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_project(scene, cam, mlp=None, bf16=False, tile=16, weight_mode=O.WEIGHT_EQ3):
+def oracle_project(scene, cam, mlp=None, bf16=False, tile=16, weight_mode=O.WEIGHT_EQ3, sortfree=None):
+    """The oracle's projection of a scene; ``sortfree`` = (sigma, beta) selects Eq. 1's weight."""
     camt = O.camera_tensors(cam)
     p = O.scene_params(scene)
     phi = m = None
-    if mlp is not None:
-        act = O.activate(p)
-        _, _, P = O.camera_space(p["mean"], camt)
-        phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp), bf16=bf16)
     with torch.no_grad():
-        return O.project(p, camt, phi, m, tile, weight_mode), camt
+        if mlp is not None:
+            act = O.activate(p)
+            _, _, P = O.camera_space(p["mean"], camt)
+            phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp), bf16=bf16)
+        if sortfree is not None:
+            weight_mode = O.WEIGHT_SORTFREE
+            sortfree = tuple(O.to64(np.asarray(v)) for v in sortfree)
+        return O.project(p, camt, phi, m, tile, weight_mode, sortfree), camt
+
+
+def rect_mismatches(decoded, pr, tol_px=1e-3):
+    """Gaussians whose GPU tile rect or visibility differs from the oracle's, and the subset of
+    them NOT explained by an edge case float32 may decide either way: a support edge
+    m +- e - 1/2 within tol_px plus the Gaussian's screen-position error bound of a pixel-centre
+    boundary, an effective opacity within the ambiguity band of alpha_min, or a depth at the near
+    plane.  Returns (differing indices, unexplained indices)."""
+    vis_o = pr["visible"].numpy()
+    vis_g = np.asarray(decoded["n_tiles"]) > 0
+    both = vis_o & vis_g
+    diff = np.nonzero((vis_o != vis_g) | (np.any(np.asarray(decoded["rect"]) != pr["rect"].numpy(), axis=1) & both))[0]
+    cov = pr["cov2d"].detach().numpy()
+    o = pr["o_eff"].detach().numpy()
+    m2 = pr["mean2d"].detach().numpy()
+    pos = pr["pos_err"].numpy()
+    dep = pr["depth"].detach().numpy()
+    bad = []
+    for g in diff:
+        k = 2.0 * np.log(max(o[g], O.ALPHA_MIN) / O.ALPHA_MIN)
+        ex, ey = np.sqrt(k * cov[g, 0, 0]), np.sqrt(k * cov[g, 1, 1])
+        edges = np.array([m2[g, 0] - ex - 0.5, m2[g, 0] + ex - 0.5, m2[g, 1] - ey - 0.5, m2[g, 1] + ey - 0.5])
+        gap = float(np.abs(edges - np.round(edges)).min())
+        opacity_at_cut = abs(np.log(max(o[g], 1e-300) / O.ALPHA_MIN)) < O.AMBIG_LOG
+        near_plane = abs(dep[g] - 0.2) < 1e-6
+        if not (gap < tol_px + pos[g] or opacity_at_cut or near_plane):
+            bad.append(int(g))
+    return diff, np.asarray(bad, np.int64)
 
 
 def compare_oit_image(gpu_img, variants, flagged, tol):

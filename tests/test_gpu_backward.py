@@ -1,9 +1,13 @@
 """Backward pass (mgs_render_backward via torch.autograd) against the oracle's FP64
 autograd gradient and against finite differences of the GPU forward.
 
-Bar: per parameter tensor ||g - g*||_2 / ||g*||_2 <= 1e-3 against the oracle,
-with the MLP's gradient taken straight through the forward's bfloat16 roundings
-on both sides (the oracle runs its BF16-emulation forward).
+Bar: per parameter tensor, and per MLP layer (W1, b1, W2, b2, w_phi, b_phi, w_o, b_o each on
+its own), ||g - g*||_2 / ||g*||_2 <= 1e-3 against the oracle; elementwise, every entry with
+|g*| > 1e-3 max|g*| of its tensor within 1e-3 |g*| (plus 1e-6 max|g*| for rounding of
+cancelling sums; 1e-5 max|g*| on dense scenes with the MLP, where the few Gaussians whose bf16
+roundings flipped change the pixel sums their neighbours' gradients read).  The MLP's gradient
+is taken straight through the forward's bfloat16 roundings on both sides (the oracle runs its
+BF16-emulation forward).
 """
 import numpy as np
 import pytest
@@ -11,7 +15,7 @@ import torch
 
 import mgs_data
 import oracle as O
-from gpu_helpers import say
+from gpu_helpers import oracle_project, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +55,7 @@ def gpu_grads(M, scene, cam, mlp, r, bg):
     return out, img.detach().double().cpu()
 
 
-def oracle_grads(M, scene, cam, mlp, r, bg, bf16=True):
+def oracle_grads(M, scene, cam, mlp, r, bg, bf16=True, mode="brute"):
     camt = O.camera_tensors(cam)
     p = O.scene_params(scene, requires_grad=True)
     mp = O.mlp_params(mlp, requires_grad=True) if mlp is not None else None
@@ -61,7 +65,7 @@ def oracle_grads(M, scene, cam, mlp, r, bg, bf16=True):
         _, _, P = O.camera_space(p["mean"], camt)
         phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), mp, bf16=bf16)
     pr = O.project(p, camt, phi, m)
-    img, _ = O.render_oit(pr, camt, np.asarray(bg))
+    img, _ = O.render_oit(pr, camt, np.asarray(bg), mode=mode)
     (img * torch.as_tensor(r, dtype=torch.float64)).sum().backward()
     n = scene["mean"].shape[1]
     out = {"mean": p["mean"].grad.numpy().T, "log_scale": p["log_scale"].grad.numpy().T,
@@ -80,14 +84,60 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def _report(M, g, go):
-    for k in go:
-        say(f"  {k}: rel {_rel(g[k], go[k]):.2e}")
-    if "mlp" in go:
+def _parts(M, g):
+    """Gradient tensors to check one by one: the five attribute tensors and each MLP layer."""
+    out = {k: g[k] for k in KEYS}
+    if "mlp" in g:
         for name, off, shape in M._lib.MLP_LAYOUT:
             sz = int(np.prod(shape)) if shape else 1
-            a, b = g["mlp"][off:off + sz], go["mlp"][off:off + sz]
-            say(f"    mlp.{name}: rel {_rel(a, b):.2e} |g*| {np.linalg.norm(b):.3e}")
+            out["mlp." + name] = g["mlp"][off:off + sz]
+    return out
+
+
+def mlp_flipped(M, scene, cam, mlp):
+    """Gaussians whose float32 MLP outputs (phi, m) differ from the oracle's BF16 emulation by more
+    than float32 rounding: a bf16 rounding of an input or hidden value fell the other way, so
+    their forward, and with it their gradient, differs from the emulation's."""
+    ds, dm = M.DeviceScene(scene), M.DeviceMLP(mlp)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    R.enhance(ds, M._lib.make_camera(cam), dm)
+    torch.cuda.synchronize()
+    camt = O.camera_tensors(cam)
+    p = O.scene_params(scene)
+    with torch.no_grad():
+        act = O.activate(p)
+        _, _, P = O.camera_space(p["mean"], camt)
+        phi, m = O.enhance(O.mlp_features(P, act["s"], act["q"], p["sh"]), O.mlp_params(mlp), bf16=True)
+    dphi = (R.phi.double().cpu() - phi).abs().numpy()
+    dm_ = (R.omod.double().cpu() - m).abs().numpy()
+    return (dphi > 1e-5 * (1 + np.abs(phi.numpy()))) | (dm_ > 1e-6)
+
+
+def _check(M, g, go, skip=None, atol=1e-6):
+    """The bar of this module for every tensor and MLP layer; prints each figure.  ``skip``: a
+    mask of Gaussians left out of the elementwise bar (their forward differs, see mlp_flipped);
+    the L2 bar covers every entry."""
+    a, b = _parts(M, g), _parts(M, go)
+    worst = {}
+    for k in b:
+        e = _rel(a[k], b[k])
+        gm = float(np.abs(b[k]).max())
+        big = np.abs(b[k]) > 1e-3 * gm
+        if skip is not None and not k.startswith("mlp."):
+            big &= ~np.broadcast_to(skip, b[k].shape)
+        d = np.abs(a[k] - b[k])
+        over = (d > 1e-3 * np.abs(b[k]) + atol * gm) & big
+        rel_e = np.where(big, d / np.maximum(np.abs(b[k]), 1e-300), 0.0)
+        say(f"  {k}: rel L2 {e:.2e}, elementwise worst {float(rel_e.max()):.2e} over bar {int(over.sum())} of "
+            f"{int(big.sum())}")
+        for flat in np.argsort(rel_e.reshape(-1))[::-1][:3] if over.any() else []:
+            ix = np.unravel_index(flat, b[k].shape)
+            say(f"    entry {tuple(int(v) for v in ix)}: |g*|/max {abs(b[k][ix]) / gm:.2e} "
+                f"|g-g*|/max {d[ix] / gm:.2e} rel {rel_e[ix]:.2e}")
+        assert e <= REL, (k, e)
+        assert int(over.sum()) == 0, (k, int(over.sum()))
+        worst[k] = e
+    return worst
 
 
 @pytest.mark.parametrize("with_mlp", [False, True])
@@ -101,10 +151,7 @@ def test_grads_match_oracle_tiny(M, with_mlp):
     bg = (0.2, 0.4, 0.1)
     g, img = gpu_grads(M, scene, cam, mlp, r, bg)
     go, imgo = oracle_grads(M, scene, cam, mlp, r, bg)
-    _report(M, g, go)
-    for k in go:
-        e = _rel(g[k], go[k])
-        assert e <= REL, (k, e)
+    _check(M, g, go)
 
 
 @pytest.mark.parametrize("with_mlp", [False, True])
@@ -117,10 +164,42 @@ def test_grads_match_oracle_small_workload(M, with_mlp):
     bg = (0.0, 0.0, 0.0)
     g, _ = gpu_grads(M, scene, cams[0], mlp, r, bg)
     go, _ = oracle_grads(M, scene, cams[0], mlp, r, bg)
-    _report(M, g, go)
-    for k in go:
-        e = _rel(g[k], go[k])
-        assert e <= REL, (k, e)
+    _check(M, g, go)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("with_mlp", [False, True])
+def test_grads_match_oracle_dense_tiles(M, with_mlp):
+    """40,000 Gaussians filling a 96x96 view: every tile list holds 1,800-3,500 Gaussians (the
+    training workload's density), so the backward walks many 256-Gaussian chunks per tile."""
+    say(f"test_grads_match_oracle_dense_tiles mlp={with_mlp}")
+    scene = mgs_data.make_scene_uniform(40000, 31, half=2.2, ls_mu=-2.5)
+    cam = mgs_data.look_at((0.1, -0.1, -4.0), width=96, height=96, f=96.0)
+    mlp = mgs_data.make_mlp(32) if with_mlp else None
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    R.render(ds, cam)
+    offs, _ = R.lists()
+    lens = (offs[1:] - offs[:-1])
+    say(f"  tile lists: min {int(lens.min())} max {int(lens.max())}")
+    assert int(lens.min()) > 1000
+    rng = np.random.default_rng(6)
+    r = rng.normal(size=(3, 96, 96))
+    bg = (0.1, 0.3, 0.2)
+    g, _ = gpu_grads(M, scene, cam, mlp, r, bg)
+    go, _ = oracle_grads(M, scene, cam, mlp, r, bg, mode="binned")
+    # A Gaussian with a pixel pair at the alpha_min cut (or the alpha_max clamp) that float32
+    # may place on either side has two admissible gradients (the pair's term in or out); with
+    # the MLP, one whose bf16 roundings flipped has a different forward.  Both are left out of
+    # the elementwise bar (the L2 bar covers them).
+    pr, camt = oracle_project(scene, cam, mlp=mlp, bf16=True)
+    skip = O.ambiguous_gaussians(pr, camt).numpy()
+    say(f"  Gaussians with a pair at a cut: {int(skip.sum())} of {skip.size}")
+    if with_mlp:
+        fl = mlp_flipped(M, scene, cam, mlp)
+        say(f"  Gaussians with a flipped bf16 rounding: {int(fl.sum())}")
+        skip = skip | fl
+    _check(M, g, go, skip, atol=1e-5 if with_mlp else 1e-6)
 
 
 def test_grads_match_finite_differences_of_gpu_forward(M):

@@ -13,7 +13,7 @@ import torch
 
 import mgs_data
 import oracle as O
-from gpu_helpers import (compare_oit_image, oracle_project, psnr, sampled_pixel_check, say,
+from gpu_helpers import (compare_oit_image, oracle_project, psnr, rect_mismatches, sampled_pixel_check, say,
                          upload_projected_from_oracle)
 
 pytestmark = pytest.mark.gpu
@@ -63,8 +63,11 @@ def test_project_matches_oracle_small(M):
     assert rel(d["A"][both], (c / det)[both]).max() < 1e-5
     assert np.abs(d["beta"][both] - (-b / c)[both]).max() < 1e-5
     assert rel(d["inv_c"][both], (1.0 / c)[both]).max() < 1e-5
-    # visibility and rects agree except for splats whose support edge sits on a pixel-centre boundary
-    diff = np.nonzero((vis_o != vis_g) | (np.any(d["rect"] != pr["rect"].numpy(), axis=1) & both))[0]
+    # visibility and rects agree except for splats whose support edge sits within 1e-3 px of a
+    # pixel-centre boundary (the float32 extent may round to either side of it)
+    diff, bad = rect_mismatches(d, pr)
+    say(f"  rect / visibility differences {len(diff)}, unexplained {len(bad)}")
+    assert len(bad) == 0, bad
     assert len(diff) <= 2, diff
 
 

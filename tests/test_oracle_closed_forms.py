@@ -233,7 +233,7 @@ def _handmade(cam, g):
     t = lambda v: torch.tensor(v, dtype=torch.float64)
     return dict(mean2d=t([x["m"] for x in g]), conic=t([[40.0, 0.0, 40.0]] * n), o_eff=t([x["o"] for x in g]),
                 color=t([x["c"] for x in g]), w=t([x["w"] for x in g]), depth=t([x.get("d", 1.0) for x in g]),
-                visible=torch.ones(n, dtype=torch.bool))
+                depth_mag=t([abs(x.get("d", 1.0)) for x in g]), visible=torch.ones(n, dtype=torch.bool))
 
 
 def test_ambiguity_variants_are_exactly_the_admissible_images():
@@ -364,22 +364,108 @@ def test_bin_lists_sorted_equals_bruteforce_depth_order():
 
 
 def test_sorted_flags_mark_exactly_the_fragile_pixels():
-    """render_sorted's flags: a near depth tie, a transmittance within 0.1% of the stop value,
-    or an ambiguous alpha cut each flag their pixel; a clean pixel is not flagged."""
+    """render_sorted's flags: a depth tie below the float32 key's error bound (8 x 2^-24 x the
+    depth's magnitude per key), a transmittance within 0.1% of the stop value, or an
+    ambiguous alpha cut each flag their pixel; a clean pixel, a gap just above the bound and a
+    tie behind the stop are not flagged."""
     amin = 1 / 255
-    cam = dict(W=4, H=1)
+    cam = dict(W=6, H=1)
     a_stop = 1.0 - 1e-4 * (1 + 2e-4)           # T before the next pair = 1e-4 (1 + 2e-4)
+    bound = 8 * 2.0 ** -24 * (2.0 + 2.0)        # tie bound of two keys at depth 2
     gs = [dict(m=[0.5, 0.5], o=0.6, c=[1, 0, 0], w=1.0, d=2.0),              # pixel 0: clean
           dict(m=[0.5, 0.5], o=0.3, c=[0, 1, 0], w=1.0, d=3.0),
           dict(m=[1.5, 0.5], o=0.6, c=[1, 0, 0], w=1.0, d=2.0),              # pixel 1: depth tie
-          dict(m=[1.5, 0.5], o=0.3, c=[0, 1, 0], w=1.0, d=2.0 * (1 + 5e-7)),
+          dict(m=[1.5, 0.5], o=0.3, c=[0, 1, 0], w=1.0, d=2.0 + 0.5 * bound),
           dict(m=[2.5, 0.5], o=a_stop, c=[1, 0, 0], w=1.0, d=2.0),           # pixel 2: near stop
           dict(m=[2.5, 0.5], o=0.5, c=[0, 0, 1], w=1.0, d=4.0),
           dict(m=[3.5, 0.5], o=amin * (1 + 1e-5), c=[1, 1, 0], w=1.0, d=2.0),  # pixel 3: ambiguous
-          dict(m=[3.5, 0.5], o=0.2, c=[0, 1, 1], w=1.0, d=3.0)]
+          dict(m=[3.5, 0.5], o=0.2, c=[0, 1, 1], w=1.0, d=3.0),
+          dict(m=[4.5, 0.5], o=0.6, c=[1, 0, 0], w=1.0, d=2.0),              # pixel 4: gap > bound
+          dict(m=[4.5, 0.5], o=0.3, c=[0, 1, 0], w=1.0, d=2.0 + 1.5 * bound),
+          dict(m=[5.5, 0.5], o=0.999, c=[1, 0, 0], w=1.0, d=1.0),            # pixel 5: stop, then a tie
+          dict(m=[5.5, 0.5], o=0.99, c=[0, 1, 0], w=1.0, d=1.5),
+          dict(m=[5.5, 0.5], o=0.5, c=[0, 0, 1], w=1.0, d=2.0),
+          dict(m=[5.5, 0.5], o=0.5, c=[1, 1, 1], w=1.0, d=2.0)]
     pr = _handmade(cam, gs)
     img, flags = O.render_sorted(pr, cam, np.zeros(3), alpha_max=0.9999, return_flags=True)
-    assert flags[0].tolist() == [False, True, True, True]
+    assert flags[0].tolist() == [False, True, True, True, False, False]
     # the clean pixel's value: front-to-back by hand
     ref0 = 0.6 * np.array([1, 0, 0]) + 0.4 * 0.3 * np.array([0, 1, 0])
     assert np.abs(img[:, 0, 0].numpy() - ref0).max() < 1e-15
+    # pixel 5 stops after two layers (T = 1e-5 < 1e-4)
+    ref5 = 0.999 * np.array([1, 0, 0]) + 0.001 * 0.99 * np.array([0, 1, 0])
+    assert np.abs(img[:, 0, 5].numpy() - ref5).max() < 1e-15
+
+
+def test_sorted_binned_equals_bruteforce():
+    """The per-tile sorted mode (each tile's list in (depth, index) order) gives the brute-force
+    image and flags: a Gaussian outside a tile's list never reaches alpha_min there."""
+    sc = mgs_data.make_scene_uniform(150, seed=17, half=0.9, ls_mu=-2.5)
+    cam = O.camera_tensors(mgs_data.look_at((0.2, 0.1, -3.3), width=57, height=41, f=50.0))
+    pr = O.project(O.scene_params(sc), cam)
+    bg = np.array([0.3, 0.2, 0.6])
+    a, fa = O.render_sorted(pr, cam, bg, return_flags=True)
+    b, fb = O.render_sorted(pr, cam, bg, return_flags=True, mode="binned")
+    assert float((a - b).abs().max()) < 1e-13 and torch.equal(fa, fb)
+    assert float(a.std()) > 1e-3
+
+
+def test_ambiguity_band_widens_with_the_screen_position_error():
+    """A pair 6e-4 (in ln) below alpha_min, 0.1 px from its Gaussian's mean with conic 40 I:
+    ln a moves by |A dx|_1 = 4 per pixel of mean error, so a position error bound of 2e-4 px
+    makes it ambiguous (4 x 2e-4 + 1e-4 > 6e-4) and one of 1e-4 px does not."""
+    amin = 1 / 255
+    cam = dict(W=1, H=1)
+    q = 40.0 * 0.1 ** 2
+    o = amin * math.exp(-6e-4) * math.exp(0.5 * q)
+    gs = [dict(m=[0.5, 0.5], o=0.4, c=[0.9, 0.1, 0.2], w=1.3),
+          dict(m=[0.5, 0.5], o=o, c=[0.1, 0.8, 0.7], w=2.1)]
+    bg = np.array([0.2, 0.2, 0.2])
+    out_img = 0.4 * np.array([0.9, 0.1, 0.2]) + 0.6 * bg          # only the clear contributor
+    a2 = amin * math.exp(-6e-4)
+    num = 0.4 * 1.3 * np.array([0.9, 0.1, 0.2]) + a2 * 2.1 * np.array([0.1, 0.8, 0.7])
+    T = 0.6 * (1 - a2)
+    in_img = (1 - T) * num / (0.4 * 1.3 + a2 * 2.1) + T * bg
+    for axis, pos, ambiguous in ((0, 2e-4, True), (0, 1e-4, False), (0, 0.0, False), (1, 2e-4, True),
+                                 (1, 1e-4, False)):
+        pr = _handmade(cam, gs)
+        pr["mean2d"][1] = torch.tensor([0.5, 0.5], dtype=torch.float64)
+        pr["mean2d"][1, axis] = 0.6                         # offset along x, then along y
+        pr["pos_err"] = torch.tensor([0.0, pos], dtype=torch.float64)
+        img, _, V, flagged = O.render_oit(pr, cam, bg, variants=True)
+        assert np.abs(img[:, 0, 0].numpy() - out_img).max() < 1e-13
+        got = [V[v, :, 0, 0].numpy() for v in range(4)]
+        has_in = min(np.abs(gv - in_img).max() for gv in got) < 1e-13
+        assert has_in == ambiguous, (axis, pos)
+        _, flags = O.render_sorted(pr, cam, bg, return_flags=True)
+        assert bool(flags[0, 0]) == ambiguous
+
+
+def test_screen_position_error_bound_closed_form():
+    """pos_err = POS_ULPS 2^-24 max over the axes of f (|R_row| . |mu| + |t_row|) / d + |c|,
+    written out for an identity-rotation camera at (0, 0, -4)."""
+    W, H, f = 64, 48, 50.0
+    cam = _cam(W, H, f)
+    pts = [(0.3, -0.2, 0.5), (-1.1, 0.4, -0.7), (0.0, 0.0, 2.0)]
+    sc = _cat(*(_gauss(p, (-2.0,) * 3, 0.0) for p in pts))
+    pr = O.project(O.scene_params(sc), cam)
+    for g, (x, y, z) in enumerate(pts):
+        x, y, z = F32(x), F32(y), F32(z)
+        d = z + 4.0
+        ref = 4.0 * 2.0 ** -24 * max(f * abs(x) / d + W / 2, f * abs(y) / d + H / 2)
+        assert abs(float(pr["pos_err"][g]) - ref) < 1e-15 * (1 + ref), g
+
+
+def test_ambiguous_gaussians_marks_pairs_at_either_cut():
+    """A Gaussian with a pixel in the alpha_min band, one with a pixel in the alpha_max band and
+    clear ones (peaks well inside, supports away from the cut at every pixel centre)."""
+    amin, amax = 1 / 255, 0.99
+    cam = dict(W=4, H=1)
+    gs = [dict(m=[0.5, 0.5], o=0.5, c=[1, 0, 0], w=1.0),
+          dict(m=[1.5, 0.5], o=amin * (1 + 3e-5), c=[0, 1, 0], w=1.0),
+          dict(m=[2.5, 0.5], o=amax * (1 - 2e-5), c=[0, 0, 1], w=1.0),
+          dict(m=[3.5, 0.5], o=0.97, c=[1, 1, 0], w=1.0)]
+    pr = _handmade(cam, gs)
+    pr.update(rect=torch.tensor([[0, 0, 0, 0]] * 4), n_tiles=torch.ones(4, dtype=torch.int64), tiles_x=1,
+              tiles_y=1, tile=16)
+    assert O.ambiguous_gaussians(pr, cam).tolist() == [False, True, True, False]
