@@ -352,6 +352,27 @@ int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *tile_offsets,
                         float *image, float *aux, void *stream);
 
 /*
+ * mgs_blend_oit_split_noalloc -- mgs_blend_oit_split without a caller workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a library-owned static device array of
+ * MGS_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first use on that GPU until the
+ * process ends; the call itself allocates and frees nothing.  Every argument, rule and result
+ * is that of mgs_blend_oit_split (same kernels); the current device must be the device of
+ * `stream` and of the buffers.  The array's device address is looked up on the first call on
+ * each device (a host call, not an allocation).
+ * MGS_ERR_CAPACITY (nothing enqueued) when the split blend of this view and capacity needs more
+ * workspace than MGS_NOALLOC_SCRATCH_BYTES (mgs_blend_oit_split_workspace reports it; about
+ * 10 bytes per unit of capacity: 1600x1063 fits up to ~12.8 M pairs).
+ * Calls share their GPU's one array, which keeps the last call's contents: calls that overlap
+ * on one GPU (other streams, other host threads) race and must be serialised by the caller.
+ */
+#define MGS_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int mgs_blend_oit_split_noalloc(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                                const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
+                                const float bg[3], float alpha_min, float alpha_max, float *image, float *aux,
+                                void *stream);
+
+/*
  * mgs_blend_sortfree / mgs_blend_sortfree_split -- mgs_blend_oit / mgs_blend_oit_split with
  * the composite of Eq. 1 (Sec. 2) in place of Eq. 2's:  C = (bg w_bg + N) / (w_bg + D), with
  * N = sum alpha w c and D = sum alpha w over the same contributors (a >= alpha_min, alpha

@@ -18,6 +18,8 @@
 //
 // Sorted path: wave w owns quadrant w and walks the depth-ordered list front to
 // back with early termination (blend_tile_sorted).
+#include <mutex>
+
 #include "batch.h"
 #include "blend_math.h"
 
@@ -453,4 +455,63 @@ extern "C" int mgs_blend_sortfree_split(const mgs_projected *proj, const uint32_
     MGS_REQUIRE(w_bg >= 0.0f && w_bg < INFINITY, "w_bg must be finite and >= 0");
     return mgs::blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, w_bg, alpha_min,
                                    alpha_max, ws, ws_bytes, image, aux, stream);
+}
+
+// ---------------------------------------------------------------- no-allocation split blend
+// The split blend's workspace (work list, split-tile tables, per-range partial sums) lives in
+// this file-scope device array instead of a caller buffer.  Every GPU the library runs on holds
+// its own copy until the process ends.  Host code never passes the array's name to a kernel:
+// it is a host-side stand-in, not a device address; the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in scratch_dev[].
+namespace mgs {
+
+static __device__ __align__(256) uint8_t scratch[MGS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void *scratch_dev[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's scratch array (looked up on the first call per device).
+static int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(MGS_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_error(MGS_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[dev] == nullptr) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return set_error(MGS_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return MGS_OK;
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_blend_oit_split_noalloc(const mgs_projected *proj, const uint32_t *tile_offsets,
+                                           const uint32_t *gids, const uint32_t *n_pairs, uint64_t capacity,
+                                           const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
+                                           float alpha_max, float *image, float *aux, void *stream) {
+    using namespace mgs;
+    int rc;
+    // size checks first, so an oversized call is refused before anything touches the device
+    MGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "bad camera");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    const uint64_t tx = (uint64_t(cam->width) + MGS_TILE - 1) / MGS_TILE;
+    const uint64_t ty = (uint64_t(cam->height) + MGS_TILE - 1) / MGS_TILE;
+    MGS_REQUIRE(tx * ty < (uint64_t(1) << 24), "2^24 or more tiles");
+    const size_t need = blend_split_workspace(uint32_t(tx * ty), capacity);
+    if (need > size_t(MGS_NOALLOC_SCRATCH_BYTES))
+        return set_error(MGS_ERR_CAPACITY,
+                         "split-blend workspace of %zu bytes (%llu tiles, capacity %llu) exceeds the %zu-byte "
+                         "no-allocation scratch; use mgs_blend_oit_split with a caller workspace",
+                         need, (unsigned long long)(tx * ty), (unsigned long long)capacity,
+                         size_t(MGS_NOALLOC_SCRATCH_BYTES));
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws)) != MGS_OK) return rc;
+    return blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, EQ2_COMPOSITE, alpha_min,
+                              alpha_max, ws, size_t(MGS_NOALLOC_SCRATCH_BYTES), image, aux, stream);
 }
