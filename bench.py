@@ -25,7 +25,12 @@ if ROOT not in sys.path:
 # evaluation of Eq. 2 (conventional count, FMA = 2): offsets 2, exponent 8,
 # exp2 1, cut + clamp 2, alpha*w 1, N (3 FMA) 6, D 1, T (FMA) 2.
 BLEND_FLOP_PER_EVAL = 23
+# Published FP32 vector peak (256 CU x 2.4 GHz x 256 flop per CU per clock, the packed-FP32
+# rate).  The kernels are built without packed FP32, and a wave-wide FP32 FMA probe issues
+# ~1.4 instructions per CU per clock (~110 TFLOP/s): the rate this instruction stream can reach.
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+REACHABLE_UNPACKED_FP32_TFLOPS = 110.0
+BLEND_BYTES_PER_PAIR = 52          # 48-byte splat record + 4-byte Gaussian id per (tile, Gaussian) pair
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 
@@ -88,6 +93,25 @@ def _oracle_binned_sample(scene, cams, mlp, n_tiles_sample, seed=0):
     return t_pre, time.perf_counter() - t1, len(sample), len(nonempty), W, H
 
 
+def cpu_info():
+    """Host CPU as lscpu reports it (model, sockets x cores per socket x threads per core) and the
+    CPU share this process may run on (its affinity set)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = dict(line.split(":", 1) for line in out.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["model"] = kv.get("Model name")
+        if kv.get("Socket(s)", "").isdigit() and kv.get("Core(s) per socket", "").isdigit():
+            info["host_physical_cores"] = int(kv["Socket(s)"]) * int(kv["Core(s) per socket"])
+        info["host_logical_cpus"] = int(kv["CPU(s)"]) if kv.get("CPU(s)", "").isdigit() else None
+    except (OSError, subprocess.SubprocessError, ValueError):
+        info["model"] = None
+    info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
 def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
     """FP64 oracle on the host cores: full enhance + project + lists for one pose,
     OIT blend on a random sample of tiles, scaled to a whole frame."""
@@ -96,6 +120,7 @@ def cpu_baseline(scene, cams, mlp, n_tiles_sample=2000, seed=0):
     t_pre, t_blend_sample, n_s, n_ne, _, _ = _oracle_binned_sample(scene, cams, mlp, n_tiles_sample, seed)
     t_frame = t_pre + t_blend_sample * (n_ne / max(1, n_s))
     return {"value": round(1.0 / t_frame, 6), "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_info(),
             "sample": (f"FP64 torch-CPU oracle, pose 0 of the 1M-Gaussian 1600x1063 workload: enhance + "
                        f"project + tile lists for all Gaussians ({t_pre:.1f} s), OIT blend of "
                        f"{n_s} random non-empty tiles ({t_blend_sample:.1f} s) scaled to all "
@@ -378,6 +403,15 @@ def main():
         mean_pairs.append(R.pairs())
     mean_P = float(np.mean(mean_pairs))
     log(f"pairs per frame: mean {mean_P:.0f}, max {max(mean_pairs)}")
+    # the blend's work per frame (outside any timed region): list entries, pixel-Gaussian
+    # evaluations it executes (exact quadrant culling), pairs that contribute (alpha >= alpha_min)
+    census = np.zeros(3)
+    for c in cams:
+        R.render(ds, c, dm, bg=bg)
+        census += np.array(R.census(M._lib.make_camera(c)), np.float64)
+    census /= len(cams)
+    log(f"blend per frame: {census[1]:.4g} evaluations executed ({census[1] / (256 * census[0]):.3f} of 256 P), "
+        f"{census[2]:.4g} contributing")
 
     stream = torch.cuda.current_stream()
 
@@ -555,7 +589,7 @@ def main():
                         mfma_frac=round(flop_f / (ep_f * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4))
         del dmf
     blend_ms = float(stages[:, 2].mean())
-    evals = 256.0 * mean_P
+    evals = float(census[1])                  # evaluations the blend executes per frame
     achieved = evals * BLEND_FLOP_PER_EVAL / (blend_ms * 1e-3) / 1e12
     # HBM bytes per blend launch from the committed rocprofv3 counter summary of this workload,
     # reported only while the blend kernel's sources are unchanged since it was taken
@@ -615,8 +649,14 @@ def main():
                      "achieved": round(achieved, 2),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                     "units": "pixel-Gaussian evaluations executed (64 per quadrant kept by the exact test)",
                      "units_per_launch": round(evals), "flop_per_unit": BLEND_FLOP_PER_EVAL,
-                     "avg_launch_ms": round(blend_ms, 4)},
+                     "avg_launch_ms": round(blend_ms, 4),
+                     "reachable_unpacked_peak": REACHABLE_UNPACKED_FP32_TFLOPS,
+                     "frac_of_reachable": round(achieved / REACHABLE_UNPACKED_FP32_TFLOPS, 4),
+                     "dense_equivalent_units": round(256.0 * mean_P),
+                     "contributing_units": round(float(census[2])),
+                     "algorithmic_bytes": round(BLEND_BYTES_PER_PAIR * mean_P + 12 * W * H)},
     }
     if not args.no_extra:
         log("large-scene leg ...")

@@ -352,6 +352,19 @@ int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *tile_offsets,
                         float *image, float *aux, void *stream);
 
 /*
+ * mgs_blend_census -- measurement of the order-independent blend's work on the lists of mgs_bin
+ * (not part of rendering).  Writes counts[0] = list entries (tile, Gaussian) P, counts[1] =
+ * pixel-Gaussian evaluations the blend executes (64 per 8x8 quadrant its exact quadrant test
+ * keeps), counts[2] = pixel-Gaussian pairs that contribute to Eq. 2 (alpha >= alpha_min at the
+ * pixel centre, pixels inside the image).  counts: device uint64[3], 8-byte aligned,
+ * overwritten.  n_pairs / capacity as for mgs_blend_oit_split (all zero when n_pairs >
+ * capacity).  Integer results, independent of scheduling.
+ */
+int mgs_blend_census(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                     const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, float alpha_min,
+                     uint64_t *counts, void *stream);
+
+/*
  * mgs_blend_oit_split_noalloc -- mgs_blend_oit_split without a caller workspace, for callers
  * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  The workspace is a library-owned static device array of

@@ -34,7 +34,7 @@ EXPORTED = [
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
     "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
-    "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc",
+    "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc", "mgs_blend_census",
 ]
 MGS_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
@@ -113,6 +113,7 @@ def load(path=LIB_PATH):
                                            f32, f32, vp, C.c_size_t, vp, vp, vp]),
         "mgs_blend_oit_split_noalloc": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), i32, P(C.c_float),
                                               f32, f32, vp, vp, vp]),
+        "mgs_blend_census": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), f32, vp, vp]),
         "mgs_bin_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_oit": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, vp, vp,

@@ -457,6 +457,85 @@ extern "C" int mgs_blend_sortfree_split(const mgs_projected *proj, const uint32_
                                    alpha_max, ws, ws_bytes, image, aux, stream);
 }
 
+// ---------------------------------------------------------------- census of the blend's work
+// One thread per list entry (tile, Gaussian): the quadrant test of the order-independent blend
+// (quadrant_mask, the same function) gives the pixels it evaluates (64 per kept quadrant); the
+// exponent of Eq. 2 at each of those pixel centres gives the pairs that contribute (alpha >=
+// alpha_min).  Wave sums, one 64-bit atomic add per wave and counter (integer: any order).
+namespace mgs {
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void __launch_bounds__(256)
+blend_census_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
+                    const uint32_t *__restrict__ gids, const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+                    uint32_t T, int tiles_x, int W, int H, float log2_amin, unsigned long long *__restrict__ counts) {
+    const uint32_t P = uint64_t(*n_pairs) > capacity ? 0u : *n_pairs;
+    unsigned long long ev = 0, con = 0, pairs = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        // tile of list position i: the last t with offs[t] <= i
+        uint32_t lo = 0, hi = T - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const int tx = int(lo % uint32_t(tiles_x)), ty = int(lo / uint32_t(tiles_x));
+        const uint32_t g = gids[i];
+        const float4 r0 = splat[3 * size_t(g)], r1 = splat[3 * size_t(g) + 1];
+        const uint32_t m = quadrant_mask(r0, r1, tx, ty, log2_amin);
+        pairs += 1;
+        ev += 64ull * __builtin_popcount(m);
+        for (int q = 0; q < 4; ++q) {
+            if (!((m >> q) & 1u)) continue;
+            for (int k = 0; k < 64; ++k) {
+                const int px = tx * 16 + (q & 1) * 8 + (k & 7), py = ty * 16 + (q >> 1) * 8 + (k >> 3);
+                if (px >= W || py >= H) continue;
+                const float dx = float(px) + 0.5f - r0.x, dy = float(py) + 0.5f - r0.y;
+                const float t = fmaf(r1.y, dy, dx);
+                const float e = r0.z + r1.x * t * t + r1.z * dy * dy;
+                con += e >= log2_amin ? 1ull : 0ull;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ev += __shfl_xor(ev, o, 64);
+        con += __shfl_xor(con, o, 64);
+        pairs += __shfl_xor(pairs, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(counts + 0, pairs);
+        atomicAdd(counts + 1, ev);
+        atomicAdd(counts + 2, con);
+    }
+}
+
+}  // namespace mgs
+
+extern "C" int mgs_blend_census(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
+                                const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, float alpha_min,
+                                uint64_t *counts, void *stream) {
+    using namespace mgs;
+    int rc;
+    if ((rc = check_camera(cam)) != MGS_OK) return rc;
+    MGS_REQUIRE(proj && proj->splat && aligned(proj->splat, 16), "splat is NULL or misaligned");
+    MGS_REQUIRE(tile_offsets && gids && n_pairs && counts, "a pointer is NULL");
+    MGS_REQUIRE(aligned(counts, 8), "counts must be 8-byte aligned");
+    MGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f, "alpha_min must be in (0, 1)");
+    MGS_REQUIRE(capacity < (uint64_t(1) << 32) - 1, "capacity out of range");
+    const CamK k = make_camk(cam);
+    const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(counts), 3);
+    MGS_LAUNCH_CHECK("zero_u64_kernel");
+    hipLaunchKernelGGL(blend_census_kernel, dim3(2048), dim3(256), 0, s, reinterpret_cast<const float4 *>(proj->splat),
+                       tile_offsets, gids, n_pairs, capacity, T, k.tiles_x, k.W, k.H, log2f(alpha_min),
+                       reinterpret_cast<unsigned long long *>(counts));
+    MGS_LAUNCH_CHECK("blend_census_kernel");
+    return MGS_OK;
+}
+
 // ---------------------------------------------------------------- no-allocation split blend
 // The split blend's workspace (work list, split-tile tables, per-range partial sums) lives in
 // this file-scope device array instead of a caller buffer.  Every GPU the library runs on holds

@@ -288,6 +288,15 @@ class Renderer:
     def pairs(self):
         return int(_u32_to_i64(self.n_pairs)[0])
 
+    def census(self, cam_s, alpha_min=ALPHA_MIN, stream=None):
+        """mgs_blend_census on the current lists: (list entries, evaluations the OIT blend
+        executes, contributing pixel-Gaussian pairs); synchronises."""
+        out = torch.empty(3, dtype=torch.int64, device=self.device)
+        L.check(L.lib().mgs_blend_census(L.C.byref(self.proj), L.ptr(self.tile_offsets), L.ptr(self.gids),
+                                         L.ptr(self.n_pairs), self.capacity, L.C.byref(cam_s), alpha_min,
+                                         L.ptr(out), L.stream_ptr(stream)))
+        return tuple(int(v) for v in out.cpu())
+
     # -- whole pass -----------------------------------------------------------
     def render(self, scene, cam, mlp=None, bg=(0.0, 0.0, 0.0), sorted_path=False, want_aux=False,
                check_capacity=True, stream=None, fused=False, split=True, weight_mode=L.MGS_WEIGHT_EQ3,

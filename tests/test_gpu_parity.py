@@ -452,3 +452,35 @@ def test_split_tile_blend_matches_oracle_and_per_tile_blend(M):
     err, nfail = compare_oit_image(split_img, V, flagged, TOL)
     say(f"  split vs oracle: max {err:.3e} fails {nfail} flagged {flagged}")
     assert nfail == 0
+
+
+def test_blend_census_counts_match_oracle(M):
+    """mgs_blend_census: list entries equal the oracle's pair count; contributing pixel-Gaussian
+    pairs equal the oracle's count of alpha >= alpha_min pairs up to pairs in the ambiguity band;
+    the executed evaluations lie between the contributing pairs and 256 P."""
+    say("test_blend_census_counts_match_oracle")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    R, _ = _render_gpu(M, scene, cam)
+    P, executed, contributing = R.census(M._lib.make_camera(cam))
+    pr, camt = oracle_project(scene, cam)
+    offs, gids = O.bin_lists(pr["rect"], pr["n_tiles"], pr["tiles_x"], pr["tiles_y"])
+    pix = O.pixel_grid(camt["W"], camt["H"])
+    ref, amb = 0, 0
+    with torch.no_grad():
+        for t in range(pr["tiles_x"] * pr["tiles_y"]):
+            g = gids[offs[t]:offs[t + 1]]
+            if g.numel() == 0:
+                continue
+            tx, ty = t % pr["tiles_x"], t // pr["tiles_x"]
+            ii = torch.arange(tx * 16, min(camt["W"], tx * 16 + 16))
+            jj = torch.arange(ty * 16, min(camt["H"], ty * 16 + 16))
+            pp = pix[(jj[:, None] * camt["W"] + ii[None, :]).reshape(-1)]
+            _, _, _, cnt, _, n_amb = O.eval_pixels_oit(pp, pr, g, track_ambiguous=True)
+            ref += int(cnt.sum())
+            amb += int(n_amb.sum())
+    say(f"  P {P}, executed {executed} ({executed / (256 * P):.3f} of 256 P), contributing {contributing} "
+        f"(oracle {ref}, ambiguous {amb})")
+    assert P == int(offs[-1]) == R.pairs()
+    assert abs(contributing - ref) <= amb
+    assert contributing <= executed <= 256 * P and executed % 64 == 0
