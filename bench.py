@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--no-sorted", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-scene and training-step legs")
-    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--serve-seconds", type=float, default=SERVE_REPLAY_S,
+                    help="length of the open-loop serving replay (seconds of arrivals, per path)")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size kernel "
@@ -156,12 +157,25 @@ def oracle_timings(n_tiles_sample=400):
 SERVE_SIZES = (200_000, 400_000, 600_000, 800_000, 1_000_000, 1_500_000, 2_000_000, 2_500_000)
 SERVE_RES = ((640, 480), (1280, 720), (1600, 1063), (1920, 1080))
 TRAFFIC_PROFILE = "blend_oit_1m_1600x1063_counters.txt"
-SERVE_SWEEP = (0.25, 0.5, 0.75, 0.9)          # offered load as a fraction of the saturated rate
 
 
-def serving_leg(n_requests, rate=2000.0):
-    """8 resident scenes, Poisson arrivals of random poses at mixed resolutions, MLP on:
-    the continuous-batching server vs a one-frame-per-launch loop on the same stream."""
+SERVE_REPLAY_S = 60.0
+SERVE_SWEEP_S = 5.0
+
+
+def serving_leg(rate=2000.0, replay_s=SERVE_REPLAY_S):
+    """8 resident scenes, Poisson arrivals of random poses at mixed resolutions, MLP on: the
+    continuous-batching server against a one-frame-per-launch loop.
+
+    * replay: ``replay_s`` seconds of open-loop arrivals at the offered ``rate`` for each
+      path (no batch or frame starts after the window; what arrived and was not started is
+      reported as unserved); offered vs achieved requests/s, latency with queueing
+      (arrival -> image) and without (GPU start -> image);
+    * images: a short mixed run, every image of the server equal to the plain loop's;
+    * load sweep around the knee: offered rates as fractions of the server's replay rate;
+    * size classes: saturated throughput of both paths for small requests (the 200k and
+      400k scenes at 640x480, where a frame is launch-latency bound) and for large ones
+      (the 2M and 2.5M scenes at 1920x1080, where a frame fills the GPU)."""
     import numpy as np
     import torch
 
@@ -174,39 +188,65 @@ def serving_leg(n_requests, rate=2000.0):
                        n_slots=2, image_budget_bytes=8 << 30, use_graphs=True)
     srv.calibrate(SERVE_RES)
     names = list(reg.scenes)
-    warm = serve.poisson_requests(names, rate, 16, seed=99, resolutions=SERVE_RES)
-    srv.run(warm)
+    srv.run(serve.poisson_requests(names, rate, 16, seed=99, resolutions=SERVE_RES))
     serve.run_plain_loop(reg, serve.poisson_requests(names, rate, 16, seed=98, resolutions=SERVE_RES))
-    reqs = serve.poisson_requests(names, rate, n_requests, seed=2, resolutions=SERVE_RES)
-    served = srv.run(reqs)
-    st_b = serve.latency_stats(served)
-    reqs_p = serve.poisson_requests(names, rate, n_requests, seed=2, resolutions=SERVE_RES)
-    served_p = serve.run_plain_loop(reg, reqs_p)
-    st_p = serve.latency_stats(served_p)
-    by_id = {r.rid: r for r in served_p}
-    same = all(torch.equal(r.image, by_id[r.rid].image) for r in served if r.rid in by_id)
-    paths = {}
-    for r in served:
-        paths[r.path] = paths.get(r.path, 0) + 1
     r3 = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
-    # load sweep below the saturation knee: offered rates as fractions of the saturated rate
-    cap = st_b["frames_per_s"]
+
+    def replay(batched, offered, seconds, seed, sizes=None, res=SERVE_RES):
+        nm = names if sizes is None else [names[k] for k in sizes]
+        reqs = serve.poisson_requests(nm, offered, int(offered * seconds * 1.02) + 32, seed=seed, resolutions=res)
+        arrived = sum(1 for r in reqs if r.arrival <= seconds)
+        if batched:
+            done = srv.run(reqs, duration=seconds, keep_images=False)
+            left = len(srv.unserved)
+        else:
+            rest = []
+            done = serve.run_plain_loop(reg, reqs, duration=seconds, keep_images=False, unserved=rest)
+            left = len(rest)
+        st = serve.latency_stats(done, t_span=seconds)
+        st.update(offered_req_per_s=round(arrived / seconds, 2), achieved_req_per_s=round(len(done) / seconds, 2),
+                  unserved_at_end=left)
+        return r3(st)
+
+    out = {"offered_req_per_s": rate, "resident_gaussians": int(sum(SERVE_SIZES)), "replay_s": replay_s}
+    log(f"serving: {replay_s:.0f} s replay at {rate:.0f} req/s offered, batched server ...")
+    out["batched"] = replay(True, rate, replay_s, seed=2)
+    log(f"serving: {replay_s:.0f} s replay, plain loop ...")
+    out["plain_loop"] = replay(False, rate, replay_s, seed=2)
+    out["batched_vs_plain_frames"] = round(out["batched"]["frames_per_s"] / out["plain_loop"]["frames_per_s"], 3)
+    # the same requests through both paths: identical images
+    few = serve.poisson_requests(names, rate, 48, seed=4, resolutions=SERVE_RES)
+    a = {r.rid: r for r in srv.run(few)}
+    b = {r.rid: r for r in serve.run_plain_loop(reg, serve.poisson_requests(names, rate, 48, seed=4,
+                                                                            resolutions=SERVE_RES))}
+    out["images_identical_to_plain"] = bool(all(torch.equal(a[k].image, b[k].image) for k in a))
+    out["paths"] = {p: sum(1 for r in a.values() if r.path == p) for p in {r.path for r in a.values()}}
+    out["rejected"] = len(srv.rejected)
+    # latency against offered load around the knee (the server's replay rate = its capacity)
+    cap = out["batched"]["achieved_req_per_s"]
     sweep = []
-    for frac in SERVE_SWEEP:
+    for frac in (0.5, 0.8, 0.95, 1.1):
+        log(f"serving: load sweep at {frac:.2f} of capacity ...")
         rr = frac * cap
-        n_sw = max(32, int(min(n_requests, 2.0 * rr)))          # about two seconds of arrivals
-        sb = serve.latency_stats(srv.run(serve.poisson_requests(names, rr, n_sw, seed=3, resolutions=SERVE_RES)))
-        sp = serve.latency_stats(serve.run_plain_loop(reg, serve.poisson_requests(names, rr, n_sw, seed=3,
-                                                                                  resolutions=SERVE_RES)))
-        sweep.append({"offered_req_per_s": round(rr, 2), "requests": n_sw,
-                      "batched": {k: round(sb[k], 3) for k in ("p50_ms", "p99_ms", "service_p50_ms", "frames_per_s")},
-                      "plain_loop": {k: round(sp[k], 3) for k in ("p50_ms", "p99_ms", "service_p50_ms",
-                                                                  "frames_per_s")}})
-    return {"offered_req_per_s": rate, "resident_gaussians": int(sum(SERVE_SIZES)),
-            "batched": r3(st_b), "plain_loop": r3(st_p),
-            "batched_vs_plain_frames": round(st_b["frames_per_s"] / st_p["frames_per_s"], 3),
-            "images_identical_to_plain": bool(same), "paths": paths, "rejected": len(srv.rejected),
-            "load_sweep": sweep}
+        bs, ps = replay(True, rr, SERVE_SWEEP_S, seed=3), replay(False, rr, SERVE_SWEEP_S, seed=3)
+        sweep.append({"offered_req_per_s": round(rr, 2),
+                      "batched": {k: bs.get(k) for k in ("achieved_req_per_s", "p50_ms", "p99_ms", "service_p50_ms",
+                                                         "unserved_at_end")},
+                      "plain_loop": {k: ps.get(k) for k in ("achieved_req_per_s", "p50_ms", "p99_ms",
+                                                            "service_p50_ms", "unserved_at_end")}})
+    out["load_sweep"] = sweep
+    # where batching pays: saturated frames/s by request size
+    classes = {}
+    for name, sizes, res in (("small_200k_400k_640x480", (0, 1), ((640, 480),)),
+                             ("large_2m_2.5m_1920x1080", (6, 7), ((1920, 1080),))):
+        log(f"serving: size class {name} ...")
+        bs = replay(True, 8000.0, SERVE_SWEEP_S, seed=5, sizes=sizes, res=res)
+        ps = replay(False, 8000.0, SERVE_SWEEP_S, seed=5, sizes=sizes, res=res)
+        classes[name] = {"batched_frames_per_s": bs["frames_per_s"], "plain_frames_per_s": ps["frames_per_s"],
+                         "batched_vs_plain": round(bs["frames_per_s"] / ps["frames_per_s"], 3),
+                         "batched_service_p50_ms": bs["service_p50_ms"], "plain_service_p50_ms": ps["service_p50_ms"]}
+    out["size_classes"] = classes
+    return out
 
 
 def large_leg(steps=24):
@@ -240,6 +280,51 @@ def large_leg(steps=24):
     out["oit_vs_sorted"] = round(out["oit_fps"] / out["sorted_fps"], 3)
     out["workload"] = "3,000,000 Gaussians uniform in a ball r=10, 1920x1080, 60 spline poses, MLP on"
     return out
+
+
+def reference_sort_leg(R, ds, dm, cams, reps=20):
+    """ROCm's library radix sort (hipCUB / rocPRIM onesweep, libmgs_refsort.so, measurement only)
+    of the keys the sorted path sorts, (tile << 32 | float32 depth bits) with the Gaussian id as
+    value, built on the device from each pose's lists: its time per frame beside mgs_bin_sorted's."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2603_11531_amd import build as B
+    lib = C.CDLL(B.REFSORT_LIB)
+    lib.mgs_ref_sort_workspace.argtypes = [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
+    lib.mgs_ref_sort_pairs.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
+    end_bit = 32 + max(1, int(np.ceil(np.log2(R.T))))
+    times, n_keys = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for c in cams[::4]:
+        R.render(ds, c, dm, fused=True)
+        offs, gids = R.tile_offsets.long(), R.gids[:R.pairs()].long()
+        tiles = torch.repeat_interleave(torch.arange(R.T, device=offs.device), offs[1:] - offs[:-1])
+        dbits = R.splat[:, 7].contiguous().view(torch.int32).long() & 0xFFFFFFFF
+        keys = ((tiles << 32) | dbits[gids]).contiguous()
+        vals = gids.to(torch.int32).contiguous()
+        ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+        nb = C.c_size_t()
+        assert lib.mgs_ref_sort_workspace(keys.numel(), end_bit, C.byref(nb)) == 0
+        tmp = torch.empty(nb.value + 256, dtype=torch.uint8, device=keys.device)
+        args = [C.c_void_p(keys.data_ptr()), C.c_void_p(ko.data_ptr()), C.c_void_p(vals.data_ptr()),
+                C.c_void_p(vo.data_ptr()), keys.numel(), end_bit, C.c_void_p(tmp.data_ptr()), nb.value,
+                C.c_void_p(torch.cuda.current_stream().cuda_stream)]
+        for _ in range(3):
+            assert lib.mgs_ref_sort_pairs(*args) == 0
+        e0.record()
+        for _ in range(reps):
+            lib.mgs_ref_sort_pairs(*args)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / reps)
+        n_keys.append(keys.numel())
+        assert bool((ko[1:] >= ko[:-1]).all())
+    return {"library": "hipCUB DeviceRadixSort::SortPairs (rocPRIM onesweep)", "key_bits": end_bit,
+            "mean_keys": round(float(np.mean(n_keys))), "sort_ms": round(float(np.mean(times)), 4),
+            "poses": len(times)}
 
 
 def _frame(R, ds, dm, cs, sorted_path, bg=(0.0, 0.0, 0.0)):
@@ -424,6 +509,8 @@ def main():
             ev[0].record(stream)
         if isinstance(src["scene"], M.DeviceNVQ):  # attributes read through the NVQ codebooks
             Rx.enhance_project_nvq(src["scene"], cs, dm)
+        elif src.get("sortfree") is not None:     # Eq. 1's weight exp(-sigma d^beta), MLP fused
+            Rx.project_sortfree(src["scene"], cs, src["sortfree"][0], src["sortfree"][1], mlp=dm)
         elif src.get("mlp_f") is not None:        # the appendix's MLP_f 256-128-64, fused
             Rx.enhance_project_mlp_f(src["scene"], cs, src["mlp_f"])
         else:  # Eq. 4 MLP fused with the projection; Eq. 3 weight or one of its ablations
@@ -436,7 +523,7 @@ def main():
         if sorted_path:
             Rx.blend_sorted(cs, bg)
         else:
-            Rx.blend_oit(cs, bg)
+            Rx.blend_oit(cs, bg, w_bg=src.get("w_bg"))
         if ev is not None:
             ev[3].record(stream)
 
@@ -495,6 +582,10 @@ def main():
         res_sorted = dict(fps=round(args.steps / wall_s, 2), ms_per_frame=round(1e3 * wall_s / args.steps, 4),
                           stage_ms=dict(zip(["enhance_project", "bin_sorted", "blend_sorted"],
                                             [round(float(v), 4) for v in stages_s.mean(axis=0)])))
+    res_refsort = None
+    if not args.no_sorted:
+        log("timing the library radix sort on the sorted path's keys ...")
+        res_refsort = reference_sort_leg(R, ds, dm, cams)
     log("timing OIT (and sorted) with consecutive frames on two streams ...")
     wall_p = run_pipelined(False)
     res_pipe = dict(streams=2, fps=round(args.steps / wall_p, 2))
@@ -543,6 +634,20 @@ def main():
                       for name, _ in modes}
         # the paper's FPS ratios for the same ablations (Table 3, another device), for context
         res_weight["paper_vs_eq3"] = dict(no_depth=round(1167 / 1125, 3), no_scale=round(1171 / 1125, 3))
+    res_sortfree = None
+    if not args.no_extra:
+        # Eq. 1 (the SortFreeGS composite the paper starts from): per-Gaussian w = exp(-sigma d^beta)
+        # and the background weight w_bg in place of Eq. 3 and the transmittance term of Eq. 2
+        log("timing OIT with the Eq. 1 weight and composite ...")
+        sig, bet = mgs_data.make_sortfree_params(ds.n, 5, sigma_range=(0.01, 0.2))
+        src["sortfree"] = (torch.as_tensor(sig).to(dev), torch.as_tensor(bet).to(dev))
+        src["w_bg"] = 0.5
+        wall_sf, stages_sf, _ = run(False)
+        src["sortfree"] = src["w_bg"] = None
+        res_sortfree = dict(fps=round(args.steps / wall_sf, 2), vs_eq2_eq3=round(wall / wall_sf, 3),
+                            stage_ms=dict(zip(["enhance_project_sortfree", "bin", "blend_sortfree"],
+                                              [round(float(v), 4) for v in stages_sf.mean(axis=0)])),
+                            w_bg=0.5, sigma_range=[0.01, 0.2], beta_range=[0.5, 1.8])
     res_sh = None
     if not args.no_extra:
         # Table 3's SH-order variants: the same Gaussians with colour SH of order 0, 2 or 3
@@ -639,9 +744,11 @@ def main():
         "peaks_measured": peaks,
         "sorted": res_sorted,
         "oit_vs_sorted": (round(fps / res_sorted["fps"], 3) if res_sorted else None),
+        "sorted_reference_sort": res_refsort,
         "two_streams": res_pipe,
         "nvq": res_nvq,
         "weighting_ablations": res_weight,
+        "eq1_sortfree": res_sortfree,
         "mlp_f": res_mlpf,
         "sh_orders": res_sh,
         "roofline": {"bound": "alu",
@@ -667,7 +774,7 @@ def main():
         log("serving leg ...")
         del R
         torch.cuda.empty_cache()
-        out["serving"] = serving_leg(args.serve_requests)
+        out["serving"] = serving_leg(replay_s=args.serve_seconds)
         out["serve_p50_ms"] = out["serving"]["batched"]["p50_ms"]
         out["serve_p99_ms"] = out["serving"]["batched"]["p99_ms"]
     if not args.no_cpu_baseline:

@@ -137,6 +137,12 @@ class BatchSlot:
     def overflowed(self):
         return (int(self.n_pairs.cpu()[0]) & 0xFFFFFFFF) > self.capacity
 
+    def rendered(self):
+        """True when the batch plan accepted every request (status = {1, count}); a batch the
+        plan refused (a request outside the slot's limits) rendered nothing."""
+        ok, count = (int(v) for v in self.status.cpu())
+        return ok == 1 and count == len(self.requests)
+
 
 def form_batch(queue, footprint, max_batch, max_gaussians, max_tiles, capacity, image_budget, image_in_use):
     """FIFO admission: pop requests from the head of ``queue`` while the batch stays within
@@ -195,15 +201,23 @@ class Server:
         return n, _tiles(r.cam.width, r.cam.height), 12 * r.cam.width * r.cam.height, pairs
 
     def admissible_alone(self, r):
+        c = r.cam
+        if not (c.width > 0 and c.height > 0 and c.fx > 0 and c.fy > 0 and c.near > 0):
+            return False                         # the library would refuse this camera
         n, t, b, p = self.footprint(r)
         return n <= self.max_gaussians and t <= self.max_tiles and b <= self.image_budget
 
     # -- one run --------------------------------------------------------------
-    def run(self, requests, clock_start=None, idle_sleep=20e-6):
-        """Serve ``requests`` (sorted by arrival, seconds from start); returns the served list."""
+    def run(self, requests, idle_sleep=20e-6, duration=None, keep_images=True):
+        """Serve ``requests`` (sorted by arrival, seconds from start); returns the served list.
+        With ``duration`` no batch starts after that many seconds: requests that arrived and were
+        not started are left in ``self.unserved`` (the queue at the end of an overloaded run),
+        later arrivals are not offered.  ``keep_images=False`` drops each image once its request
+        is complete (long replays)."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         served = []
+        self.unserved = []
         free = list(self.slots)
         busy = []
         ref = torch.cuda.Event(enable_timing=True)
@@ -212,6 +226,13 @@ class Server:
         ref.record()
         while pending or queue or busy:
             now = time.perf_counter() - t0
+            if duration is not None and now >= duration:
+                self.unserved.extend(queue)
+                self.unserved.extend(r for r in pending if r.arrival <= duration)
+                queue.clear()
+                pending.clear()
+                if not busy:
+                    break
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
                 if self.admissible_alone(r):
@@ -226,7 +247,9 @@ class Server:
                     progressed = True
                     t_start = ref.elapsed_time(slot.start_event) * 1e-3
                     t_done = ref.elapsed_time(slot.done_event) * 1e-3
-                    if slot.overflowed():
+                    if slot.overflowed() or not slot.rendered():
+                        # pair capacity exceeded, or the plan refused the batch: each request
+                        # is rendered on the single-view path
                         for r in slot.requests:
                             r.start = time.perf_counter() - t0
                             self._render_alone(r)
@@ -238,6 +261,8 @@ class Server:
                             r.path = "batch"
                     for r in slot.requests:
                         self.image_bytes_in_use -= 12 * r.cam.width * r.cam.height
+                        if not keep_images:
+                            r.image = None
                     served.extend(slot.requests)
             while free and queue:
                 batch = form_batch(queue, self.footprint, self.max_batch, self.max_gaussians, self.max_tiles,
@@ -267,8 +292,10 @@ class Server:
         r.image = img.clone()
 
 
-def run_plain_loop(registry, requests, device="cuda"):
-    """Baseline: one request at a time, one frame per launch sequence (single-view path), FIFO."""
+def run_plain_loop(registry, requests, device="cuda", duration=None, keep_images=True, unserved=None):
+    """Baseline: one request at a time, one frame per launch sequence (single-view path), FIFO.
+    ``duration`` / ``keep_images`` as for Server.run; requests that arrived before the end and
+    were not started are appended to ``unserved`` (a list) when given."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     renderers = {}
     served = []
@@ -277,8 +304,14 @@ def run_plain_loop(registry, requests, device="cuda"):
     t0 = time.perf_counter()
     ref.record()
     while pending:
-        r = pending.popleft()
         now = time.perf_counter() - t0
+        if duration is not None and now >= duration:
+            if unserved is not None:
+                unserved.extend(r for r in pending if r.arrival <= duration)
+            break
+        if duration is not None and pending[0].arrival > duration:
+            break                                   # no arrival left inside the window
+        r = pending.popleft()
         if r.arrival > now:
             time.sleep(r.arrival - now)
         ds, dm = registry[r.scene]
@@ -296,6 +329,8 @@ def run_plain_loop(registry, requests, device="cuda"):
         r.start = ref.elapsed_time(ev0) * 1e-3
         r.done = ref.elapsed_time(ev) * 1e-3
         r.path = "plain"
+        if not keep_images:
+            r.image = None
         served.append(r)
     torch.cuda.synchronize()
     return served

@@ -150,3 +150,26 @@ def test_capacity_overflow_falls_back_to_single_view(S):
     assert len(served) == 6 and {r.path for r in served} == {"single-view retry"}
     for r in served:
         _same(r.image, _alone(M, reg, r), r.rid)
+
+
+def test_timed_replay_reports_unserved_and_drops_images(S):
+    """An overloaded open-loop window: batches start only inside it, what arrived and was not
+    started is reported as unserved, and completed requests drop their images."""
+    M, serve, reg = S
+    say("test_timed_replay_reports_unserved_and_drops_images")
+    srv = serve.Server(reg, max_batch=4, max_gaussians=200_000, max_tiles=4 * 2000, capacity=4_000_000, n_slots=2,
+                       use_graphs=True)
+    reqs = serve.poisson_requests(["a", "b", "c"], rate=50000.0, count=3000, seed=8,
+                                  resolutions=((160, 90), (200, 133)))
+    served = srv.run(reqs, duration=0.05, keep_images=False)
+    arrived = sum(1 for r in reqs if r.arrival <= 0.05)
+    say(f"  arrived {arrived}, served {len(served)}, unserved {len(srv.unserved)}")
+    assert served and srv.unserved
+    assert len(served) + len(srv.unserved) == arrived
+    assert all(r.image is None and r.path == "batch" for r in served)
+    assert all(r.start <= 0.05 + 1e-3 for r in served)
+    unserved = []
+    plain = serve.run_plain_loop(reg, serve.poisson_requests(["a", "b", "c"], rate=50000.0, count=3000, seed=8,
+                                                             resolutions=((160, 90), (200, 133))),
+                                 duration=0.05, keep_images=False, unserved=unserved)
+    assert plain and unserved and len(plain) + len(unserved) == arrived
