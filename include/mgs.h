@@ -109,6 +109,24 @@ typedef struct mgs_projected {
 
 /* Thread-local message of the last error (static storage, never NULL). */
 const char *mgs_last_error(void);
+
+/*
+ * Checked builds.  libmgs_checked.so is this library built with MGS_CHECK_BOUNDS: its kernels
+ * check the indices they derive (list positions and writes against the pair count and capacity,
+ * rectangles against the tile grid, split-blend items and backward slots against their
+ * workspace bounds); a failed check skips the access and sets a bit (MGS_BOUNDS_*).
+ * mgs_bounds_checked: 1 in a checked build, else 0.
+ * mgs_bounds_status: synchronises the device, writes the OR of the bits set since the last
+ * clear to *flags (always 0 in an unchecked build) and, if `clear`, clears them.
+ */
+#define MGS_BOUNDS_EXPAND_WRITE 0x01u
+#define MGS_BOUNDS_RECT_GRID    0x02u
+#define MGS_BOUNDS_LIST_WRITE   0x04u
+#define MGS_BOUNDS_LIST_READ    0x08u
+#define MGS_BOUNDS_SPLIT_ITEM   0x10u
+#define MGS_BOUNDS_BWD_SLOT     0x20u
+int mgs_bounds_checked(void);
+int mgs_bounds_status(uint32_t *flags, int clear);
 /* Library version string. */
 const char *mgs_version(void);
 

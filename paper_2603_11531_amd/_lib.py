@@ -12,7 +12,8 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmgs.so")
+# MGS_LIBRARY=checked loads libmgs_checked.so (the bounds-checked build of the same sources)
+LIB_PATH = os.path.join(_PKG, "libmgs_checked.so" if os.environ.get("MGS_LIBRARY") == "checked" else "libmgs.so")
 
 MGS_OK = 0
 MGS_ERR_INVALID_ARG = -1
@@ -34,7 +35,8 @@ EXPORTED = [
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
     "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
-    "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc", "mgs_blend_census",
+    "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc", "mgs_blend_census", "mgs_bounds_checked",
+    "mgs_bounds_status",
 ]
 MGS_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
@@ -114,6 +116,8 @@ def load(path=LIB_PATH):
         "mgs_blend_oit_split_noalloc": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), i32, P(C.c_float),
                                               f32, f32, vp, vp, vp]),
         "mgs_blend_census": (i32, [P(mgs_projected), vp, vp, vp, u64, P(mgs_camera), f32, vp, vp]),
+        "mgs_bounds_checked": (i32, []),
+        "mgs_bounds_status": (i32, [P(C.c_uint32), i32]),
         "mgs_bin_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
         "mgs_blend_oit": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, vp, vp,

@@ -39,9 +39,12 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+CHECKED_LIB = os.path.join(PKG, "libmgs_checked.so")
+
+
+def _compile(src, checked=False):
+    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + (".checked.o" if checked else ".o"))
+    cmd = [HIPCC, *CFLAGS, *(["-DMGS_CHECK_BOUNDS"] if checked else []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -63,21 +66,29 @@ def _build_refsort():
     return REFSORT_LIB
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
-        ref = ex.submit(_build_refsort)
-        objs = list(ex.map(_compile, srcs))
-        ref.result()
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    """libmgs.so, libmgs_checked.so (the same sources with MGS_CHECK_BOUNDS: kernels check the
+    indices they derive and report failures through mgs_bounds_status) and libmgs_refsort.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        ref = ex.submit(_build_refsort)
+        objs = list(ex.map(_compile, srcs))
+        objs_checked = list(ex.map(lambda src: _compile(src, checked=True), srcs))
+        ref.result()
+    _link(objs, LIB)
+    _link(objs_checked, CHECKED_LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources, and {REFSORT_LIB}")
+        print(f"built {LIB} from {len(srcs)} sources, {CHECKED_LIB} and {REFSORT_LIB}")
     return LIB
 
 

@@ -123,9 +123,8 @@ bwd_blend_kernel(const float4 *__restrict__ splat, const uint2 *__restrict__ rec
         }
         if (active) {
             const uint2 rc = rect[g];
-            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
-            const uint64_t slot = uint64_t(first[g]) + uint64_t(ty - int(y0)) * (x1 - x0 + 1) + uint64_t(tx - int(x0));
-            if (slot < cap) {
+            const uint64_t slot = pair_slot(first[g], unpack_rect(rc.x, rc.y), uint32_t(tx), uint32_t(ty));
+            if (MGS_GUARD(slot < cap, BS_BWD_SLOT)) {
 #pragma unroll
                 for (int k = 0; k < NPART; ++k) part[k * cap + slot] = acc[k];
             }

@@ -15,6 +15,7 @@
 // over 8x8-tile supertiles and then over the tiles of each supertile (see the comment
 // above super_count_kernel).
 #include "batch.h"
+#include "index_math.h"
 
 namespace mgs {
 
@@ -30,10 +31,6 @@ constexpr int RADIX_MAX_BITS = 8;
 constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
 constexpr int RADIX_MAX_GRID = 2048;                      // resident blocks striding over the used ones
 
-constexpr int SUPER_SHIFT = 3;                            // supertile = 8 x 8 tiles (two-level binning)
-constexpr int SUPER = 1 << SUPER_SHIFT;
-constexpr int SUPER_TILES = SUPER * SUPER;
-constexpr int CHUNK = 256;                                // supertile entries per level-2 block
 constexpr int SUPER_MAX_GRID = 8192;                      // resident blocks striding over the level-2 chunks
 constexpr int SUPER_RADIX_ITERS = 4;                      // level-1 sort: 1024 keys per block (a short sort,
 constexpr int SUPER_RADIX_TILE = RADIX_THREADS * SUPER_RADIX_ITERS;   // so more, shorter blocks)
@@ -44,10 +41,7 @@ constexpr unsigned PLAN_REPLICAS = 8;                    // blocks of a single-p
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
 // Supertiles of a rectangle of tiles (inclusive bounds packed as in mgs_projected.rect).
-__device__ __forceinline__ uint32_t n_super(uint2 r) {
-    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-    return ((x1 >> SUPER_SHIFT) - (x0 >> SUPER_SHIFT) + 1) * ((y1 >> SUPER_SHIFT) - (y0 >> SUPER_SHIFT) + 1);
-}
+__device__ __forceinline__ uint32_t n_super(uint2 r) { return rect_n_super(unpack_rect(r.x, r.y)); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned l = lane_id();
@@ -210,17 +204,14 @@ struct GridMap {
 // coordinate (lx0 | ly0 << 3 | lx1 << 6 | ly1 << 9): the sort orders by the id alone
 // (ST_KEY_SHIFT up) and the level-2 passes read the rectangle from the key instead of
 // gathering the Gaussian's rectangle by index.
-constexpr int ST_KEY_SHIFT = 12;
 template <int SHIFT, typename KeyFn>
 __device__ __forceinline__ auto entry_key(const KeyFn &keyfn, uint32_t id, float depth, uint2 r, uint32_t sx,
                                           uint32_t sy) {
     if constexpr (SHIFT == 0) {
         return keyfn(id, depth);
     } else {
-        const uint32_t ox = sx << SHIFT, oy = sy << SHIFT, last = (1u << SHIFT) - 1u;
-        const uint32_t lx0 = max(r.x & 0xFFFFu, ox) - ox, ly0 = max(r.x >> 16, oy) - oy;
-        const uint32_t lx1 = min((r.y & 0xFFFFu) - ox, last), ly1 = min((r.y >> 16) - oy, last);
-        return uint32_t((id << ST_KEY_SHIFT) | lx0 | (ly0 << 3) | (lx1 << 6) | (ly1 << 9));
+        static_assert(SHIFT == SUPER_SHIFT, "supertile keys are 8 x 8 tiles");
+        return super_entry_key(id, unpack_rect(r.x, r.y), sx, sy);
     }
 }
 
@@ -253,6 +244,7 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
         uint32_t p = base;
         for (uint32_t ty = y0; ty <= y1; ++ty)
             for (uint32_t tx = x0; tx <= x1; ++tx, ++p) {
+                if (!MGS_CHECK(p < capacity, BS_EXPAND_WRITE)) continue;
                 keys[p] = entry_key<SHIFT>(keyfn, tbase + ty * tiles_x + tx, depth, r, tx, ty);
                 vals[p] = uint32_t(g);
             }
@@ -271,6 +263,7 @@ expand_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntile
         const uint32_t wdt = x1j - xj + 1;
         for (uint32_t p = l; p < cj; p += 64) {
             const uint32_t ty = yj + p / wdt, tx = xj + p % wdt;
+            if (!MGS_CHECK(uint64_t(bj) + p < capacity, BS_EXPAND_WRITE)) continue;
             keys[bj + p] = entry_key<SHIFT>(keyfn, tbj + ty * txj + tx, dj, rj, tx, ty);
             vals[bj + p] = gj;
         }
@@ -721,15 +714,7 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
     }
 }
 
-// An entry's covered tiles of its supertile as a 64-bit mask (bit ky * 8 + kx), from the
-// local rectangle in the low bits of its level-1 key (never empty: the entry exists because
-// the rectangle overlaps the supertile).
-__device__ __forceinline__ uint64_t local_mask(uint32_t key) {
-    const uint32_t lx0 = key & 7u, ly0 = (key >> 3) & 7u, lx1 = (key >> 6) & 7u, ly1 = (key >> 9) & 7u;
-    const uint64_t row = uint64_t((2u << lx1) - (1u << lx0));                    // columns lx0 .. lx1
-    const uint64_t rows = (0x0101010101010101ull << (8 * ly0)) & (~0ull >> (8 * (SUPER - 1 - ly1)));
-    return rows * row;                                                           // no carries: row < 256
-}
+// An entry's covered tiles of its supertile: local_mask (index_math.h).
 
 // 64 x 64 bit transpose across the wave: on return lane k holds, in bit j, bit k of lane j's
 // input.  Six butterfly stages; stage s exchanges, between lanes l and l ^ s, the s-bit
@@ -968,14 +953,16 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < L; i += CHUNK) {
                 const int k = s_tile[i];
-                gids[s_first[k] + (i - s_lpre[k])] = s_out[i];
+                const uint32_t dst = s_first[k] + (i - s_lpre[k]);
+                if (MGS_CHECK(dst < *n_pairs, BS_LIST_WRITE)) gids[dst] = s_out[i];
             }
         } else if (col) {
             uint32_t pos = s_first[l] + (s_lw[w][l] - s_lpre[l]);
             while (col) {
                 const int j = __builtin_ctzll(col);
                 col &= col - 1;
-                gids[pos++] = s_gid[w][j];
+                if (MGS_CHECK(pos < *n_pairs, BS_LIST_WRITE)) gids[pos] = s_gid[w][j];
+                ++pos;
             }
         }
         __syncthreads();
@@ -1096,7 +1083,7 @@ inline Bin2Layout bin2_layout(int64_t n, uint32_t st_max, uint32_t t_max, uint64
     const size_t cap = size_t(capacity > 0 ? capacity : 1);     // entries <= pairs <= capacity
     const int64_t nb = int64_t((cap + SUPER_RADIX_TILE - 1) / SUPER_RADIX_TILE);
     L.nblocks = int(nb > 0 ? nb : 1);
-    L.chunks_max = uint32_t(cap / CHUNK + st_max + 1);
+    L.chunks_max = uint32_t(bin_max_chunks(cap, st_max));
     const size_t nsums = size_t((n + 255) / 256) + 1;
     size_t o = 0;
     L.sums_e = o;   o = align_up(o + nsums * 8, 256);

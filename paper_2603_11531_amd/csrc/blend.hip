@@ -42,7 +42,6 @@ blend_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs
 }
 
 // ---------------------------------------------------------------- split-tile OIT blend
-constexpr uint32_t SPLIT_RANGE = 1024;        // Gaussians per range of a long tile list
 constexpr uint32_t MERGE_GRID = 2048;         // workgroups of the range merge
 constexpr int PART_FLOATS = 5 * 256;          // per-range partial sums (N rgb, D, T) x 256 pixels
 
@@ -212,7 +211,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
 #pragma unroll
             for (int q = 0; q < SPLIT_FILL_ILP; ++q) {
                 const uint32_t k = i + q * fill_stride;
-                if (k < n_items) {
+                if (k < n_items && MGS_CHECK(uint64_t(ibase) + k < split_max_items(t_host, capacity), BS_SPLIT_ITEM)) {
                     const uint32_t r = k - s_item0[lo[q]], sl = s_slot0[lo[q]];
                     items[ibase + k] = (c * SPLIT_TILE + lo[q]) | (r << 24);
                     item_slot[ibase + k] = sl == 0xFFFFFFFFu ? sl : sl + r;
@@ -227,20 +226,24 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
     }
 }
 
+// n_pairs / max_slots are read only by the checks of a checked build (MGS_CHECK_BOUNDS).
 template <typename Loc>
 __global__ void __launch_bounds__(BLEND_THREADS, 7)
 blend_range_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs,
                    const uint32_t *__restrict__ gids, const uint32_t *__restrict__ items,
                    const uint32_t *__restrict__ item_slot, const uint32_t *__restrict__ counts, Loc loc,
-                   float log2_amin, float amax, float *__restrict__ part) {
+                   float log2_amin, float amax, float *__restrict__ part, const uint32_t *__restrict__ n_pairs,
+                   uint32_t max_slots) {
     const uint32_t k = blockIdx.x;
     if (k >= counts[0]) return;                                           // block-uniform
     const uint32_t it = items[k], t = it & 0xFFFFFFu, r = it >> 24;
     const uint32_t start = offs[t], end = offs[t + 1];
+    if (!MGS_CHECK(start <= end && end <= *n_pairs, BS_LIST_READ)) return;
     const uint32_t L = end - start, rl = range_len(L, SPLIT_RANGE);
     const TileView v = loc(t);
     // a tile with one range is composited here; a range of a split tile leaves its sums in part
     const bool whole = n_ranges(L, SPLIT_RANGE) == 1;
+    if (!whole && !MGS_CHECK(item_slot[k] < max_slots && r < n_ranges(L, SPLIT_RANGE), BS_SPLIT_ITEM)) return;
     const uint32_t s = whole ? start : start + r * rl;
     const uint32_t e = (whole || end - s <= rl) ? end : s + rl;
     blend_tile_oit(splat, gids, s, e, v.tx, v.ty, v.W, v.H, v.bg[0], v.bg[1], v.bg[2], v.wbg, log2_amin, amax,
@@ -279,8 +282,8 @@ struct SplitLayout {
 
 inline SplitLayout split_layout(uint32_t T, uint64_t capacity) {
     SplitLayout L;
-    L.max_items = uint32_t(T + capacity / SPLIT_RANGE + 1);
-    const size_t max_slots = size_t(2 * (capacity / SPLIT_RANGE) + 2);
+    L.max_items = uint32_t(split_max_items(T, capacity));
+    const size_t max_slots = size_t(split_max_slots(capacity));
     size_t o = 0;
     L.items = o;  o = align_up(o + size_t(L.max_items) * 4, 256);
     L.slot = o;   o = align_up(o + size_t(L.max_items) * 4, 256);
@@ -326,7 +329,8 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     }
     MGS_LAUNCH_CHECK("split_plan_kernel");
     hipLaunchKernelGGL(blend_range_kernel<Loc>, dim3(L.max_items), dim3(BLEND_THREADS), 0, s, splat, offs, gids,
-                       items, slot, counts, loc, log2f(alpha_min), alpha_max, part);
+                       items, slot, counts, loc, log2f(alpha_min), alpha_max, part, n_pairs,
+                       uint32_t(split_max_slots(capacity)));
     MGS_LAUNCH_CHECK("blend_range_kernel");
     // split tiles are at most T; a bounded grid walks them (most tiles are not split)
     hipLaunchKernelGGL(merge_ranges_kernel<Loc>, dim3(T == 0 ? 1u : (T < MERGE_GRID ? T : MERGE_GRID)),

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "index_math.h"
 
 namespace mgs {
 
@@ -428,19 +429,8 @@ __device__ __forceinline__ void blend_tile_oit(const float4 *__restrict__ splat,
 }
 
 // ---------------------------------------------------------------- split tiles
-// Order independence makes the per-pixel state additive (N and D add, T multiplies), so
-// a long tile list can be cut into ranges rendered by different workgroups and merged
-// exactly.  A list of L Gaussians has n_ranges(L) ranges of equal length (the last up to
-// n - 1 shorter): at most `split` Gaussians each (more for extremely long lists, so a tile
-// has at most 255 ranges); item = tile | range << 24.
-__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return a / b + (a % b != 0u); }
-__device__ __forceinline__ uint32_t n_ranges(uint32_t L, uint32_t split) {
-    if (L == 0) return 1u;
-    if (L <= 255u * split) return ceil_div(L, split);
-    return ceil_div(L, ceil_div(L, 255u));        // longer lists: ranges of ceil(L / 255)
-}
-// Every range is non-empty: with n = n_ranges(L) and len = ceil(L / n), (n - 1) len < L
-// because n (n - 1) < L for every n this plan produces.
-__device__ __forceinline__ uint32_t range_len(uint32_t L, uint32_t split) { return ceil_div(L, n_ranges(L, split)); }
+// Order independence makes the per-pixel state additive (N and D add, T multiplies), so a long
+// tile list can be cut into ranges rendered by different workgroups and merged exactly: the
+// range plan (n_ranges, range_len; item = tile | range << 24) is in index_math.h.
 
 }  // namespace mgs

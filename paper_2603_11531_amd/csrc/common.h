@@ -90,6 +90,51 @@ inline int check_projected(const mgs_projected *p, int64_t n) {
 
 constexpr float LOG2E = 1.4426950408889634f;
 
+// ---------------------------------------------------------------- checked builds
+// A build with -DMGS_CHECK_BOUNDS checks the indices the kernels derive (list positions against
+// the pair count, list writes against the capacity, rectangles against the tile grid, backward
+// slots against the capacity).  A failed check sets its site's bit in this translation unit's
+// flag word and the access is skipped, so a wrong index is reported, never followed;
+// mgs_bounds_status() gathers the words of every translation unit.  Without the macro a
+// MGS_CHECK is the constant true and a MGS_GUARD its condition.
+enum BoundsSite : uint32_t {
+    BS_EXPAND_WRITE = 1u << 0,     // level-1 / sorted-path entry written past the capacity
+    BS_RECT_GRID = 1u << 1,        // a rectangle outside the tile grid
+    BS_LIST_WRITE = 1u << 2,       // a tile-list write past the pair count
+    BS_LIST_READ = 1u << 3,        // a tile-list range past the pair count
+    BS_SPLIT_ITEM = 1u << 4,       // a split-blend work item or slot past its workspace bound
+    BS_BWD_SLOT = 1u << 5,         // a backward pair slot past the capacity
+};
+#ifdef MGS_CHECK_BOUNDS
+static __device__ uint32_t tu_bounds_flags;
+__device__ __forceinline__ bool bounds_ok(bool ok, uint32_t site) {
+    if (!ok) atomicOr(&tu_bounds_flags, site);
+    return ok;
+}
+// MGS_CHECK: a check a normal build leaves out; MGS_GUARD: a guard every build keeps, which a
+// checked build also reports when it fails
+#define MGS_CHECK(cond, site) (::mgs::bounds_ok(bool(cond), (site)))
+#define MGS_GUARD(cond, site) (::mgs::bounds_ok(bool(cond), (site)))
+// Reader / clearer of this translation unit's flag word, registered at load time.
+void register_bounds_word(int (*read)(uint32_t *), int (*clear)());
+static int tu_bounds_read(uint32_t *out) {
+    return hipMemcpyFromSymbol(out, HIP_SYMBOL(tu_bounds_flags), sizeof(uint32_t)) == hipSuccess ? 0 : -1;
+}
+static int tu_bounds_clear() {
+    const uint32_t z = 0;
+    return hipMemcpyToSymbol(HIP_SYMBOL(tu_bounds_flags), &z, sizeof(uint32_t)) == hipSuccess ? 0 : -1;
+}
+namespace {
+struct BoundsRegistration {
+    BoundsRegistration() { register_bounds_word(&tu_bounds_read, &tu_bounds_clear); }
+};
+static BoundsRegistration bounds_registration;
+}  // namespace
+#else
+#define MGS_CHECK(cond, site) (true)
+#define MGS_GUARD(cond, site) (bool(cond))
+#endif
+
 // Device-wide exclusive scan of uint32 values (bin.hip); tmp holds scan_tmp_elems(n) uint64,
 // *total receives the sum clamped to 2^32 - 1.
 size_t scan_tmp_elems(int64_t n);

@@ -183,6 +183,9 @@ __device__ __forceinline__ ProjOut project_gaussian(const GaussIn &in, const Cam
     if (vis) {
         const uint32_t tx0 = uint32_t(i0) / MGS_TILE, tx1 = uint32_t(i1) / MGS_TILE;
         const uint32_t ty0 = uint32_t(j0) / MGS_TILE, ty1 = uint32_t(j1) / MGS_TILE;
+        if (!MGS_CHECK(tx0 <= tx1 && ty0 <= ty1 && tx1 < uint32_t(cam.tiles_x) && ty1 < uint32_t(cam.tiles_y),
+                       BS_RECT_GRID))
+            return o;
         o.n_tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         o.rect = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
     }
