@@ -506,6 +506,7 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
                                    const float *aux, const float *dL_dimage, const float bg[3], float alpha_min,
                                    float alpha_max, void *ws, size_t ws_bytes, mgs_gaussians_grad *out,
                                    float *dmlp, void *stream) {
+    MGS_TRACE("mgs_render_backward");
     using namespace mgs;
     int rc;
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;

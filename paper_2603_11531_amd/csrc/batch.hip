@@ -152,6 +152,7 @@ extern "C" int mgs_batch_workspace(int64_t max_gaussians, int64_t max_tiles, uin
 extern "C" int mgs_render_batch(const mgs_request *requests, const int32_t *n_requests, int64_t max_gaussians,
                                 int64_t max_tiles, uint64_t capacity, float alpha_min, float alpha_max, void *ws,
                                 size_t ws_bytes, uint32_t *n_pairs, int32_t *status, void *stream) {
+    MGS_TRACE("mgs_render_batch");
     using namespace mgs;
     MGS_REQUIRE(requests && n_requests && n_pairs, "requests / n_requests / n_pairs is NULL");
     MGS_REQUIRE(max_gaussians > 0 && max_gaussians < (int64_t(1) << 31), "max_gaussians out of range");

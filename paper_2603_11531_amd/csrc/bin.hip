@@ -1291,6 +1291,7 @@ extern "C" int mgs_bin_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t c
 extern "C" int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
                        size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
                        uint32_t *n_pairs, void *stream) {
+    MGS_TRACE("mgs_bin");
     MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
     const uint32_t st_x = uint32_t((tiles_x + mgs::SUPER - 1) / mgs::SUPER);
     return mgs::bin2_impl(proj, n, nullptr, mgs::SuperGrid{uint32_t(tiles_x), uint32_t(tiles_y), st_x},
@@ -1309,6 +1310,7 @@ extern "C" int mgs_bin_sorted_workspace(int64_t n, int tiles_x, int tiles_y, uin
 extern "C" int mgs_bin_sorted(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void *ws,
                               size_t ws_bytes, uint32_t *tile_offsets, uint32_t *gids, uint64_t capacity,
                               uint32_t *n_pairs, void *stream) {
+    MGS_TRACE("mgs_bin_sorted");
     MGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && tiles_x <= 65535 && tiles_y <= 65535, "bad tile grid");
     const int tile_bits = mgs::bits_for(uint64_t(tiles_x) * uint64_t(tiles_y));
     return mgs::bin_impl<uint64_t, mgs::TileDepthKey>(proj, n, mgs::GridMap{uint32_t(tiles_x)},

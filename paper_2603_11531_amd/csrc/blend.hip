@@ -406,6 +406,7 @@ inline int blend_split_single(const mgs_projected *proj, const uint32_t *tile_of
 extern "C" int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
                              const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
                              float alpha_max, float *image, float *aux, void *stream) {
+    MGS_TRACE("mgs_blend_oit");
     return mgs::blend_whole_tiles(proj, tile_offsets, gids, cam, tile, bg, mgs::EQ2_COMPOSITE, alpha_min, alpha_max,
                                   image, aux, stream);
 }
@@ -413,6 +414,7 @@ extern "C" int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_off
 extern "C" int mgs_blend_sortfree(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
                                   const mgs_camera *cam, int tile, const float bg[3], float w_bg, float alpha_min,
                                   float alpha_max, float *image, float *aux, void *stream) {
+    MGS_TRACE("mgs_blend_sortfree");
     MGS_REQUIRE(w_bg >= 0.0f && w_bg < INFINITY, "w_bg must be finite and >= 0");
     return mgs::blend_whole_tiles(proj, tile_offsets, gids, cam, tile, bg, w_bg, alpha_min, alpha_max, image, aux,
                                   stream);
@@ -421,6 +423,7 @@ extern "C" int mgs_blend_sortfree(const mgs_projected *proj, const uint32_t *til
 extern "C" int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
                                 const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
                                 float alpha_max, float t_stop, float *image, void *stream) {
+    MGS_TRACE("mgs_blend_sorted");
     using namespace mgs;
     int rc;
     if ((rc = blend_common_checks(proj, tile_offsets, gids, cam, tile, bg, alpha_min, alpha_max, image)) != MGS_OK)
@@ -447,6 +450,7 @@ extern "C" int mgs_blend_oit_split(const mgs_projected *proj, const uint32_t *ti
                                    const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, int tile,
                                    const float bg[3], float alpha_min, float alpha_max, void *ws, size_t ws_bytes,
                                    float *image, float *aux, void *stream) {
+    MGS_TRACE("mgs_blend_oit_split");
     return mgs::blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, mgs::EQ2_COMPOSITE,
                                    alpha_min, alpha_max, ws, ws_bytes, image, aux, stream);
 }
@@ -456,6 +460,7 @@ extern "C" int mgs_blend_sortfree_split(const mgs_projected *proj, const uint32_
                                         const mgs_camera *cam, int tile, const float bg[3], float w_bg,
                                         float alpha_min, float alpha_max, void *ws, size_t ws_bytes, float *image,
                                         float *aux, void *stream) {
+    MGS_TRACE("mgs_blend_sortfree_split");
     MGS_REQUIRE(w_bg >= 0.0f && w_bg < INFINITY, "w_bg must be finite and >= 0");
     return mgs::blend_split_single(proj, tile_offsets, gids, n_pairs, capacity, cam, tile, bg, w_bg, alpha_min,
                                    alpha_max, ws, ws_bytes, image, aux, stream);
@@ -520,6 +525,7 @@ blend_census_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict
 extern "C" int mgs_blend_census(const mgs_projected *proj, const uint32_t *tile_offsets, const uint32_t *gids,
                                 const uint32_t *n_pairs, uint64_t capacity, const mgs_camera *cam, float alpha_min,
                                 uint64_t *counts, void *stream) {
+    MGS_TRACE("mgs_blend_census");
     using namespace mgs;
     int rc;
     if ((rc = check_camera(cam)) != MGS_OK) return rc;
@@ -578,6 +584,7 @@ extern "C" int mgs_blend_oit_split_noalloc(const mgs_projected *proj, const uint
                                            const uint32_t *gids, const uint32_t *n_pairs, uint64_t capacity,
                                            const mgs_camera *cam, int tile, const float bg[3], float alpha_min,
                                            float alpha_max, float *image, float *aux, void *stream) {
+    MGS_TRACE("mgs_blend_oit_split_noalloc");
     using namespace mgs;
     int rc;
     // size checks first, so an oversized call is refused before anything touches the device

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 #include <stdio.h>
 
@@ -13,6 +14,16 @@ namespace mgs {
 int set_error(int code, const char *fmt, ...);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// A roctx range over an entry point's host call (argument checks and enqueue), visible to
+// rocprofv3 --marker-trace; a few hundred nanoseconds when no tool listens.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+#define MGS_TRACE(name) ::mgs::TraceRange mgs_trace_range_(name)
 
 inline bool aligned(const void *p, size_t a) {
     return (reinterpret_cast<uintptr_t>(p) % a) == 0;

@@ -71,6 +71,7 @@ enhance_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict__ packed, fl
 }  // namespace mgs
 
 extern "C" int mgs_mlp_pack(const float *params, void *packed, void *stream) {
+    MGS_TRACE("mgs_mlp_pack");
     using namespace mgs;
     MGS_REQUIRE(params && packed, "params / packed is NULL");
     MGS_REQUIRE(aligned(params, 4) && aligned(packed, 16), "packed must be 16-byte aligned");
@@ -82,6 +83,7 @@ extern "C" int mgs_mlp_pack(const float *params, void *packed, void *stream) {
 
 extern "C" int mgs_enhance(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp, float *phi,
                            float *omod, void *stream) {
+    MGS_TRACE("mgs_enhance");
     using namespace mgs;
     int rc;
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;

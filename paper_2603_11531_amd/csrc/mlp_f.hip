@@ -285,6 +285,7 @@ enhance_project_mlpf_kernel(mgs_gaussians g, CamK cam, const uint8_t *__restrict
 }  // namespace mgs
 
 extern "C" int mgs_mlp_f_pack(const float *params, void *packed, void *stream) {
+    MGS_TRACE("mgs_mlp_f_pack");
     using namespace mgs;
     MGS_REQUIRE(params && packed, "params / packed is NULL");
     MGS_REQUIRE(aligned(params, 4) && aligned(packed, 16), "packed must be 16-byte aligned");
@@ -297,6 +298,7 @@ extern "C" int mgs_mlp_f_pack(const float *params, void *packed, void *stream) {
 extern "C" int mgs_enhance_project_mlp_f(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp_f,
                                          int tile, float alpha_min, mgs_projected *out, float *phi, float *omod,
                                          void *stream) {
+    MGS_TRACE("mgs_enhance_project_mlp_f");
     using namespace mgs;
     int rc;
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;

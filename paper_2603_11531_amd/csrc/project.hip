@@ -213,6 +213,7 @@ inline NvqSource nvq_source(const mgs_gaussians_nvq *q) {
 extern "C" int mgs_enhance_project_weighted(const mgs_gaussians *g, const mgs_camera *cam,
                                             const void *packed_mlp, int tile, float alpha_min, int weight_mode,
                                             mgs_projected *out, float *phi, float *omod, void *stream) {
+    MGS_TRACE("mgs_enhance_project_weighted");
     using namespace mgs;
     int rc;
     MGS_REQUIRE(valid_weight_mode(weight_mode), "unknown weight_mode %d", weight_mode);
@@ -245,6 +246,7 @@ extern "C" int mgs_enhance_project(const mgs_gaussians *g, const mgs_camera *cam
 extern "C" int mgs_enhance_project_sh(const mgs_gaussians *g, int sh_degree, const mgs_camera *cam,
                                       const void *packed_mlp, int tile, float alpha_min, mgs_projected *out,
                                       float *phi, float *omod, void *stream) {
+    MGS_TRACE("mgs_enhance_project_sh");
     using namespace mgs;
     int rc;
     MGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "sh_degree %d outside 0..3", sh_degree);
@@ -280,6 +282,7 @@ extern "C" int mgs_enhance_project_sh(const mgs_gaussians *g, int sh_degree, con
 extern "C" int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *cam, const float *phi,
                                     const float *omod, int tile, float alpha_min, int weight_mode,
                                     mgs_projected *out, void *stream) {
+    MGS_TRACE("mgs_project_weighted");
     using namespace mgs;
     int rc;
     MGS_REQUIRE(valid_weight_mode(weight_mode), "unknown weight_mode %d", weight_mode);
@@ -302,6 +305,7 @@ extern "C" int mgs_project_weighted(const mgs_gaussians *g, const mgs_camera *ca
 extern "C" int mgs_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const float *omod,
                                     const float *sigma, const float *beta, int tile, float alpha_min,
                                     mgs_projected *out, void *stream) {
+    MGS_TRACE("mgs_project_sortfree");
     using namespace mgs;
     int rc;
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;
@@ -324,6 +328,7 @@ extern "C" int mgs_project_sortfree(const mgs_gaussians *g, const mgs_camera *ca
 extern "C" int mgs_enhance_project_sortfree(const mgs_gaussians *g, const mgs_camera *cam, const void *packed_mlp,
                                             const float *sigma, const float *beta, int tile, float alpha_min,
                                             mgs_projected *out, float *phi, float *omod, void *stream) {
+    MGS_TRACE("mgs_enhance_project_sortfree");
     using namespace mgs;
     int rc;
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;
@@ -356,6 +361,7 @@ extern "C" int mgs_project(const mgs_gaussians *g, const mgs_camera *cam, const 
 
 extern "C" int mgs_nvq_decode(const mgs_gaussians_nvq *q, float *log_scale, float *quat, float *opacity_logit,
                               float *sh, void *stream) {
+    MGS_TRACE("mgs_nvq_decode");
     using namespace mgs;
     int rc;
     if ((rc = check_nvq(q)) != MGS_OK) return rc;
@@ -371,6 +377,7 @@ extern "C" int mgs_nvq_decode(const mgs_gaussians_nvq *q, float *log_scale, floa
 extern "C" int mgs_enhance_project_nvq(const mgs_gaussians_nvq *q, const mgs_camera *cam, const void *packed_mlp,
                                        int tile, float alpha_min, mgs_projected *out, float *phi, float *omod,
                                        void *stream) {
+    MGS_TRACE("mgs_enhance_project_nvq");
     using namespace mgs;
     int rc;
     if ((rc = check_nvq(q)) != MGS_OK) return rc;

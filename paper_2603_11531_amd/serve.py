@@ -161,22 +161,71 @@ def form_batch(queue, footprint, max_batch, max_gaussians, max_tiles, capacity, 
     return batch
 
 
+class GpuBackend:
+    """What the server needs from the device: batch slots, a clock, images, a single-view retry
+    and the GPU time stamps of a finished slot.  A test can pass a simulated backend with the
+    same methods (and a clock it controls) to exercise the scheduling on the CPU."""
+
+    def __init__(self, device="cuda", use_graphs=True):
+        self.device = torch.device(device)
+        self.use_graphs = use_graphs
+
+    def new_slot(self, max_gaussians, max_tiles, capacity):
+        return BatchSlot(max_gaussians, max_tiles, capacity, self.device, self.use_graphs)
+
+    def start(self):
+        """Begin a run: the origin of now() and of slot_times()."""
+        self.ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+        self.ref.record()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def sleep(self, seconds):
+        time.sleep(seconds)
+
+    def image(self, W, H):
+        return torch.empty(3, H, W, dtype=torch.float32, device=self.device)
+
+    def slot_times(self, slot):
+        """(GPU start, GPU end) of a finished slot's batch, seconds from start()."""
+        return self.ref.elapsed_time(slot.start_event) * 1e-3, self.ref.elapsed_time(slot.done_event) * 1e-3
+
+    def render_alone(self, registry, r):
+        ds, dm = registry[r.scene]
+        R = Renderer(ds.n, r.cam.width, r.cam.height, device=self.device)
+        img = R.render(ds, r.cam, dm, bg=r.bg)
+        torch.cuda.synchronize()
+        r.image = img.clone()
+
+    def finish(self):
+        torch.cuda.synchronize()
+
+
 class Server:
-    """Open-loop continuous-batching server (see the module docstring)."""
+    """Open-loop continuous-batching server (see the module docstring).  ``timeout_s``: a
+    request still queued that long after its arrival is cancelled (``self.timed_out``) instead
+    of rendered."""
 
     def __init__(self, registry, max_batch=16, max_gaussians=8_000_000, max_tiles=None, capacity=64_000_000,
-                 n_slots=2, image_budget_bytes=2 << 30, use_graphs=True, device="cuda"):
+                 n_slots=2, image_budget_bytes=2 << 30, use_graphs=True, device="cuda", timeout_s=None,
+                 backend=None):
         self.reg = registry
         self.max_batch = min(int(max_batch), MAX_REQ)
         self.max_gaussians = int(max_gaussians)
         self.max_tiles = int(max_tiles if max_tiles is not None else self.max_batch * _tiles(1920, 1080))
         self.capacity = int(capacity)
         self.image_budget = int(image_budget_bytes)
-        self.device = torch.device(device)
-        self.slots = [BatchSlot(self.max_gaussians, self.max_tiles, self.capacity, device, use_graphs)
-                      for _ in range(n_slots)]
+        self.timeout_s = timeout_s
+        self.backend = backend if backend is not None else GpuBackend(device, use_graphs)
+        self.device = getattr(self.backend, "device", None)
+        self.slots = [self.backend.new_slot(self.max_gaussians, self.max_tiles, self.capacity) for _ in range(n_slots)]
         self.image_bytes_in_use = 0
         self.rejected = []
+        self.timed_out = []
+        self.unserved = []
         self.pair_est = {}           # (scene, W, H) -> pairs of one view (from calibrate)
 
     def calibrate(self, resolutions, margin=1.3, radius=4.0):
@@ -214,18 +263,16 @@ class Server:
         not started are left in ``self.unserved`` (the queue at the end of an overloaded run),
         later arrivals are not offered.  ``keep_images=False`` drops each image once its request
         is complete (long replays)."""
+        be = self.backend
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         served = []
         self.unserved = []
         free = list(self.slots)
         busy = []
-        ref = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ref.record()
+        be.start()
         while pending or queue or busy:
-            now = time.perf_counter() - t0
+            now = be.now()
             if duration is not None and now >= duration:
                 self.unserved.extend(queue)
                 self.unserved.extend(r for r in pending if r.arrival <= duration)
@@ -239,21 +286,25 @@ class Server:
                     queue.append(r)
                 else:
                     self.rejected.append(r)
+            if self.timeout_s is not None:
+                while queue and now - queue[0].arrival > self.timeout_s:     # FIFO: the oldest first
+                    r = queue.popleft()
+                    r.path = "timed out"
+                    self.timed_out.append(r)
             progressed = False
             for slot in list(busy):
                 if slot.ready():
                     busy.remove(slot)
                     free.append(slot)
                     progressed = True
-                    t_start = ref.elapsed_time(slot.start_event) * 1e-3
-                    t_done = ref.elapsed_time(slot.done_event) * 1e-3
+                    t_start, t_done = be.slot_times(slot)
                     if slot.overflowed() or not slot.rendered():
                         # pair capacity exceeded, or the plan refused the batch: each request
                         # is rendered on the single-view path
                         for r in slot.requests:
-                            r.start = time.perf_counter() - t0
-                            self._render_alone(r)
-                            r.done = time.perf_counter() - t0
+                            r.start = be.now()
+                            be.render_alone(self.reg, r)
+                            r.done = be.now()
                             r.path = "single-view retry"
                     else:
                         for r in slot.requests:
@@ -268,7 +319,7 @@ class Server:
                 batch = form_batch(queue, self.footprint, self.max_batch, self.max_gaussians, self.max_tiles,
                                    self.capacity, self.image_budget, self.image_bytes_in_use)
                 for r in batch:
-                    r.image = torch.empty(3, r.cam.height, r.cam.width, dtype=torch.float32, device=self.device)
+                    r.image = be.image(r.cam.width, r.cam.height)
                     self.image_bytes_in_use += 12 * r.cam.width * r.cam.height
                 if not batch:
                     break
@@ -278,18 +329,14 @@ class Server:
                 progressed = True
             if not progressed:
                 if pending and not queue and not busy:
-                    time.sleep(max(0.0, min(pending[0].arrival - now, 1e-3)))
+                    be.sleep(max(0.0, min(pending[0].arrival - now, 1e-3)))
                 else:
-                    time.sleep(idle_sleep)
-        torch.cuda.synchronize()
+                    be.sleep(idle_sleep)
+        be.finish()
         return served
 
     def _render_alone(self, r):
-        ds, dm = self.reg[r.scene]
-        R = Renderer(ds.n, r.cam.width, r.cam.height, device=self.device)
-        img = R.render(ds, r.cam, dm, bg=r.bg)
-        torch.cuda.synchronize()
-        r.image = img.clone()
+        self.backend.render_alone(self.reg, r)
 
 
 def run_plain_loop(registry, requests, device="cuda", duration=None, keep_images=True, unserved=None):
