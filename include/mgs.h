@@ -125,6 +125,7 @@ const char *mgs_last_error(void);
 #define MGS_BOUNDS_LIST_READ    0x08u
 #define MGS_BOUNDS_SPLIT_ITEM   0x10u
 #define MGS_BOUNDS_BWD_SLOT     0x20u
+#define MGS_BOUNDS_BWD_ITEM     0x40u
 int mgs_bounds_checked(void);
 int mgs_bounds_status(uint32_t *flags, int clear);
 /* Library version string. */

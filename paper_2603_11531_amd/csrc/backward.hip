@@ -12,153 +12,308 @@
 // then alpha = o exp(-q/2) carries it to o and to the quadratic form.
 //
 // Deterministic reduction without float atomics:
-//   1. bwd_blend: one workgroup per tile, one thread per listed Gaussian; the
-//      thread walks the tile's pixels (per-pixel terms staged in LDS) and writes
-//      its 10 partial sums to the pair's slot in Gaussian-major order
-//      (slot = first[g] + index of the tile inside g's rectangle);
-//   2. bwd_reduce: one wave per Gaussian sums its contiguous slots (fixed tree);
-//   3. bwd_gauss: per-Gaussian chain rule to mean, log-scale, quaternion,
+//   1. bwd_plan: the tile lists are cut into work items of at most BWD_CHUNK list
+//      positions (a chunk count per tile, an exclusive scan, the items written);
+//   2. bwd_blend: one workgroup per item, one lane per listed Gaussian.  Each wave
+//      lists its Gaussians' (Gaussian, quadrant) entries for the tile quadrants they
+//      reach and evaluates them 64 at a time (a lane walks one quadrant's pixels, the
+//      per-pixel terms staged in LDS); the entries' sums are gathered, in entry order,
+//      by the lane that owns the Gaussian, which writes its 10 partial sums as one
+//      record to the pair's slot in Gaussian-major order (slot = first[g] + index of
+//      the tile inside g's rectangle);
+//   3. bwd_reduce: 16 lanes per Gaussian sum its contiguous slots (fixed tree);
+//   4. bwd_gauss: per-Gaussian chain rule to mean, log-scale, quaternion,
 //      opacity logit, SH and (with the MLP) to phi and the opacity factor;
-//   4. bwd_mlp: per-Gaussian MLP backward in float32 (straight through the
+//   5. bwd_mlp: per-Gaussian MLP backward in float32 (straight through the
 //      bfloat16 roundings of the forward) -> input gradients, and the per-Gaussian
 //      vectors whose outer products give the weight gradients;
-//   5. wgrad_partial / wgrad_sum: chunked outer-product sums, summed in chunk order.
+//   6. wgrad_partial / wgrad_sum: chunked outer-product sums (float32 matrix
+//      instructions), summed in chunk order.
 #include "blend_math.h"
 #include "proj_math.h"
 
 namespace mgs {
 
-constexpr int NPART = 10;   // mx, my, A, beta, gamma, o, w, r, g, b
-constexpr int WG_CHUNK = 2048;
+constexpr int NPART = 10;        // mx, my, A, beta, gamma, o, w, r, g, b
+constexpr int PART_STRIDE = 12;  // floats per pair record: the 10 sums and 2 zeros (48-byte records)
+constexpr uint32_t BWD_CHUNK = 256;   // list positions per blend work item (one per thread)
+constexpr unsigned BWD_GRID_MAX = 1u << 20;   // blend workgroups; more items are walked in a grid stride
+constexpr int WG_CHUNK = 512;    // Gaussians per weight-gradient workgroup (128 per wave)
 constexpr int MLP_VEC = 24 + 64 + 64 + 64 + 64 + 2;   // xb(22, padded), h1b, Fb, dH1, dF, (dphi, dm)
 constexpr int OFF_XB = 0, OFF_H1 = 24, OFF_FB = 88, OFF_DH1 = 152, OFF_DF = 216, OFF_DHD = 280;
 
-// ------------------------------------------------------------------ 1. blend backward
+// Work items of the blend backward for T tiles and at most `capacity` pairs: sum over tiles of
+// ceil(L_t / BWD_CHUNK) <= capacity / BWD_CHUNK + T.
+inline uint64_t bwd_max_items(uint64_t T, uint64_t capacity) { return T + capacity / BWD_CHUNK + 1; }
+
+// ------------------------------------------------------------------ 1. work items
+// Chunks per tile; none at all when the forward's lists overflowed their capacity (the lists
+// and offsets were not built: nothing is read and every gradient is zero).
+__global__ void __launch_bounds__(256)
+bwd_chunks_kernel(const uint32_t *__restrict__ offs, uint32_t T, const uint32_t *__restrict__ n_pairs,
+                  uint64_t cap, uint32_t *__restrict__ chunks) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= T) return;
+    uint32_t c = 0;
+    if (uint64_t(*n_pairs) <= cap) {
+        const uint32_t s = offs[t], e = offs[t + 1];
+        if (MGS_CHECK(s <= e && e <= *n_pairs, BS_LIST_READ)) c = ceil_div(e - s, BWD_CHUNK);
+    }
+    chunks[t] = c;
+}
+
+// Item j of tile t (j < chunks[t]) = (t, first list position of its chunk), at cbase[t] + j.
+__global__ void __launch_bounds__(256)
+bwd_items_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ chunks,
+                 const uint32_t *__restrict__ cbase, uint32_t T, uint64_t max_items, uint2 *__restrict__ items) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= T) return;
+    const uint32_t c = chunks[t], b = cbase[t], s = offs[t];
+    for (uint32_t j = 0; j < c; ++j)
+        if (MGS_CHECK(uint64_t(b) + j < max_items, BS_BWD_ITEM)) items[b + j] = make_uint2(t, s + j * BWD_CHUNK);
+}
+
+// ------------------------------------------------------------------ 2. blend backward
+// Sums over the pixels of one (Gaussian, quadrant) entry.  With a = alpha before the clamp and
+// ada = a dL/dalpha (0 where alpha was clamped or below alpha_min):
+//   sc = sum alpha G1 (times w at the end), sw = sum alpha u, so = sum ada,
+//   and the quadratic-form sums with t = dx + beta dy:
+//   st = sum ada t, stt = sum ada t^2, sty = sum ada t dy, sy = sum ada dy, syy = sum ada dy^2
+// (each -2 times the sum of the corresponding dq = d alpha / d(quadratic form) terms).
+constexpr int BWD_SUMS = 10;
+struct BwdSums {
+    float v[BWD_SUMS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+};
+enum { S_CR, S_CG, S_CB, S_W, S_O, S_T, S_TT, S_TY, S_Y, S_YY };
+
+// LDS strides of the per-pixel terms per quadrant (float4 and float units): the four quadrants
+// of one read fall in different banks.
+constexpr int QS4 = 65, QS1 = 68;
+
+// One entry: the Gaussian's pixels in quadrant (xb, yb) of the tile, row by row.  The exponent
+// is the forward's (same polynomial about the tile centre, same pixel offsets X = c + xb,
+// Y = row + yb), so the alpha_min cut and alpha are bit-identical to the forward's.  Within a row
+// dy is fixed and t = tY + X, so a pixel adds ada, ada c and ada c^2 (c the column, a literal)
+// to row sums combined once per row.
+template <bool CLAMP>
+__device__ __forceinline__ void bwd_entry(const float4 &qa, const float4 &qb, float beta, float t0, float v0, float cr,
+                                          float cg, float cb, float wgt, bool act0, float xb, float yb,
+                                          float log2_amin, float amax, const float4 *__restrict__ pa_q,
+                                          const float *__restrict__ pb_q, BwdSums &S) {
+    for (int row = 0; row < 8; ++row) {
+        const float Y = float(row) + yb;
+        const float P = fmaf(fmaf(qb.y, Y, qa.z), Y, qa.x);
+        const float R = fmaf(qb.x, Y, qa.y);
+        const float4 *pa_r = pa_q + row * 8;
+        const float *pb_r = pb_q + row * 8;
+        float r0 = 0.f, rx = 0.f, rxx = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float X = float(c) + xb;
+            const float e = fmaf(fmaf(qa.w, X, R), X, P);
+            const float4 pa = pa_r[c];
+            const float pb = pb_r[c];
+            const float a = (act0 && e >= log2_amin) ? fast_exp2(e) : 0.0f;
+            const float al = CLAMP ? fminf(a, amax) : a;
+            const float u = fmaf(pa.z, cb, fmaf(pa.y, cg, fmaf(pa.x, cr, pa.w)));
+            S.v[S_CR] = fmaf(al, pa.x, S.v[S_CR]);
+            S.v[S_CG] = fmaf(al, pa.y, S.v[S_CG]);
+            S.v[S_CB] = fmaf(al, pa.z, S.v[S_CB]);
+            S.v[S_W] = fmaf(al, u, S.v[S_W]);
+            const float dal = fmaf(wgt, u, -pb * __builtin_amdgcn_rcpf(1.0f - al));
+            const float ada = (CLAMP && a > amax) ? 0.0f : a * dal;
+            r0 += ada;
+            rx = fmaf(ada, float(c), rx);
+            rxx = fmaf(ada, float(c * c), rxx);
+        }
+        const float tc = fmaf(beta, Y, t0) + xb, dyr = v0 + Y;   // t at column 0 of the row
+        const float s1 = fmaf(tc, r0, rx);                         // sum ada t over the row
+        S.v[S_O] += r0;
+        S.v[S_T] += s1;
+        S.v[S_TT] += fmaf(tc, fmaf(tc, r0, 2.0f * rx), rxx);     // sum ada (tc + c)^2
+        S.v[S_TY] = fmaf(s1, dyr, S.v[S_TY]);
+        S.v[S_Y] = fmaf(r0, dyr, S.v[S_Y]);
+        S.v[S_YY] = fmaf(r0 * dyr, dyr, S.v[S_YY]);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 bwd_blend_kernel(const float4 *__restrict__ splat, const uint2 *__restrict__ rect,
                  const uint32_t *__restrict__ first, const uint32_t *__restrict__ offs,
-                 const uint32_t *__restrict__ gids, CamK cam, float bgr, float bgg, float bgb,
-                 float log2_amin, float amax, const float *__restrict__ aux, const float *__restrict__ dimg,
-                 float *__restrict__ part, uint64_t cap) {
-    __shared__ float4 s_pa[256];   // G1 rgb, gF
-    __shared__ float2 s_pb[256];   // gT, T
-    const int tile = blockIdx.x;
-    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    {
-        const int t = threadIdx.x;
-        const int px = tx * 16 + (t & 15), py = ty * 16 + (t >> 4);
-        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 pb = make_float2(0.f, 1.f);
-        if (px < cam.W && py < cam.H) {
-            const size_t hw = size_t(cam.W) * cam.H, p = size_t(py) * cam.W + px;
-            const float D = aux[3 * hw + p];
-            if (D > 0.f) {
-                const float T = aux[4 * hw + p];
-                const float Fr = aux[p], Fg = aux[hw + p], Fb = aux[2 * hw + p];
-                const float gr = dimg[p], gg = dimg[hw + p], gb = dimg[2 * hw + p];
-                const float k = (1.0f - T) / D;
-                pa = make_float4(gr * k, gg * k, gb * k, 0.f);
-                pa.w = pa.x * Fr + pa.y * Fg + pa.z * Fb;
-                pb = make_float2(gr * (bgr - Fr) + gg * (bgg - Fg) + gb * (bgb - Fb), T);
-            }
-        }
-        s_pa[t] = pa;
-        s_pb[t] = pb;
-    }
-    __syncthreads();
-    const uint32_t start = offs[tile], end = offs[tile + 1];
+                 const uint32_t *__restrict__ gids, const uint2 *__restrict__ items,
+                 const uint32_t *__restrict__ n_items, uint64_t max_items, const uint32_t *__restrict__ n_pairs,
+                 CamK cam, float bgr, float bgg, float bgb, float log2_amin, float amax,
+                 const float *__restrict__ aux, const float *__restrict__ dimg, float *__restrict__ part,
+                 uint64_t cap) {
+    // per pixel of quadrant q, row r, column c (at q * QS + 8 r + c): (G1 rgb, -gF) and gT T
+    __shared__ float4 s_pa[4 * QS4];
+    __shared__ float s_pb[4 * QS1];
+    // per wave: its Gaussians' (lane, quadrant) entries, Gaussian-major (lane << 2 | quadrant)
+    __shared__ uint8_t s_ent[4][4 * 64];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
     const float inv_k = -2.0f / LOG2E;      // kA = -(1/2) log2(e) A  ->  A = kA * inv_k
-    for (uint32_t base = start; base < end; base += 256) {
-        const uint32_t i = base + threadIdx.x;
-        const bool active = i < end;
-        float4 r0 = make_float4(0.f, 0.f, -1000.f, 0.f), r1 = make_float4(-1.f, 0.f, -1.f, 1.f),
-               r2 = make_float4(0.f, 0.f, 0.f, 1.f);
-        uint32_t g = 0, mask = 0;
-        if (active) {
-            g = gids[i];
-            r0 = splat[3 * size_t(g) + 0];
-            r1 = splat[3 * size_t(g) + 1];
-            r2 = splat[3 * size_t(g) + 2];
-            mask = quadrant_mask(r0, r1, tx, ty, log2_amin);
+    const float log2_amax_safe = __log2f(amax) - OIT_CLAMP_MARGIN;
+    const uint32_t ni = *n_items;
+    for (uint32_t k = blockIdx.x; k < ni; k += gridDim.x) {             // block-uniform
+        if (!MGS_CHECK(k < max_items, BS_BWD_ITEM)) return;
+        const uint2 it = items[k];
+        const uint32_t tile = it.x, start = it.y, tend = offs[tile + 1];
+        const uint32_t end = tend - start > BWD_CHUNK ? start + BWD_CHUNK : tend;
+        if (!MGS_CHECK(start < end && end <= *n_pairs, BS_LIST_READ)) return;
+        const int tx = int(tile % uint32_t(cam.tiles_x)), ty = int(tile / uint32_t(cam.tiles_x));
+        __syncthreads();                    // the previous item's LDS reads are done
+        {
+            const int q = threadIdx.x >> 6, row = (threadIdx.x >> 3) & 7, cl = threadIdx.x & 7;
+            const int px = tx * 16 + (q & 1) * 8 + cl, py = ty * 16 + (q >> 1) * 8 + row;
+            float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+            float pb = 0.f;
+            if (px < cam.W && py < cam.H) {
+                const size_t hw = size_t(cam.W) * cam.H, p = size_t(py) * cam.W + px;
+                const float D = aux[3 * hw + p];
+                if (D > 0.f) {
+                    const float T = aux[4 * hw + p];
+                    const float Fr = aux[p], Fg = aux[hw + p], Fb = aux[2 * hw + p];
+                    const float gr = dimg[p], gg = dimg[hw + p], gb = dimg[2 * hw + p];
+                    const float kk = (1.0f - T) / D;
+                    pa = make_float4(gr * kk, gg * kk, gb * kk, 0.f);
+                    pa.w = -(pa.x * Fr + pa.y * Fg + pa.z * Fb);
+                    pb = (gr * (bgr - Fr) + gg * (bgg - Fg) + gb * (bgb - Fb)) * T;
+                }
+            }
+            s_pa[q * QS4 + row * 8 + cl] = pa;
+            s_pb[q * QS1 + row * 8 + cl] = pb;
         }
-        const float A = r1.x * inv_k, beta = r1.y, gam = r1.z * inv_k;
-        const float inv_o = 1.0f / r2.w;
-        float acc[NPART];
-#pragma unroll
-        for (int k = 0; k < NPART; ++k) acc[k] = 0.f;
-        for (int q = 0; q < 4; ++q) {
-            const bool mine = active && ((mask >> q) & 1u);
-            if (__ballot(mine) == 0ull) continue;
-            const int qx = (q & 1) * 8, qy = (q >> 1) * 8;
-            for (int pp = 0; pp < 64; ++pp) {
-                const int lx = qx + (pp & 7), ly = qy + (pp >> 3);
-                const int k = ly * 16 + lx;
-                const float4 pa = s_pa[k];
-                const float2 pb = s_pb[k];
-                const float dx = float(tx * 16 + lx) + 0.5f - r0.x;
-                const float dy = float(ty * 16 + ly) + 0.5f - r0.y;
-                const float t = fmaf(beta, dy, dx);
-                const float e = fmaf(r1.x * t, t, fmaf(r1.z * dy, dy, r0.z));
-                if (mine && e >= log2_amin) {
-                    const float a = fast_exp2(e);
-                    const float al = fminf(a, amax);
-                    const float u = pa.x * r2.x + pa.y * r2.y + pa.z * r2.z - pa.w;
-                    const float aw = al * r0.w;
-                    acc[7] = fmaf(aw, pa.x, acc[7]);
-                    acc[8] = fmaf(aw, pa.y, acc[8]);
-                    acc[9] = fmaf(aw, pa.z, acc[9]);
-                    acc[6] = fmaf(al, u, acc[6]);
-                    const float dal = r0.w * u - pb.x * pb.y / (1.0f - al);
-                    const float da = a > amax ? 0.0f : dal;
-                    acc[5] = fmaf(da * a, inv_o, acc[5]);
-                    const float dq = -0.5f * a * da;
-                    acc[2] = fmaf(dq * t, t, acc[2]);
-                    acc[4] = fmaf(dq * dy, dy, acc[4]);
-                    const float s1 = 2.0f * dq * A * t;
-                    acc[3] = fmaf(s1, dy, acc[3]);
-                    acc[0] -= s1;
-                    acc[1] -= fmaf(s1, beta, 2.0f * dq * gam * dy);
+        // the lane's list position: culling; a Gaussian that reaches no quadrant has a zero record
+        const uint32_t i = start + threadIdx.x;
+        uint32_t g = 0, mask = 0;
+        if (i < end) {
+            g = gids[i];
+            mask = quadrant_mask(splat[3 * size_t(g) + 0], splat[3 * size_t(g) + 1], tx, ty, log2_amin);
+            if (mask == 0u) {
+                const uint2 rc = rect[g];
+                const uint64_t slot = pair_slot(first[g], unpack_rect(rc.x, rc.y), uint32_t(tx), uint32_t(ty));
+                if (MGS_GUARD(slot < cap, BS_BWD_SLOT)) {
+                    float4 *o = reinterpret_cast<float4 *>(part + slot * PART_STRIDE);
+                    o[0] = o[1] = o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
         }
-        if (active) {
+        // the wave's entries: lane l's quadrants at base .. base + popc(mask) - 1
+        const uint32_t cnt = uint32_t(__popc(mask));
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= uint32_t(o)) inc += y;
+        }
+        const uint32_t base = inc - cnt;
+        const uint32_t E = __shfl(inc, 63, 64);
+        {
+            uint32_t m = mask, e = base;
+            while (m) {
+                const uint32_t q = uint32_t(__builtin_ctz(m));
+                s_ent[w][e++] = uint8_t((lane << 2) | q);
+                m &= m - 1u;
+            }
+        }
+        __syncthreads();                    // pixel terms and entries are visible
+        BwdSums acc;                        // the lane's own Gaussian
+        const float tcx = float(tx * 16) + 8.0f, tcy = float(ty * 16) + 8.0f;
+        for (uint32_t c0 = 0; c0 < E; c0 += 64) {                          // wave-uniform
+            const uint32_t e = c0 + lane;
+            const bool have = e < E;
+            const uint32_t ent = have ? s_ent[w][e] : 0u;
+            const int src = int(ent >> 2), q = int(ent & 3u);
+            const uint32_t ge = uint32_t(__shfl(int(g), src, 64));
+            float4 r0 = make_float4(0.f, 0.f, -1000.f, 0.f), r1 = make_float4(-1.f, 0.f, -1.f, 1.f),
+                   r2 = make_float4(0.f, 0.f, 0.f, 1.f);
+            if (have) {
+                r0 = splat[3 * size_t(ge) + 0];
+                r1 = splat[3 * size_t(ge) + 1];
+                r2 = splat[3 * size_t(ge) + 2];
+            }
+            float4 qa, qb = make_float4(0.f, 0.f, 0.f, 0.f);
+            quad_poly(r0, r1, tcx, tcy, qa, qb);
+            const float beta = r1.y;
+            const float v0 = tcy - r0.y, t0 = fmaf(beta, v0, tcx - r0.x);
+            const float xb = (q & 1) ? 0.5f : -7.5f, yb = (q >> 1) ? 0.5f : -7.5f;
+            BwdSums S;
+            const float4 *pa_q = s_pa + q * QS4;
+            const float *pb_q = s_pb + q * QS1;
+            if (__ballot(have && r0.z > log2_amax_safe) != 0ull)
+                bwd_entry<true>(qa, qb, beta, t0, v0, r2.x, r2.y, r2.z, r0.w, have, xb, yb, log2_amin, amax, pa_q,
+                                pb_q, S);
+            else
+                bwd_entry<false>(qa, qb, beta, t0, v0, r2.x, r2.y, r2.z, r0.w, have, xb, yb, log2_amin, amax, pa_q,
+                                 pb_q, S);
+            // each lane adds its Gaussian's entries of this chunk, in entry order
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t ej = base + j;
+                const bool mine = j < cnt && ej >= c0 && ej < c0 + 64u;
+                const int from = int(ej - c0) & 63;
+#pragma unroll
+                for (int v = 0; v < BWD_SUMS; ++v) {
+                    const float x = __shfl(S.v[v], from, 64);
+                    if (mine) acc.v[v] += x;
+                }
+            }
+        }
+        if (mask != 0u) {
+            const float4 r0 = splat[3 * size_t(g) + 0], r1 = splat[3 * size_t(g) + 1];
+            const float r2w = splat[3 * size_t(g) + 2].w;
+            const float A = r1.x * inv_k, gam = r1.z * inv_k, beta = r1.y, wgt = r0.w;
             const uint2 rc = rect[g];
             const uint64_t slot = pair_slot(first[g], unpack_rect(rc.x, rc.y), uint32_t(tx), uint32_t(ty));
             if (MGS_GUARD(slot < cap, BS_BWD_SLOT)) {
-#pragma unroll
-                for (int k = 0; k < NPART; ++k) part[k * cap + slot] = acc[k];
+                // dq = -ada / 2: dL/dA = sum dq t^2, dL/dgamma = sum dq dy^2, dL/dbeta = 2 A sum dq t dy,
+                // dL/dmx = -2 A sum dq t, dL/dmy = -2 A beta sum dq t - 2 gamma sum dq dy
+                const float *v = acc.v;
+                float4 *o = reinterpret_cast<float4 *>(part + slot * PART_STRIDE);
+                o[0] = make_float4(A * v[S_T], fmaf(A * beta, v[S_T], gam * v[S_Y]), -0.5f * v[S_TT], -A * v[S_TY]);
+                o[1] = make_float4(-0.5f * v[S_YY], v[S_O] / r2w, v[S_W], wgt * v[S_CR]);
+                o[2] = make_float4(wgt * v[S_CG], wgt * v[S_CB], 0.f, 0.f);
             }
         }
     }
 }
 
-// ------------------------------------------------------------------ 2. per-Gaussian reduce
+// ------------------------------------------------------------------ 3. per-Gaussian reduce
+// 16 lanes per Gaussian: lane j sums slots j, j + 16, ... of the Gaussian, then a fixed
+// butterfly over the 16 lanes.
 __global__ void __launch_bounds__(256)
 bwd_reduce_kernel(const uint32_t *__restrict__ first, const uint32_t *__restrict__ ntiles, int64_t n,
                   const float *__restrict__ part, uint64_t cap, const uint32_t *__restrict__ n_pairs,
                   float *__restrict__ gr) {
-    const int64_t g = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int l = threadIdx.x & 63;
-    if (g >= n) return;
+    const int64_t g = int64_t(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const int l = threadIdx.x & 15;
+    const bool ok = g < n;
     // lists that overflowed their capacity in the forward carry no gradient
-    const uint32_t nt = uint64_t(*n_pairs) <= cap ? ntiles[g] : 0u;
-    const uint64_t e0 = first[g];
+    const uint32_t nt = (ok && uint64_t(*n_pairs) <= cap) ? ntiles[g] : 0u;
+    const uint64_t e0 = ok ? first[g] : 0u;
     float acc[NPART];
 #pragma unroll
     for (int k = 0; k < NPART; ++k) acc[k] = 0.f;
-    for (uint32_t j = l; j < nt; j += 64) {
-#pragma unroll
-        for (int k = 0; k < NPART; ++k) acc[k] += part[k * cap + e0 + j];
+    for (uint32_t j = l; j < nt; j += 16) {
+        const float4 *rec = reinterpret_cast<const float4 *>(part + (e0 + j) * PART_STRIDE);
+        const float4 a = rec[0], b = rec[1];
+        const float2 c = *reinterpret_cast<const float2 *>(rec + 2);
+        acc[0] += a.x; acc[1] += a.y; acc[2] += a.z; acc[3] += a.w;
+        acc[4] += b.x; acc[5] += b.y; acc[6] += b.z; acc[7] += b.w;
+        acc[8] += c.x; acc[9] += c.y;
     }
 #pragma unroll
     for (int k = 0; k < NPART; ++k) {
         float v = acc[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
         acc[k] = v;
     }
-    if (l == 0) {
+    if (ok && l < NPART) {
+        float v = acc[0];
 #pragma unroll
-        for (int k = 0; k < NPART; ++k) gr[k * n + g] = acc[k];
+        for (int k = 1; k < NPART; ++k) v = l == k ? acc[k] : v;
+        gr[int64_t(l) * n + g] = v;
     }
 }
 
@@ -399,58 +554,81 @@ bwd_mlp_kernel(mgs_gaussians gs, CamK cam, const float *__restrict__ prm, const 
 
 // ------------------------------------------------------------------ 5. weight gradients
 // Outer-product sums: out[r][c] = sum_g L[g][r] * R[g][c] for c < nc, and the
-// bias column out[r][nc] = sum_g L[g][r].  Partial sums per chunk of WG_CHUNK
-// Gaussians; the chunks are added in order by wgrad_sum_kernel.
+// bias column out[r][nc] = sum_g L[g][r], over the per-Gaussian vectors of bwd_mlp.
+// wgrad_partial: one workgroup per chunk of WG_CHUNK Gaussians; each wave takes a quarter of
+// the chunk and forms the sums with float32 matrix instructions (32 x 32 output blocks, two
+// Gaussians per step: lane l supplies L[g + l / 32][r0 + l % 32] and R[g + l / 32][c0 + l % 32]);
+// the four waves' sums are added in wave order.  wgrad_sum adds the chunks in chunk order.
 struct WJob {
     int loff, roff, nr, nc, out_off;   // vector offsets in the per-Gaussian record; result layout
 };
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __global__ void __launch_bounds__(256)
 wgrad_partial_kernel(const float *__restrict__ vec, int64_t n, WJob job, float *__restrict__ partial) {
-    __shared__ float sL[64][65];
-    __shared__ float sR[64][65];
-    const int64_t g0 = int64_t(blockIdx.x) * WG_CHUNK;
-    const int nout = job.nr * (job.nc + 1);
-    float acc[17];
-#pragma unroll
-    for (int k = 0; k < 17; ++k) acc[k] = 0.f;
-    for (int64_t sub = 0; sub < WG_CHUNK; sub += 64) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-            const int r = e / 64, c = e % 64;
-            const int64_t g = g0 + sub + r;
-            const bool ok = g < n;
-            sL[r][c] = (ok && c < job.nr) ? vec[size_t(g) * MLP_VEC + job.loff + c] : 0.f;
-            sR[r][c] = (ok && c < job.nc) ? vec[size_t(g) * MLP_VEC + job.roff + c] : 0.f;
+    __shared__ float s_out[64][65];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int kk = l >> 5, mm = l & 31;
+    const int64_t g0 = int64_t(blockIdx.x) * WG_CHUNK + int64_t(w) * (WG_CHUNK / 4);
+    const int64_t g1 = g0 + WG_CHUNK / 4 < n ? g0 + WG_CHUNK / 4 : n;
+    const bool two_r = job.nr > 32, two_c = job.nc > 32;                  // block-uniform
+    f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+    float bias0 = 0.f, bias1 = 0.f;
+    for (int64_t g = g0; g < g1; g += 2) {
+        const int64_t gi = g + kk;
+        const bool ok = gi < g1;
+        const float *row = vec + size_t(ok ? gi : 0) * MLP_VEC;
+        const float a0 = (ok && mm < job.nr) ? row[job.loff + mm] : 0.f;
+        const float b0 = (ok && mm < job.nc) ? row[job.roff + mm] : 0.f;
+        const float a1 = (ok && two_r && mm + 32 < job.nr) ? row[job.loff + 32 + mm] : 0.f;
+        const float b1 = (ok && two_c && mm + 32 < job.nc) ? row[job.roff + 32 + mm] : 0.f;
+        acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
+        if (two_c) acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
+        if (two_r) {
+            acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
+            if (two_c) acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
         }
-        if (threadIdx.x < 64) sR[threadIdx.x][64] = (g0 + sub + threadIdx.x < n) ? 1.f : 0.f;
-        __syncthreads();
+        bias0 += a0;
+        bias1 += a1;
+    }
+    bias0 += __shfl_xor(bias0, 32, 64);                 // the two Gaussians of each step
+    bias1 += __shfl_xor(bias1, 32, 64);
+    // output element v of lane l of a 32 x 32 block: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww) {
 #pragma unroll
-        for (int k = 0; k < 17; ++k) {
-            const int o = threadIdx.x + k * 256;
-            if (o < nout) {
-                const int r = o / (job.nc + 1), c = o % (job.nc + 1);
-                const int cc = c == job.nc ? 64 : c;
-                float a = acc[k];
-                for (int j = 0; j < 64; ++j) a = fmaf(sL[j][r], sR[j][cc], a);
-                acc[k] = a;
+            for (int v = 0; v < 16; ++v) {
+                const int r = 8 * (v / 4) + 4 * kk + (v % 4), c = mm;
+                const float x00 = acc00[v], x01 = acc01[v], x10 = acc10[v], x11 = acc11[v];
+                s_out[r][c] = ww == 0 ? x00 : s_out[r][c] + x00;
+                s_out[r][c + 32] = ww == 0 ? x01 : s_out[r][c + 32] + x01;
+                s_out[r + 32][c] = ww == 0 ? x10 : s_out[r + 32][c] + x10;
+                s_out[r + 32][c + 32] = ww == 0 ? x11 : s_out[r + 32][c + 32] + x11;
+            }
+            if (kk == 0) {
+                s_out[mm][64] = ww == 0 ? bias0 : s_out[mm][64] + bias0;
+                s_out[mm + 32][64] = ww == 0 ? bias1 : s_out[mm + 32][64] + bias1;
             }
         }
+        __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < 17; ++k) {
-        const int o = threadIdx.x + k * 256;
-        if (o < nout) partial[size_t(blockIdx.x) * nout + o] = acc[k];
+    const int nout = job.nr * (job.nc + 1);
+    for (int o = threadIdx.x; o < nout; o += 256) {
+        const int r = o / (job.nc + 1), c = o % (job.nc + 1);
+        partial[size_t(blockIdx.x) * nout + o] = s_out[r][c == job.nc ? 64 : c];
     }
 }
 
+// One wave per output: lanes sum chunks lane, lane + 64, ... in order, then a fixed butterfly.
 __global__ void __launch_bounds__(256)
 wgrad_sum_kernel(const float *__restrict__ partial, int nchunks, WJob job, float *__restrict__ dmlp) {
     const int nout = job.nr * (job.nc + 1);
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    if (o >= nout) return;                              // wave-uniform
     float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += partial[size_t(c) * nout + o];
+    for (int c = l; c < nchunks; c += 64) s += partial[size_t(c) * nout + o];
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (l != 0) return;
     const int r = o / (job.nc + 1), c = o % (job.nc + 1);
     // job.out_off encodes where weights / biases go (see launch site)
     if (job.out_off == 0) {           // W1 [64][22] + b1
@@ -470,23 +648,29 @@ __global__ void fill_zero_kernel(float *__restrict__ p, int n) {
 
 // ------------------------------------------------------------------ host side
 struct BwdLayout {
-    size_t first, scan, part, gr, gphi, gom, vec, wpart, total;
+    size_t first, scan, chunks, cbase, tscan, items, part, gr, gphi, gom, vec, wpart, total;
+    uint64_t max_items;
     int nchunks;
 };
 
-inline BwdLayout bwd_layout(int64_t n, uint64_t cap, bool mlp) {
+inline BwdLayout bwd_layout(int64_t n, uint32_t T, uint64_t cap, bool mlp) {
     BwdLayout L;
-    const size_t nn = size_t(n > 0 ? n : 1), cc = size_t(cap > 0 ? cap : 1);
+    const size_t nn = size_t(n > 0 ? n : 1), cc = size_t(cap > 0 ? cap : 1), tt = size_t(T > 0 ? T : 1);
     L.nchunks = int((nn + WG_CHUNK - 1) / WG_CHUNK);
+    L.max_items = bwd_max_items(T, cc);
     size_t o = 0;
-    L.first = o; o = align_up(o + nn * 4, 256);
-    L.scan = o;  o = align_up(o + scan_tmp_elems(n) * 8 + 16, 256);
-    L.part = o;  o = align_up(o + cc * NPART * 4, 256);
-    L.gr = o;    o = align_up(o + nn * NPART * 4, 256);
-    L.gphi = o;  o = align_up(o + (mlp ? nn * 4 : 0), 256);
-    L.gom = o;   o = align_up(o + (mlp ? nn * 4 : 0), 256);
-    L.vec = o;   o = align_up(o + (mlp ? nn * MLP_VEC * 4 : 0), 256);
-    L.wpart = o; o = align_up(o + (mlp ? size_t(L.nchunks) * 64 * 65 * 4 : 0), 256);
+    L.first = o;  o = align_up(o + nn * 4, 256);
+    L.scan = o;   o = align_up(o + scan_tmp_elems(n) * 8 + 16, 256);
+    L.chunks = o; o = align_up(o + tt * 4, 256);
+    L.cbase = o;  o = align_up(o + tt * 4, 256);
+    L.tscan = o;  o = align_up(o + scan_tmp_elems(int64_t(tt)) * 8 + 16, 256);
+    L.items = o;  o = align_up(o + size_t(L.max_items) * 8, 256);
+    L.part = o;   o = align_up(o + cc * PART_STRIDE * 4, 256);
+    L.gr = o;     o = align_up(o + nn * NPART * 4, 256);
+    L.gphi = o;   o = align_up(o + (mlp ? nn * 4 : 0), 256);
+    L.gom = o;    o = align_up(o + (mlp ? nn * 4 : 0), 256);
+    L.vec = o;    o = align_up(o + (mlp ? nn * MLP_VEC * 4 : 0), 256);
+    L.wpart = o;  o = align_up(o + (mlp ? size_t(L.nchunks) * 64 * 65 * 4 : 0), 256);
     L.total = o;
     return L;
 }
@@ -496,7 +680,8 @@ inline BwdLayout bwd_layout(int64_t n, uint64_t cap, bool mlp) {
 extern "C" int mgs_render_backward_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity,
                                              int with_mlp, size_t *bytes) {
     MGS_REQUIRE(bytes && n >= 0 && tiles_x > 0 && tiles_y > 0, "bad arguments");
-    *bytes = mgs::bwd_layout(n, capacity, with_mlp != 0).total;
+    MGS_REQUIRE(uint64_t(tiles_x) * uint64_t(tiles_y) < (uint64_t(1) << 31), "tile grid too large");
+    *bytes = mgs::bwd_layout(n, uint32_t(tiles_x) * uint32_t(tiles_y), capacity, with_mlp != 0).total;
     return MGS_OK;
 }
 
@@ -512,13 +697,15 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
     if ((rc = check_gaussians(g)) != MGS_OK) return rc;
     if ((rc = check_camera(cam)) != MGS_OK) return rc;
     if ((rc = check_projected(proj, g->n)) != MGS_OK) return rc;
-    MGS_REQUIRE(out && bg && tile_offsets && aux && dL_dimage, "a required pointer is NULL");
+    MGS_REQUIRE(out && bg && tile_offsets && gids && aux && dL_dimage, "a required pointer is NULL");
     MGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f && alpha_max > alpha_min && alpha_max < 1.f, "bad alpha range");
     const bool mlp = mlp_params != nullptr;
     MGS_REQUIRE(!mlp || (phi && omod && dmlp), "the MLP path needs phi, omod and dmlp");
     MGS_REQUIRE(capacity < (uint64_t(1) << 32), "capacity too large");
     const int64_t n = g->n;
-    const BwdLayout L = bwd_layout(n, capacity, mlp);
+    const CamK k = make_camk(cam);
+    const uint32_t T = uint32_t(k.tiles_x) * uint32_t(k.tiles_y);
+    const BwdLayout L = bwd_layout(n, T, capacity, mlp);
     MGS_REQUIRE(ws && aligned(ws, 256) && ws_bytes >= L.total, "workspace too small (%zu < %zu)", ws_bytes, L.total);
     if (n > 0) MGS_REQUIRE(out->mean && out->log_scale && out->quat && out->opacity_logit && out->sh,
                            "a gradient pointer is NULL");
@@ -527,13 +714,17 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
     uint32_t *first = reinterpret_cast<uint32_t *>(w + L.first);
     uint64_t *stmp = reinterpret_cast<uint64_t *>(w + L.scan);
     uint32_t *ptot = reinterpret_cast<uint32_t *>(w + L.scan + scan_tmp_elems(n) * 8);
+    uint32_t *chunks = reinterpret_cast<uint32_t *>(w + L.chunks);
+    uint32_t *cbase = reinterpret_cast<uint32_t *>(w + L.cbase);
+    uint64_t *ttmp = reinterpret_cast<uint64_t *>(w + L.tscan);
+    uint32_t *n_items = reinterpret_cast<uint32_t *>(w + L.tscan + scan_tmp_elems(int64_t(T > 0 ? T : 1)) * 8);
+    uint2 *items = reinterpret_cast<uint2 *>(w + L.items);
     float *part = reinterpret_cast<float *>(w + L.part);
     float *gr = reinterpret_cast<float *>(w + L.gr);
     float *gphi = mlp ? reinterpret_cast<float *>(w + L.gphi) : nullptr;
     float *gom = mlp ? reinterpret_cast<float *>(w + L.gom) : nullptr;
     float *vec = reinterpret_cast<float *>(w + L.vec);
     float *wpart = reinterpret_cast<float *>(w + L.wpart);
-    const CamK k = make_camk(cam);
     if (n == 0) {
         if (mlp) {
             hipLaunchKernelGGL(fill_zero_kernel, dim3((MGS_MLP_PARAMS + 255) / 256), dim3(256), 0, s, dmlp,
@@ -543,13 +734,21 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
         return MGS_OK;
     }
     if ((rc = scan_exclusive(proj->n_tiles, first, n, stmp, ptot, s)) != MGS_OK) return rc;
-    const unsigned T = unsigned(k.tiles_x) * unsigned(k.tiles_y);
-    hipLaunchKernelGGL(bwd_blend_kernel, dim3(T), dim3(256), 0, s, reinterpret_cast<const float4 *>(proj->splat),
-                       reinterpret_cast<const uint2 *>(proj->rect), first, tile_offsets, gids, k, bg[0], bg[1], bg[2],
-                       log2f(alpha_min), alpha_max, aux, dL_dimage, part, uint64_t(capacity > 0 ? capacity : 1));
+    const uint64_t cap1 = uint64_t(capacity > 0 ? capacity : 1);
+    hipLaunchKernelGGL(bwd_chunks_kernel, dim3((T + 255) / 256), dim3(256), 0, s, tile_offsets, T, ptot, cap1, chunks);
+    MGS_LAUNCH_CHECK("bwd_chunks_kernel");
+    if ((rc = scan_exclusive(chunks, cbase, int64_t(T), ttmp, n_items, s)) != MGS_OK) return rc;
+    hipLaunchKernelGGL(bwd_items_kernel, dim3((T + 255) / 256), dim3(256), 0, s, tile_offsets, chunks, cbase, T,
+                       L.max_items, items);
+    MGS_LAUNCH_CHECK("bwd_items_kernel");
+    const unsigned grid = unsigned(L.max_items < BWD_GRID_MAX ? L.max_items : BWD_GRID_MAX);
+    hipLaunchKernelGGL(bwd_blend_kernel, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float4 *>(proj->splat),
+                       reinterpret_cast<const uint2 *>(proj->rect), first, tile_offsets, gids, items, n_items,
+                       L.max_items, ptot, k, bg[0], bg[1], bg[2], log2f(alpha_min), alpha_max, aux, dL_dimage, part,
+                       cap1);
     MGS_LAUNCH_CHECK("bwd_blend_kernel");
-    hipLaunchKernelGGL(bwd_reduce_kernel, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, first, proj->n_tiles, n,
-                       part, uint64_t(capacity > 0 ? capacity : 1), ptot, gr);
+    hipLaunchKernelGGL(bwd_reduce_kernel, dim3(unsigned((n + 15) / 16)), dim3(256), 0, s, first, proj->n_tiles, n,
+                       part, cap1, ptot, gr);
     MGS_LAUNCH_CHECK("bwd_reduce_kernel");
     hipLaunchKernelGGL(bwd_gauss_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, *g, k, phi, omod,
                        proj->n_tiles, gr, *out, gphi, gom);
@@ -563,7 +762,7 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
             hipLaunchKernelGGL(wgrad_partial_kernel, dim3(unsigned(L.nchunks)), dim3(256), 0, s, vec, n, jobs[j], wpart);
             MGS_LAUNCH_CHECK("wgrad_partial_kernel");
             const int nout = jobs[j].nr * (jobs[j].nc + 1);
-            hipLaunchKernelGGL(wgrad_sum_kernel, dim3(unsigned((nout + 255) / 256)), dim3(256), 0, s, wpart,
+            hipLaunchKernelGGL(wgrad_sum_kernel, dim3(unsigned((nout + 3) / 4)), dim3(256), 0, s, wpart,
                                L.nchunks, jobs[j], dmlp);
             MGS_LAUNCH_CHECK("wgrad_sum_kernel");
         }

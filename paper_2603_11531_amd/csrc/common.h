@@ -115,6 +115,7 @@ enum BoundsSite : uint32_t {
     BS_LIST_READ = 1u << 3,        // a tile-list range past the pair count
     BS_SPLIT_ITEM = 1u << 4,       // a split-blend work item or slot past its workspace bound
     BS_BWD_SLOT = 1u << 5,         // a backward pair slot past the capacity
+    BS_BWD_ITEM = 1u << 6,         // a backward work item past its workspace bound
 };
 #ifdef MGS_CHECK_BOUNDS
 static __device__ uint32_t tu_bounds_flags;
