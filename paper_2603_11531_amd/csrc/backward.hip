@@ -24,11 +24,10 @@
 //   3. bwd_reduce: 16 lanes per Gaussian sum its contiguous slots (fixed tree);
 //   4. bwd_gauss: per-Gaussian chain rule to mean, log-scale, quaternion,
 //      opacity logit, SH and (with the MLP) to phi and the opacity factor;
-//   5. bwd_mlp: per-Gaussian MLP backward in float32 (straight through the
-//      bfloat16 roundings of the forward) -> input gradients, and the per-Gaussian
-//      vectors whose outer products give the weight gradients;
-//   6. wgrad_partial / wgrad_sum: chunked outer-product sums (float32 matrix
-//      instructions), summed in chunk order.
+//   5. bwd_mlp: the MLP backward in float32 (straight through the bfloat16
+//      roundings of the forward) on matrix instructions, 64 Gaussians per workgroup
+//      step: input gradients, and per-workgroup sums of the weight gradients;
+//   6. mlp_wsum: the workgroups' weight-gradient sums added in workgroup order.
 #include "blend_math.h"
 #include "proj_math.h"
 
@@ -38,9 +37,6 @@ constexpr int NPART = 10;        // mx, my, A, beta, gamma, o, w, r, g, b
 constexpr int PART_STRIDE = 12;  // floats per pair record: the 10 sums and 2 zeros (48-byte records)
 constexpr uint32_t BWD_CHUNK = 256;   // list positions per blend work item (one per thread)
 constexpr unsigned BWD_GRID_MAX = 1u << 20;   // blend workgroups; more items are walked in a grid stride
-constexpr int WG_CHUNK = 512;    // Gaussians per weight-gradient workgroup (128 per wave)
-constexpr int MLP_VEC = 24 + 64 + 64 + 64 + 64 + 2;   // xb(22, padded), h1b, Fb, dH1, dF, (dphi, dm)
-constexpr int OFF_XB = 0, OFF_H1 = 24, OFF_FB = 88, OFF_DH1 = 152, OFF_DF = 216, OFF_DHD = 280;
 
 // Work items of the blend backward for T tiles and at most `capacity` pairs: sum over tiles of
 // ceil(L_t / BWD_CHUNK) <= capacity / BWD_CHUNK + T.
@@ -441,204 +437,340 @@ bwd_gauss_kernel(mgs_gaussians gs, CamK cam, const float *__restrict__ phi_in, c
 }
 
 // ------------------------------------------------------------------ 4. MLP backward
-__global__ void __launch_bounds__(128)
+// Super tiles of 64 Gaussians per workgroup, 16 per wave, all products on float32 matrix
+// instructions (v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16 x 4 by 4 x 16 product; output element v of lane l is D[4 (l / 16) + v][l % 16]).
+// Per wave and its 16 Gaussians: the features x (bfloat16-rounded as the forward rounds them),
+// layer 1 and 2 recomputed (pre-activations kept as ReLU masks, activations rounded to
+// bfloat16), the heads, dF (dL/d layer-2 output), dH1 = (dF W2) masked, dx = dH1 W1 -> input
+// gradients.  The weight gradients dW2 += dF^T h1 and dW1 += dH1^T x are shared out by rows:
+// wave w accumulates rows 16 w .. 16 w + 15 over all 64 Gaussians of the super tile (read from
+// the other waves' LDS between workgroup barriers), in registers over the workgroup's super
+// tiles; bias and head sums per lane.  One record of sums per workgroup; mlp_wsum adds the
+// workgroups in order.
+constexpr int MT = 16;                  // Gaussians per wave per super tile
+constexpr int XS = 25, HS = 65;         // LDS row strides (floats) of x and of the 64-wide rows
+constexpr int W1S = 23, W2S = 65;       // LDS row strides of W1 [64][22] and W2 [64][64]
+constexpr int MLP_WAVE_LDS = MT * XS + 2 * MT * HS + 2 * MT + 12 * MT;   // floats per wave
+constexpr unsigned MLP_BLOCKS_MAX = 512;   // persistent workgroups
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// LDS written by some lanes of a wave and read by others after this point (a wave's LDS
+// accesses are performed in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ f32x4v mfma16(float a, float b, f32x4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+inline unsigned mlp_blocks(int64_t n) {
+    const int64_t tiles = (n + 4 * MT - 1) / (4 * MT);
+    return unsigned(tiles < 1 ? 1 : (tiles < int64_t(MLP_BLOCKS_MAX) ? tiles : int64_t(MLP_BLOCKS_MAX)));
+}
+
+__global__ void __launch_bounds__(256)
 bwd_mlp_kernel(mgs_gaussians gs, CamK cam, const float *__restrict__ prm, const float *__restrict__ gphi_in,
-               const float *__restrict__ gom_in, mgs_gaussians_grad out, float *__restrict__ vec) {
-    __shared__ float sW1[64 * 22];
-    __shared__ float sW2[64 * 64];
-    __shared__ float sB1[64], sB2[64], sWp[64], sWo[64];
-    for (int e = threadIdx.x; e < 64 * 22; e += blockDim.x) sW1[e] = bf16_round(prm[MGS_MLP_OFF_W1 + e]);
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) sW2[e] = bf16_round(prm[MGS_MLP_OFF_W2 + e]);
-    for (int e = threadIdx.x; e < 64; e += blockDim.x) {
-        sB1[e] = prm[MGS_MLP_OFF_B1 + e];
-        sB2[e] = prm[MGS_MLP_OFF_B2 + e];
-        sWp[e] = bf16_round(prm[MGS_MLP_OFF_WPHI + e]);
-        sWo[e] = bf16_round(prm[MGS_MLP_OFF_WO + e]);
+               const float *__restrict__ gom_in, mgs_gaussians_grad out, float *__restrict__ wpart) {
+    __shared__ float sW1[64 * W1S];
+    __shared__ float sW2[64 * W2S];
+    __shared__ float sV[4][64];             // w_phi, w_o (bfloat16-rounded), b1, b2
+    __shared__ float s_wave[4][MLP_WAVE_LDS];
+    for (int e = threadIdx.x; e < 64 * 22; e += 256) sW1[(e / 22) * W1S + e % 22] = bf16_round(prm[MGS_MLP_OFF_W1 + e]);
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) sW2[(e / 64) * W2S + e % 64] = bf16_round(prm[MGS_MLP_OFF_W2 + e]);
+    {
+        const int r = threadIdx.x >> 6, c = threadIdx.x & 63;
+        const int off[4] = {MGS_MLP_OFF_WPHI, MGS_MLP_OFF_WO, MGS_MLP_OFF_B1, MGS_MLP_OFF_B2};
+        sV[r][c] = r < 2 ? bf16_round(prm[off[r] + c]) : prm[off[r] + c];
     }
     __syncthreads();
-    const float bphi = prm[MGS_MLP_OFF_BPHI], bo = prm[MGS_MLP_OFF_BO];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    // wave ww's buffers: x [MT][XS]; P: h1, then dH1 [MT][HS]; Q: layer-2 output, then dF, then dx
+    // [MT][HS]; (dphi, dmo) [MT][2]; P, 1/|v|, q, 1/|q|, s of its Gaussians [12][MT]
+    auto bufX = [&](int ww) { return s_wave[ww]; };
+    auto bufP = [&](int ww) { return s_wave[ww] + MT * XS; };
+    auto bufQ = [&](int ww) { return s_wave[ww] + MT * XS + MT * HS; };
+    float *sX = bufX(w), *sP = bufP(w), *sQ = bufQ(w);
+    float *sD = sQ + MT * HS;
+    float *sG = sD + 2 * MT;
     const int64_t n = gs.n;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float *V = vec + size_t(i) * MLP_VEC;
-    // features, rounded as the forward rounds them
-    const float mx = gs.mean[i], my = gs.mean[n + i], mz = gs.mean[2 * n + i];
-    const float v0 = mx - cam.campos[0], v1 = my - cam.campos[1], v2 = mz - cam.campos[2];
-    const float vl = sqrtf(v0 * v0 + v1 * v1 + v2 * v2), ivl = 1.0f / vl;
-    const float P[3] = {v0 * ivl, v1 * ivl, v2 * ivl};
-    float q[4], s[3];
+    const float bphi = prm[MGS_MLP_OFF_BPHI], bo = prm[MGS_MLP_OFF_BO];
+    // rows 16 w .. 16 w + 15 of dW2 (four column blocks) and dW1 (two); per lane j = l: sums of
+    // db1, db2, dw_phi, dw_o over this wave's Gaussians; dbphi, dbo (the same in every lane)
+    f32x4v gW2[4], gW1[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = gs.quat[k * n + i];
-    const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const float iqn = qn > 0.f ? 1.0f / qn : 0.f;
+    for (int b = 0; b < 4; ++b) gW2[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    gW1[0] = gW1[1] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    float gb1 = 0.f, gb2 = 0.f, gwp = 0.f, gwo = 0.f, gbphi = 0.f, gbo = 0.f;
+    const int64_t tiles = (n + 4 * MT - 1) / (4 * MT);
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {   // block-uniform
+        const int64_t g0 = tile * (4 * MT) + w * MT;
+        // 1. features of Gaussian g0 + l (lanes 0 .. 15)
+        const int64_t gi = g0 + li;
+        const bool mine = l < MT && gi < n;
+        if (l < MT) {
+            float P[3] = {0.f, 0.f, 0.f}, q[4] = {0.f, 0.f, 0.f, 0.f}, sc[3] = {0.f, 0.f, 0.f}, ivl = 0.f, iqn = 0.f;
+            float x[22];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] *= iqn;
+            for (int k = 0; k < 22; ++k) x[k] = 0.f;
+            if (mine) {
+                const float v0 = gs.mean[gi] - cam.campos[0], v1 = gs.mean[n + gi] - cam.campos[1],
+                            v2 = gs.mean[2 * n + gi] - cam.campos[2];
+                const float vl = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                ivl = 1.0f / vl;
+                P[0] = v0 * ivl; P[1] = v1 * ivl; P[2] = v2 * ivl;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s[k] = expf(gs.log_scale[k * n + i]);
-    float x[22];
+                for (int k = 0; k < 4; ++k) q[k] = gs.quat[k * n + gi];
+                const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+                iqn = qn > 0.f ? 1.0f / qn : 0.f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { x[k] = P[k]; x[3 + k] = s[k]; }
+                for (int k = 0; k < 4; ++k) q[k] *= iqn;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[6 + k] = q[k];
+                for (int k = 0; k < 3; ++k) sc[k] = expf(gs.log_scale[k * n + gi]);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x[10 + k] = gs.sh[k * n + i];
+                for (int k = 0; k < 3; ++k) { x[k] = P[k]; x[3 + k] = sc[k]; }
 #pragma unroll
-    for (int k = 0; k < 22; ++k) { x[k] = bf16_round(x[k]); V[OFF_XB + k] = x[k]; }
-    V[OFF_XB + 22] = 0.f;
-    V[OFF_XB + 23] = 0.f;
-    // forward, layer 1
-    float h[64];
-    uint64_t m1 = 0;
+                for (int k = 0; k < 4; ++k) x[6 + k] = q[k];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        float acc = sB1[j];
-#pragma unroll
-        for (int k = 0; k < 22; ++k) acc = fmaf(sW1[j * 22 + k], x[k], acc);
-        m1 |= uint64_t(acc > 0.f) << j;
-        h[j] = bf16_round(fmaxf(acc, 0.f));
-        V[OFF_H1 + j] = h[j];
-    }
-    // forward, layer 2 and heads
-    uint64_t m2 = 0;
-    float php = bphi, mop = bo;
-#pragma unroll 4
-    for (int j = 0; j < 64; ++j) {
-        float acc = sB2[j];
-#pragma unroll
-        for (int k = 0; k < 64; ++k) acc = fmaf(sW2[j * 64 + k], h[k], acc);
-        m2 |= uint64_t(acc > 0.f) << j;
-        const float fb = bf16_round(fmaxf(acc, 0.f));
-        V[OFF_FB + j] = fb;
-        php = fmaf(sWp[j], fb, php);
-        mop = fmaf(sWo[j], fb, mop);
-    }
-    const float m = 1.0f / (1.0f + expf(-mop));
-    const float dphi = php > 0.f ? gphi_in[i] : 0.f;
-    const float dmo = gom_in[i] * m * (1.0f - m);
-    V[OFF_DHD + 0] = dphi;
-    V[OFF_DHD + 1] = dmo;
-    // backward, layer 2 (h is reused as dL/dh1)
-#pragma unroll
-    for (int k = 0; k < 64; ++k) h[k] = 0.f;
-#pragma unroll 4
-    for (int j = 0; j < 64; ++j) {
-        const float dF = ((m2 >> j) & 1ull) ? fmaf(dphi, sWp[j], dmo * sWo[j]) : 0.f;
-        V[OFF_DF + j] = dF;
-#pragma unroll
-        for (int k = 0; k < 64; ++k) h[k] = fmaf(sW2[j * 64 + k], dF, h[k]);
-    }
-    // backward, layer 1
-    float dx[22];
-#pragma unroll
-    for (int k = 0; k < 22; ++k) dx[k] = 0.f;
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        const float d = ((m1 >> j) & 1ull) ? h[j] : 0.f;
-        V[OFF_DH1 + j] = d;
-#pragma unroll
-        for (int k = 0; k < 22; ++k) dx[k] = fmaf(sW1[j * 22 + k], d, dx[k]);
-    }
-    // input gradients: P -> mean, s -> log_scale, q -> raw quaternion, Y -> sh
-    const float pd = P[0] * dx[0] + P[1] * dx[1] + P[2] * dx[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        out.mean[k * n + i] += (dx[k] - P[k] * pd) * ivl;
-        out.log_scale[k * n + i] += dx[3 + k] * s[k];
-    }
-    const float qd = q[0] * dx[6] + q[1] * dx[7] + q[2] * dx[8] + q[3] * dx[9];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) out.quat[k * n + i] += (dx[6 + k] - q[k] * qd) * iqn;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) out.sh[k * n + i] += dx[10 + k];
-}
-
-// ------------------------------------------------------------------ 5. weight gradients
-// Outer-product sums: out[r][c] = sum_g L[g][r] * R[g][c] for c < nc, and the
-// bias column out[r][nc] = sum_g L[g][r], over the per-Gaussian vectors of bwd_mlp.
-// wgrad_partial: one workgroup per chunk of WG_CHUNK Gaussians; each wave takes a quarter of
-// the chunk and forms the sums with float32 matrix instructions (32 x 32 output blocks, two
-// Gaussians per step: lane l supplies L[g + l / 32][r0 + l % 32] and R[g + l / 32][c0 + l % 32]);
-// the four waves' sums are added in wave order.  wgrad_sum adds the chunks in chunk order.
-struct WJob {
-    int loff, roff, nr, nc, out_off;   // vector offsets in the per-Gaussian record; result layout
-};
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-__global__ void __launch_bounds__(256)
-wgrad_partial_kernel(const float *__restrict__ vec, int64_t n, WJob job, float *__restrict__ partial) {
-    __shared__ float s_out[64][65];
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int kk = l >> 5, mm = l & 31;
-    const int64_t g0 = int64_t(blockIdx.x) * WG_CHUNK + int64_t(w) * (WG_CHUNK / 4);
-    const int64_t g1 = g0 + WG_CHUNK / 4 < n ? g0 + WG_CHUNK / 4 : n;
-    const bool two_r = job.nr > 32, two_c = job.nc > 32;                  // block-uniform
-    f32x16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-    float bias0 = 0.f, bias1 = 0.f;
-    for (int64_t g = g0; g < g1; g += 2) {
-        const int64_t gi = g + kk;
-        const bool ok = gi < g1;
-        const float *row = vec + size_t(ok ? gi : 0) * MLP_VEC;
-        const float a0 = (ok && mm < job.nr) ? row[job.loff + mm] : 0.f;
-        const float b0 = (ok && mm < job.nc) ? row[job.roff + mm] : 0.f;
-        const float a1 = (ok && two_r && mm + 32 < job.nr) ? row[job.loff + 32 + mm] : 0.f;
-        const float b1 = (ok && two_c && mm + 32 < job.nc) ? row[job.roff + 32 + mm] : 0.f;
-        acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
-        if (two_c) acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
-        if (two_r) {
-            acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
-            if (two_c) acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
-        }
-        bias0 += a0;
-        bias1 += a1;
-    }
-    bias0 += __shfl_xor(bias0, 32, 64);                 // the two Gaussians of each step
-    bias1 += __shfl_xor(bias1, 32, 64);
-    // output element v of lane l of a 32 x 32 block: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
-    for (int ww = 0; ww < 4; ++ww) {
-        if (w == ww) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = 8 * (v / 4) + 4 * kk + (v % 4), c = mm;
-                const float x00 = acc00[v], x01 = acc01[v], x10 = acc10[v], x11 = acc11[v];
-                s_out[r][c] = ww == 0 ? x00 : s_out[r][c] + x00;
-                s_out[r][c + 32] = ww == 0 ? x01 : s_out[r][c + 32] + x01;
-                s_out[r + 32][c] = ww == 0 ? x10 : s_out[r + 32][c] + x10;
-                s_out[r + 32][c + 32] = ww == 0 ? x11 : s_out[r + 32][c + 32] + x11;
+                for (int k = 0; k < 12; ++k) x[10 + k] = gs.sh[k * n + gi];
             }
-            if (kk == 0) {
-                s_out[mm][64] = ww == 0 ? bias0 : s_out[mm][64] + bias0;
-                s_out[mm + 32][64] = ww == 0 ? bias1 : s_out[mm + 32][64] + bias1;
+#pragma unroll
+            for (int k = 0; k < 22; ++k) sX[l * XS + k] = bf16_round(x[k]);
+            sX[l * XS + 22] = 0.f;
+            sX[l * XS + 23] = 0.f;
+            const float st[12] = {P[0], P[1], P[2], ivl, q[0], q[1], q[2], q[3], iqn, sc[0], sc[1], sc[2]};
+#pragma unroll
+            for (int k = 0; k < 12; ++k) sG[k * MT + l] = st[k];
+        }
+        wave_sync_lds();
+        // 2. layer 1: H1[g][j] = b1[j] + sum_k x[g][k] W1[j][k]
+        uint32_t m1 = 0, m2 = 0;           // ReLU masks, bit 4 nb + v for (g = 4 lk + v, j = 16 nb + li)
+        {
+            f32x4v acc[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int k = 4 * st + lk;
+                const float a = sX[li * XS + k];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb)
+                    acc[nb] = mfma16(a, k < 22 ? sW1[(16 * nb + li) * W1S + k] : 0.f, acc[nb]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float h = acc[nb][v] + sV[2][16 * nb + li];
+                    m1 |= uint32_t(h > 0.f) << (4 * nb + v);
+                    sP[(4 * lk + v) * HS + 16 * nb + li] = bf16_round(fmaxf(h, 0.f));
+                }
+        }
+        wave_sync_lds();
+        // 3. layer 2: F[g][j] = b2[j] + sum_k h1[g][k] W2[j][k]
+        {
+            f32x4v acc[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int st = 0; st < 16; ++st) {
+                const int k = 4 * st + lk;
+                const float a = sP[li * HS + k];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, sW2[(16 * nb + li) * W2S + k], acc[nb]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float f = acc[nb][v] + sV[3][16 * nb + li];
+                    m2 |= uint32_t(f > 0.f) << (4 * nb + v);
+                    sQ[(4 * lk + v) * HS + 16 * nb + li] = bf16_round(fmaxf(f, 0.f));
+                }
+        }
+        wave_sync_lds();
+        // 4. heads for Gaussian li (lane group lk takes neurons 16 lk .. 16 lk + 15), their
+        //    gradients, and the head weight-gradient sums (lane l = neuron j)
+        {
+            float php = 0.f, mop = 0.f;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int j = 16 * lk + c;
+                const float fb = sQ[li * HS + j];
+                php = fmaf(sV[0][j], fb, php);
+                mop = fmaf(sV[1][j], fb, mop);
+            }
+            php += __shfl_xor(php, 16, 64);
+            mop += __shfl_xor(mop, 16, 64);
+            php += __shfl_xor(php, 32, 64);
+            mop += __shfl_xor(mop, 32, 64);
+            php += bphi;
+            mop += bo;
+            const bool gok = g0 + li < n;
+            const float m = 1.0f / (1.0f + expf(-mop));
+            const float dphi = (gok && php > 0.f) ? gphi_in[g0 + li] : 0.f;
+            const float dmo = gok ? gom_in[g0 + li] * m * (1.0f - m) : 0.f;
+            if (lk == 0) {
+                sD[2 * li] = dphi;
+                sD[2 * li + 1] = dmo;
             }
         }
-        __syncthreads();
+        wave_sync_lds();
+#pragma unroll
+        for (int g = 0; g < MT; ++g) {
+            const float dphi = sD[2 * g], dmo = sD[2 * g + 1], fb = sQ[g * HS + l];
+            gwp = fmaf(dphi, fb, gwp);
+            gwo = fmaf(dmo, fb, gwo);
+            gbphi += dphi;
+            gbo += dmo;
+        }
+        wave_sync_lds();                    // the layer-2 outputs are read; Q takes dF
+        // 5. dF[g][j] = (F > 0) (dphi w_phi[j] + dmo w_o[j])
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int g = 4 * lk + v;
+            const float dphi = sD[2 * g], dmo = sD[2 * g + 1];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                sQ[g * HS + 16 * nb + li] =
+                    ((m2 >> (4 * nb + v)) & 1u) ? fmaf(dphi, sV[0][16 * nb + li], dmo * sV[1][16 * nb + li]) : 0.f;
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int g = 0; g < MT; ++g) gb2 += sQ[g * HS + l];
+        __syncthreads();                    // every wave's dF and h1 are written
+        // 6. rows 16 w .. of dW2[j][k] += sum_g dF[g][j] h1[g][k] over the super tile's 64 Gaussians
+#pragma unroll 1
+        for (int ww = 0; ww < 4; ++ww) {
+            const float *qF = bufQ(ww), *qH = bufP(ww);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int g = 4 * st + lk;
+                const float a = qF[g * HS + 16 * w + li];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) gW2[nb] = mfma16(a, qH[g * HS + 16 * nb + li], gW2[nb]);
+            }
+        }
+        __syncthreads();                    // every wave's h1 is read; P takes dH1
+        // 7. dH1[g][k] = (H1 > 0) sum_j dF[g][j] W2[j][k]
+        {
+            f32x4v acc[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int st = 0; st < 16; ++st) {
+                const int j = 4 * st + lk;
+                const float a = sQ[li * HS + j];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, sW2[j * W2S + 16 * nb + li], acc[nb]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    sP[(4 * lk + v) * HS + 16 * nb + li] = ((m1 >> (4 * nb + v)) & 1u) ? acc[nb][v] : 0.f;
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int g = 0; g < MT; ++g) gb1 += sP[g * HS + l];
+        // 9. dx[g][k] = sum_j dH1[g][j] W1[j][k]  (into Q: this wave's dF is read)
+        {
+            f32x4v acc[2] = {f32x4v{0.f, 0.f, 0.f, 0.f}, f32x4v{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 4
+            for (int st = 0; st < 16; ++st) {
+                const int j = 4 * st + lk;
+                const float a = sP[li * HS + j];
+                acc[0] = mfma16(a, sW1[j * W1S + li], acc[0]);
+                acc[1] = mfma16(a, li < 6 ? sW1[j * W1S + 16 + li] : 0.f, acc[1]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sQ[(4 * lk + v) * HS + li] = acc[0][v];
+                if (li < 6) sQ[(4 * lk + v) * HS + 16 + li] = acc[1][v];
+            }
+        }
+        __syncthreads();                    // every wave's dH1 is written
+        // 8. rows 16 w .. of dW1[j][k] += sum_g dH1[g][j] x[g][k] over the super tile
+#pragma unroll 1
+        for (int ww = 0; ww < 4; ++ww) {
+            const float *qD = bufP(ww), *qX = bufX(ww);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int g = 4 * st + lk;
+                const float a = qD[g * HS + 16 * w + li];
+                gW1[0] = mfma16(a, qX[g * XS + li], gW1[0]);
+                gW1[1] = mfma16(a, li < 8 ? qX[g * XS + 16 + li] : 0.f, gW1[1]);
+            }
+        }
+        // 10. input gradients of Gaussian g0 + l: P -> mean, s -> log_scale, q -> raw quaternion, Y -> sh
+        if (mine) {
+            const float *dx = sQ + l * HS;
+            const float P[3] = {sG[0 * MT + l], sG[1 * MT + l], sG[2 * MT + l]}, ivl = sG[3 * MT + l];
+            const float q[4] = {sG[4 * MT + l], sG[5 * MT + l], sG[6 * MT + l], sG[7 * MT + l]}, iqn = sG[8 * MT + l];
+            const float sc[3] = {sG[9 * MT + l], sG[10 * MT + l], sG[11 * MT + l]};
+            const float pd = P[0] * dx[0] + P[1] * dx[1] + P[2] * dx[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                out.mean[k * n + gi] += (dx[k] - P[k] * pd) * ivl;
+                out.log_scale[k * n + gi] += dx[3 + k] * sc[k];
+            }
+            const float qd = q[0] * dx[6] + q[1] * dx[7] + q[2] * dx[8] + q[3] * dx[9];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out.quat[k * n + gi] += (dx[6 + k] - q[k] * qd) * iqn;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) out.sh[k * n + gi] += dx[10 + k];
+        }
+        __syncthreads();                    // the super tile's LDS is reused by the next one
     }
-    const int nout = job.nr * (job.nc + 1);
-    for (int o = threadIdx.x; o < nout; o += 256) {
-        const int r = o / (job.nc + 1), c = o % (job.nc + 1);
-        partial[size_t(blockIdx.x) * nout + o] = s_out[r][c == job.nc ? 64 : c];
+    // this workgroup's sums, in the parameter layout: dW2 / dW1 rows of this wave; the per-lane
+    // vector sums added over the four waves in wave order
+    float *o = wpart + size_t(blockIdx.x) * MGS_MLP_PARAMS;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int j = 16 * w + 4 * lk + v;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) o[MGS_MLP_OFF_W2 + j * 64 + 16 * nb + li] = gW2[nb][v];
+        o[MGS_MLP_OFF_W1 + j * 22 + li] = gW1[0][v];
+        if (li < 6) o[MGS_MLP_OFF_W1 + j * 22 + 16 + li] = gW1[1][v];
+    }
+    float *red = s_wave[0];                 // [4 waves][4][64] + [4][2], after the loop's last barrier
+    red[(w * 4 + 0) * 64 + l] = gb1;
+    red[(w * 4 + 1) * 64 + l] = gb2;
+    red[(w * 4 + 2) * 64 + l] = gwp;
+    red[(w * 4 + 3) * 64 + l] = gwo;
+    if (l == 0) {
+        red[16 * 64 + 2 * w] = gbphi;
+        red[16 * 64 + 2 * w + 1] = gbo;
+    }
+    __syncthreads();
+    {
+        const int r = threadIdx.x >> 6, c = threadIdx.x & 63;   // vector r, element c
+        float acc = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) acc += red[(ww * 4 + r) * 64 + c];
+        const int off[4] = {MGS_MLP_OFF_B1, MGS_MLP_OFF_B2, MGS_MLP_OFF_WPHI, MGS_MLP_OFF_WO};
+        o[off[r] + c] = acc;
+        if (threadIdx.x < 2) {
+            float h = 0.f;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) h += red[16 * 64 + 2 * ww + threadIdx.x];
+            o[threadIdx.x == 0 ? MGS_MLP_OFF_BPHI : MGS_MLP_OFF_BO] = h;
+        }
     }
 }
 
-// One wave per output: lanes sum chunks lane, lane + 64, ... in order, then a fixed butterfly.
+// dmlp[p] = sum over the workgroups' records, in workgroup order (one wave per parameter:
+// lanes take records lane, lane + 64, ..., then a fixed butterfly).
 __global__ void __launch_bounds__(256)
-wgrad_sum_kernel(const float *__restrict__ partial, int nchunks, WJob job, float *__restrict__ dmlp) {
-    const int nout = job.nr * (job.nc + 1);
-    const int o = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
-    if (o >= nout) return;                              // wave-uniform
+mlp_wsum_kernel(const float *__restrict__ wpart, int nrec, float *__restrict__ dmlp) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    if (p >= MGS_MLP_PARAMS) return;                                   // wave-uniform
     float s = 0.f;
-    for (int c = l; c < nchunks; c += 64) s += partial[size_t(c) * nout + o];
+    for (int k = l; k < nrec; k += 64) s += wpart[size_t(k) * MGS_MLP_PARAMS + p];
     for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (l != 0) return;
-    const int r = o / (job.nc + 1), c = o % (job.nc + 1);
-    // job.out_off encodes where weights / biases go (see launch site)
-    if (job.out_off == 0) {           // W1 [64][22] + b1
-        if (c < 22) dmlp[MGS_MLP_OFF_W1 + r * 22 + c] = s; else dmlp[MGS_MLP_OFF_B1 + r] = s;
-    } else if (job.out_off == 1) {    // W2 [64][64] + b2
-        if (c < 64) dmlp[MGS_MLP_OFF_W2 + r * 64 + c] = s; else dmlp[MGS_MLP_OFF_B2 + r] = s;
-    } else {                          // heads: row 0 phi, row 1 opacity
-        if (r == 0) { if (c < 64) dmlp[MGS_MLP_OFF_WPHI + c] = s; else dmlp[MGS_MLP_OFF_BPHI] = s; }
-        else        { if (c < 64) dmlp[MGS_MLP_OFF_WO + c] = s; else dmlp[MGS_MLP_OFF_BO] = s; }
-    }
+    if (l == 0) dmlp[p] = s;
 }
 
 __global__ void fill_zero_kernel(float *__restrict__ p, int n) {
@@ -648,15 +780,13 @@ __global__ void fill_zero_kernel(float *__restrict__ p, int n) {
 
 // ------------------------------------------------------------------ host side
 struct BwdLayout {
-    size_t first, scan, chunks, cbase, tscan, items, part, gr, gphi, gom, vec, wpart, total;
+    size_t first, scan, chunks, cbase, tscan, items, part, gr, gphi, gom, wpart, total;
     uint64_t max_items;
-    int nchunks;
 };
 
 inline BwdLayout bwd_layout(int64_t n, uint32_t T, uint64_t cap, bool mlp) {
     BwdLayout L;
     const size_t nn = size_t(n > 0 ? n : 1), cc = size_t(cap > 0 ? cap : 1), tt = size_t(T > 0 ? T : 1);
-    L.nchunks = int((nn + WG_CHUNK - 1) / WG_CHUNK);
     L.max_items = bwd_max_items(T, cc);
     size_t o = 0;
     L.first = o;  o = align_up(o + nn * 4, 256);
@@ -669,8 +799,7 @@ inline BwdLayout bwd_layout(int64_t n, uint32_t T, uint64_t cap, bool mlp) {
     L.gr = o;     o = align_up(o + nn * NPART * 4, 256);
     L.gphi = o;   o = align_up(o + (mlp ? nn * 4 : 0), 256);
     L.gom = o;    o = align_up(o + (mlp ? nn * 4 : 0), 256);
-    L.vec = o;    o = align_up(o + (mlp ? nn * MLP_VEC * 4 : 0), 256);
-    L.wpart = o;  o = align_up(o + (mlp ? size_t(L.nchunks) * 64 * 65 * 4 : 0), 256);
+    L.wpart = o;  o = align_up(o + (mlp ? size_t(mlp_blocks(n)) * MGS_MLP_PARAMS * 4 : 0), 256);
     L.total = o;
     return L;
 }
@@ -723,7 +852,6 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
     float *gr = reinterpret_cast<float *>(w + L.gr);
     float *gphi = mlp ? reinterpret_cast<float *>(w + L.gphi) : nullptr;
     float *gom = mlp ? reinterpret_cast<float *>(w + L.gom) : nullptr;
-    float *vec = reinterpret_cast<float *>(w + L.vec);
     float *wpart = reinterpret_cast<float *>(w + L.wpart);
     if (n == 0) {
         if (mlp) {
@@ -754,18 +882,11 @@ extern "C" int mgs_render_backward(const mgs_gaussians *g, const mgs_camera *cam
                        proj->n_tiles, gr, *out, gphi, gom);
     MGS_LAUNCH_CHECK("bwd_gauss_kernel");
     if (mlp) {
-        hipLaunchKernelGGL(bwd_mlp_kernel, dim3(unsigned((n + 127) / 128)), dim3(128), 0, s, *g, k, mlp_params, gphi,
-                           gom, *out, vec);
+        const unsigned mb = mlp_blocks(n);
+        hipLaunchKernelGGL(bwd_mlp_kernel, dim3(mb), dim3(256), 0, s, *g, k, mlp_params, gphi, gom, *out, wpart);
         MGS_LAUNCH_CHECK("bwd_mlp_kernel");
-        const WJob jobs[3] = {{OFF_DH1, OFF_XB, 64, 22, 0}, {OFF_DF, OFF_H1, 64, 64, 1}, {OFF_DHD, OFF_FB, 2, 64, 2}};
-        for (int j = 0; j < 3; ++j) {
-            hipLaunchKernelGGL(wgrad_partial_kernel, dim3(unsigned(L.nchunks)), dim3(256), 0, s, vec, n, jobs[j], wpart);
-            MGS_LAUNCH_CHECK("wgrad_partial_kernel");
-            const int nout = jobs[j].nr * (jobs[j].nc + 1);
-            hipLaunchKernelGGL(wgrad_sum_kernel, dim3(unsigned((nout + 3) / 4)), dim3(256), 0, s, wpart,
-                               L.nchunks, jobs[j], dmlp);
-            MGS_LAUNCH_CHECK("wgrad_sum_kernel");
-        }
+        hipLaunchKernelGGL(mlp_wsum_kernel, dim3((MGS_MLP_PARAMS + 3) / 4), dim3(256), 0, s, wpart, int(mb), dmlp);
+        MGS_LAUNCH_CHECK("mlp_wsum_kernel");
     }
     return MGS_OK;
 }
