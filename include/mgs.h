@@ -451,6 +451,8 @@ int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_offsets, co
  * Out: *out (same SoA layout as mgs_gaussians, fully overwritten) and, with the
  * MLP, dmlp [MGS_MLP_PARAMS] (overwritten).  The MLP gradient passes straight
  * through the forward's bfloat16 roundings.
+ * If the forward's pair count (the sum of proj->n_tiles) exceeds `capacity`, its
+ * lists overflowed and were not built: no list is read and every output is zero.
  * ws: mgs_render_backward_workspace() bytes, 256-byte aligned.
  */
 int mgs_render_backward_workspace(int64_t n, int tiles_x, int tiles_y, uint64_t capacity, int with_mlp,

@@ -319,3 +319,71 @@ def test_backward_is_bit_reproducible(M):
     b, _ = gpu_grads(M, scene, cams[0], mlp, r, (0, 0, 0))
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def _backward_raw(M, R, scene_d, cam_s, capacity, gimg, mlp_params=None):
+    """mgs_render_backward through the C ABI on a forward's buffers, with the given capacity."""
+    L = M._lib
+    n = scene_d.n
+    g = {k: torch.full_like(scene_d.t[k], float("nan")) for k in KEYS}
+    gs = L.mgs_gaussians_grad()
+    gs.mean, gs.log_scale, gs.quat = (L.ptr(g[k]).value for k in ("mean", "log_scale", "quat"))
+    gs.opacity_logit, gs.sh = L.ptr(g["opacity_logit"]).value, L.ptr(g["sh"]).value
+    nb = L.C.c_size_t()
+    L.check(L.lib().mgs_render_backward_workspace(n, R.tiles_x, R.tiles_y, capacity, int(mlp_params is not None),
+                                                  L.C.byref(nb)))
+    ws = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device="cuda")
+    dmlp = torch.full((L.MGS_MLP_PARAMS,), float("nan"), device="cuda") if mlp_params is not None else None
+    use = mlp_params is not None
+    L.check(L.lib().mgs_render_backward(
+        L.C.byref(scene_d.struct), L.C.byref(cam_s), L.ptr(mlp_params) if use else None,
+        L.ptr(R.phi) if use else None, L.ptr(R.omod) if use else None, L.C.byref(R.proj),
+        L.ptr(R.tile_offsets), L.ptr(R.gids), capacity, L.ptr(R.aux), L.ptr(gimg), L.bg_array((0.1, 0.2, 0.3)),
+        1 / 255, 0.99, L.ptr(ws), ws.numel() * 4, L.C.byref(gs), L.ptr(dmlp) if use else None, L.stream_ptr()))
+    torch.cuda.synchronize()
+    out = {k: g[k].cpu() for k in KEYS}
+    if use:
+        out["mlp"] = dmlp.cpu()
+    return out
+
+
+@pytest.mark.parametrize("with_mlp", [False, True])
+def test_backward_after_overflowed_lists_is_zero(M, with_mlp):
+    """A capacity below the forward's pair count means the lists overflowed: the backward reads
+    no list (the work plan is empty) and every gradient is zero.  The same buffers with the full
+    capacity give nonzero gradients, so the zeros come from the overflow rule."""
+    say(f"test_backward_after_overflowed_lists_is_zero[{with_mlp}]")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = cams[0]
+    mlp = mgs_data.make_mlp(3) if with_mlp else None
+    ds = M.DeviceScene(scene)
+    dm = M.DeviceMLP(mlp) if with_mlp else None
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    R.render(ds, cam, dm, bg=(0.1, 0.2, 0.3), want_aux=True, fused=False)
+    P = R.pairs()
+    assert 1000 < P <= R.capacity
+    gimg = torch.as_tensor(np.random.default_rng(9).normal(size=(3, cam.height, cam.width)), dtype=torch.float32,
+                           device="cuda")
+    cam_s = M._lib.make_camera(cam)
+    mp = dm.params if with_mlp else None
+    full = _backward_raw(M, R, ds, cam_s, R.capacity, gimg, mp)
+    over = _backward_raw(M, R, ds, cam_s, P - 1, gimg, mp)
+    for k in full:
+        assert torch.isfinite(full[k]).all() and torch.isfinite(over[k]).all(), k
+        assert float(full[k].abs().max()) > 0, k
+        assert float(over[k].abs().max()) == 0.0, k
+
+
+def test_backward_with_no_pairs_is_zero(M):
+    """A camera that sees no Gaussian: no pair, no work item, zero gradients."""
+    say("test_backward_with_no_pairs_is_zero")
+    scene, cams, _, _ = mgs_data.make_config("small", seed=0)
+    cam = mgs_data.look_at((0.0, 0.0, -3.0), target=(0.0, 0.0, -10.0), width=96, height=80, f=96.0)
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    R.render(ds, cam, bg=(0.1, 0.2, 0.3), want_aux=True)
+    assert R.pairs() == 0
+    gimg = torch.ones(3, cam.height, cam.width, device="cuda")
+    out = _backward_raw(M, R, ds, M._lib.make_camera(cam), R.capacity, gimg)
+    for k in out:
+        assert float(out[k].abs().max()) == 0.0, k
