@@ -529,6 +529,9 @@ struct SuperBatch {
         sx = ls % plan->st_x[r]; sy = ls / plan->st_x[r];
     }
 };
+// Supertiles per row of a single view (the level-1 path from the rectangles is for single views).
+inline uint32_t geo_st_x(const SuperGrid &g) { return g.st_x; }
+inline uint32_t geo_st_x(const SuperBatch &) { return 0u; }
 
 // Per 256 Gaussians: number of supertile entries and of tile pairs.
 __global__ void __launch_bounds__(256)
@@ -646,20 +649,22 @@ chunk_sum_kernel(const uint32_t *__restrict__ st_offs, const uint32_t *__restric
     }
 }
 
-__global__ void __launch_bounds__(1024)
-chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
-                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
-                  const uint64_t *__restrict__ total, uint32_t *__restrict__ sc0, uint32_t *__restrict__ chunk_st,
-                  uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks,
-                  const uint32_t *__restrict__ digit_total, uint32_t *st_offs_out) {
-    __shared__ uint64_t s_wsum[16];
-    __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
-    __shared__ uint32_t s_offs[ST_FROM_DIGITS + 1];
+// The plan for workgroup `bid` of `nblk` (1024 threads; LDS: s_wsum[16], s_pre[PLAN_TILE + 1],
+// s_offs[ST_FROM_DIGITS + 1]).
+__device__ __forceinline__ void chunk_plan_body(const uint32_t *st_offs, const uint32_t *__restrict__ st_count,
+                                                uint32_t st_host, const uint32_t *__restrict__ n_pairs,
+                                                uint64_t capacity, const uint64_t *__restrict__ part,
+                                                const uint64_t *__restrict__ total, uint32_t *__restrict__ sc0,
+                                                uint32_t *__restrict__ chunk_st, uint32_t *__restrict__ chunk_lo,
+                                                uint32_t *__restrict__ n_chunks,
+                                                const uint32_t *__restrict__ digit_total, uint32_t *st_offs_out,
+                                                uint32_t bid, uint32_t nblk, uint64_t *s_wsum, uint32_t *s_pre,
+                                                uint32_t *s_offs) {
     // part == NULL (few pieces): every block walks every piece with a running carry and writes
     // every grid-th 1024 chunk entries; block 0 writes the per-supertile outputs
     const uint32_t S = live_supertiles(st_count, st_host, n_pairs, capacity);
     const bool replicated = part == nullptr;
-    const bool writer = !replicated || blockIdx.x == 0;
+    const bool writer = !replicated || bid == 0;
     // digit_total != NULL (one block, S <= ST_FROM_DIGITS): the supertile sort took a single
     // radix pass over the whole supertile id, so its digit totals are the supertiles' entry
     // counts; their exclusive scan is st_offs, written here instead of by a pass over the keys
@@ -675,8 +680,8 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
     }
     const uint32_t *offs_in = digit_total ? s_offs : st_offs;
     uint32_t carry = 0;
-    const uint32_t fill0 = replicated ? blockIdx.x * 1024u : 0u, fill_step = 1024u * (replicated ? gridDim.x : 1u);
-    for (uint32_t c = replicated ? 0u : blockIdx.x; c < plan_chunks(S); c += replicated ? 1u : gridDim.x) {
+    const uint32_t fill0 = replicated ? bid * 1024u : 0u, fill_step = 1024u * (replicated ? nblk : 1u);
+    for (uint32_t c = replicated ? 0u : bid; c < plan_chunks(S); c += replicated ? 1u : nblk) {
         const uint32_t base = c * PLAN_TILE, k0 = threadIdx.x * PLAN_ITEMS, s0 = base + k0;
         uint32_t o[PLAN_ITEMS + 1];
 #pragma unroll
@@ -707,11 +712,24 @@ chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count
         __syncthreads();
         carry += uint32_t(tot);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         const uint32_t nct = S == 0 ? 0u : (part ? uint32_t(*total) : carry);
         sc0[S] = nct;
         *n_chunks = nct;
     }
+}
+
+__global__ void __launch_bounds__(1024)
+chunk_plan_kernel(const uint32_t *st_offs, const uint32_t *__restrict__ st_count, uint32_t st_host,
+                  const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
+                  const uint64_t *__restrict__ total, uint32_t *__restrict__ sc0, uint32_t *__restrict__ chunk_st,
+                  uint32_t *__restrict__ chunk_lo, uint32_t *__restrict__ n_chunks,
+                  const uint32_t *__restrict__ digit_total, uint32_t *st_offs_out) {
+    __shared__ uint64_t s_wsum[16];
+    __shared__ uint32_t s_pre[PLAN_TILE + 1];    // first chunk of each supertile of the piece (piece-relative)
+    __shared__ uint32_t s_offs[ST_FROM_DIGITS + 1];
+    chunk_plan_body(st_offs, st_count, st_host, n_pairs, capacity, part, total, sc0, chunk_st, chunk_lo, n_chunks,
+                    digit_total, st_offs_out, blockIdx.x, gridDim.x, s_wsum, s_pre, s_offs);
 }
 
 // An entry's covered tiles of its supertile: local_mask (index_math.h).
@@ -780,35 +798,6 @@ chunk_count_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
     }
 }
 
-// Per (supertile, tile of it): exclusive scan of the chunk counts in place, and the tile's
-// total pair count -> tile_total[global tile] for every tile inside its view.
-template <typename Geo>
-__global__ void __launch_bounds__(64)
-chunk_colscan_kernel(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ sc0,
-                     const uint32_t *__restrict__ st_count, uint32_t st_host, const uint32_t *__restrict__ n_pairs,
-                     uint64_t capacity, Geo geo, uint32_t *__restrict__ tile_total) {
-    uint32_t S = st_count ? *st_count : st_host;
-    if (S > st_host) S = st_host;
-    if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
-    const unsigned l = lane_id();
-    for (uint32_t job = blockIdx.x; job < S * SUPER_TILES; job += gridDim.x) {
-        const uint32_t s = job / SUPER_TILES, k = job % SUPER_TILES;
-        uint32_t tbase, tw, th, sx, sy;
-        geo.view(s, tbase, tw, th, sx, sy);
-        const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
-        const uint32_t c0 = sc0[s], c1 = sc0[s + 1];
-        uint32_t carry = 0;
-        for (uint32_t cb = c0; cb < c1; cb += 64) {
-            const uint32_t c = cb + l;
-            const uint32_t v = c < c1 ? cnt[size_t(c) * SUPER_TILES + k] : 0u;
-            const uint32_t inc = wave_incl_scan(v);
-            if (c < c1) cnt[size_t(c) * SUPER_TILES + k] = carry + inc - v;
-            carry += __shfl(inc, 63, 64);
-        }
-        if (l == 0 && tx < tw && ty < th) tile_total[tbase + ty * tw + tx] = carry;
-    }
-}
-
 // Exclusive scan of the per-tile totals -> tile_offsets[0 .. T], skipped on overflow (then
 // only n_pairs has been written).  Chunked scan: pass 1 sums, pass 2 writes.
 __device__ __forceinline__ uint32_t live_tiles(const uint32_t *t_count, uint32_t t_host) {
@@ -832,16 +821,16 @@ tile_sum_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restr
     }
 }
 
-__global__ void __launch_bounds__(1024)
-tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restrict__ t_count, uint32_t t_host,
-                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
-                 uint32_t *__restrict__ offs) {
-    __shared__ uint64_t s_wsum[16];
+__device__ __forceinline__ void tile_scan_body(const uint32_t *__restrict__ tile_total,
+                                               const uint32_t *__restrict__ t_count, uint32_t t_host,
+                                               const uint32_t *__restrict__ n_pairs, uint64_t capacity,
+                                               const uint64_t *__restrict__ part, uint32_t *__restrict__ offs,
+                                               uint32_t bid, uint32_t nblk, uint64_t *s_wsum) {
     if (uint64_t(*n_pairs) > capacity) return;                  // grid-uniform
     // part == NULL: one block walks every chunk with a running carry (few chunks)
     const uint32_t T = live_tiles(t_count, t_host);
     uint64_t carry = 0;
-    for (uint32_t c = blockIdx.x; c < plan_chunks(T); c += gridDim.x) {
+    for (uint32_t c = bid; c < plan_chunks(T); c += nblk) {
         const uint32_t t0 = c * PLAN_TILE + threadIdx.x * PLAN_ITEMS;
         uint32_t v[PLAN_ITEMS], sum = 0;
 #pragma unroll
@@ -858,7 +847,45 @@ tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__rest
         }
         carry += tot;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) offs[T] = *n_pairs;
+    if (bid == 0 && threadIdx.x == 0) offs[T] = *n_pairs;
+}
+
+__global__ void __launch_bounds__(1024)
+tile_scan_kernel(const uint32_t *__restrict__ tile_total, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                 const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint64_t *__restrict__ part,
+                 uint32_t *__restrict__ offs) {
+    __shared__ uint64_t s_wsum[16];
+    tile_scan_body(tile_total, t_count, t_host, n_pairs, capacity, part, offs, blockIdx.x, gridDim.x, s_wsum);
+}
+
+// Per (supertile, tile of it), one wave each: exclusive scan of the chunk counts in place, and
+// the tile's total pair count -> tile_total[global tile] for every tile inside its view.
+template <typename Geo>
+__global__ void __launch_bounds__(1024)
+chunk_colscan_kernel(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ sc0,
+                     const uint32_t *__restrict__ st_count, uint32_t st_host, const uint32_t *__restrict__ n_pairs,
+                     uint64_t capacity, Geo geo, uint32_t *__restrict__ tile_total) {
+    uint32_t S = st_count ? *st_count : st_host;
+    if (S > st_host) S = st_host;
+    if (uint64_t(*n_pairs) > capacity) S = 0;                  // lists are not built
+    const unsigned l = lane_id();
+    const uint32_t wpb = blockDim.x >> 6;
+    for (uint32_t job = blockIdx.x * wpb + (threadIdx.x >> 6); job < S * SUPER_TILES; job += gridDim.x * wpb) {
+        const uint32_t s = job / SUPER_TILES, k = job % SUPER_TILES;
+        uint32_t tbase, tw, th, sx, sy;
+        geo.view(s, tbase, tw, th, sx, sy);
+        const uint32_t tx = sx * SUPER + (k & (SUPER - 1)), ty = sy * SUPER + k / SUPER;
+        const uint32_t c0 = sc0[s], c1 = sc0[s + 1];
+        uint32_t carry = 0;
+        for (uint32_t cb = c0; cb < c1; cb += 64) {
+            const uint32_t c = cb + l;
+            const uint32_t v = c < c1 ? cnt[size_t(c) * SUPER_TILES + k] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (c < c1) cnt[size_t(c) * SUPER_TILES + k] = carry + inc - v;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (l == 0 && tx < tw && ty < th) tile_total[tbase + ty * tw + tx] = carry;
+    }
 }
 
 // Level-2 pass 2: the Gaussian indices go into the tile lists.  After the wave transpose,
@@ -969,6 +996,256 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
     }
 }
 
+// ----------------------------------------------------------------- level 1 from the rectangles
+// Single view with at most 2^8 supertiles: the supertile entries are counted, placed and
+// stably ordered straight from the Gaussians' rectangles, with no entry array in between:
+//   super_hist:    per block of L1_GB Gaussians, entries per supertile (digit-major
+//                  counts[s * nbg + b]) and the block's pair count;
+//   super_colscan: one block per supertile: exclusive scan of its counts over the Gaussian
+//                  blocks, and its total; block 0 also sums the pair counts -> n_pairs;
+//   super_scatter: per Gaussian block, its entries staged in LDS in Gaussian order (a
+//                  Gaussian's supertiles row by row), ranked by supertile with ballot-matched
+//                  digits as in the radix downsweep and written out in runs.
+// The result is the one-pass supertile sort of the expanded entries: per supertile, its
+// entries in ascending Gaussian index.
+constexpr int L1_GPT = 4;                          // Gaussians per thread
+constexpr int L1_GB = 256 * L1_GPT;                // Gaussians per block
+constexpr int L1_ITERS = 16;                       // 64-entry steps per wave and round
+constexpr uint32_t L1_STAGE = 256u * L1_ITERS;     // entries staged per round
+constexpr uint32_t L1_SMALL = 4;                   // supertiles a lane handles alone; larger: the wave
+
+__device__ __forceinline__ void super_rect(uint2 r, uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1) {
+    x0 = (r.x & 0xFFFFu) >> SUPER_SHIFT;
+    y0 = (r.x >> 16) >> SUPER_SHIFT;
+    x1 = (r.y & 0xFFFFu) >> SUPER_SHIFT;
+    y1 = (r.y >> 16) >> SUPER_SHIFT;
+}
+
+__global__ void __launch_bounds__(256)
+super_hist_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles, int64_t n, uint32_t st_x,
+                  uint32_t S, uint32_t nbg, uint32_t *__restrict__ counts, uint64_t *__restrict__ psum) {
+    __shared__ uint32_t s_h[RADIX_MAX_DIGITS];
+    __shared__ uint64_t s_p[4];
+    for (int i = threadIdx.x; i < RADIX_MAX_DIGITS; i += 256) s_h[i] = 0u;
+    __syncthreads();
+    const uint32_t b = blockIdx.x;
+    const int64_t g0 = int64_t(b) * L1_GB + int64_t(threadIdx.x) * L1_GPT;
+    uint64_t p = 0;
+    const unsigned l = lane_id();
+#pragma unroll
+    for (int j = 0; j < L1_GPT; ++j) {
+        const int64_t g = g0 + j;
+        const uint32_t nt = g < n ? ntiles[g] : 0u;
+        p += nt;
+        uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, ec = 0;
+        if (nt > 0) {
+            super_rect(rect[g], x0, y0, x1, y1);
+            ec = (x1 - x0 + 1) * (y1 - y0 + 1);
+        }
+        // counts are order-free: LDS atomics.  Up to L1_SMALL supertiles a lane adds its own;
+        // the wave adds a larger footprint's together, one supertile per lane
+        if (ec > 0 && ec <= L1_SMALL) {
+            for (uint32_t sy = y0; sy <= y1; ++sy)
+                for (uint32_t sx = x0; sx <= x1; ++sx) {
+                    const uint32_t id = sy * st_x + sx;
+                    if (MGS_CHECK(id < S, BS_RECT_GRID)) atomicAdd(&s_h[id], 1u);
+                }
+        }
+        for (uint64_t big = __ballot(ec > L1_SMALL); big; big &= big - 1) {
+            const int src = __builtin_ctzll(big);
+            const uint32_t bx0 = __shfl(x0, src, 64), by0 = __shfl(y0, src, 64), bx1 = __shfl(x1, src, 64);
+            const uint32_t bc = __shfl(ec, src, 64), wdt = bx1 - bx0 + 1;
+            for (uint32_t k = l; k < bc; k += 64) {
+                const uint32_t id = (by0 + k / wdt) * st_x + bx0 + k % wdt;
+                if (MGS_CHECK(id < S, BS_RECT_GRID)) atomicAdd(&s_h[id], 1u);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+    if (lane_id() == 0) s_p[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) psum[b] = s_p[0] + s_p[1] + s_p[2] + s_p[3];
+    for (uint32_t sid = threadIdx.x; sid < S; sid += 256) counts[size_t(sid) * nbg + b] = s_h[sid];
+}
+
+__global__ void __launch_bounds__(1024)
+super_colscan_kernel(uint32_t *__restrict__ counts, const uint64_t *__restrict__ psum, uint32_t nbg,
+                     uint32_t *__restrict__ digit_total, uint32_t *__restrict__ n_pairs) {
+    __shared__ uint64_t s_wsum[16];
+    uint32_t *row = counts + size_t(blockIdx.x) * nbg;
+    uint64_t carry = 0;
+    constexpr int ITEMS = 4;
+    for (uint32_t b0 = 0; b0 < nbg; b0 += 1024 * ITEMS) {
+        const uint32_t i0 = b0 + threadIdx.x * ITEMS;
+        uint32_t v[ITEMS], sm = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            v[k] = i0 + k < nbg ? row[i0 + k] : 0u;
+            sm += v[k];
+        }
+        uint64_t tot;
+        uint32_t pre = uint32_t(block_scan1024(sm, s_wsum, &tot) + carry);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (i0 + k < nbg) row[i0 + k] = pre;
+            pre += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = uint32_t(carry);
+    if (blockIdx.x == 0) {                             // block-uniform: the pair total
+        uint64_t p = 0;
+        for (uint32_t i = threadIdx.x; i < nbg; i += 1024) p += psum[i];
+        uint64_t P;
+        block_scan1024(p, s_wsum, &P);
+        if (threadIdx.x == 0) *n_pairs = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(P);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+super_scatter_kernel(const uint2 *__restrict__ rect, const uint32_t *__restrict__ ntiles, int64_t n, uint32_t st_x,
+                     uint32_t S, int bits, uint32_t nbg, const uint32_t *__restrict__ colscan,
+                     const uint32_t *__restrict__ digit_total, const uint32_t *__restrict__ n_pairs,
+                     uint64_t capacity, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+    __shared__ uint32_t cnt[RADIX_WAVES][RADIX_MAX_DIGITS];
+    __shared__ uint32_t s_lstart[RADIX_MAX_DIGITS], s_gstart[RADIX_MAX_DIGITS], s_rtot[RADIX_MAX_DIGITS];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_eb;
+    __shared__ uint32_t sk[L1_STAGE], sv[L1_STAGE];
+    if (uint64_t(*n_pairs) > capacity) return;                           // block-uniform: no lists
+    const uint32_t b = blockIdx.x;
+    const int t = threadIdx.x, w = t >> 6;
+    const unsigned l = lane_id();
+    const uint32_t mask = (1u << bits) - 1u;
+    // this thread's Gaussians (contiguous indices) and their entry counts; every global load of
+    // the block is issued before the first scan waits on any
+    const int64_t g0 = int64_t(b) * L1_GB + int64_t(t) * L1_GPT;
+    uint2 r[L1_GPT];
+    uint32_t ec[L1_GPT], esum = 0;
+#pragma unroll
+    for (int j = 0; j < L1_GPT; ++j) {
+        const int64_t g = g0 + j;
+        r[j] = g < n ? rect[g] : make_uint2(0u, 0u);
+        ec[j] = g < n ? ntiles[g] : 0u;
+    }
+    const uint32_t dt = uint32_t(t) < S ? digit_total[t] : 0u;
+    const uint32_t gcol = uint32_t(t) < S ? colscan[size_t(t) * nbg + b] : 0u;
+#pragma unroll
+    for (int j = 0; j < L1_GPT; ++j) {
+        ec[j] = ec[j] > 0 ? n_super(r[j]) : 0u;
+        esum += ec[j];
+    }
+    {
+        const uint32_t dex = block_excl_scan256<uint32_t>(dt, s_wsum);  // contains __syncthreads
+        s_gstart[t] = uint32_t(t) < S ? dex + gcol : 0u;
+    }
+    const uint32_t ebase = block_excl_scan256<uint32_t>(esum, s_wsum);
+    if (t == 255) s_eb = ebase + esum;
+    __syncthreads();
+    const uint32_t Eb = s_eb;
+    for (uint32_t r0 = 0; r0 < Eb; r0 += L1_STAGE) {                    // block-uniform rounds
+        const uint32_t rn = Eb - r0 < L1_STAGE ? Eb - r0 : L1_STAGE;
+        // stage the round's entries in Gaussian order
+        uint32_t e = ebase;
+#pragma unroll
+        for (int j = 0; j < L1_GPT; ++j) {
+            const uint32_t c = ec[j];
+            const bool in_round = c > 0 && e < r0 + rn && e + c > r0;
+            uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+            if (in_round) super_rect(r[j], x0, y0, x1, y1);
+            if (in_round && c <= L1_SMALL) {
+                const uint32_t wdt = x1 - x0 + 1;
+                const uint32_t k0 = e < r0 ? r0 - e : 0u, k1 = e + c > r0 + rn ? r0 + rn - e : c;
+                for (uint32_t k = k0; k < k1; ++k) {
+                    const uint32_t sx = x0 + k % wdt, sy = y0 + k / wdt;
+                    sk[e + k - r0] = super_entry_key(sy * st_x + sx, unpack_rect(r[j].x, r[j].y), sx, sy);
+                    sv[e + k - r0] = uint32_t(g0 + j);
+                }
+            }
+            // a larger footprint: the wave writes its entries together, one per lane
+            for (uint64_t big = __ballot(in_round && c > L1_SMALL); big; big &= big - 1) {
+                const int src = __builtin_ctzll(big);
+                const uint32_t be = __shfl(e, src, 64), bc = __shfl(c, src, 64);
+                const uint32_t bx0 = __shfl(x0, src, 64), by0 = __shfl(y0, src, 64), bx1 = __shfl(x1, src, 64);
+                const uint2 br = make_uint2(__shfl(r[j].x, src, 64), __shfl(r[j].y, src, 64));
+                const uint32_t bg = uint32_t(__shfl(uint32_t(g0 + j), src, 64)), wdt = bx1 - bx0 + 1;
+                const uint32_t k0 = be < r0 ? r0 - be : 0u, k1 = be + bc > r0 + rn ? r0 + rn - be : bc;
+                for (uint32_t k = k0 + l; k < k1; k += 64) {
+                    const uint32_t sx = bx0 + k % wdt, sy = by0 + k / wdt;
+                    sk[be + k - r0] = super_entry_key(sy * st_x + sx, unpack_rect(br.x, br.y), sx, sy);
+                    sv[be + k - r0] = bg;
+                }
+            }
+            e += c;
+        }
+        for (int i = t; i < RADIX_WAVES * RADIX_MAX_DIGITS; i += 256) (&cnt[0][0])[i] = 0u;
+        __syncthreads();
+        // rank by supertile: the round's entries split evenly, in order, over the four waves
+        // (wave w takes [w * seg, (w + 1) * seg), seg a multiple of 64)
+        uint32_t key[L1_ITERS], val[L1_ITERS], rank[L1_ITERS], dig[L1_ITERS];
+        const uint32_t nit = (rn + 255u) / 256u, seg = 64u * nit;
+        const uint32_t base = uint32_t(w) * seg, wend = base + seg < rn ? base + seg : rn;
+#pragma unroll
+        for (int it = 0; it < L1_ITERS; ++it) {
+            const uint32_t idx = base + uint32_t(it) * 64u + l;
+            const bool ok = uint32_t(it) < nit && idx < wend;
+            key[it] = ok ? sk[idx] : 0u;
+            val[it] = ok ? sv[idx] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < L1_ITERS; ++it) {
+            if (uint32_t(it) >= nit) break;                              // wave-uniform
+            const uint32_t idx = base + uint32_t(it) * 64u + l;
+            const bool ok = idx < wend;
+            const uint64_t active = __ballot(ok);
+            const uint32_t d = ok ? (key[it] >> ST_KEY_SHIFT) & mask : 0u;
+            dig[it] = d;
+            rank[it] = 0;
+            if (active != 0) {
+                const uint64_t peers = match_digit(d, bits, active);
+                const uint32_t before = ok ? cnt[w][d] : 0u;
+                rank[it] = before + uint32_t(__popcll(peers & lanemask_lt()));
+                __builtin_amdgcn_wave_barrier();
+                if (ok && (peers >> l) == 1ull) cnt[w][d] = before + uint32_t(__popcll(peers));
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int ww = 0; ww < RADIX_WAVES; ++ww) {
+            const uint32_t c = cnt[ww][t];
+            cnt[ww][t] = tot;
+            tot += c;
+        }
+        const uint32_t lex = block_excl_scan256<uint32_t>(tot, s_wsum);  // contains __syncthreads
+        s_lstart[t] = lex;
+        s_rtot[t] = tot;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < L1_ITERS; ++it) {
+            const uint32_t idx = base + uint32_t(it) * 64u + l;
+            if (uint32_t(it) < nit && idx < wend) {
+                const uint32_t lp = s_lstart[dig[it]] + cnt[w][dig[it]] + rank[it];
+                sk[lp] = key[it];
+                sv[lp] = val[it];
+            }
+        }
+        __syncthreads();
+        for (uint32_t lp = t; lp < rn; lp += 256) {
+            const uint32_t k = sk[lp];
+            const uint32_t d = (k >> ST_KEY_SHIFT) & mask;
+            const uint32_t dst = s_gstart[d] + lp - s_lstart[d];
+            if (MGS_CHECK(uint64_t(dst) < capacity, BS_EXPAND_WRITE)) {
+                keys_out[dst] = k;
+                vals_out[dst] = sv[lp];
+            }
+        }
+        __syncthreads();
+        s_gstart[t] += s_rtot[t];                  // the next round's entries follow this round's
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------------- host side
 inline int bits_for(uint64_t v) {
     int b = 0;
@@ -1072,8 +1349,8 @@ int bin_impl(const mgs_projected *proj, int64_t n, Map map, uint32_t T, void *ws
 
 // Two-level order-independent binning (see the comment above super_count_kernel).
 struct Bin2Layout {
-    size_t sums_e, sums_p, etot, keys0, keys1, vals0, vals1, hist, dtot, st_offs, sc0, chunk_st, chunk_lo, nch, cnt,
-        ttot, part_e, part_p, part_c, part_t, totals, total;
+    size_t sums_e, sums_p, etot, keys0, keys1, vals0, vals1, hist, hist_g, dtot, st_offs, sc0, chunk_st, chunk_lo,
+        nch, cnt, ttot, part_e, part_p, part_c, part_t, totals, total;
     int nblocks;
     uint32_t chunks_max;
 };
@@ -1094,6 +1371,7 @@ inline Bin2Layout bin2_layout(int64_t n, uint32_t st_max, uint32_t t_max, uint64
     L.vals0 = o;    o = align_up(o + cap * 4, 256);
     L.vals1 = o;    o = align_up(o + cap * 4, 256);
     L.hist = o;     o = align_up(o + size_t(RADIX_MAX_DIGITS) * L.nblocks * 4, 256);
+    L.hist_g = o;   o = align_up(o + size_t(RADIX_MAX_DIGITS) * (size_t((n + L1_GB - 1) / L1_GB) + 1) * 4, 256);
     L.dtot = o;     o = align_up(o + RADIX_MAX_DIGITS * 4, 256);
     L.st_offs = o;  o = align_up(o + (size_t(st_max) + 1) * 4, 256);
     L.sc0 = o;      o = align_up(o + (size_t(st_max) + 1) * 4, 256);
@@ -1151,60 +1429,86 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
     const uint2 *rect = reinterpret_cast<const uint2 *>(proj->rect);
     const unsigned nb256 = unsigned((n + 255) / 256);
 
-    // level 1: entry counts (and the pair total P), their scan, the entries, the supertile sort
-    if (nb256 > 0) {
-        hipLaunchKernelGGL(super_count_kernel, dim3(nb256), dim3(256), 0, s, rect, proj->n_tiles, n, n_live, sums_e,
-                           sums_p);
-        MGS_LAUNCH_CHECK("super_count_kernel");
-    }
-    const uint32_t nce = plan_chunks(nb256);
-    if (nce <= PLAN_ONE_BLOCK) {                 // few chunks: one block with a running carry
-        hipLaunchKernelGGL(super_scan_kernel, dim3(1), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
-                           static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), capacity,
-                           etot, n_pairs);
-    } else {
-        hipLaunchKernelGGL(super_sum_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
-                           part_e, part_p);
-        MGS_LAUNCH_CHECK("super_sum_kernel");
-        hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_e, part_p, nce, totals, totals + 1);
-        MGS_LAUNCH_CHECK("part_scan_kernel");
-        hipLaunchKernelGGL(super_scan_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
-                           part_e, totals, capacity, etot, n_pairs);
-    }
-    MGS_LAUNCH_CHECK("super_scan_kernel");
-    if (nb256 > 0) {
-        hipLaunchKernelGGL((expand_kernel<uint32_t, TileKey, Geo, SUPER_SHIFT>), dim3(nb256), dim3(256), 0, s, rect,
-                           proj->n_tiles, sums_e, reinterpret_cast<const float4 *>(proj->splat), n, geo, n_pairs,
-                           capacity, keys[0], vals[0], TileKey(), n_live);
-        MGS_LAUNCH_CHECK("expand_kernel<supertile>");
-    }
     const int key_bits = bits_for(st_max) > 0 ? bits_for(st_max) : 1;
     const int npass = (key_bits + RADIX_MAX_BITS - 1) / RADIX_MAX_BITS;
     int cur = 0;
-    if (capacity > 0) {
-        const unsigned grid = unsigned(L.nblocks < RADIX_MAX_GRID ? L.nblocks : RADIX_MAX_GRID);
-        int shift = ST_KEY_SHIFT;                        // the local rectangle below the id is not sorted
-        for (int p = 0; p < npass; ++p) {
-            const int bits = (key_bits - (shift - ST_KEY_SHIFT) + (npass - p) - 1) / (npass - p);
-            hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
-                               s, keys[cur], etot, capacity, shift, bits, hist, L.nblocks);
-            MGS_LAUNCH_CHECK("radix_upsweep_kernel");
-            hipLaunchKernelGGL(radix_colscan_kernel<SUPER_RADIX_ITERS>, dim3(1u << bits), dim3(256), 0, s, hist,
-                               L.nblocks, etot, capacity, dtot);
-            MGS_LAUNCH_CHECK("radix_colscan_kernel");
-            hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
-                               s, keys[cur],
-                               vals[cur], etot, capacity, shift, bits, hist, dtot, L.nblocks, keys[cur ^ 1],
-                               vals[cur ^ 1]);
-            MGS_LAUNCH_CHECK("radix_downsweep_kernel");
-            cur ^= 1;
-            shift += bits;
+    // a single view with few supertiles: level 1 straight from the rectangles (super_hist,
+    // super_colscan, super_scatter); otherwise entry counts, their scan, the entries and a
+    // radix sort of them by supertile
+    const bool direct = n_live == nullptr && st_count == nullptr && t_count == nullptr && capacity > 0 &&
+                        st_max <= uint32_t(RADIX_MAX_DIGITS) && st_max <= uint32_t(ST_FROM_DIGITS);
+    if (direct) {
+        const uint32_t nbg = uint32_t((n + L1_GB - 1) / L1_GB);
+        uint32_t *hist_g = reinterpret_cast<uint32_t *>(w + L.hist_g);
+        const uint32_t st_x = geo_st_x(geo);
+        if (nbg > 0) {
+            hipLaunchKernelGGL(super_hist_kernel, dim3(nbg), dim3(256), 0, s, rect, proj->n_tiles, n, st_x, st_max,
+                               nbg, hist_g, sums_p);
+            MGS_LAUNCH_CHECK("super_hist_kernel");
+        }
+        hipLaunchKernelGGL(super_colscan_kernel, dim3(st_max), dim3(1024), 0, s, hist_g,
+                           static_cast<const uint64_t *>(sums_p), nbg, dtot, n_pairs);
+        MGS_LAUNCH_CHECK("super_colscan_kernel");
+        if (nbg > 0) {
+            hipLaunchKernelGGL(super_scatter_kernel, dim3(nbg), dim3(256), 0, s, rect, proj->n_tiles, n, st_x, st_max,
+                               key_bits, nbg, static_cast<const uint32_t *>(hist_g), static_cast<const uint32_t *>(dtot),
+                               static_cast<const uint32_t *>(n_pairs), capacity, keys[0], vals[0]);
+            MGS_LAUNCH_CHECK("super_scatter_kernel");
+        }
+    } else {
+        // level 1: entry counts (and the pair total P), their scan, the entries, the supertile sort
+        if (nb256 > 0) {
+            hipLaunchKernelGGL(super_count_kernel, dim3(nb256), dim3(256), 0, s, rect, proj->n_tiles, n, n_live, sums_e,
+                               sums_p);
+            MGS_LAUNCH_CHECK("super_count_kernel");
+        }
+        const uint32_t nce = plan_chunks(nb256);
+        if (nce <= PLAN_ONE_BLOCK) {                 // few chunks: one block with a running carry
+            hipLaunchKernelGGL(super_scan_kernel, dim3(1), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                               static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr), capacity,
+                               etot, n_pairs);
+        } else {
+            hipLaunchKernelGGL(super_sum_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                               part_e, part_p);
+            MGS_LAUNCH_CHECK("super_sum_kernel");
+            hipLaunchKernelGGL(part_scan_kernel<>, dim3(1), dim3(1024), 0, s, part_e, part_p, nce, totals, totals + 1);
+            MGS_LAUNCH_CHECK("part_scan_kernel");
+            hipLaunchKernelGGL(super_scan_kernel, dim3(plan_grid(nce)), dim3(1024), 0, s, sums_e, sums_p, int(nb256),
+                               part_e, totals, capacity, etot, n_pairs);
+        }
+        MGS_LAUNCH_CHECK("super_scan_kernel");
+        if (nb256 > 0) {
+            hipLaunchKernelGGL((expand_kernel<uint32_t, TileKey, Geo, SUPER_SHIFT>), dim3(nb256), dim3(256), 0, s, rect,
+                               proj->n_tiles, sums_e, reinterpret_cast<const float4 *>(proj->splat), n, geo, n_pairs,
+                               capacity, keys[0], vals[0], TileKey(), n_live);
+            MGS_LAUNCH_CHECK("expand_kernel<supertile>");
+        }
+        if (capacity > 0) {
+            const unsigned grid = unsigned(L.nblocks < RADIX_MAX_GRID ? L.nblocks : RADIX_MAX_GRID);
+            int shift = ST_KEY_SHIFT;                        // the local rectangle below the id is not sorted
+            for (int p = 0; p < npass; ++p) {
+                const int bits = (key_bits - (shift - ST_KEY_SHIFT) + (npass - p) - 1) / (npass - p);
+                hipLaunchKernelGGL((radix_upsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
+                                   s, keys[cur], etot, capacity, shift, bits, hist, L.nblocks);
+                MGS_LAUNCH_CHECK("radix_upsweep_kernel");
+                hipLaunchKernelGGL(radix_colscan_kernel<SUPER_RADIX_ITERS>, dim3(1u << bits), dim3(256), 0, s, hist,
+                                   L.nblocks, etot, capacity, dtot);
+                MGS_LAUNCH_CHECK("radix_colscan_kernel");
+                hipLaunchKernelGGL((radix_downsweep_kernel<uint32_t, SUPER_RADIX_ITERS>), dim3(grid), dim3(RADIX_THREADS), 0,
+                                   s, keys[cur],
+                                   vals[cur], etot, capacity, shift, bits, hist, dtot, L.nblocks, keys[cur ^ 1],
+                                   vals[cur ^ 1]);
+                MGS_LAUNCH_CHECK("radix_downsweep_kernel");
+                cur ^= 1;
+                shift += bits;
+            }
         }
     }
     // supertile ranges: from the sort's digit totals when one radix pass covered the whole id
     // (the plan scans them), else from the sorted keys
     const uint32_t ncs = plan_chunks(st_max);
-    const bool from_digits = capacity > 0 && npass == 1 && st_max <= uint32_t(ST_FROM_DIGITS) && ncs <= PLAN_ONE_BLOCK;
+    const bool from_digits =
+        direct || (capacity > 0 && npass == 1 && st_max <= uint32_t(ST_FROM_DIGITS) && ncs <= PLAN_ONE_BLOCK);
     if (!from_digits) {
         const uint64_t rblocks = (capacity + 1 + 255) / 256;
         hipLaunchKernelGGL((tile_ranges_kernel<uint32_t>), dim3(unsigned(rblocks < 4096 ? rblocks : 4096)), dim3(256),
@@ -1235,8 +1539,11 @@ int bin2_impl(const mgs_projected *proj, int64_t n, const uint32_t *n_live, Geo 
                        chunk_lo, st_offs, nch, geo, cnt);
     MGS_LAUNCH_CHECK("chunk_count_kernel");
     const uint64_t jobs = uint64_t(st_max) * SUPER_TILES;
-    hipLaunchKernelGGL((chunk_colscan_kernel<Geo>), dim3(unsigned(jobs < 16384 ? jobs : 16384)), dim3(64), 0, s, cnt,
-                       sc0, st_count, st_max, n_pairs, capacity, geo, ttot);
+    {                                            // a wave per job, 4 per workgroup
+        const uint64_t nb = (jobs + 3) / 4;
+        hipLaunchKernelGGL((chunk_colscan_kernel<Geo>), dim3(unsigned(nb < 16384 ? nb : 16384)), dim3(256), 0, s, cnt,
+                           sc0, st_count, st_max, n_pairs, capacity, geo, ttot);
+    }
     MGS_LAUNCH_CHECK("chunk_colscan_kernel");
     const uint32_t nct = plan_chunks(T);
     if (nct <= PLAN_ONE_BLOCK) {

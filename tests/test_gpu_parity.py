@@ -95,6 +95,27 @@ def test_bin_lists_bit_exact_on_oracle_rects(M, W, H, n, seed):
     assert torch.equal(offs2, s_offs) and torch.equal(gids2, s_gids)
 
 
+@pytest.mark.parametrize("W,H,n,ls_mu", [(2048, 2048, 6000, -2.0), (1000, 700, 4000, -1.5)])
+def test_bin_lists_bit_exact_large_footprints(M, W, H, n, ls_mu):
+    """Gaussians covering many supertiles (up to 2^8 supertiles, tens of thousands of supertile
+    entries per block of 1024 Gaussians, so the level-1 staging runs many rounds): the lists
+    equal the oracle's bit for bit."""
+    say(f"test_bin_lists_bit_exact_large_footprints W={W} H={H} n={n}")
+    scene = mgs_data.make_scene_uniform(n, 3, ls_mu=ls_mu)
+    cam = mgs_data.look_at((0.3, 0.1, -3.0), width=W, height=H, f=float(W))
+    pr, camt = oracle_project(scene, cam)
+    P = int(pr["n_tiles"].sum())
+    R = M.Renderer(n, W, H, capacity=P)
+    upload_projected_from_oracle(R, pr, camt)
+    R.bin()
+    torch.cuda.synchronize()
+    offs, gids = R.lists()
+    o_offs, o_gids = O.bin_lists(pr["rect"], pr["n_tiles"], R.tiles_x, R.tiles_y)
+    say(f"  pairs {P}")
+    assert R.pairs() == P
+    assert torch.equal(offs, o_offs) and torch.equal(gids, o_gids)
+
+
 def test_bin_is_deterministic_and_overflow_is_reported(M):
     say("test_bin_is_deterministic_and_overflow_is_reported")
     scene, cams, _, _ = mgs_data.make_config("small", seed=0)
