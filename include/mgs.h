@@ -438,6 +438,22 @@ int mgs_blend_sorted(const mgs_projected *proj, const uint32_t *tile_offsets, co
                      float alpha_max, float t_stop, float *image, void *stream);
 
 /*
+ * mgs_tile_sort -- the lists of the sorted comparison path (Eq. 11's front-to-back order) as a
+ * segmented sort: each tile list of mgs_bin (ascending Gaussian index) sorted in place by the
+ * float32 camera depth of its record, ties by Gaussian index.  The result equals mgs_bin_sorted's
+ * lists entry for entry; mgs_blend_sorted then composites them.
+ * In: proj / n (the projection mgs_bin read), tile_offsets (device, T + 1 entries), n_pairs
+ * (device, mgs_bin's count), capacity (the gids capacity passed to mgs_bin).  In/out: gids
+ * (device).  When *n_pairs > capacity (mgs_bin overflowed) nothing is read or written.
+ * ws: mgs_tile_sort_workspace() bytes, 256-byte aligned (16 bytes per unit of capacity: the
+ * copies through which lists longer than 4,096 entries are sorted).
+ */
+int mgs_tile_sort_workspace(int tiles_x, int tiles_y, uint64_t capacity, size_t *bytes);
+int mgs_tile_sort(const mgs_projected *proj, int64_t n, const uint32_t *tile_offsets, uint32_t *gids,
+                  int tiles_x, int tiles_y, uint64_t capacity, const uint32_t *n_pairs, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/*
  * mgs_render_backward -- gradients of the OIT pass (Eq. 2, Eq. 3, Eq. 4) with
  * respect to the raw Gaussian attributes and, with the MLP, its parameters.
  * It recomputes per-pixel-pair terms from the forward's aux (N/D rgb, D, T):

@@ -31,7 +31,7 @@ EXPORTED = [
     "mgs_last_error", "mgs_version", "mgs_mlp_pack", "mgs_enhance", "mgs_project", "mgs_enhance_project",
     "mgs_bin_workspace", "mgs_bin", "mgs_blend_oit", "mgs_blend_oit_split_workspace", "mgs_blend_oit_split",
     "mgs_bin_sorted_workspace",
-    "mgs_bin_sorted", "mgs_blend_sorted", "mgs_render_backward_workspace",
+    "mgs_bin_sorted", "mgs_blend_sorted", "mgs_tile_sort_workspace", "mgs_tile_sort", "mgs_render_backward_workspace",
     "mgs_render_backward", "mgs_batch_workspace", "mgs_render_batch", "mgs_nvq_decode", "mgs_enhance_project_nvq",
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
     "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
@@ -127,6 +127,8 @@ def load(path=LIB_PATH):
                                       vp, C.c_size_t, vp, vp, vp]),
         "mgs_bin_sorted_workspace": (i32, [i64, i32, i32, u64, P(C.c_size_t)]),
         "mgs_bin_sorted": (i32, [P(mgs_projected), i64, i32, i32, vp, C.c_size_t, vp, vp, u64, vp, vp]),
+        "mgs_tile_sort_workspace": (i32, [i32, i32, u64, P(C.c_size_t)]),
+        "mgs_tile_sort": (i32, [P(mgs_projected), i64, vp, vp, i32, i32, u64, vp, vp, C.c_size_t, vp]),
         "mgs_blend_sorted": (i32, [P(mgs_projected), vp, vp, P(mgs_camera), i32, P(C.c_float), f32, f32, f32,
                                    vp, vp]),
         "mgs_nvq_decode": (i32, [P(mgs_gaussians_nvq), vp, vp, vp, vp, vp]),

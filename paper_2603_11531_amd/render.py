@@ -150,6 +150,7 @@ class Renderer:
         self.ws = None
         self.ws_sorted = None
         self.ws_split = None
+        self.ws_tsort, self.ws_tsort_cap = None, -1
         self.ensure_capacity(capacity if capacity is not None else max(1024, 4 * self.n))
 
     # -- capacity -----------------------------------------------------------
@@ -249,6 +250,18 @@ class Renderer:
                    L.ptr(self.tile_offsets), L.ptr(self.gids), self.capacity, L.ptr(self.n_pairs),
                    L.stream_ptr(stream)))
 
+    def tile_sort(self, stream=None):
+        """mgs_tile_sort: the current (order-independent) lists sorted in place by depth, ties by
+        index -- the sorted path's lists, from the two-level binning plus a per-tile sort."""
+        if self.ws_tsort is None or self.ws_tsort_cap != self.capacity:
+            nb = L.C.c_size_t()
+            L.check(L.lib().mgs_tile_sort_workspace(self.tiles_x, self.tiles_y, self.capacity, L.C.byref(nb)))
+            self.ws_tsort = torch.empty((nb.value + 255) // 256 * 64, dtype=torch.float32, device=self.device)
+            self.ws_tsort_cap = self.capacity
+        L.check(L.lib().mgs_tile_sort(L.C.byref(self.proj), self.n, L.ptr(self.tile_offsets), L.ptr(self.gids),
+                                      self.tiles_x, self.tiles_y, self.capacity, L.ptr(self.n_pairs),
+                                      L.ptr(self.ws_tsort), self.ws_tsort.numel() * 4, L.stream_ptr(stream)))
+
     def blend_oit(self, cam_s, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, want_aux=False,
                   stream=None, split=True, w_bg=None):
         """Eq. 2 composite (Eq. 1's with a background weight ``w_bg``); ``split`` (default) uses the
@@ -305,7 +318,9 @@ class Renderer:
         attributes are read through its codebooks).  With check_capacity the host reads the
         pair count once and re-bins with a larger capacity on overflow.  ``weight_mode``
         selects Eq. 3 or one of its ablations (MGS_WEIGHT_*); ``sortfree`` = (sigma, beta)
-        device arrays with ``w_bg`` selects Eq. 1 (SortFreeGS weight and composite)."""
+        device arrays with ``w_bg`` selects Eq. 1 (SortFreeGS weight and composite).  ``sorted_path``
+        True sorts all pairs by (tile, depth); "tile_sort" bins as the order-independent path and
+        sorts each tile's list by depth (identical lists, mgs_tile_sort)."""
         cam_s = L.make_camera(cam)
         if (sortfree is None) != (w_bg is None):
             raise ValueError("Eq. 1 needs both sortfree=(sigma, beta) and w_bg")
@@ -331,12 +346,17 @@ class Renderer:
             if mlp is not None:
                 self.enhance(scene, cam_s, mlp, stream)
             self.project(scene, cam_s, use_mlp=mlp is not None, stream=stream, weight_mode=weight_mode)
-        self.bin(sorted_path, stream)
+        # sorted_path: True = global (tile, depth) radix sort of the pairs; "tile_sort" = the
+        # order-independent binning followed by a per-tile depth sort (the same lists)
+        global_sort = bool(sorted_path) and sorted_path != "tile_sort"
+        self.bin(global_sort, stream)
         if check_capacity:
             P = self.pairs()      # synchronises
             if P > self.capacity:
-                self.ensure_capacity(int(P * 1.25) + 1024, sorted_path)
-                self.bin(sorted_path, stream)
+                self.ensure_capacity(int(P * 1.25) + 1024, global_sort)
+                self.bin(global_sort, stream)
+        if sorted_path == "tile_sort":
+            self.tile_sort(stream)
         if sorted_path:
             self.blend_sorted(cam_s, bg, stream=stream)
         else:

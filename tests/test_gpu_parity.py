@@ -116,6 +116,65 @@ def test_bin_lists_bit_exact_large_footprints(M, W, H, n, ls_mu):
     assert torch.equal(offs, o_offs) and torch.equal(gids, o_gids)
 
 
+@pytest.mark.parametrize("W,H,n,ls_mu", [(128, 128, 9000, -1.0), (200, 120, 3000, -2.5), (1000, 700, 4000, -1.5)])
+def test_tile_sort_lists_equal_depth_sorted_lists(M, W, H, n, ls_mu):
+    """mgs_bin + mgs_tile_sort gives the oracle's depth-sorted lists (ties by index) and exactly
+    the lists of the global (tile, depth) sort; the first case has lists longer than the
+    4,096 entries sorted in LDS (the chunked path)."""
+    say(f"test_tile_sort_lists_equal_depth_sorted_lists W={W} H={H} n={n}")
+    scene = mgs_data.make_scene_uniform(n, 5, ls_mu=ls_mu)
+    cam = mgs_data.look_at((0.3, 0.1, -3.0), width=W, height=H, f=float(W))
+    pr, camt = oracle_project(scene, cam)
+    P = int(pr["n_tiles"].sum())
+    R = M.Renderer(n, W, H, capacity=P)
+    upload_projected_from_oracle(R, pr, camt)
+    R.bin()
+    R.tile_sort()
+    torch.cuda.synchronize()
+    offs, gids = R.lists()
+    depth32 = pr["depth"].detach().to(torch.float32).to(torch.float64)
+    s_offs, s_gids = O.bin_lists_sorted(pr["rect"], pr["n_tiles"], depth32, R.tiles_x, R.tiles_y)
+    longest = int((offs[1:] - offs[:-1]).max())
+    say(f"  pairs {P}, longest list {longest}")
+    assert R.pairs() == P
+    assert torch.equal(offs, s_offs) and torch.equal(gids, s_gids)
+    R.bin(sorted_path=True)
+    torch.cuda.synchronize()
+    offs2, gids2 = R.lists()
+    assert torch.equal(offs2, offs) and torch.equal(gids2, gids)
+    if W == 128:
+        assert longest > 4096
+
+
+def test_tile_sort_frame_equals_global_sort_frame(M):
+    """The 1M-Gaussian 1600x1063 frame (pose 0; 188 lists longer than 4,096): the two sorted
+    variants give the same lists and the same image bit for bit; an overflowed binning is left
+    untouched."""
+    say("test_tile_sort_frame_equals_global_sort_frame")
+    scene, cams, mlp, _ = mgs_data.make_config("unbounded", seed=0)
+    ds, dm = M.DeviceScene(scene), M.DeviceMLP(mlp)
+    cam = cams[0]
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    a = R.render(ds, cam, dm, sorted_path=True, fused=True).clone()
+    la = [t.clone() for t in R.lists()]
+    b = R.render(ds, cam, dm, sorted_path="tile_sort", fused=True).clone()
+    lb = R.lists()
+    torch.cuda.synchronize()
+    longest = int((lb[0][1:] - lb[0][:-1]).max())
+    say(f"  pairs {R.pairs()}, longest list {longest}")
+    assert longest > 4096
+    assert torch.equal(la[0], lb[0]) and torch.equal(la[1], lb[1])
+    assert torch.equal(a, b)
+    # overflow: mgs_bin reports the count and builds nothing; mgs_tile_sort reads and writes nothing
+    R2 = M.Renderer(ds.n, cam.width, cam.height, capacity=1024)
+    R2.enhance_project(ds, M._lib.make_camera(cam), dm)
+    R2.bin()
+    R2.gids.fill_(7)
+    R2.tile_sort()
+    torch.cuda.synchronize()
+    assert R2.pairs() > R2.capacity and bool((R2.gids == 7).all())
+
+
 def test_bin_is_deterministic_and_overflow_is_reported(M):
     say("test_bin_is_deterministic_and_overflow_is_reported")
     scene, cams, _, _ = mgs_data.make_config("small", seed=0)
