@@ -83,7 +83,9 @@ class mgs_request(C.Structure):
                 ("image", C.c_void_p)]
 
 
-def load(path=LIB_PATH):
+def load(path=None):
+    """Open the library at ``path`` (default: the module's LIB_PATH as it is at call time)."""
+    path = LIB_PATH if path is None else path
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2603_11531_amd.build`")
     lib = C.CDLL(path)

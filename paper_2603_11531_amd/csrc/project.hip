@@ -155,20 +155,18 @@ enhance_project_kernel(Src src, CamK cam, const uint8_t *__restrict__ packed, fl
         const int64_t i = grp * 64 + l;
         const bool valid = i < n;
         f32x8 f[4];
+        GaussIn in;
         if (valid) {
-            const GaussIn a = src.load(i);
-            lane_features(a.mu, a.ls, a.q, a.sh, cam, f);
+            in = src.load(i);
+            lane_features(in.mu, in.ls, in.q, in.sh, cam, f);
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c) f[c] = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
         float ph, om;
         mlp_wave(f, F, s_x[w], ph, om);
-        // The projection reads the attributes again (cache hits) instead of keeping them in
-        // registers across the MLP: fewer live registers, more waves in flight.
-        __asm__ volatile("" ::: "memory");
+        // the attributes stay in registers across the MLP (one read per Gaussian)
         if (valid) {
-            GaussIn in = src.load(i);
             in.phi = ph;
             in.om = om;
             store_proj(project_gaussian(in, cam, alpha_min), i, splat, rect_out, ntiles_out);

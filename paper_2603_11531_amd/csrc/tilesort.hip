@@ -22,7 +22,7 @@ namespace tsort {
 #define MGS_TS_THREADS 256
 #endif
 #ifndef MGS_TS_ITERS
-#define MGS_TS_ITERS 16
+#define MGS_TS_ITERS 8
 #endif
 constexpr int TS_THREADS = MGS_TS_THREADS;               // 256 or 512: a thread per digit and more
 constexpr int TS_WAVES = TS_THREADS / 64;
