@@ -894,8 +894,10 @@ chunk_colscan_kernel(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ sc
 // column prefix), the waves' parts in wave order.  The runs are assembled tile by tile in
 // LDS (with each pair's tile in a byte map), then copied out by consecutive threads, so the
 // global stores are coalesced; a chunk with more than CHUNK_STAGE pairs has its lanes write
-// their runs straight to memory.
-constexpr int CHUNK_STAGE = 4096;
+// their runs straight to memory.  3,072 staged pairs (19 KB of LDS per workgroup) let eight
+// workgroups share a CU (4,096: six); most chunks still fit (8.5 M pairs over ~4,300 chunks on a 1M-Gaussian
+// frame).
+constexpr int CHUNK_STAGE = 3072;
 
 template <typename Geo>
 __global__ void __launch_bounds__(CHUNK)
@@ -1010,7 +1012,9 @@ chunk_write_kernel(const uint32_t *__restrict__ vals, const uint32_t *__restrict
 // entries in ascending Gaussian index.
 constexpr int L1_GPT = 4;                          // Gaussians per thread
 constexpr int L1_GB = 256 * L1_GPT;                // Gaussians per block
-constexpr int L1_ITERS = 16;                       // 64-entry steps per wave and round
+// 8 steps (110 VGPRs, 24 KB of LDS) keep four workgroups on a CU, one wave per SIMD each, so a
+// 1M-Gaussian scene's 977 workgroups run in one round; 16 steps held three
+constexpr int L1_ITERS = 8;                        // 64-entry steps per wave and round
 constexpr uint32_t L1_STAGE = 256u * L1_ITERS;     // entries staged per round
 constexpr uint32_t L1_SMALL = 4;                   // supertiles a lane handles alone; larger: the wave
 

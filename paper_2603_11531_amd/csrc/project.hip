@@ -131,6 +131,19 @@ struct SoaShSource {
     }
 };
 
+// Whether the fused pass holds a source's attributes in registers across the MLP (one read) or
+// reads them again after it (cache hits).  Holding them pays for the float32 first-order planes;
+// the higher SH orders (up to 48 planes and their basis) run faster re-read, and the quantised and
+// Eq. 1 sources keep the re-read they were measured with.
+template <typename Src>
+struct KeepAcrossMlp {
+    static constexpr bool value = false;
+};
+template <>
+struct KeepAcrossMlp<SoaSource> {
+    static constexpr bool value = true;
+};
+
 // Enhancement MLP and projection in one pass: each wave builds its 64 Gaussians'
 // features, runs the MLP on MFMA (weights read from an LDS copy), hands every lane its
 // own (phi, m) and projects.  Same results as mgs_enhance followed by mgs_project.
@@ -165,7 +178,10 @@ enhance_project_kernel(Src src, CamK cam, const uint8_t *__restrict__ packed, fl
         }
         float ph, om;
         mlp_wave(f, F, s_x[w], ph, om);
-        // the attributes stay in registers across the MLP (one read per Gaussian)
+        if constexpr (!KeepAcrossMlp<Src>::value) {
+            __asm__ volatile("" ::: "memory");      // a second read, not the first one's registers
+            if (valid) in = src.load(i);
+        }
         if (valid) {
             in.phi = ph;
             in.om = om;
