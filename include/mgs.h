@@ -342,6 +342,16 @@ int mgs_bin(const mgs_projected *proj, int64_t n, int tiles_x, int tiles_y, void
             uint32_t *n_pairs, void *stream);
 
 /*
+ * mgs_check_capacity -- the caller's overflow check after mgs_bin / mgs_bin_sorted (the tile
+ * lists that the per-pixel sums of Eq. 2, Sec. 3.1, run over).  Waits for `stream`, reads the
+ * pair count P that the binning wrote to n_pairs (device, 1 uint32), stores it in *pairs (host;
+ * may be NULL) and returns MGS_ERR_CAPACITY when P > capacity (then the lists were not written:
+ * re-bin with a workspace and gids for at least P pairs), else MGS_OK.  MGS_ERR_INVALID_ARG for
+ * a NULL n_pairs, MGS_ERR_HIP if the stream reports an error.  Synchronises: not for capture.
+ */
+int mgs_check_capacity(const uint32_t *n_pairs, uint64_t capacity, uint64_t *pairs, void *stream);
+
+/*
  * mgs_blend_oit -- the depth-aware order-independent composite, Eq. 2.
  * For every pixel p over its tile's list: a = o_eff exp(-q/2),
  * q = dx^T Sigma'^-1 dx; pairs with a < alpha_min are skipped;

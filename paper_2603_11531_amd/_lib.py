@@ -36,7 +36,7 @@ EXPORTED = [
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
     "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
     "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc", "mgs_blend_census", "mgs_bounds_checked",
-    "mgs_bounds_status",
+    "mgs_bounds_status", "mgs_check_capacity",
 ]
 MGS_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
@@ -94,6 +94,7 @@ def load(path=None):
     sig = {
         "mgs_last_error": (C.c_char_p, []),
         "mgs_version": (C.c_char_p, []),
+        "mgs_check_capacity": (i32, [vp, u64, P(C.c_uint64), vp]),
         "mgs_mlp_pack": (i32, [vp, vp, vp]),
         "mgs_enhance": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, vp]),
         "mgs_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, P(mgs_projected), vp]),

@@ -56,5 +56,20 @@ extern "C" int mgs_bounds_status(uint32_t *flags, int clear) {
     return MGS_OK;
 }
 
+extern "C" int mgs_check_capacity(const uint32_t *n_pairs, uint64_t capacity, uint64_t *pairs, void *stream) {
+    using namespace mgs;
+    MGS_REQUIRE(n_pairs != nullptr, "n_pairs is NULL");
+    uint32_t P = 0;
+    const hipStream_t s = as_stream(stream);
+    if (hipMemcpyAsync(&P, n_pairs, sizeof(P), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MGS_ERR_HIP, "reading the pair count failed: %s", hipGetErrorString(hipGetLastError()));
+    if (pairs) *pairs = P;
+    if (uint64_t(P) > capacity)
+        return set_error(MGS_ERR_CAPACITY, "%u tile/Gaussian pairs exceed the capacity of %llu", P,
+                         (unsigned long long)capacity);
+    return MGS_OK;
+}
+
 extern "C" const char *mgs_last_error(void) { return mgs::g_err; }
 extern "C" const char *mgs_version(void) { return "mgs 0.1.0 gfx950"; }

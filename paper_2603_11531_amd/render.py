@@ -301,6 +301,15 @@ class Renderer:
     def pairs(self):
         return int(_u32_to_i64(self.n_pairs)[0])
 
+    def check_capacity(self, stream=None):
+        """mgs_check_capacity after a binning: waits for the stream and returns the pair count
+        (above self.capacity the lists were not written)."""
+        P = L.C.c_uint64()
+        rc = L.lib().mgs_check_capacity(L.ptr(self.n_pairs), self.capacity, L.C.byref(P), L.stream_ptr(stream))
+        if rc != L.MGS_ERR_CAPACITY:
+            L.check(rc)
+        return int(P.value)
+
     def census(self, cam_s, alpha_min=ALPHA_MIN, stream=None):
         """mgs_blend_census on the current lists: (list entries, evaluations the OIT blend
         executes, contributing pixel-Gaussian pairs); synchronises."""
@@ -351,7 +360,7 @@ class Renderer:
         global_sort = bool(sorted_path) and sorted_path != "tile_sort"
         self.bin(global_sort, stream)
         if check_capacity:
-            P = self.pairs()      # synchronises
+            P = self.check_capacity(stream)      # synchronises
             if P > self.capacity:
                 self.ensure_capacity(int(P * 1.25) + 1024, global_sort)
                 self.bin(global_sort, stream)

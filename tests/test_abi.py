@@ -57,6 +57,7 @@ def test_host_side_validation(lib):
     assert lib.mgs_blend_oit_split_workspace(4096, 4096, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_batch_workspace(1000, 1 << 20, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_bin_sorted_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK
+    assert lib.mgs_check_capacity(None, 1000, None, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
     # invalid camera / arguments are rejected before any device work
     cam = L.mgs_camera()

@@ -186,8 +186,15 @@ def test_bin_is_deterministic_and_overflow_is_reported(M):
     torch.cuda.synchronize()
     P = R.pairs()
     assert P > 1                       # overflow reported through n_pairs
+    # ... and by the caller-side check of the C ABI, which hands back the same count
+    L = M._lib
+    got = L.C.c_uint64()
+    assert L.lib().mgs_check_capacity(L.ptr(R.n_pairs), R.capacity, L.C.byref(got), None) == L.MGS_ERR_CAPACITY
+    assert got.value == P and "exceed" in L.lib().mgs_last_error().decode()
+    assert L.lib().mgs_check_capacity(L.ptr(R.n_pairs), P, None, None) == L.MGS_OK
     R.ensure_capacity(P)
     R.bin()
+    assert R.check_capacity() == P
     a = [t.clone() for t in R.lists()]
     R.bin()
     b = R.lists()
