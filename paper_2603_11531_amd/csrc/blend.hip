@@ -226,6 +226,146 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
     }
 }
 
+// Work items longest first.  The range workgroups are dispatched in item order as earlier ones
+// finish, so items in tile order leave whichever long items come last running alone at the end;
+// putting the longest first (list scheduling by decreasing length) shortens that tail.  A tile's
+// ranges all go to the length bucket of its range length (LEN_BUCKETS buckets of SPLIT_RANGE /
+// LEN_BUCKETS), buckets in decreasing length, tile order inside a bucket; the partial-sum slots
+// stay in tile order.  The order changes no result: an item owns its tile's pixels or its slot.
+constexpr int LEN_BUCKETS = 16;
+constexpr int LEN_WORDS = LEN_BUCKETS / 3 + 1;          // 21-bit counters, three per word
+static_assert(uint64_t(SPLIT_TILE) * SPLIT_MAX_RANGES < (1ull << 21), "21-bit bucket counters");
+static_assert(SPLIT_REPLICAS == 1024 / 64, "each replica writes the tiles of one of the 16 waves");
+__device__ __forceinline__ uint32_t len_bucket(uint32_t len) {
+    const uint32_t b = len == 0u ? 0u : (len - 1u) / (SPLIT_RANGE / LEN_BUCKETS);
+    return b < uint32_t(LEN_BUCKETS - 1) ? b : uint32_t(LEN_BUCKETS - 1);
+}
+// Counter b of packed bucket counters in v[0 .. LEN_WORDS): an OR of masked words, not an indexed
+// read, so the array stays in registers.
+template <int N>
+__device__ __forceinline__ uint32_t len_field(const uint64_t (&v)[N], uint32_t b) {
+    static_assert(N >= LEN_WORDS, "bucket counter words");
+    const uint32_t wi = b / 3u;
+    uint64_t w = 0;
+#pragma unroll
+    for (int k = 0; k < LEN_WORDS; ++k) w |= v[k] & (0ull - uint64_t(wi == uint32_t(k)));
+    return uint32_t(w >> (21u * (b - 3u * wi))) & 0x1FFFFFu;
+}
+
+// The plan of a single chunk of tiles (T <= SPLIT_TILE: every single view up to 1920 x 1080) in
+// longest-first order.  SPLIT_REPLICAS blocks each compute the whole plan; block b writes the
+// items and split-tile entries of the tiles of its wave b (scattered writes spread over CUs).
+// Per thread: its tiles' items per length bucket and its split-tile slots / count, scanned over
+// the block in one pass (K packed words, one LDS exchange); the buckets' first positions
+// (longest bucket first) go through LDS.
+__global__ void __launch_bounds__(1024)
+split_plan_ordered_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                          const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
+                          uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
+                          uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
+    constexpr int K = LEN_WORDS + 1;                     // bucket counters, then slots | split tiles << 32
+    __shared__ uint64_t s_w[K][16];                      // per word and wave: the wave's sums
+    __shared__ uint32_t s_base[LEN_BUCKETS + 1];         // first position of each bucket; [LEN_BUCKETS] = items
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    const uint32_t t0 = threadIdx.x * SPLIT_ITEMS;
+    uint32_t o[SPLIT_ITEMS + 1];
+#pragma unroll
+    for (int j = 0; j <= SPLIT_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
+    // the tiles' range counts (8 bits each) and length buckets (4 bits each), packed in registers
+    static_assert(SPLIT_ITEMS == 8 && LEN_BUCKETS <= 16, "packing of the per-tile values");
+    uint64_t nrp = 0;
+    uint32_t bkp = 0, cs = 0, cm = 0;
+    uint64_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0;
+#pragma unroll
+    for (int j = 0; j < SPLIT_ITEMS; ++j) {
+        const uint32_t L = o[j + 1] - o[j];
+        const uint32_t n = t0 + j < T ? n_ranges(L, SPLIT_RANGE) : 0u;
+        const uint32_t b = len_bucket(t0 + j < T ? range_len(L, SPLIT_RANGE) : 0u);
+        nrp |= uint64_t(n) << (8 * j);
+        bkp |= b << (4 * j);
+        const uint32_t wi = b / 3u;
+        const uint64_t add = uint64_t(n) << (21u * (b - 3u * wi));
+#pragma unroll
+        for (int k = 0; k < LEN_WORDS; ++k) v[k] += wi == uint32_t(k) ? add : 0ull;
+        cs += n > 1 ? n : 0u;
+        cm += n > 1 ? 1u : 0u;
+    }
+    v[K - 1] = uint64_t(cs) | (uint64_t(cm) << 32);
+    // exclusive scans of the K words over the block: wave scans, then the waves' sums via LDS
+    uint64_t inc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) inc[k] = v[k];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t u = __shfl_up(inc[k], d, 64);
+            if (l >= d) inc[k] += u;
+        }
+    }
+    if (l == 63) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s_w[k][w] = inc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        uint64_t pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += s_w[k][ww];
+        v[k] = pre + inc[k] - v[k];
+    }
+    if (threadIdx.x == 0) {
+        // bucket totals, and their first positions with the longest bucket first
+        uint64_t tot[LEN_WORDS];
+#pragma unroll
+        for (int k = 0; k < LEN_WORDS; ++k) {
+            tot[k] = 0;
+            for (int ww = 0; ww < 16; ++ww) tot[k] += s_w[k][ww];
+        }
+        uint32_t run = 0;
+        for (int b = LEN_BUCKETS - 1; b >= 0; --b) {
+            s_base[b] = run;
+            run += len_field(tot, uint32_t(b));
+        }
+        s_base[LEN_BUCKETS] = run;
+        if (blockIdx.x == 0) {
+            uint64_t m = 0;
+            for (int ww = 0; ww < 16; ++ww) m += s_w[K - 1][ww];
+            counts[0] = run;
+            counts[1] = uint32_t(m >> 32);
+        }
+    }
+    __syncthreads();
+    if (w != int(blockIdx.x % SPLIT_REPLICAS)) return;                      // wave-uniform
+    const uint64_t max_items = split_max_items(t_host, capacity);
+    uint32_t s0 = uint32_t(v[K - 1]), js = uint32_t(v[K - 1] >> 32);
+    for (uint32_t j = 0; j < uint32_t(SPLIT_ITEMS); ++j) {
+        const uint32_t n = uint32_t(nrp >> (8 * j)) & 0xFFu, b = (bkp >> (4 * j)) & 0xFu;
+        uint32_t before = 0;                                // this thread's earlier items in bucket b
+        for (uint32_t jj = 0; jj < j; ++jj)
+            before += ((bkp >> (4 * jj)) & 0xFu) == b ? uint32_t(nrp >> (8 * jj)) & 0xFFu : 0u;
+        const uint32_t pos = s_base[b] + len_field(v, b) + before;
+        const bool split = n > 1;
+        if (split) {
+            split_tile[js] = (t0 + j) | (n << 24);
+            split_slot0[js] = s0;
+        }
+        for (uint32_t r = 0; r < n; ++r) {
+            if (MGS_CHECK(uint64_t(pos) + r < max_items, BS_SPLIT_ITEM)) {
+                items[pos + r] = (t0 + j) | (r << 24);
+                item_slot[pos + r] = split ? s0 + r : 0xFFFFFFFFu;
+            }
+        }
+        if (split) {
+            s0 += n;
+            ++js;
+        }
+    }
+}
+
 // n_pairs / max_slots are read only by the checks of a checked build (MGS_CHECK_BOUNDS).
 template <typename Loc>
 __global__ void __launch_bounds__(BLEND_THREADS, 7)
@@ -314,7 +454,10 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
     uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
     const uint32_t nc = split_chunks(T);
-    if (nc <= PLAN_ONE_BLOCK) {                  // few chunks: replicated blocks with running carries
+    if (nc <= 1) {                               // one chunk: the plan in longest-first order
+        hipLaunchKernelGGL(split_plan_ordered_kernel, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T, n_pairs,
+                           capacity, items, slot, stile, sslot, counts);
+    } else if (nc <= PLAN_ONE_BLOCK) {           // few chunks: replicated blocks with running carries
         hipLaunchKernelGGL(split_plan_kernel, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T, n_pairs,
                            capacity, static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
                            static_cast<const uint64_t *>(nullptr), items, slot, stile, sslot, counts);
