@@ -773,7 +773,7 @@ def main():
         "mlp_f": res_mlpf,
         "sh_orders": res_sh,
         "roofline": {"bound": "alu",
-                     "kernel": "mgs_blend_oit_split (split_plan_kernel + blend_range_kernel + merge_ranges_kernel)",
+                     "kernel": "mgs_blend_oit_split (split_plan_ordered_kernel + blend_range_kernel + merge_ranges_kernel)",
                      "achieved": round(achieved, 2),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,

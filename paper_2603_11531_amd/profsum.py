@@ -10,7 +10,7 @@ plain device-to-device copy of known size that ``bench.py --calib-copy-mib`` run
 
     python -m paper_2603_11531_amd.profsum pmc --fetch <f>/p_counter_collection.csv \
         --write <w>/p_counter_collection.csv [--sq <s>/p_counter_collection.csv] \
-        --kernel "split_plan_kernel;blend_range_kernel;merge_ranges_kernel" --calib-mib 1024 \
+        --kernel "split_plan_ordered_kernel;blend_range_kernel;merge_ranges_kernel" --calib-mib 1024 \
         --cmd "<command>"
 
 The pmc summary records a hash of the kernel's sources; ``bench.py`` reports the
