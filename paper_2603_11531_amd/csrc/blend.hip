@@ -232,7 +232,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
 // ranges all go to the length bucket of its range length (LEN_BUCKETS buckets of SPLIT_RANGE /
 // LEN_BUCKETS), buckets in decreasing length, tile order inside a bucket; the partial-sum slots
 // stay in tile order.  The order changes no result: an item owns its tile's pixels or its slot.
-constexpr int LEN_BUCKETS = 16;
+constexpr int LEN_BUCKETS = 8;
 constexpr int LEN_WORDS = LEN_BUCKETS / 3 + 1;          // 21-bit counters, three per word
 static_assert(uint64_t(SPLIT_TILE) * SPLIT_MAX_RANGES < (1ull << 21), "21-bit bucket counters");
 static_assert(SPLIT_REPLICAS == 1024 / 64, "each replica writes the tiles of one of the 16 waves");
