@@ -16,7 +16,9 @@
 namespace mgs {
 
 // ---------------------------------------------------------------- split tile lists (blend)
-constexpr uint32_t SPLIT_RANGE = 1024;       // Gaussians per range of a long tile list
+// 2,048: with the work items dispatched longest first, longer ranges (fewer partial sums to merge)
+// measured faster than 1,024 on the 1M- and 3M-Gaussian frames (1,024 was best in tile order)
+constexpr uint32_t SPLIT_RANGE = 2048;       // Gaussians per range of a long tile list
 constexpr uint32_t SPLIT_MAX_RANGES = 255;   // ranges per tile (8-bit range index in a work item)
 
 MGS_HD uint32_t ceil_div(uint32_t a, uint32_t b) { return a / b + (a % b != 0u); }

@@ -30,9 +30,9 @@ CSRC = os.path.join(PKG, "csrc")
 
 # sources each profiled kernel group is built from (a summary is valid while they hash the same)
 SOURCES = {
-    "blend": ("blend.hip", "blend_math.h", "batch.h", "common.h"),
+    "blend": ("blend.hip", "blend_math.h", "index_math.h", "batch.h", "common.h"),
     "enhance_project": ("project.hip", "proj_math.h", "mlp_math.h", "common.h"),
-    "bin": ("bin.hip", "batch.h", "common.h"),
+    "bin": ("bin.hip", "index_math.h", "batch.h", "common.h"),
 }
 BLEND_SOURCES = SOURCES["blend"]
 

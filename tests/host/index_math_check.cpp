@@ -27,8 +27,10 @@ static int fails = 0;
 // Split plan: the ranges of one list partition it, at most 255, none empty; over a view, items
 // and partial-sum slots stay within the workspace bounds.
 static void check_split(std::mt19937_64 &rng) {
-    const uint32_t special[] = {0u, 1u, 2u, 1023u, 1024u, 1025u, 2048u, 255u * 1024u, 255u * 1024u + 1u,
-                                300000u, 1u << 20, (1u << 24) + 7u, 0x7FFFFFFFu, 0xFFFFFFFEu};
+    const uint32_t special[] = {0u, 1u, 2u, 1023u, 1024u, 1025u, 2048u, SPLIT_RANGE - 1u, SPLIT_RANGE,
+                                SPLIT_RANGE + 1u, 255u * 1024u, 255u * 1024u + 1u, 255u * SPLIT_RANGE,
+                                255u * SPLIT_RANGE + 1u, 300000u, 1u << 20, (1u << 24) + 7u, 0x7FFFFFFFu,
+                                0xFFFFFFFEu};
     for (uint32_t L : special) {
         const uint32_t n = n_ranges(L, SPLIT_RANGE), len = range_len(L, SPLIT_RANGE);
         CHECK(n >= 1 && n <= SPLIT_MAX_RANGES, "L=%u n=%u", L, n);

@@ -6,6 +6,8 @@ against the oracle's BF16 emulation, and <= 2e-2 / PSNR >= 50 dB against the
 plain FP64 oracle.
 """
 import math
+import os
+import re
 
 import numpy as np
 import pytest
@@ -493,11 +495,18 @@ def test_fused_enhance_project_equals_separate_calls(M):
     assert torch.equal(ia, ib)
 
 
+def _split_range():
+    """Gaussians per range of the split blend (SPLIT_RANGE of the kernels' index_math.h)."""
+    text = open(os.path.join(os.path.dirname(__file__), "..", "paper_2603_11531_amd", "csrc", "index_math.h")).read()
+    return int(re.search(r"constexpr uint32_t SPLIT_RANGE = (\d+);", text).group(1))
+
+
 def test_split_tile_longer_than_255_full_ranges(M):
-    """One tile with more than 255 x 1024 Gaussians: its list is cut into 255 ranges of
-    ceil(L / 255) > 1024 (the long-list rule of the split plan), merged in order."""
+    """One tile with more than 255 x SPLIT_RANGE Gaussians: its list is cut into 255 ranges of
+    ceil(L / 255) > SPLIT_RANGE (the long-list rule of the split plan), merged in order."""
     say("test_split_tile_longer_than_255_full_ranges")
-    scene = mgs_data.make_scene_uniform(270_000, 21, half=0.5, ls_mu=-4.5)
+    rl = _split_range()
+    scene = mgs_data.make_scene_uniform(int(255 * rl * 1.04), 21, half=0.5, ls_mu=-4.5)
     cam = mgs_data.look_at((0.0, 0.0, -4.0), width=16, height=16, f=16.0)
     bg = (0.1, 0.2, 0.3)
     ds = M.DeviceScene(scene)
@@ -506,9 +515,9 @@ def test_split_tile_longer_than_255_full_ranges(M):
     offs, _ = R.lists()
     L = int(offs[1] - offs[0])
     say(f"  one tile, list length {L}")
-    assert L > 255 * 1024
+    assert L > 255 * rl
     tile_img = R.render(ds, cam, bg=bg, split=False).double().cpu()
-    # 270k-term float32 sums in two different orders (255 ranges vs four waves)
+    # L-term float32 sums in two different orders (255 ranges vs four waves)
     d = float((split_img - tile_img).abs().max())
     say(f"  split vs per-tile blend: {d:.3e}")
     assert d < TOL
@@ -520,9 +529,9 @@ def test_split_tile_longer_than_255_full_ranges(M):
 
 
 def test_split_tile_blend_matches_oracle_and_per_tile_blend(M):
-    """Dense tiles (lists far longer than one 1024-Gaussian range) through the split blend."""
+    """Dense tiles (lists several SPLIT_RANGE-Gaussian ranges long) through the split blend."""
     say("test_split_tile_blend_matches_oracle_and_per_tile_blend")
-    scene = mgs_data.make_scene_uniform(40000, 12, ls_mu=-3.0)
+    scene = mgs_data.make_scene_uniform(40000 * _split_range() // 1024, 12, ls_mu=-3.0)
     cam = mgs_data.look_at((0.1, -0.2, -4.0), width=136, height=120, f=136.0)
     bg = (0.2, 0.3, 0.4)
     ds = M.DeviceScene(scene)
@@ -531,7 +540,7 @@ def test_split_tile_blend_matches_oracle_and_per_tile_blend(M):
     offs, _ = R.lists()
     longest = int((offs[1:] - offs[:-1]).max())
     say(f"  P={R.pairs()} longest list {longest}")
-    assert longest > 3 * 1024
+    assert longest > 3 * _split_range()
     tile_img = R.render(ds, cam, bg=bg, split=False).double().cpu()
     assert float((split_img - tile_img).abs().max()) < 2e-6
     pr, camt = oracle_project(scene, cam)
