@@ -157,6 +157,12 @@ __device__ __forceinline__ void key_bits(Lds &S, uint32_t kor, uint32_t kand) {
     __syncthreads();
 }
 
+// Long lists first.  Workgroups start in launch order as earlier ones finish, so in tile order the
+// lists longer than TS_CHUNK (sorted through the workspace, several times the work of an LDS sort)
+// that come last would run alone at the end.  The launch therefore walks the tiles twice: work
+// item k < T sorts tile k only if its list is long, item T + k only if it is not, so every long
+// list starts before any short one with no ordering pass; a skipped item costs two offset reads.
+// The short lists keep tile order (neighbouring tiles share records in the caches).
 __global__ void __launch_bounds__(TS_THREADS)
 tile_sort_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ offs, uint32_t *__restrict__ gids,
                  uint32_t T, const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ tk0,
@@ -165,10 +171,13 @@ tile_sort_kernel(const float4 *__restrict__ splat, const uint32_t *__restrict__ 
     if (uint64_t(*n_pairs) > capacity) return;                            // grid-uniform: no lists
     const uint32_t P = *n_pairs;
     const int t = threadIdx.x;
-    for (uint32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {       // block-uniform
+    for (uint64_t k = blockIdx.x; k < 2 * uint64_t(T); k += gridDim.x) { // block-uniform
+        const bool long_pass = k < T;
+        const uint32_t tile = uint32_t(long_pass ? k : k - T);
         const uint32_t s = offs[tile], e = offs[tile + 1];
         if (!MGS_CHECK(s <= e && e <= P, BS_LIST_READ)) continue;
         const uint32_t n = e - s;
+        if ((n > TS_CHUNK) != long_pass) continue;                        // the other pass's list
         if (n <= 1u) continue;
         if (n <= TS_CHUNK) {
             uint32_t kor = 0u, kand = ~0u;
@@ -288,7 +297,7 @@ extern "C" int mgs_tile_sort(const mgs_projected *proj, int64_t n, const uint32_
     const uint64_t T = uint64_t(tiles_x) * uint64_t(tiles_y);
     if (capacity == 0 || n == 0) return MGS_OK;
     char *w = static_cast<char *>(ws);
-    const unsigned grid = unsigned(T < tsort::TS_GRID_MAX ? T : tsort::TS_GRID_MAX);
+    const unsigned grid = unsigned(2 * T < tsort::TS_GRID_MAX ? 2 * T : tsort::TS_GRID_MAX);
     hipLaunchKernelGGL(tsort::tile_sort_kernel, dim3(grid), dim3(tsort::TS_THREADS), 0, as_stream(stream),
                        reinterpret_cast<const float4 *>(proj->splat), tile_offsets, gids, uint32_t(T), n_pairs,
                        capacity, reinterpret_cast<uint32_t *>(w + L.tk0), reinterpret_cast<uint32_t *>(w + L.tk1),
