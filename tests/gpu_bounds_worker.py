@@ -28,13 +28,18 @@ def cases():
                     None, {}))
     empty = {k: v[..., :0].copy() for k, v in mgs_data.make_scene_uniform(1, 0).items()}
     out.append(("empty", empty, mgs_data.look_at((0, 0, -4), width=40, height=24, f=40.0), None, {}))
-    dense = mgs_data.make_scene_uniform(270_000, 21, half=0.5, ls_mu=-4.5)
-    out.append(("one_tile_270k", dense, mgs_data.look_at((0.0, 0.0, -4.0), width=16, height=16, f=16.0), None, {}))
+    # one tile whose list is longer than 255 ranges of 2,048 (the split plan's long-list rule), and
+    # the per-tile depth sort of that list (its workspace path)
+    dense = mgs_data.make_scene_uniform(540_000, 21, half=0.5, ls_mu=-4.5)
+    cam16 = mgs_data.look_at((0.0, 0.0, -4.0), width=16, height=16, f=16.0)
+    out.append(("one_tile_540k", dense, cam16, None, {}))
+    out.append(("one_tile_540k_tile_sort", dense, cam16, None, {"sorted_path": "tile_sort"}))
     ub = mgs_data.make_scene_unbounded(30000, 8)
     cam = mgs_data.circle_poses(8, 10.0, 240, 160, f=240.0)[5]
     mlp = mgs_data.make_mlp(9)
     out.append(("mlp_fused", ub, cam, mlp, {"fused": True}))
     out.append(("mlp_sorted", ub, cam, mlp, {"fused": True, "sorted_path": True}))
+    out.append(("mlp_tile_sort", ub, cam, mlp, {"fused": True, "sorted_path": "tile_sort"}))
     sig, bet = mgs_data.make_sortfree_params(30000, 3)
     out.append(("eq1", ub, cam, mlp, {"fused": True, "w_bg": 0.4,
                                       "sortfree": (torch.as_tensor(sig).cuda(), torch.as_tensor(bet).cuda())}))
