@@ -152,6 +152,7 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--top", type=int, default=24, help="kernels listed, by total time")
     p = sub.add_parser("pmc")
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
@@ -162,7 +163,7 @@ def main(argv=None):
     p.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.mode == "stats":
-        sys.stdout.write(stats(a.csv, a.cmd))
+        sys.stdout.write(stats(a.csv, a.cmd, a.top))
     else:
         sys.stdout.write(pmc(a.fetch, a.write, a.sq.split(",") if a.sq else None, a.kernel.split(";"), a.calib_mib,
                              a.cmd, a.group))
