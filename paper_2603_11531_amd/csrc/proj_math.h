@@ -63,6 +63,11 @@ __device__ __forceinline__ GaussIn load_gauss(const mgs_gaussians &g, int64_t i,
     return in;
 }
 
+// Reciprocals (v_rcp_f32, ~1 ulp) stand in for the divisions of the quantities whose float32 error
+// is compared relatively: the rotation, opacity, view direction, weight and conic coefficients.
+// The screen mean keeps the correctly rounded 1 / z, since the ambiguity band of the alpha cut is
+// sized from its rounding error; the pass is latency bound and the shorter dependent chains saved
+// ~3% of it.
 __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK &cam) {
     GaussFwd f;
     const float *R = cam.R;
@@ -75,20 +80,20 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
     for (int k = 0; k < 3; ++k) f.s[k] = expf(in.ls[k]);
     const float qn2 = in.q[0] * in.q[0] + in.q[1] * in.q[1] + in.q[2] * in.q[2] + in.q[3] * in.q[3];
     f.qnorm = sqrtf(qn2);
-    const float qi = qn2 > 0.f ? 1.0f / f.qnorm : 0.f;
+    const float qi = qn2 > 0.f ? __builtin_amdgcn_rcpf(f.qnorm) : 0.f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) f.qn[k] = in.q[k] * qi;
     const float w = f.qn[0], x = f.qn[1], y = f.qn[2], z = f.qn[3];
     f.r[0][0] = 1.f - 2.f * (y * y + z * z); f.r[0][1] = 2.f * (x * y - w * z); f.r[0][2] = 2.f * (x * z + w * y);
     f.r[1][0] = 2.f * (x * y + w * z); f.r[1][1] = 1.f - 2.f * (x * x + z * z); f.r[1][2] = 2.f * (y * z - w * x);
     f.r[2][0] = 2.f * (x * z - w * y); f.r[2][1] = 2.f * (y * z + w * x); f.r[2][2] = 1.f - 2.f * (x * x + y * y);
-    f.sig = 1.0f / (1.0f + expf(-in.logit));
+    f.sig = __builtin_amdgcn_rcpf(1.0f + expf(-in.logit));
     f.o = f.sig * in.om;
 
 #pragma unroll
     for (int k = 0; k < 3; ++k) f.v[k] = in.mu[k] - cam.campos[k];
     f.vlen = sqrtf(f.v[0] * f.v[0] + f.v[1] * f.v[1] + f.v[2] * f.v[2]);
-    const float vi = 1.0f / f.vlen;
+    const float vi = __builtin_amdgcn_rcpf(f.vlen);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f.P[k] = f.v[k] * vi;
 #pragma unroll
@@ -117,8 +122,9 @@ __device__ __forceinline__ GaussFwd gauss_forward(const GaussIn &in, const CamK 
         f.esd = 0.0f;
         f.w = expf(-in.wsig * powf(f.z, in.wbeta));
     } else {
-        f.esd = expf(f.smax / f.z);
-        f.w = in.phi * in.phi + in.phi / (f.z * f.z) + f.esd;
+        const float izw = __builtin_amdgcn_rcpf(f.z);
+        f.esd = expf(f.smax * izw);
+        f.w = in.phi * in.phi + in.phi * izw * izw + f.esd;
     }
 
     const float limx = FRUSTUM_CLAMP * (0.5f * cam.W) / cam.fx;
@@ -189,9 +195,10 @@ __device__ __forceinline__ ProjOut project_gaussian(const GaussIn &in, const Cam
         o.n_tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         o.rect = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
     }
-    const float kA = -0.5f * LOG2E * (f.c / f.det);   // log2(alpha) = log2(o) + kA t^2 + kG dy^2
-    const float beta = -f.b / f.c;                   // t = dx + beta * dy
-    const float kG = -0.5f * LOG2E / f.c;
+    const float ic = __builtin_amdgcn_rcpf(f.c);
+    const float kA = -0.5f * LOG2E * (f.c * __builtin_amdgcn_rcpf(f.det));   // log2(alpha) = log2(o) + kA t^2 + kG dy^2
+    const float beta = -f.b * ic;                    // t = dx + beta * dy
+    const float kG = -0.5f * LOG2E * ic;
     o.r0 = make_float4(f.mx, f.my, log2f(fmaxf(f.o, 1e-30f)), f.w);
     o.r1 = make_float4(kA, beta, kG, f.front ? f.z : -1.0f);
     o.r2 = make_float4(f.col[0], f.col[1], f.col[2], f.o);
