@@ -367,9 +367,10 @@ int mgs_blend_oit(const mgs_projected *proj, const uint32_t *tile_offsets, const
 /*
  * mgs_blend_oit_split -- mgs_blend_oit with long tile lists cut into equal ranges of at
  * most 2048 Gaussians (of about L / 255 for lists longer than 255 x 2048, so a tile has at
- * most 255 ranges), rendered by separate workgroups (the longest first) and merged exactly in
- * range order (Eq. 2's sums are order-independent: N and D add, T multiplies), which balances
- * the work of dense tiles.  Results equal mgs_blend_oit up to float32 summation order.
+ * most 255 ranges), rendered by separate workgroups (the longest first for views of up to
+ * 65,536 tiles, in tile order beyond) and merged exactly in range order (Eq. 2's sums are
+ * order-independent: N and D add, T multiplies), which balances the work of dense tiles.
+ * Results equal mgs_blend_oit up to float32 summation order.
  * n_pairs / capacity: as written / used by mgs_bin (nothing is drawn if n_pairs >
  * capacity).  ws: mgs_blend_oit_split_workspace() bytes, 256-byte aligned.
  * MGS_ERR_INVALID_ARG for a view of 2^24 or more 16x16 tiles.

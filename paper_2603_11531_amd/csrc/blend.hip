@@ -147,7 +147,7 @@ split_sum_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__
 
 static_assert(SPLIT_TILE == 8192, "split_plan_kernel searches an 8192-entry table in 13 steps");
 constexpr int SPLIT_FILL_ILP = 4;                // item searches a thread keeps in flight
-constexpr unsigned SPLIT_REPLICAS = 16;          // blocks of a single-pass plan, each writing a share of the items
+constexpr unsigned SPLIT_REPLICAS = 16;          // blocks of the ordered plan, each writing one wave's tiles
 
 __global__ void __launch_bounds__(1024)
 split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
@@ -155,28 +155,21 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
                   const uint64_t *__restrict__ part_m, const uint64_t *__restrict__ totals,
                   uint32_t *__restrict__ items, uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
                   uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
-    // part_is == NULL (few chunks): every block walks every chunk with running carries and
-    // writes every grid-th 1024 items of each
+    // block c (and c + grid ...) takes chunk c, its first item / slot / split tile from part_is, part_m
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_item0[SPLIT_TILE];     // chunk-relative first item of each tile
     __shared__ uint32_t s_slot0[SPLIT_TILE];     // first partial-sum slot of a split tile, else ~0
     const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
-    uint64_t c_is = 0, c_m = 0;
-    const bool replicated = part_is == nullptr;
-    const bool writer = !replicated || blockIdx.x == 0;     // writes the split-tile table and counts
-    const uint32_t fill0 = replicated ? blockIdx.x * 1024u : 0u;
-    const uint32_t fill_stride = 1024u * (replicated ? gridDim.x : 1u);
-    for (uint32_t c = replicated ? 0u : blockIdx.x; c < split_chunks(T); c += replicated ? 1u : gridDim.x) {
+    constexpr uint32_t fill_stride = 1024u;
+    for (uint32_t c = blockIdx.x; c < split_chunks(T); c += gridDim.x) {
         const uint32_t t0 = c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS;
         uint32_t ci, cs, cm;
         const uint64_t nr = tile_ranges(offs, t0, T, ci, cs, cm);
         uint64_t t;
         const uint64_t x = block_scan1024(split_pack(ci, cs, cm), s_wsum, &t);
-        const uint64_t b1 = part_is ? part_is[c] : c_is;       // items | slots << 32 before the chunk
-        const uint64_t b2 = part_is ? part_m[c] : c_m;
+        const uint64_t b1 = part_is[c];          // items | slots << 32 before the chunk
+        const uint64_t b2 = part_m[c];
         const uint32_t t1 = split_items(t);
-        c_is += t1 | (uint64_t(split_slots(t)) << 32);
-        c_m += split_tiles(t);
         uint32_t i0 = split_items(x), s0 = uint32_t(b1 >> 32) + split_slots(x), js = uint32_t(b2) + split_tiles(x);
 #pragma unroll
         for (int j = 0; j < SPLIT_ITEMS; ++j) {
@@ -184,7 +177,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
             const bool m = nj > 1;
             s_item0[threadIdx.x * SPLIT_ITEMS + j] = i0;
             s_slot0[threadIdx.x * SPLIT_ITEMS + j] = m ? s0 : 0xFFFFFFFFu;
-            if (m && writer) {
+            if (m) {
                 split_tile[js] = (t0 + j) | (nj << 24);          // the merge needs no list offsets
                 split_slot0[js] = s0;
             }
@@ -198,7 +191,7 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         // item i of the chunk belongs to its last tile whose first item is <= i (tiles with
         // no item share the next tile's start and are never chosen); s_item0[0] = 0 <= i
         const uint32_t n_items = uint32_t(t1), ibase = uint32_t(b1);
-        for (uint32_t i = fill0 + threadIdx.x; i < n_items; i += fill_stride * SPLIT_FILL_ILP) {
+        for (uint32_t i = threadIdx.x; i < n_items; i += fill_stride * SPLIT_FILL_ILP) {
             uint32_t lo[SPLIT_FILL_ILP];
 #pragma unroll
             for (int q = 0; q < SPLIT_FILL_ILP; ++q) lo[q] = 0;
@@ -221,8 +214,8 @@ split_plan_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict_
         __syncthreads();                         // the tables are rewritten by the next chunk
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counts[0] = T == 0 ? 0u : uint32_t(part_is ? totals[0] : c_is);   // items (low half of items | slots << 32)
-        counts[1] = T == 0 ? 0u : uint32_t(part_is ? totals[1] : c_m);    // split tiles
+        counts[0] = T == 0 ? 0u : uint32_t(totals[0]);   // items (low half of items | slots << 32)
+        counts[1] = T == 0 ? 0u : uint32_t(totals[1]);   // split tiles
     }
 }
 
@@ -252,33 +245,29 @@ __device__ __forceinline__ uint32_t len_field(const uint64_t (&v)[N], uint32_t b
     return uint32_t(w >> (21u * (b - 3u * wi))) & 0x1FFFFFu;
 }
 
-// The plan of a single chunk of tiles (T <= SPLIT_TILE: every single view up to 1920 x 1080) in
-// longest-first order.  SPLIT_REPLICAS blocks each compute the whole plan; block b writes the
-// items and split-tile entries of the tiles of its wave b (scattered writes spread over CUs).
-// Per thread: its tiles' items per length bucket and its split-tile slots / count, scanned over
-// the block in one pass (K packed words, one LDS exchange); the buckets' first positions
-// (longest bucket first) go through LDS.
-__global__ void __launch_bounds__(1024)
-split_plan_ordered_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
-                          const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ items,
-                          uint32_t *__restrict__ item_slot, uint32_t *__restrict__ split_tile,
-                          uint32_t *__restrict__ split_slot0, uint32_t *__restrict__ counts) {
-    constexpr int K = LEN_WORDS + 1;                     // bucket counters, then slots | split tiles << 32
-    __shared__ uint64_t s_w[K][16];                      // per word and wave: the wave's sums
-    __shared__ uint32_t s_base[LEN_BUCKETS + 1];         // first position of each bucket; [LEN_BUCKETS] = items
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
-    const uint32_t t0 = threadIdx.x * SPLIT_ITEMS;
+// The plan in longest-first order, for up to ORDER_CHUNKS chunks of SPLIT_TILE tiles (a single view
+// up to 4K, or a batch of up to eight 1920 x 1080 views).  Per thread: its tiles' items per length
+// bucket and its split-tile slots / count, scanned over the block in one pass (PLAN_WORDS packed
+// words, one LDS exchange).  Inside a bucket the items keep tile order, across chunks too.
+constexpr uint32_t ORDER_CHUNKS = 8;
+constexpr int PLAN_WORDS = LEN_WORDS + 1;        // bucket counters, then slots | split tiles << 32
+constexpr int CHUNK_TOTALS = LEN_BUCKETS + 2;    // per chunk: items per bucket, slots, split tiles
+static_assert(ORDER_CHUNKS * CHUNK_TOTALS <= 1024, "one chunk total per thread");
+
+// Chunk c, this thread's tiles t0 .. t0 + 7 (t0 returned): range counts (8 bits each) and length
+// buckets (4 bits each) packed in nrp / bkp, per-bucket item counts and slots / split tiles in v.
+__device__ __forceinline__ uint32_t plan_tiles(const uint32_t *__restrict__ offs, uint32_t T, uint32_t c,
+                                               uint64_t &nrp, uint32_t &bkp, uint64_t (&v)[PLAN_WORDS]) {
+    static_assert(SPLIT_ITEMS == 8 && LEN_BUCKETS <= 16, "packing of the per-tile values");
+    const uint32_t t0 = c * SPLIT_TILE + threadIdx.x * SPLIT_ITEMS;
     uint32_t o[SPLIT_ITEMS + 1];
 #pragma unroll
     for (int j = 0; j <= SPLIT_ITEMS; ++j) o[j] = t0 + j <= T ? offs[t0 + j] : 0u;
-    // the tiles' range counts (8 bits each) and length buckets (4 bits each), packed in registers
-    static_assert(SPLIT_ITEMS == 8 && LEN_BUCKETS <= 16, "packing of the per-tile values");
-    uint64_t nrp = 0;
-    uint32_t bkp = 0, cs = 0, cm = 0;
-    uint64_t v[K];
+    nrp = 0;
+    bkp = 0;
+    uint32_t cs = 0, cm = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0;
+    for (int k = 0; k < PLAN_WORDS; ++k) v[k] = 0;
 #pragma unroll
     for (int j = 0; j < SPLIT_ITEMS; ++j) {
         const uint32_t L = o[j + 1] - o[j];
@@ -293,23 +282,91 @@ split_plan_ordered_kernel(const uint32_t *__restrict__ offs, const uint32_t *__r
         cs += n > 1 ? n : 0u;
         cm += n > 1 ? 1u : 0u;
     }
-    v[K - 1] = uint64_t(cs) | (uint64_t(cm) << 32);
-    // exclusive scans of the K words over the block: wave scans, then the waves' sums via LDS
-    uint64_t inc[K];
+    v[PLAN_WORDS - 1] = uint64_t(cs) | (uint64_t(cm) << 32);
+    return t0;
+}
+
+// Inclusive wave scan of the words (inc); lane 63 leaves the wave's sums in s_w[k][wave].
+__device__ __forceinline__ void plan_wave_scan(const uint64_t (&v)[PLAN_WORDS], uint64_t (&inc)[PLAN_WORDS],
+                                               uint64_t (*s_w)[16]) {
+    const int l = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < K; ++k) inc[k] = v[k];
+    for (int k = 0; k < PLAN_WORDS; ++k) inc[k] = v[k];
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < PLAN_WORDS; ++k) {
             const uint64_t u = __shfl_up(inc[k], d, 64);
             if (l >= d) inc[k] += u;
         }
     }
     if (l == 63) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) s_w[k][w] = inc[k];
+        for (int k = 0; k < PLAN_WORDS; ++k) s_w[k][threadIdx.x >> 6] = inc[k];
     }
+}
+
+// Block sums of the words from s_w (after a barrier): per-bucket items, slots, split tiles.
+__device__ __forceinline__ void plan_totals(const uint64_t (*s_w)[16], uint32_t (&tot)[CHUNK_TOTALS]) {
+    uint64_t t[PLAN_WORDS];
+#pragma unroll
+    for (int k = 0; k < PLAN_WORDS; ++k) {
+        t[k] = 0;
+        for (int ww = 0; ww < 16; ++ww) t[k] += s_w[k][ww];
+    }
+#pragma unroll
+    for (int b = 0; b < LEN_BUCKETS; ++b) tot[b] = len_field(t, uint32_t(b));
+    tot[LEN_BUCKETS] = uint32_t(t[PLAN_WORDS - 1]);
+    tot[LEN_BUCKETS + 1] = uint32_t(t[PLAN_WORDS - 1] >> 32);
+}
+
+// Several chunks, first launch: block c writes chunk c's CHUNK_TOTALS totals to ctot.
+__global__ void __launch_bounds__(1024)
+split_chunk_totals_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                          const uint32_t *__restrict__ n_pairs, uint64_t capacity, uint32_t *__restrict__ ctot) {
+    __shared__ uint64_t s_w[PLAN_WORDS][16];
+    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    uint64_t nrp, v[PLAN_WORDS], inc[PLAN_WORDS];
+    uint32_t bkp;
+    plan_tiles(offs, T, blockIdx.x, nrp, bkp, v);
+    plan_wave_scan(v, inc, s_w);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot[CHUNK_TOTALS];
+        plan_totals(s_w, tot);
+#pragma unroll
+        for (int k = 0; k < CHUNK_TOTALS; ++k) ctot[blockIdx.x * CHUNK_TOTALS + k] = tot[k];
+    }
+}
+
+// The items and split-tile tables.  SPLIT_REPLICAS blocks per chunk (block b: chunk b / 16) each
+// scan the chunk and write the items and split-tile entries of the tiles of one wave (b % 16),
+// which spreads the scattered writes over CUs.  ONE (a single chunk): the bucket totals come from
+// the block's own scan; else from every chunk's totals in ctot (the first launch), which give the
+// chunk's first position in each bucket and its first slot and split tile.
+template <bool ONE>
+__global__ void __launch_bounds__(1024)
+split_plan_ordered_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ t_count, uint32_t t_host,
+                          const uint32_t *__restrict__ n_pairs, uint64_t capacity, const uint32_t *__restrict__ ctot,
+                          uint32_t *__restrict__ items, uint32_t *__restrict__ item_slot,
+                          uint32_t *__restrict__ split_tile, uint32_t *__restrict__ split_slot0,
+                          uint32_t *__restrict__ counts) {
+    constexpr int K = PLAN_WORDS;
+    __shared__ uint64_t s_w[K][16];                      // per word and wave: the wave's sums
+    __shared__ uint32_t s_ctot[ONE ? 1 : ORDER_CHUNKS * CHUNK_TOTALS];
+    __shared__ uint32_t s_first[LEN_BUCKETS];            // the chunk's first position in each bucket
+    __shared__ uint32_t s_slot0, s_split0;               // the chunk's first slot and split tile
+    const int w = threadIdx.x >> 6;
+    const uint32_t c = ONE ? 0u : blockIdx.x / SPLIT_REPLICAS;
+    const uint32_t nc = ONE ? 1u : gridDim.x / SPLIT_REPLICAS;
+    const uint32_t T = live_tiles(t_count, t_host, n_pairs, capacity);
+    uint32_t ct = 0;                                     // one chunk total per thread, loaded before the scan
+    if (!ONE && threadIdx.x < nc * CHUNK_TOTALS) ct = ctot[threadIdx.x];
+    uint64_t nrp, v[K], inc[K];
+    uint32_t bkp;
+    const uint32_t t0 = plan_tiles(offs, T, c, nrp, bkp, v);
+    plan_wave_scan(v, inc, s_w);
+    if (!ONE && threadIdx.x < nc * CHUNK_TOTALS) s_ctot[threadIdx.x] = ct;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -318,36 +375,48 @@ split_plan_ordered_kernel(const uint32_t *__restrict__ offs, const uint32_t *__r
         v[k] = pre + inc[k] - v[k];
     }
     if (threadIdx.x == 0) {
-        // bucket totals, and their first positions with the longest bucket first
-        uint64_t tot[LEN_WORDS];
-#pragma unroll
-        for (int k = 0; k < LEN_WORDS; ++k) {
-            tot[k] = 0;
-            for (int ww = 0; ww < 16; ++ww) tot[k] += s_w[k][ww];
+        // first positions, longest bucket first, chunks in order inside a bucket
+        uint32_t run = 0, slot = 0, split = 0;
+        if (ONE) {
+            uint32_t tot[CHUNK_TOTALS];
+            plan_totals(s_w, tot);
+            for (int b = LEN_BUCKETS - 1; b >= 0; --b) {
+                s_first[b] = run;
+                run += tot[b];
+            }
+            split = tot[LEN_BUCKETS + 1];
+            s_slot0 = 0;
+            s_split0 = 0;
+        } else {
+            for (int b = LEN_BUCKETS - 1; b >= 0; --b)
+                for (uint32_t cc = 0; cc < nc; ++cc) {
+                    if (cc == c) s_first[b] = run;
+                    run += s_ctot[cc * CHUNK_TOTALS + b];
+                }
+            for (uint32_t cc = 0; cc < nc; ++cc) {
+                if (cc == c) {
+                    s_slot0 = slot;
+                    s_split0 = split;
+                }
+                slot += s_ctot[cc * CHUNK_TOTALS + LEN_BUCKETS];
+                split += s_ctot[cc * CHUNK_TOTALS + LEN_BUCKETS + 1];
+            }
         }
-        uint32_t run = 0;
-        for (int b = LEN_BUCKETS - 1; b >= 0; --b) {
-            s_base[b] = run;
-            run += len_field(tot, uint32_t(b));
-        }
-        s_base[LEN_BUCKETS] = run;
         if (blockIdx.x == 0) {
-            uint64_t m = 0;
-            for (int ww = 0; ww < 16; ++ww) m += s_w[K - 1][ww];
             counts[0] = run;
-            counts[1] = uint32_t(m >> 32);
+            counts[1] = split;
         }
     }
     __syncthreads();
-    if (w != int(blockIdx.x % SPLIT_REPLICAS)) return;                      // wave-uniform
+    if (w != int(blockIdx.x % SPLIT_REPLICAS)) return;   // the writer wave
     const uint64_t max_items = split_max_items(t_host, capacity);
-    uint32_t s0 = uint32_t(v[K - 1]), js = uint32_t(v[K - 1] >> 32);
+    uint32_t s0 = s_slot0 + uint32_t(v[K - 1]), js = s_split0 + uint32_t(v[K - 1] >> 32);
     for (uint32_t j = 0; j < uint32_t(SPLIT_ITEMS); ++j) {
         const uint32_t n = uint32_t(nrp >> (8 * j)) & 0xFFu, b = (bkp >> (4 * j)) & 0xFu;
-        uint32_t before = 0;                                // this thread's earlier items in bucket b
+        uint32_t before = 0;                             // this thread's earlier items in bucket b
         for (uint32_t jj = 0; jj < j; ++jj)
             before += ((bkp >> (4 * jj)) & 0xFu) == b ? uint32_t(nrp >> (8 * jj)) & 0xFFu : 0u;
-        const uint32_t pos = s_base[b] + len_field(v, b) + before;
+        const uint32_t pos = s_first[b] + len_field(v, b) + before;
         const bool split = n > 1;
         if (split) {
             split_tile[js] = (t0 + j) | (n << 24);
@@ -416,7 +485,7 @@ merge_ranges_kernel(const uint32_t *__restrict__ split_tile, const uint32_t *__r
 }
 
 struct SplitLayout {
-    size_t items, slot, stile, sslot, counts, part, part_is, part_m, totals, total;
+    size_t items, slot, stile, sslot, counts, part, part_is, part_m, totals, ctot, total;
     uint32_t max_items;
 };
 
@@ -434,6 +503,7 @@ inline SplitLayout split_layout(uint32_t T, uint64_t capacity) {
     L.part_is = o; o = align_up(o + (size_t(split_chunks(T)) + 1) * 8, 256);
     L.part_m = o;  o = align_up(o + (size_t(split_chunks(T)) + 1) * 8, 256);
     L.totals = o;  o = align_up(o + 2 * 8, 256);
+    L.ctot = o;    o = align_up(o + ORDER_CHUNKS * CHUNK_TOTALS * 4, 256);
     L.total = o;
     return L;
 }
@@ -453,15 +523,19 @@ int blend_split_launch(const float4 *splat, const uint32_t *offs, const uint32_t
     uint64_t *part_is = reinterpret_cast<uint64_t *>(w + L.part_is);
     uint64_t *part_m = reinterpret_cast<uint64_t *>(w + L.part_m);
     uint64_t *totals = reinterpret_cast<uint64_t *>(w + L.totals);
+    uint32_t *ctot = reinterpret_cast<uint32_t *>(w + L.ctot);
     const uint32_t nc = split_chunks(T);
     if (nc <= 1) {                               // one chunk: the plan in longest-first order
-        hipLaunchKernelGGL(split_plan_ordered_kernel, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T, n_pairs,
-                           capacity, items, slot, stile, sslot, counts);
-    } else if (nc <= PLAN_ONE_BLOCK) {           // few chunks: replicated blocks with running carries
-        hipLaunchKernelGGL(split_plan_kernel, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T, n_pairs,
-                           capacity, static_cast<const uint64_t *>(nullptr), static_cast<const uint64_t *>(nullptr),
-                           static_cast<const uint64_t *>(nullptr), items, slot, stile, sslot, counts);
-    } else {
+        hipLaunchKernelGGL(split_plan_ordered_kernel<true>, dim3(SPLIT_REPLICAS), dim3(1024), 0, s, offs, t_count, T,
+                           n_pairs, capacity, static_cast<const uint32_t *>(nullptr), items, slot, stile, sslot,
+                           counts);
+    } else if (nc <= ORDER_CHUNKS) {             // a few chunks: longest first, chunk totals first
+        hipLaunchKernelGGL(split_chunk_totals_kernel, dim3(nc), dim3(1024), 0, s, offs, t_count, T, n_pairs, capacity,
+                           ctot);
+        MGS_LAUNCH_CHECK("split_chunk_totals_kernel");
+        hipLaunchKernelGGL(split_plan_ordered_kernel<false>, dim3(nc * SPLIT_REPLICAS), dim3(1024), 0, s, offs,
+                           t_count, T, n_pairs, capacity, ctot, items, slot, stile, sslot, counts);
+    } else {                                     // many chunks (beyond eight 1920 x 1080 views): tile order
         hipLaunchKernelGGL(split_sum_kernel, dim3(plan_grid(nc)), dim3(1024), 0, s, offs, t_count, T, n_pairs,
                            capacity, part_is, part_m);
         MGS_LAUNCH_CHECK("split_sum_kernel");

@@ -34,6 +34,10 @@ def cases():
     cam16 = mgs_data.look_at((0.0, 0.0, -4.0), width=16, height=16, f=16.0)
     out.append(("one_tile_540k", dense, cam16, None, {}))
     out.append(("one_tile_540k_tile_sort", dense, cam16, None, {"sorted_path": "tile_sort"}))
+    # a view of two split-plan chunks (14,400 tiles), dense middle tiles split
+    big = mgs_data.make_scene_uniform(100_000, 31, ls_mu=-3.1)
+    out.append(("view_2560x1440", big, mgs_data.look_at((0.1, 0.2, -4.0), width=2560, height=1440, f=1536.0), None,
+                {}))
     ub = mgs_data.make_scene_unbounded(30000, 8)
     cam = mgs_data.circle_poses(8, 10.0, 240, 160, f=240.0)[5]
     mlp = mgs_data.make_mlp(9)
