@@ -343,6 +343,57 @@ def _frame(R, ds, dm, cs, sorted_path, bg=(0.0, 0.0, 0.0)):
         R.blend_oit(cs, bg)
 
 
+def prune_leg(reps=50):
+    """Contribution-based pruning (Sec. 3.3, Appendix C's tau = 0.2): one iteration's votes on the
+    1M-Gaussian unbounded scene and on the 500k-Gaussian training scene, and the end of an
+    interval (compaction, then the gather of the 23 attribute planes of the survivors)."""
+    import numpy as np
+    import torch
+    import mgs_data
+    from paper_2603_11531_amd import prune
+
+    def timed(fn, before=None):
+        ts = []
+        for _ in range(reps):
+            if before is not None:
+                before()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    out = {}
+    for name, (scene, _, _, _) in (("unbounded_1m", mgs_data.make_config("unbounded", seed=0)),
+                                   ("train_500k", mgs_data.make_config("train", seed=0))):
+        t = {k: torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.float32)).cuda()
+             for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+        n = int(t["opacity_logit"].numel())
+        pr = prune.Pruner(n)
+        for _ in range(3):
+            pr.vote(t["opacity_logit"], t["log_scale"])
+        vote_ms = timed(lambda: pr.vote(t["opacity_logit"], t["log_scale"]))
+        # votes of a finished interval: about a fifth of the Gaussians over the bound
+        rng = np.random.default_rng(1)
+        saved = torch.as_tensor(np.where(rng.random(n) < 0.2, 700, 300).astype(np.int32)).cuda()
+        compact_ms = timed(pr.compact, before=lambda: pr.votes[:n].copy_(saved))
+        pr.votes[:n].copy_(saved)
+        pr.compact()
+        m = int(pr.n_keep.cpu()[0])
+        gather_ms = timed(lambda: [pr.gather(x, m) for x in t.values()])
+        planes = sum(int(x.numel()) // n for x in t.values())
+        vote_bytes = n * (16 + 8)                      # logit + 3 log-scales read, votes read + written
+        gather_bytes = planes * 4 * 2 * m + 4 * m       # survivors' planes read and written, the index
+        out[name] = dict(n=n, vote_ms=round(vote_ms, 4), vote_gbs=round(vote_bytes / vote_ms / 1e6, 1),
+                         vote_hbm_frac=round(vote_bytes / vote_ms / 1e6 / PEAK_HBM_GBS, 4),
+                         compact_ms=round(compact_ms, 4), survivors=m, planes=planes,
+                         gather_ms=round(gather_ms, 4), gather_gbs=round(gather_bytes / gather_ms / 1e6, 1))
+        del pr, t
+    return out
+
+
 def train_leg(steps=4):
     """Differentiable training step: 500k Gaussians, 4 views at 1600x1063, L1 loss against images of a
     perturbed copy, backward to every attribute and the MLP parameters."""
@@ -791,6 +842,8 @@ def main():
         out["large"] = large_leg()
         log("training-step leg ...")
         out["train"] = train_leg()
+        log("pruning leg ...")
+        out["prune"] = prune_leg()
     if not args.no_serve:
         log("serving leg ...")
         del R

@@ -532,6 +532,54 @@ int mgs_render_batch(const mgs_request *requests, const int32_t *n_requests, int
                      int64_t max_tiles, uint64_t capacity, float alpha_min, float alpha_max, void *ws,
                      size_t ws_bytes, uint32_t *n_pairs, int32_t *status, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Contribution-based pruning (Sec. 3.3; settings in Appendix C: tau = 0.2, I_prune = 1000,
+ * v = 0.6).  Per training iteration, a Gaussian whose opacity o = sigmoid(opacity_logit) lies
+ * under the tau-quantile of all opacities AND whose largest scale s_max = exp(max log_scale)
+ * lies under the tau-quantile of all largest scales is a pruning candidate and gains a vote.
+ * At the end of a pruning interval the Gaussians with more than I_prune * v votes are removed.
+ * Q_tau interpolates linearly between the sorted values at positions floor(tau (N - 1)) and
+ * the next; the candidate tests "o < Q_tau(o)" and "s_max < Q_tau(s_max)" are decided exactly
+ * (no rounding of Q_tau), on the stored logits and log-scales (sigmoid and exp are increasing).
+ * -0.0 and +0.0 count as equal; NaN parameters are not supported.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Workspace bytes of mgs_prune_vote / mgs_prune_compact for n Gaussians (n in [0, 2^31)). */
+int mgs_prune_workspace(int64_t n, size_t *bytes);
+
+/*
+ * mgs_prune_vote -- one iteration's votes.  opacity_logit [n], log_scale [3][n] (the
+ * mgs_gaussians layout), device, read only.  tau in [0, 1].  votes [n] uint32, device, in/out:
+ * votes[g] += 1 for every candidate g.  candidates [n] uint8 (device) receives 1 / 0 per
+ * Gaussian, or is NULL.  ws: mgs_prune_workspace(n) bytes, 256-byte aligned, no initial
+ * contents needed.  n = 0 enqueues nothing.  MGS_ERR_INVALID_ARG for NULL buffers, n out of
+ * range, tau outside [0, 1] or a small workspace.  Asynchronous on `stream`.
+ */
+int mgs_prune_vote(const float *opacity_logit, const float *log_scale, int64_t n, double tau, void *ws,
+                   size_t ws_bytes, uint32_t *votes, uint8_t *candidates, void *stream);
+
+/*
+ * mgs_prune_compact -- the end of a pruning interval.  Gaussian g survives when votes[g] <=
+ * max_votes, where max_votes = floor(I_prune * v) (votes are integers, so "more than I_prune
+ * * v votes" is "more than floor(I_prune * v)").  keep_index [n] uint32 (device) receives the
+ * survivors' indices in ascending order, *n_keep (device uint32) their count; entries of
+ * keep_index past *n_keep are unspecified.  votes [n] is reset to zero (the next interval
+ * counts from zero).  ws as for mgs_prune_vote.  Asynchronous on `stream`.
+ */
+int mgs_prune_compact(uint32_t *votes, int64_t n, uint32_t max_votes, void *ws, size_t ws_bytes,
+                      uint32_t *keep_index, uint32_t *n_keep, void *stream);
+
+/*
+ * mgs_gather_planes -- applies a compaction to SoA attribute planes: for p < planes and
+ * i < min(*n_index, n_max), dst[p * dst_stride + i] = src[p * src_stride + index[i]] (float32,
+ * device).  index (device uint32) holds indices into the source planes (each below the source
+ * count), as written by mgs_prune_compact; n_index (device uint32) its count; n_max is an upper
+ * bound of that count (rows past n_max are not written), dst_stride >= n_max.  dst must not
+ * overlap src.  Asynchronous on `stream`.
+ */
+int mgs_gather_planes(const float *src, int64_t src_stride, int planes, const uint32_t *index,
+                      const uint32_t *n_index, int64_t n_max, float *dst, int64_t dst_stride, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

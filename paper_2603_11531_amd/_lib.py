@@ -36,7 +36,8 @@ EXPORTED = [
     "mgs_project_weighted", "mgs_enhance_project_weighted", "mgs_mlp_f_pack", "mgs_enhance_project_mlp_f",
     "mgs_enhance_project_sh", "mgs_project_sortfree", "mgs_enhance_project_sortfree", "mgs_blend_sortfree",
     "mgs_blend_sortfree_split", "mgs_blend_oit_split_noalloc", "mgs_blend_census", "mgs_bounds_checked",
-    "mgs_bounds_status", "mgs_check_capacity",
+    "mgs_bounds_status", "mgs_check_capacity", "mgs_prune_workspace", "mgs_prune_vote", "mgs_prune_compact",
+    "mgs_gather_planes",
 ]
 MGS_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 # the appendix's MLP_f (hidden layers 256, 128, 64): name, offset, shape in the mgs.h layout
@@ -95,6 +96,10 @@ def load(path=None):
         "mgs_last_error": (C.c_char_p, []),
         "mgs_version": (C.c_char_p, []),
         "mgs_check_capacity": (i32, [vp, u64, P(C.c_uint64), vp]),
+        "mgs_prune_workspace": (i32, [i64, P(C.c_size_t)]),
+        "mgs_prune_vote": (i32, [vp, vp, i64, C.c_double, vp, C.c_size_t, vp, vp, vp]),
+        "mgs_prune_compact": (i32, [vp, i64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]),
+        "mgs_gather_planes": (i32, [vp, i64, i32, vp, vp, i64, vp, i64, vp]),
         "mgs_mlp_pack": (i32, [vp, vp, vp]),
         "mgs_enhance": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, vp, vp]),
         "mgs_project": (i32, [P(mgs_gaussians), P(mgs_camera), vp, vp, i32, f32, P(mgs_projected), vp]),

@@ -58,6 +58,16 @@ def test_host_side_validation(lib):
     assert lib.mgs_batch_workspace(1000, 1 << 20, 1000, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_bin_sorted_workspace(100, 4, 4, 1000, C.byref(nb)) == L.MGS_OK
     assert lib.mgs_check_capacity(None, 1000, None, None) == L.MGS_ERR_INVALID_ARG
+    # pruning: n in [0, 2^31), tau in [0, 1], n = 0 enqueues nothing
+    assert lib.mgs_prune_workspace(1000, C.byref(nb)) == L.MGS_OK and nb.value > 0
+    assert lib.mgs_prune_workspace(-1, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_workspace(1 << 31, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 0, 0.2, None, 0, None, None, None) == L.MGS_OK
+    assert lib.mgs_prune_vote(None, None, 10, 1.5, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 10, 0.2, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_compact(None, 10, 600, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_gather_planes(None, 10, 0, None, None, 10, None, 10, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_gather_planes(None, 10, 1, None, None, 10, None, 5, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
     # invalid camera / arguments are rejected before any device work
     cam = L.mgs_camera()
