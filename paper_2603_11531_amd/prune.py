@@ -75,6 +75,7 @@ class Pruner:
         index tensor) for every [.., n] float32 tensor of ``tensors``; the next interval's votes
         start from zero for the survivors.  Reads the survivor count back to the host."""
         self.compact(stream)
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
         m = int(self.n_keep.cpu()[0])
         out = {k: self.gather(t, m, stream) for k, t in tensors.items()}
         kept = self.keep_index[:m].clone()
