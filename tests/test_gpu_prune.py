@@ -149,3 +149,44 @@ def test_argument_checks(M):
     with pytest.raises(L.MgsError):
         L.check(L.lib().mgs_prune_vote(L.ptr(x), L.ptr(x), 10, 0.2, L.ptr(pr.ws), 16, L.ptr(pr.votes), None,
                                        L.stream_ptr()))
+
+
+def test_training_continues_on_the_pruned_scene(M):
+    """Pruning inside a training loop: three iterations of render, L1 loss, backward and a small
+    gradient step, each followed by the vote (checked against the oracle's votes on the same
+    parameter values); at the interval's end the pruned scene is the oracle's survivors in order,
+    renders bit-identically to the scene indexed by them, and trains on (backward runs)."""
+    say("test_training_continues_on_the_pruned_scene")
+    from paper_2603_11531_amd.autograd import render
+    scene = mgs_data.make_scene_uniform(3000, 9)
+    cam = mgs_data.look_at((0.2, -0.1, -4.0), width=96, height=80, f=96.0)
+    keys = mgs_data_keys()
+    params = {k: torch.tensor(np.ascontiguousarray(scene[k], np.float32), device="cuda", requires_grad=True)
+              for k in keys}
+    target = torch.full((3, 80, 96), 0.25, device="cuda")
+    pr = M.Pruner(3000, tau=0.2, interval=3, v=0.5)
+    want = np.zeros(3000, np.int64)
+    for it in range(3):
+        for p in params.values():
+            p.grad = None
+        (render(params, cam) - target).abs().mean().backward()
+        with torch.no_grad():
+            for k in ("opacity_logit", "log_scale"):
+                params[k] -= 50.0 * params[k].grad
+        pr.vote(params["opacity_logit"].detach(), params["log_scale"].detach())
+        want = P.prune_vote(want, params["opacity_logit"].detach().cpu().numpy(),
+                            params["log_scale"].detach().cpu().numpy(), 0.2)
+    torch.cuda.synchronize()
+    assert np.array_equal(pr.votes.cpu().numpy(), want)
+    keep = P.prune_survivors(want, 3, 0.5)
+    say(f"  survivors {keep.size} of 3000")
+    assert 0 < keep.size < 3000
+    host = {k: p.detach().cpu().numpy() for k, p in params.items()}
+    pruned, kept = pr.prune({k: p.detach() for k, p in params.items()})
+    assert np.array_equal(kept.cpu().numpy(), keep)
+    pruned = {k: t.requires_grad_(True) for k, t in pruned.items()}
+    indexed = {k: torch.tensor(np.ascontiguousarray(host[k][..., keep]), device="cuda") for k in keys}
+    img = render(pruned, cam)
+    assert torch.equal(img.detach(), render(indexed, cam))
+    (img - target).abs().mean().backward()
+    assert pruned["mean"].grad.shape == (3, keep.size) and torch.isfinite(pruned["mean"].grad).all()
