@@ -33,14 +33,16 @@ def _noalloc(M, R, cam_s, bg, out, aux):
 
 def test_noalloc_split_blend_equals_workspace_call(M):
     L = M._lib
-    cases = [  # dense lists first (split tiles, partial sums in the scratch), then a smaller view
-        (mgs_data.make_scene_uniform(40000, 12, ls_mu=-3.0), (0.1, -0.2, -4.0), 136, 120, (0.2, 0.3, 0.4)),
-        (mgs_data.make_scene_uniform(3000, 5, ls_mu=-2.8), (0.3, 0.1, -3.5), 72, 40, (0.5, 0.1, 0.0)),
+    cases = [  # a view of two split-plan chunks (14,400 tiles; the chunk totals in the scratch too),
+        # then dense lists (split tiles, partial sums in the scratch), then a smaller view
+        (mgs_data.make_scene_uniform(30000, 31, ls_mu=-3.1), (0.1, 0.2, -4.0), 2560, 1440, (0.25, 0.1, 0.4), 0.6),
+        (mgs_data.make_scene_uniform(40000, 12, ls_mu=-3.0), (0.1, -0.2, -4.0), 136, 120, (0.2, 0.3, 0.4), 1.0),
+        (mgs_data.make_scene_uniform(3000, 5, ls_mu=-2.8), (0.3, 0.1, -3.5), 72, 40, (0.5, 0.1, 0.0), 1.0),
     ]
-    for k, (scene, eye, W, H, bg) in enumerate(cases):
+    for k, (scene, eye, W, H, bg, fs) in enumerate(cases):
         say(f"test_noalloc_split_blend_equals_workspace_call: call {k + 1}, {scene['mean'].shape[1]} Gaussians "
             f"{W}x{H}")
-        cam = mgs_data.look_at(eye, width=W, height=H, f=float(W))
+        cam = mgs_data.look_at(eye, width=W, height=H, f=float(W) * fs)
         ds = M.DeviceScene(scene)
         R = M.Renderer(ds.n, W, H)
         ref = R.render(ds, cam, bg=bg, split=True, want_aux=True).clone()
@@ -53,6 +55,8 @@ def test_noalloc_split_blend_equals_workspace_call(M):
         torch.cuda.synchronize()
         say(f"  P = {R.pairs()}, longest list {longest}")
         if k == 0:
+            assert R.tiles_x * R.tiles_y > 8192
+        if k == 1:
             assert longest > 3 * 1024
         assert torch.equal(out, ref) and torch.equal(aux, ref_aux)
 
