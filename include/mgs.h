@@ -114,7 +114,8 @@ const char *mgs_last_error(void);
  * Checked builds.  libmgs_checked.so is this library built with MGS_CHECK_BOUNDS: its kernels
  * check the indices they derive (list positions and writes against the pair count and capacity,
  * rectangles against the tile grid, split-blend items and backward slots against their
- * workspace bounds); a failed check skips the access and sets a bit (MGS_BOUNDS_*).
+ * workspace bounds, pruning's survivor and gather indices); a failed check skips the access and
+ * sets a bit (MGS_BOUNDS_*).
  * mgs_bounds_checked: 1 in a checked build, else 0.
  * mgs_bounds_status: synchronises the device, writes the OR of the bits set since the last
  * clear to *flags (always 0 in an unchecked build) and, if `clear`, clears them.
@@ -126,6 +127,7 @@ const char *mgs_last_error(void);
 #define MGS_BOUNDS_SPLIT_ITEM   0x10u
 #define MGS_BOUNDS_BWD_SLOT     0x20u
 #define MGS_BOUNDS_BWD_ITEM     0x40u
+#define MGS_BOUNDS_PRUNE_INDEX  0x80u
 int mgs_bounds_checked(void);
 int mgs_bounds_status(uint32_t *flags, int clear);
 /* Library version string. */
@@ -572,8 +574,8 @@ int mgs_prune_compact(uint32_t *votes, int64_t n, uint32_t max_votes, void *ws, 
 /*
  * mgs_gather_planes -- applies a compaction to SoA attribute planes: for p < planes and
  * i < min(*n_index, n_max), dst[p * dst_stride + i] = src[p * src_stride + index[i]] (float32,
- * device).  index (device uint32) holds indices into the source planes (each below the source
- * count), as written by mgs_prune_compact; n_index (device uint32) its count; n_max is an upper
+ * device).  src_stride is at least the source count (also for one plane).  index (device
+ * uint32) holds indices into the source planes (each below the source count), as written by mgs_prune_compact; n_index (device uint32) its count; n_max is an upper
  * bound of that count (rows past n_max are not written), dst_stride >= n_max.  dst must not
  * overlap src.  Asynchronous on `stream`.
  */

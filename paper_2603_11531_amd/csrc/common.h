@@ -116,6 +116,7 @@ enum BoundsSite : uint32_t {
     BS_SPLIT_ITEM = 1u << 4,       // a split-blend work item or slot past its workspace bound
     BS_BWD_SLOT = 1u << 5,         // a backward pair slot past the capacity
     BS_BWD_ITEM = 1u << 6,         // a backward work item past its workspace bound
+    BS_PRUNE_INDEX = 1u << 7,      // a survivor index past n, or a gather index past its plane
 };
 #ifdef MGS_CHECK_BOUNDS
 static __device__ uint32_t tu_bounds_flags;

@@ -206,7 +206,10 @@ prune_write_kernel(uint32_t *__restrict__ votes, int64_t n, uint32_t max_votes, 
 #pragma unroll
         for (int j = 0; j < PLAN_ITEMS; ++j) {
             if (g0 + j < n) {
-                if ((bits >> j) & 1u) keep_index[o++] = uint32_t(g0 + j);
+                if ((bits >> j) & 1u) {
+                    if (MGS_CHECK(o < uint64_t(n), BS_PRUNE_INDEX)) keep_index[o] = uint32_t(g0 + j);
+                    ++o;
+                }
                 votes[g0 + j] = 0u;              // the next interval counts from zero
             }
         }
@@ -221,6 +224,7 @@ gather_planes_kernel(const float *__restrict__ src, int64_t src_stride, int plan
     const int64_t m = *n_index < uint64_t(n_max) ? int64_t(*n_index) : n_max;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < m; i += int64_t(gridDim.x) * 256) {
         const int64_t s = index[i];
+        if (!MGS_CHECK(s < src_stride, BS_PRUNE_INDEX)) continue;
         for (int p = 0; p < planes; ++p) dst[p * dst_stride + i] = src[p * src_stride + s];
     }
 }
@@ -316,7 +320,7 @@ extern "C" int mgs_gather_planes(const float *src, int64_t src_stride, int plane
     MGS_TRACE("mgs_gather_planes");
     using namespace mgs;
     MGS_REQUIRE(planes >= 1 && n_max >= 0 && n_max <= int64_t(INT32_MAX), "planes must be >= 1, n_max in [0, 2^31)");
-    MGS_REQUIRE(dst_stride >= n_max && src_stride >= 0, "dst_stride must be >= n_max");
+    MGS_REQUIRE(dst_stride >= n_max && src_stride >= 1, "dst_stride must be >= n_max, src_stride >= 1");
     if (n_max == 0) return MGS_OK;
     MGS_REQUIRE(src && index && n_index && dst, "src / index / n_index / dst is NULL");
     const int64_t b = (n_max + 255) / 256;

@@ -74,6 +74,19 @@ def main(path):
     slot.done_event.synchronize()
     for r in reqs:
         images[f"batch_{r.rid}"] = r.image.cpu().numpy().copy()
+    # pruning: two iterations' votes (the same candidates twice: more than I_prune v = 1), the
+    # compaction and the gather of every attribute plane
+    from paper_2603_11531_amd import prune
+    sc = mgs_data.make_scene_uniform(20_000, 41)
+    ts = {k: torch.from_numpy(np.ascontiguousarray(sc[k], np.float32)).cuda()
+          for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+    pr = prune.Pruner(20_000, interval=2, v=0.5)
+    for _ in range(2):
+        pr.vote(ts["opacity_logit"], ts["log_scale"])
+    pruned, kept = pr.prune(ts)
+    images["prune_kept"] = kept.cpu().numpy().copy()
+    for k, v in pruned.items():
+        images[f"prune_{k}"] = v.cpu().numpy().copy()
     # backward on dense tile lists, with the MLP
     scene = mgs_data.make_scene_uniform(40000, 31, half=2.2, ls_mu=-2.5)
     cam = mgs_data.look_at((0.1, -0.1, -4.0), width=96, height=96, f=96.0)

@@ -68,6 +68,7 @@ def test_host_side_validation(lib):
     assert lib.mgs_prune_compact(None, 10, 600, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_gather_planes(None, 10, 0, None, None, 10, None, 10, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_gather_planes(None, 10, 1, None, None, 10, None, 5, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_gather_planes(None, 0, 1, None, None, 10, None, 10, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_render_backward_workspace(100, 4, 4, 1000, 1, C.byref(nb)) == L.MGS_OK and nb.value > 0
     # invalid camera / arguments are rejected before any device work
     cam = L.mgs_camera()
