@@ -62,6 +62,29 @@ def test_sortfree_small_matches_oracle(M, w_bg):
     assert float((img - ref2).abs().max()) > 1e-2
 
 
+
+def test_sortfree_split_on_a_view_of_two_plan_chunks(M):
+    """Eq. 1 through the split blend on 2560x1440 (14,400 tiles: the longest-first plan over two
+    chunks) with dense middle tiles cut into ranges: equal to the per-tile Eq. 1 blend, which
+    the test above pins to the oracle."""
+    say("test_sortfree_split_on_a_view_of_two_plan_chunks")
+    scene = mgs_data.make_scene_uniform(100000, 31, ls_mu=-3.1)
+    cam = mgs_data.look_at((0.1, 0.2, -4.0), width=2560, height=1440, f=1536.0)
+    sigma, beta = mgs_data.make_sortfree_params(scene["mean"].shape[1], 6)
+    sf = (_dev(sigma), _dev(beta))
+    bg = (0.2, 0.4, 0.1)
+    ds = M.DeviceScene(scene)
+    R = M.Renderer(ds.n, cam.width, cam.height)
+    img = R.render(ds, cam, bg=bg, sortfree=sf, w_bg=0.35).double().cpu()
+    offs, _ = R.lists()
+    n = offs[1:] - offs[:-1]
+    img_tile = R.render(ds, cam, bg=bg, sortfree=sf, w_bg=0.35, split=False).double().cpu()
+    d = float((img - img_tile).abs().max())
+    say(f"  P={R.pairs()} longest {int(n.max())}; split vs per-tile {d:.3e}")
+    assert int(n.max()) > 2048 and R.tiles_x * R.tiles_y > 8192
+    assert d < 2e-6
+
+
 def test_sortfree_with_mlp_fused_and_unfused(M):
     """With the enhancement MLP (opacity head on): the fused enhance + project and the separate
     calls agree bit for bit, and the image follows the oracle's BF16 emulation."""
