@@ -57,7 +57,9 @@ def test_batch_equals_alone_across_graph_replays(S):
     slot = serve.BatchSlot(max_gaussians=200_000, max_tiles=4 * 8160, capacity=4_000_000, use_graphs=True)
     for rep, (names, res) in enumerate([
             (["a", "b", "c", "a"], [(96, 64), (130, 77), (200, 120), (33, 17)]),
-            (["c", "c", "b"], [(64, 64), (250, 140), (17, 33)])]):
+            (["c", "c", "b"], [(64, 64), (250, 140), (17, 33)]),
+            # 18,460 live tiles: the batch's split plan spans three chunks
+            (["c", "b", "a"], [(1920, 1080), (1600, 1063), (1280, 720)])]):
         reqs = _reqs(serve, names, 10 * rep, res)
         for r in reqs:
             r.image = torch.full((3, r.cam.height, r.cam.width), -1.0, device="cuda")
