@@ -19,6 +19,8 @@ Readings (the paper leaves these open):
   from zero (a Gaussian goes when its votes exceed the bound within an interval).
 * Survivors keep their order.
 
+Table 4 ablates the two criteria: ``criteria`` selects opacity alone, scale alone or both.
+
 Parity pins: ``tests/test_oracle_prune.py`` (rank counts, hand-computed fixtures with ties,
 an independent library quantile, special cases, the vote bound).
 """
@@ -54,20 +56,28 @@ def quantile(x, tau):
     return s[k] + (h - k) * (s[k + 1] - s[k])
 
 
-def prune_candidates(opacity_logit, log_scale, tau=PRUNE_TAU):
-    """C_prune = C_opacity and C_scale: o_g < Q_tau(o) and s_max(g) < Q_tau(s_max) (Sec. 3.3)."""
+def prune_candidates(opacity_logit, log_scale, tau=PRUNE_TAU, criteria="both"):
+    """C_prune = C_opacity and C_scale: o_g < Q_tau(o) and s_max(g) < Q_tau(s_max) (Sec. 3.3).
+    ``criteria`` "opacity" or "scale" keeps one of the two sets alone (Table 4's ablation)."""
+    if criteria not in ("both", "opacity", "scale"):
+        raise ValueError(f"unknown criteria {criteria!r}")
     o = prune_opacity(opacity_logit)
     s = prune_max_scale(log_scale)
     if o.size == 0:
         return np.zeros(0, dtype=bool)
     c_opacity = o < quantile(o, tau)
     c_scale = s < quantile(s, tau)
+    if criteria == "opacity":
+        return c_opacity
+    if criteria == "scale":
+        return c_scale
     return c_opacity & c_scale
 
 
-def prune_vote(votes, opacity_logit, log_scale, tau=PRUNE_TAU):
+def prune_vote(votes, opacity_logit, log_scale, tau=PRUNE_TAU, criteria="both"):
     """V^(t+1) = V^(t) + 1[g in C_prune^(t)] (Sec. 3.3)."""
-    return np.asarray(votes) + prune_candidates(opacity_logit, log_scale, tau).astype(np.asarray(votes).dtype)
+    cand = prune_candidates(opacity_logit, log_scale, tau, criteria)
+    return np.asarray(votes) + cand.astype(np.asarray(votes).dtype)
 
 
 def prune_survivors(votes, interval=PRUNE_INTERVAL, v=PRUNE_V):

@@ -102,6 +102,25 @@ def test_candidates_need_both_criteria_and_the_largest_axis():
     np.testing.assert_array_equal(got, np.arange(_below_count_distinct(n, 0.3)))
 
 
+
+def test_single_criterion_ablations():
+    """Table 4's ablation: opacity alone and scale alone are the rank-count sets of one attribute;
+    both is their intersection."""
+    rng = np.random.default_rng(7)
+    n = 200
+    logit = (rng.permutation(n) * 0.05 - 5.0).astype(np.float32)        # distinct, inside sigmoid's range
+    ls = rng.normal(-3.0, 0.5, (3, n)).astype(np.float32)
+    for tau in (0.2, 0.5):
+        want = _below_count_distinct(n, tau)
+        co = P.prune_candidates(logit, ls, tau, "opacity")
+        cs = P.prune_candidates(logit, ls, tau, "scale")
+        assert int(co.sum()) == want and int(cs.sum()) == want
+        np.testing.assert_array_equal(co, logit < np.sort(logit)[want])  # the `want` smallest logits
+        np.testing.assert_array_equal(P.prune_candidates(logit, ls, tau), co & cs)
+    with pytest.raises(ValueError):
+        P.prune_candidates(logit, ls, 0.2, "neither")
+
+
 def test_votes_and_the_removal_bound():
     votes = np.array([0, 599, 600, 601, 1000], np.uint32)
     # I_prune * v = 600 (Appendix C): 600 votes stay, 601 go
