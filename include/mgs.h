@@ -549,16 +549,22 @@ int mgs_render_batch(const mgs_request *requests, const int32_t *n_requests, int
 /* Workspace bytes of mgs_prune_vote / mgs_prune_compact for n Gaussians (n in [0, 2^31)). */
 int mgs_prune_workspace(int64_t n, size_t *bytes);
 
+/* Candidate criteria of mgs_prune_vote: Sec. 3.3 uses both; Table 4 ablates each alone. */
+#define MGS_PRUNE_OPACITY 1
+#define MGS_PRUNE_SCALE   2
+#define MGS_PRUNE_BOTH    3
+
 /*
  * mgs_prune_vote -- one iteration's votes.  opacity_logit [n], log_scale [3][n] (the
- * mgs_gaussians layout), device, read only.  tau in [0, 1].  votes [n] uint32, device, in/out:
+ * mgs_gaussians layout), device, read only.  tau in [0, 1].  criteria: MGS_PRUNE_BOTH (the
+ * method), or MGS_PRUNE_OPACITY / MGS_PRUNE_SCALE alone.  votes [n] uint32, device, in/out:
  * votes[g] += 1 for every candidate g.  candidates [n] uint8 (device) receives 1 / 0 per
  * Gaussian, or is NULL.  ws: mgs_prune_workspace(n) bytes, 256-byte aligned, no initial
  * contents needed.  n = 0 enqueues nothing.  MGS_ERR_INVALID_ARG for NULL buffers, n out of
- * range, tau outside [0, 1] or a small workspace.  Asynchronous on `stream`.
+ * range, tau outside [0, 1], unknown criteria or a small workspace.  Asynchronous on `stream`.
  */
-int mgs_prune_vote(const float *opacity_logit, const float *log_scale, int64_t n, double tau, void *ws,
-                   size_t ws_bytes, uint32_t *votes, uint8_t *candidates, void *stream);
+int mgs_prune_vote(const float *opacity_logit, const float *log_scale, int64_t n, double tau, int criteria,
+                   void *ws, size_t ws_bytes, uint32_t *votes, uint8_t *candidates, void *stream);
 
 /*
  * mgs_prune_compact -- the end of a pruning interval.  Gaussian g survives when votes[g] <=

@@ -47,6 +47,7 @@ MLPF_LAYOUT = (("W1", 0, (256, 22)), ("b1", 5632, (256,)), ("W2", 5888, (128, 25
 MGS_MLPF_PARAMS, MGS_MLPF_PACKED_BYTES = 47170, 104208
 MGS_WEIGHT_EQ3, MGS_WEIGHT_NO_DEPTH, MGS_WEIGHT_NO_SCALE, MGS_WEIGHT_SORTFREE = 0, 1, 2, 3
 MGS_NVQ_GROUPS, MGS_NVQ_DIM, MGS_NVQ_CODEWORDS = 5, 4, 1024
+MGS_PRUNE_OPACITY, MGS_PRUNE_SCALE, MGS_PRUNE_BOTH = 1, 2, 3
 
 
 class MgsError(RuntimeError):
@@ -97,7 +98,7 @@ def load(path=None):
         "mgs_version": (C.c_char_p, []),
         "mgs_check_capacity": (i32, [vp, u64, P(C.c_uint64), vp]),
         "mgs_prune_workspace": (i32, [i64, P(C.c_size_t)]),
-        "mgs_prune_vote": (i32, [vp, vp, i64, C.c_double, vp, C.c_size_t, vp, vp, vp]),
+        "mgs_prune_vote": (i32, [vp, vp, i64, C.c_double, i32, vp, C.c_size_t, vp, vp, vp]),
         "mgs_prune_compact": (i32, [vp, i64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]),
         "mgs_gather_planes": (i32, [vp, i64, i32, vp, vp, i64, vp, i64, vp]),
         "mgs_mlp_pack": (i32, [vp, vp, vp]),

@@ -21,7 +21,8 @@ namespace {
 constexpr int PR_THREADS = 1024;
 constexpr int PR_BINS = 2048;                    // bins of the 11-bit passes (the last has 1,024)
 constexpr int PR_PASSES = 3;
-constexpr int PR_KEYS = 2;                       // opacity, largest scale
+constexpr int PR_KEYS = 2;                       // opacity, largest scale (criteria bits 0 and 1)
+static_assert(MGS_PRUNE_OPACITY == 1 && MGS_PRUNE_SCALE == 2, "criteria bit q selects key q");
 constexpr int PR_HIST_WORDS = PR_PASSES * PR_KEYS * PR_BINS;
 constexpr unsigned PR_GRID_MAX = 1024;
 
@@ -146,7 +147,7 @@ prune_hist_kernel(const float *__restrict__ logit, const float *__restrict__ log
 // and votes[g] += candidate (candidates[g] too, if requested).
 __global__ void __launch_bounds__(PR_THREADS)
 prune_vote_kernel(const float *__restrict__ logit, const float *__restrict__ log_scale, int64_t n, uint32_t k,
-                  int frac, const uint32_t *__restrict__ hist, uint32_t *__restrict__ votes,
+                  int frac, int criteria, const uint32_t *__restrict__ hist, uint32_t *__restrict__ votes,
                   uint8_t *__restrict__ candidates) {
     __shared__ uint64_t s_wsum[16];
     __shared__ uint32_t s_out[PR_KEYS][3];
@@ -161,10 +162,10 @@ prune_vote_kernel(const float *__restrict__ logit, const float *__restrict__ log
     for (int64_t g = int64_t(blockIdx.x) * PR_THREADS + threadIdx.x; g < n; g += int64_t(gridDim.x) * PR_THREADS) {
         uint32_t key[PR_KEYS];
         gaussian_keys(logit, log_scale, n, g, key);
-        bool cand = true;
+        bool cand = true;                        // the criteria selected (bit q: key q), all must hold
 #pragma unroll
         for (int q = 0; q < PR_KEYS; ++q)
-            cand = cand && (inclusive[q] ? key[q] <= st.prefix[q] : key[q] < st.prefix[q]);
+            cand = cand && (!((criteria >> q) & 1) || (inclusive[q] ? key[q] <= st.prefix[q] : key[q] < st.prefix[q]));
         votes[g] += cand ? 1u : 0u;
         if (candidates) candidates[g] = cand ? 1 : 0;
     }
@@ -257,12 +258,13 @@ extern "C" int mgs_prune_workspace(int64_t n, size_t *bytes) {
     return MGS_OK;
 }
 
-extern "C" int mgs_prune_vote(const float *opacity_logit, const float *log_scale, int64_t n, double tau, void *ws,
-                              size_t ws_bytes, uint32_t *votes, uint8_t *candidates, void *stream) {
+extern "C" int mgs_prune_vote(const float *opacity_logit, const float *log_scale, int64_t n, double tau, int criteria,
+                              void *ws, size_t ws_bytes, uint32_t *votes, uint8_t *candidates, void *stream) {
     MGS_TRACE("mgs_prune_vote");
     using namespace mgs;
     MGS_REQUIRE(n >= 0 && n <= int64_t(INT32_MAX), "n must be in [0, 2^31)");
     MGS_REQUIRE(tau >= 0.0 && tau <= 1.0, "tau must be in [0, 1]");
+    MGS_REQUIRE(criteria >= 1 && criteria <= (MGS_PRUNE_OPACITY | MGS_PRUNE_SCALE), "unknown criteria %d", criteria);
     if (n == 0) return MGS_OK;
     MGS_REQUIRE(opacity_logit && log_scale && votes, "opacity_logit / log_scale / votes is NULL");
     const PruneLayout L = prune_layout(n);
@@ -284,7 +286,7 @@ extern "C" int mgs_prune_vote(const float *opacity_logit, const float *log_scale
     hipLaunchKernelGGL(prune_hist_kernel<2>, dim3(grid), dim3(PR_THREADS), 0, s, opacity_logit, log_scale, n, k, hist);
     MGS_LAUNCH_CHECK("prune_hist_kernel<2>");
     hipLaunchKernelGGL(prune_vote_kernel, dim3(grid), dim3(PR_THREADS), 0, s, opacity_logit, log_scale, n, k, frac,
-                       static_cast<const uint32_t *>(hist), votes, candidates);
+                       criteria, static_cast<const uint32_t *>(hist), votes, candidates);
     MGS_LAUNCH_CHECK("prune_vote_kernel");
     return MGS_OK;
 }

@@ -19,8 +19,14 @@ TAU, INTERVAL, V = 0.2, 1000, 0.6   # Appendix C: tau, I_prune, v
 class Pruner:
     """Vote counts (device uint32, stored as int32) and the pruning workspace for n Gaussians."""
 
-    def __init__(self, n, tau=TAU, interval=INTERVAL, v=V, device="cuda"):
+    CRITERIA = {"both": L.MGS_PRUNE_BOTH, "opacity": L.MGS_PRUNE_OPACITY, "scale": L.MGS_PRUNE_SCALE}
+
+    def __init__(self, n, tau=TAU, interval=INTERVAL, v=V, criteria="both", device="cuda"):
+        """``criteria``: "both" (Sec. 3.3), or "opacity" / "scale" alone (Table 4's ablation)."""
+        if criteria not in self.CRITERIA:
+            raise ValueError(f"criteria must be one of {sorted(self.CRITERIA)}")
         self.tau, self.interval, self.v, self.device = float(tau), int(interval), float(v), device
+        self.criteria = self.CRITERIA[criteria]
         self._resize(int(n))
 
     def _resize(self, n):
@@ -46,7 +52,8 @@ class Pruner:
             raise ValueError("opacity_logit / log_scale must be contiguous")
         if candidates is not None and (candidates.dtype != torch.uint8 or candidates.numel() < self.n):
             raise ValueError("candidates must be uint8 with n entries")
-        L.check(L.lib().mgs_prune_vote(L.ptr(opacity_logit), L.ptr(log_scale), self.n, self.tau, L.ptr(self.ws),
+        L.check(L.lib().mgs_prune_vote(L.ptr(opacity_logit), L.ptr(log_scale), self.n, self.tau, self.criteria,
+                                       L.ptr(self.ws),
                                        self.ws.numel() * 4, L.ptr(self.votes), L.ptr(candidates),
                                        L.stream_ptr(stream)))
 

@@ -62,9 +62,11 @@ def test_host_side_validation(lib):
     assert lib.mgs_prune_workspace(1000, C.byref(nb)) == L.MGS_OK and nb.value > 0
     assert lib.mgs_prune_workspace(-1, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_prune_workspace(1 << 31, C.byref(nb)) == L.MGS_ERR_INVALID_ARG
-    assert lib.mgs_prune_vote(None, None, 0, 0.2, None, 0, None, None, None) == L.MGS_OK
-    assert lib.mgs_prune_vote(None, None, 10, 1.5, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
-    assert lib.mgs_prune_vote(None, None, 10, 0.2, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 0, 0.2, 3, None, 0, None, None, None) == L.MGS_OK
+    assert lib.mgs_prune_vote(None, None, 10, 1.5, 3, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 10, 0.2, 3, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 10, 0.2, 0, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
+    assert lib.mgs_prune_vote(None, None, 10, 0.2, 4, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_prune_compact(None, 10, 600, None, 0, None, None, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_gather_planes(None, 10, 0, None, None, 10, None, 10, None) == L.MGS_ERR_INVALID_ARG
     assert lib.mgs_gather_planes(None, 10, 1, None, None, 10, None, 5, None) == L.MGS_ERR_INVALID_ARG

@@ -42,8 +42,8 @@ def _attrs(n, seed, ties=False, zeros=False):
     return logit, ls
 
 
-def _gpu_candidates(M, logit, ls, tau):
-    pr = M.Pruner(logit.size, tau=tau)
+def _gpu_candidates(M, logit, ls, tau, criteria="both"):
+    pr = M.Pruner(logit.size, tau=tau, criteria=criteria)
     cand = torch.zeros(max(logit.size, 1), dtype=torch.uint8, device="cuda")
     lt, lst = torch.from_numpy(logit).cuda(), torch.from_numpy(np.ascontiguousarray(ls)).cuda()
     pr.vote(lt, lst, cand)
@@ -61,6 +61,18 @@ def test_candidates_equal_oracle(M, n, kind):
         want = P.prune_candidates(logit, ls, tau)
         assert np.array_equal(got, want), f"{int((got != want).sum())} flags differ"
         assert np.array_equal(votes, want.astype(np.int32))
+
+
+
+@pytest.mark.parametrize("criteria", ["opacity", "scale"])
+def test_single_criterion_ablation_equals_oracle(M, criteria):
+    """Table 4's ablation: one criterion alone, on random attributes and with ties."""
+    for n, ties in ((5000, False), (20_001, True)):
+        logit, ls = _attrs(n, 77 + n, ties=ties)
+        for tau in (0.2, 0.6):
+            say(f"test_single_criterion_ablation_equals_oracle {criteria} n={n} tau={tau}")
+            got, _ = _gpu_candidates(M, logit, ls, tau, criteria)
+            assert np.array_equal(got, P.prune_candidates(logit, ls, tau, criteria))
 
 
 def test_all_equal_and_constant_axes(M):
@@ -144,10 +156,10 @@ def test_argument_checks(M):
     pr = M.Pruner(10)
     x = torch.zeros(10, device="cuda")
     with pytest.raises(L.MgsError):
-        L.check(L.lib().mgs_prune_vote(L.ptr(x), L.ptr(x), 10, 1.5, L.ptr(pr.ws), pr.ws.numel() * 4, L.ptr(pr.votes),
-                                       None, L.stream_ptr()))
+        L.check(L.lib().mgs_prune_vote(L.ptr(x), L.ptr(x), 10, 1.5, 3, L.ptr(pr.ws), pr.ws.numel() * 4,
+                                       L.ptr(pr.votes), None, L.stream_ptr()))
     with pytest.raises(L.MgsError):
-        L.check(L.lib().mgs_prune_vote(L.ptr(x), L.ptr(x), 10, 0.2, L.ptr(pr.ws), 16, L.ptr(pr.votes), None,
+        L.check(L.lib().mgs_prune_vote(L.ptr(x), L.ptr(x), 10, 0.2, 3, L.ptr(pr.ws), 16, L.ptr(pr.votes), None,
                                        L.stream_ptr()))
 
 
