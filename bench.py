@@ -346,7 +346,8 @@ def _frame(R, ds, dm, cs, sorted_path, bg=(0.0, 0.0, 0.0)):
 def prune_leg(reps=50):
     """Contribution-based pruning (Sec. 3.3, Appendix C's tau = 0.2): one iteration's votes on the
     1M-Gaussian unbounded scene and on the 500k-Gaussian training scene, and the end of an
-    interval (compaction, then the gather of the 23 attribute planes of the survivors)."""
+    interval (compaction, then the gather of the 23 attribute planes of the survivors); then
+    Table 5's threshold sweep (Gaussians left and frame rate) on the 1M scene."""
     import numpy as np
     import torch
     import mgs_data
@@ -391,6 +392,42 @@ def prune_leg(reps=50):
                          compact_ms=round(compact_ms, 4), survivors=m, planes=planes,
                          gather_ms=round(gather_ms, 4), gather_gbs=round(gather_bytes / gather_ms / 1e6, 1))
         del pr, t
+    # Table 5's threshold sweep on the 1M scene: Gaussians left after one pruning interval of
+    # unchanged attributes (every candidate votes in every iteration, so I_prune = 1 and v = 0.5
+    # prune the same set) and the OIT frame rate of what is left (MLP on, 1600x1063, 32 poses)
+    import paper_2603_11531_amd as M
+    scene, cams, mlp, _ = mgs_data.make_config("unbounded", seed=0)
+    full = {k: torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.float32)).cuda()
+            for k in ("mean", "log_scale", "quat", "opacity_logit", "sh")}
+    dm = M.DeviceMLP(mlp)
+    sweep = []
+    for tau in (None, 0.1, 0.2, 0.4, 0.6):
+        if tau is None:
+            kept = full
+        else:
+            pr = prune.Pruner(int(full["opacity_logit"].numel()), tau=tau, interval=1, v=0.5)
+            pr.vote(full["opacity_logit"], full["log_scale"])
+            kept, _ = pr.prune(full)
+            del pr
+        ds = M.DeviceScene.from_tensors(kept)
+        R = M.Renderer(ds.n, cams[0].width, cams[0].height)
+        for c in cams:                                  # every pose once with the capacity check
+            R.render(ds, c, dm)
+        torch.cuda.synchronize()
+        frames = 64
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(frames):
+            R.render(ds, cams[k % len(cams)], dm, check_capacity=False, fused=True)
+        e1.record()
+        e1.synchronize()
+        if R.pairs() > R.capacity:
+            raise RuntimeError("pair capacity exceeded inside the threshold sweep")
+        sweep.append(dict(tau=tau, gaussians=ds.n, fps=round(frames / (e0.elapsed_time(e1) * 1e-3), 1)))
+        del R, ds
+    out["threshold_sweep"] = sweep
+    # Table 5 (trained scenes, mobile GPU), for context: baseline, tau = 0.1, 0.2, 0.4, 0.6
+    out["paper_table5"] = dict(gaussians_million=[0.56, 0.55, 0.47, 0.34, 0.18], fps=[109, 111, 127, 141, 164])
     return out
 
 
