@@ -14,6 +14,7 @@ import torch
 from . import _lib as L
 
 TAU, INTERVAL, V = 0.2, 1000, 0.6   # Appendix C: tau, I_prune, v
+UNTIL = 25_000                      # Appendix C: pruning only during the first 25k iterations
 
 
 class Pruner:
@@ -88,3 +89,15 @@ class Pruner:
         kept = self.keep_index[:m].clone()
         self._resize(m)
         return out, kept
+
+    def step(self, iteration, tensors, until=UNTIL, stream=None):
+        """Appendix C's schedule for training iteration ``iteration`` (0-based): below ``until``,
+        vote on tensors["opacity_logit"] / tensors["log_scale"], and at the end of every pruning
+        interval prune every tensor.  Returns (tensors, kept index or None): the pruned tensors
+        at an interval's end, else the same tensors."""
+        if iteration >= until:
+            return tensors, None
+        self.vote(tensors["opacity_logit"], tensors["log_scale"], stream=stream)
+        if (iteration + 1) % self.interval:
+            return tensors, None
+        return self.prune(tensors, stream=stream)

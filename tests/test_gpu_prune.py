@@ -202,3 +202,31 @@ def test_training_continues_on_the_pruned_scene(M):
     assert torch.equal(img.detach(), render(indexed, cam))
     (img - target).abs().mean().backward()
     assert pruned["mean"].grad.shape == (3, keep.size) and torch.isfinite(pruned["mean"].grad).all()
+
+
+def test_schedule_prunes_at_interval_ends_and_stops(M):
+    """Pruner.step: votes every iteration below `until`, prunes at each interval's end (the
+    oracle's survivors of that interval, votes restarting at zero), nothing from `until` on."""
+    say("test_schedule_prunes_at_interval_ends_and_stops")
+    scene = mgs_data.make_scene_uniform(8000, 13)
+    t = {k: torch.tensor(np.ascontiguousarray(scene[k], np.float32), device="cuda") for k in mgs_data_keys()}
+    pr = M.Pruner(8000, tau=0.3, interval=2, v=0.5)
+    host = {k: np.ascontiguousarray(scene[k], np.float32) for k in mgs_data_keys()}
+    votes = np.zeros(8000, np.int64)
+    sizes = []
+    for it in range(6):
+        t, kept = pr.step(it, t, until=4)
+        if it < 4:
+            votes = P.prune_vote(votes, host["opacity_logit"], host["log_scale"], 0.3)
+        if it in (1, 3):
+            keep = P.prune_survivors(votes, 2, 0.5)
+            assert kept is not None and np.array_equal(kept.cpu().numpy(), keep)
+            host = {k: v[..., keep] for k, v in host.items()}
+            votes = np.zeros(keep.size, np.int64)
+        else:
+            assert kept is None
+        sizes.append(pr.n)
+        assert np.array_equal(t["sh"].cpu().numpy(), host["sh"])
+    torch.cuda.synchronize()
+    say(f"  sizes {sizes}")
+    assert sizes[0] == 8000 and sizes[1] < 8000 and sizes[3] < sizes[1] and sizes[3] == sizes[5]
